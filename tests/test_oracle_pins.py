@@ -1,0 +1,335 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests needs a GPU.  Each one checks the oracle against something
+other than itself: brute-force loops, closed forms of the planted data model,
+exhaustive NNLS, exact invariants of the projection/dual update, the paper's
+own form of the iteration, the block-partitioned form of Appendix B, and the
+mean RFE values printed in Tables 1 and 2.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import ntf_synth
+from oracle import ntf_oracle as orc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_factors(dims, F, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.random((d, F)) for d in dims]
+
+
+# --------------------------------------------------------------------------- Section II
+
+def test_khatri_rao_entries():
+    rng = np.random.default_rng(1)
+    P, Q = rng.random((3, 4)), rng.random((5, 4))
+    KR = orc.khatri_rao(P, Q)
+    for p in range(3):
+        for q in range(5):
+            for f in range(4):
+                assert KR[p * 5 + q, f] == P[p, f] * Q[q, f]
+
+
+def test_unfoldings_match_cp_model_bruteforce():
+    # eq. f_X_matr: W^(1) = A (C.B)^T, W^(2) = B (C.A)^T, W^(3) = C (B.A)^T,
+    # against a CP tensor built with explicit index loops.
+    I, J, K, F = 3, 4, 5, 2
+    A, B, C = _rand_factors((I, J, K), F, 2)
+    W = np.zeros((I, J, K))
+    for i in range(I):
+        for j in range(J):
+            for k in range(K):
+                W[i, j, k] = sum(A[i, f] * B[j, f] * C[k, f] for f in range(F))
+    np.testing.assert_allclose(orc.reconstruct([A, B, C]), W, rtol=1e-14)
+    for n, Hn in enumerate((A, B, C)):
+        np.testing.assert_allclose(orc.unfold(W, n), Hn @ orc.kr_for_mode([A, B, C], n).T, rtol=1e-13)
+
+
+def test_mttkrp_bruteforce_loops():
+    I, J, K, F = 4, 3, 5, 3
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((I, J, K))
+    Hs = _rand_factors((I, J, K), F, 4)
+    dims = (I, J, K)
+    for n in range(3):
+        Wb = np.zeros((dims[n], F))
+        for i in range(I):
+            for j in range(J):
+                for k in range(K):
+                    idx = (i, j, k)
+                    for f in range(F):
+                        prod = X[i, j, k]
+                        for m in range(3):
+                            if m != n:
+                                prod *= Hs[m][idx[m], f]
+                        Wb[idx[n], f] += prod
+        np.testing.assert_allclose(orc.mttkrp(X, Hs, n), Wb, rtol=1e-12, atol=1e-13)
+
+
+def test_mttkrp_planted_closed_form():
+    # Noiseless planted X = [A0,B0,C0]:  W_1 = A0 ((B0^T H2) * (C0^T H3)) and
+    # cyclically; derived from eq. f_X_matr and the Gram identity of IV-A.
+    dims, F = (20, 30, 25), 4
+    pt = ntf_synth.planted(dims, F, seed=11, dtype=np.float64)
+    Hs = _rand_factors(dims, 6, 12)   # a different rank for the probes
+    P0 = [pt.A0, pt.B0, pt.C0]
+    for n in range(3):
+        others = [m for m in range(3) if m != n]
+        closed = P0[n] @ ((P0[others[0]].T @ Hs[others[0]]) * (P0[others[1]].T @ Hs[others[1]]))
+        np.testing.assert_allclose(orc.mttkrp(pt.X, Hs, n), closed, rtol=1e-12)
+
+
+def test_gram_hadamard_identity():
+    Hs = _rand_factors((6, 7, 8), 5, 5)
+    for n in range(3):
+        KR = orc.kr_for_mode(Hs, n)
+        np.testing.assert_allclose(orc.gram_hadamard(Hs, n), KR.T @ KR, rtol=1e-13)
+
+
+def test_rho_trace_and_guard():
+    G = np.diag([1.0, 2.0, 3.0, 6.0])
+    assert orc.rho_trace(G) == 3.0
+    assert orc.rho_trace(np.zeros((3, 3)), rho0=1.0) == 1.0
+    assert orc.rho_trace(np.full((2, 2), np.nan), rho0=2.5) == 2.5
+
+
+# --------------------------------------------------------------------------- inner sweep
+
+def _spd(F, seed, cond=None):
+    rng = np.random.default_rng(seed)
+    M = rng.random((F + 3, F))
+    return M.T @ M
+
+
+def test_inner_invariants_exact_every_iteration():
+    # H >= 0, U >= 0 and H * U == 0 exactly after every iteration (either h or
+    # u is exactly zero because u = h - v with h = max(0, v)).
+    F = 7
+    G = _spd(F, 21)
+    rng = np.random.default_rng(22)
+    W = rng.standard_normal((50, F)) * 3
+    H = rng.random((50, F))
+    U = np.zeros((50, F))
+    rho = orc.rho_trace(G)
+    for _ in range(25):
+        H, U, Ht, _ = orc.inner_sweep(W, H, U, G, rho, 1)
+        assert np.all(H >= 0) and np.all(U >= 0)
+        assert np.all(H * U == 0.0)
+        assert np.all(np.isfinite(U))
+
+
+@pytest.mark.parametrize("F", [1, 3, 6])
+def test_inner_converges_to_bruteforce_nnls(F):
+    G = _spd(F, 30 + F)
+    rng = np.random.default_rng(31)
+    W = rng.standard_normal((12, F)) * 2
+    H, U, _, _ = orc.inner_sweep(W, np.zeros_like(W), np.zeros_like(W), G, orc.rho_trace(G), 4000)
+    for i in range(W.shape[0]):
+        np.testing.assert_allclose(H[i], orc.nnls_bruteforce(G, W[i]), atol=1e-9)
+    # stationarity of eq. KKT_NTF with Y = -rho U:  rho U = H G - W
+    rho = orc.rho_trace(G)
+    np.testing.assert_allclose(rho * U, H @ G - W, atol=1e-8)
+
+
+def test_inner_converges_to_lawson_hanson_larger_F():
+    F = 12
+    G = _spd(F, 40)
+    rng = np.random.default_rng(41)
+    W = rng.standard_normal((20, F))
+    H, _, _, _ = orc.inner_sweep(W, np.zeros_like(W), np.zeros_like(W), G, orc.rho_trace(G), 20000)
+    np.testing.assert_allclose(H, orc.nnls_rows(G, W), atol=1e-8)
+    assert np.max(orc.kkt_violation(G, W, H)) < 1e-8
+
+
+def test_F1_closed_form():
+    # F = 1: the per-row NNLS is h* = max(0, w/g).
+    g = 2.5
+    w = np.array([[3.0], [-1.0], [0.5], [0.0]])
+    H, _, _, _ = orc.inner_sweep(w, np.zeros_like(w), np.zeros_like(w), np.array([[g]]), 1.7, 3000)
+    np.testing.assert_allclose(H[:, 0], np.maximum(0.0, w[:, 0] / g), atol=1e-12)
+
+
+def test_bruteforce_nnls_is_the_minimiser():
+    # The exhaustive solver must beat random feasible points (sanity of the pin itself).
+    F = 5
+    G = _spd(F, 50)
+    w = np.random.default_rng(51).standard_normal(F)
+    h = orc.nnls_bruteforce(G, w)
+    val = 0.5 * h @ G @ h - w @ h
+    rng = np.random.default_rng(52)
+    for _ in range(2000):
+        z = np.maximum(0.0, h + 0.1 * rng.standard_normal(F))
+        assert 0.5 * z @ G @ z - w @ z >= val - 1e-12
+
+
+def test_early_stop_rows():
+    F = 6
+    G = _spd(F, 60)
+    rng = np.random.default_rng(61)
+    W = rng.standard_normal((30, F))
+    z = np.zeros_like(W)
+    rho = orc.rho_trace(G)
+    Hf, _, _, inf_f = orc.inner_sweep(W, z, z, G, rho, 50)
+    He, _, _, inf_e = orc.inner_sweep(W, z, z, G, rho, 50, eps_abs=1e-30, eps_rel=1e-30)
+    np.testing.assert_array_equal(Hf, He)            # never met -> same as fixed T
+    assert np.all(inf_e["iters"] == 50)
+    H3, _, _, inf3 = orc.inner_sweep(W, z, z, G, rho, 5000, eps_abs=1e-9, eps_rel=1e-9)
+    assert np.all(inf3["iters"] < 5000) and np.all(inf3["iters"] >= 1)
+    assert np.max(orc.kkt_violation(G, W, H3)) < 1e-6
+
+
+# --------------------------------------------------------------------------- outer loop
+
+def test_exact_block_coordinate_descent_is_monotone():
+    # Inner iterations run to convergence -> each mode update is an exact NNLS
+    # block update (NALS), so f never increases.
+    dims, F = (9, 10, 11), 3
+    pt = ntf_synth.planted(dims, F, seed=70, sigma2=1e-2, dtype=np.float64)
+    st = orc.init_state(ntf_synth.init_factors(dims, F, 70))
+    opts = orc.Opts(inner_iters=3000, eps_abs=1e-13, eps_rel=1e-13)
+    f_prev = orc.objective(pt.X, st.H)
+    for _ in range(8):
+        orc.outer_step(pt.X, st, opts)
+        f = orc.objective(pt.X, st.H)
+        assert f <= f_prev * (1 + 1e-12) + 1e-14
+        f_prev = f
+
+
+def test_planted_noiseless_recovery():
+    # Noiseless exact-rank data: no error floor (Section VI-C).  Restarts from
+    # another random point are allowed, as in the paper's restart strategy.
+    dims, F = (10, 12, 14), 3
+    pt = ntf_synth.planted(dims, F, seed=80, dtype=np.float64)
+    best = 1.0
+    for restart in range(4):
+        st = orc.init_state(ntf_synth.init_factors(dims, F, 80 + 17 * restart))
+        orc.run(pt.X, st, orc.Opts(inner_iters=5), 1500)
+        best = min(best, orc.rfe(pt.X, st.H))
+        if best < 1e-6:
+            break
+    assert best < 1e-6
+
+
+def test_kkt_at_convergence():
+    # eq. KKT_NTF at a converged point, with Y = -rho U.
+    dims, F = (8, 9, 10), 2
+    pt = ntf_synth.planted(dims, F, seed=90, sigma2=1e-3, dtype=np.float64)
+    st = orc.init_state(ntf_synth.init_factors(dims, F, 90))
+    orc.run(pt.X, st, orc.Opts(inner_iters=5), 3000)
+    scale = np.linalg.norm(pt.X)
+    for n in range(3):
+        KR = orc.kr_for_mode(st.H, n)
+        Y = -st.rho[n] * st.U[n]
+        grad = (orc.unfold(pt.X, n) - st.H[n] @ KR.T) @ KR - Y
+        assert np.linalg.norm(grad) < 1e-6 * scale ** 2
+        assert np.linalg.norm(st.H[n] - st.P[n]) < 1e-8 * np.linalg.norm(st.H[n])
+        assert np.all(Y <= 0) and np.all(Y * st.H[n] == 0)
+
+
+def test_paper_form_equals_inner_sweep_form():
+    # Eq. ADMoM_NTF / ADMM_NTF_ALS_C as printed (explicit Y, explicit KR^T KR,
+    # general solve) equals the sweep form with T = 1, fixed rho, the primal
+    # fed forward and the paper's initialisation, under H = A-tilde, U = -Y/rho.
+    dims, F = (7, 8, 9), 3
+    pt = ntf_synth.planted(dims, F, seed=100, sigma2=1e-2, dtype=np.float64)
+    H0 = ntf_synth.init_factors(dims, F, 100)
+    rho = [1.3, 0.7, 2.1]
+    P = [h.copy() for h in H0]
+    Aux = [np.zeros_like(h) for h in H0]
+    Y = [np.zeros_like(h) for h in H0]
+    st = orc.init_state(H0, paper=True)
+    st.rho = list(rho)
+    opts = orc.Opts(inner_iters=1, rho_policy=orc.RHO_FIXED, factor_source=1)
+    for _ in range(6):
+        P, Aux, Y = orc.paper_admom_iteration(pt.X, P, Aux, Y, rho)
+        orc.outer_step(pt.X, st, opts)
+        for n in range(3):
+            np.testing.assert_allclose(st.P[n], P[n], rtol=1e-9, atol=1e-11)
+            np.testing.assert_allclose(st.H[n], Aux[n], rtol=1e-9, atol=1e-11)
+            np.testing.assert_allclose(-rho[n] * st.U[n], Y[n], rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("blocks", [2, 3])
+def test_partitioned_update_equals_centralized(blocks):
+    # Appendix B: the block-partitioned update evolves exactly like the centralized one.
+    dims, F = (9, 11, 7), 3
+    pt = ntf_synth.planted(dims, F, seed=110, sigma2=1e-2, dtype=np.float64)
+    Hs = ntf_synth.init_factors(dims, F, 110)
+    rng = np.random.default_rng(111)
+    for n in range(3):
+        U = rng.random(Hs[n].shape) * 0.1
+        W = orc.mttkrp(pt.X, Hs, n)
+        G = orc.gram_hadamard(Hs, n)
+        rho = orc.rho_trace(G)
+        Hc, Uc, _, _ = orc.inner_sweep(W, Hs[n], U, G, rho, 3)
+        Hp, Up = orc.partitioned_mode_update(pt.X, Hs, Hs[n], U, n, rho, 3, blocks)
+        np.testing.assert_allclose(Hp, Hc, rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(Up, Uc, rtol=1e-11, atol=1e-12)
+
+
+def test_adaptive_rho_rule():
+    # eq. varying_penalty_rule
+    o = orc.Opts(mu=8, tau_incr=4, tau_decr=2)
+    assert orc._adapt_rho(1.0, 9.0, 1.0, o) == 4.0
+    assert orc._adapt_rho(1.0, 1.0, 9.0, o) == 0.5
+    assert orc._adapt_rho(1.0, 1.0, 1.0, o) == 1.0
+
+
+# --------------------------------------------------------------------------- noise floor
+
+def _rfe_floor(dims, F, sigma2=None, snr_db=None, factor_ms=None):
+    I, J, K = dims
+    n = I * J * K
+    dof = (I + J + K - 2) * F
+    if snr_db is not None:
+        base = math.sqrt(1.0 / (1.0 + 10 ** (snr_db / 10)))
+    else:
+        ex2 = F * F / 64.0 + F * (1 / 27.0 - 1 / 64.0)    # E[x0^2] for iid U[0,1] factors
+        base = math.sqrt(sigma2 / (ex2 + sigma2))
+    return base * math.sqrt(1.0 - dof / n)
+
+
+def test_noise_floor_formula_reproduces_tables():
+    # The closed-form noise floor (derived for U[0,1] planted factors) against
+    # every mean RFE printed in Tables 1 and 2.
+    with open(os.path.join(GOLDEN, "table1_mean_rfe.json")) as fh:
+        rows = json.load(fh)["rows"]
+    for r in rows:
+        pred = _rfe_floor(r["dims"], r["F"], sigma2=r["sigma2"])
+        assert abs(pred - r["mean_rfe"]) <= 0.01 * r["mean_rfe"] + 5e-5, r
+
+
+def test_oracle_reaches_noise_floor_40cubed():
+    # 40^3, F = 5, 20 dB (the small FP64 workload): the converged RFE sits on
+    # the noise floor of the data model (statistical, +-3%).
+    dims, F = (40, 40, 40), 5
+    pt = ntf_synth.planted(dims, F, seed=ntf_synth.config_seed(1), snr_db=20.0, clip=True,
+                           dtype=np.float64)
+    st = orc.init_state(ntf_synth.init_factors(dims, F, ntf_synth.config_seed(1)))
+    orc.run(pt.X, st, orc.Opts(inner_iters=5), 400)
+    r = orc.rfe(pt.X, st.H)
+    assert abs(r - _rfe_floor(dims, F, snr_db=20.0)) < 0.03 * r
+
+
+# --------------------------------------------------------------------------- mixed precision input
+
+def test_slab_quantisation_against_torch_bfloat16():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(120)
+    X = (rng.random((5, 6, 7)) * np.array([1e-3, 1.0, 7.0, 300.0, 0.0])[:, None, None]).astype(np.float32)
+    Xq, s = orc.quantize_slabs_bf16(X)
+    for i in range(5):
+        m = np.max(np.abs(X[i]))
+        if m == 0:
+            assert s[i] == 1.0
+            continue
+        assert 1.0 <= m / s[i] < 2.0
+        assert math.log2(s[i]) == int(math.log2(s[i]))
+        ref = torch.from_numpy(X[i] / np.float32(s[i])).to(torch.bfloat16).to(torch.float64).numpy()
+        np.testing.assert_array_equal(Xq[i], ref)
