@@ -1,0 +1,270 @@
+"""Benchmark of the ADMoM NTF hot path on one MI355X.
+
+A step is one outer ADMoM iteration (three mode updates: MTTKRP, Gram
+Hadamard product, FP64 Cholesky, fused inner sweep) over a synthetic planted
+tensor resident in HBM.  Default workload: 1000 x 800 x 600 tensor of F = 64
+Exponential(1) planted factors at 30 dB SNR, 10 inner iterations, in the
+mixed-precision arm (BF16 MTTKRP with FP32 accumulation, FP32 Gram, FP64
+Cholesky/solves); the FP32 arm is timed beside it.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--ttt]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: dims, F, factor distribution, SNR dB, clip, inner iterations, arms
+    "c1": dict(dims=(40, 40, 40), F=5, dist="uniform", snr=20.0, clip=True, T=5, config=1,
+               arms=("fp64",)),
+    "c2": dict(dims=(400, 400, 400), F=20, dist="uniform", snr=20.0, clip=False, T=10, config=2,
+               arms=("fp32", "mixed")),
+    "c3": dict(dims=(1000, 800, 600), F=64, dist="exponential", snr=30.0, clip=False, T=10,
+               config=3, arms=("mixed", "fp32")),
+}
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1409_2383_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_solver(ntf, torch, Xd, H0, arm, T, dev):
+    prec = {"fp32": ntf.PREC_F32, "mixed": ntf.PREC_BF16_MIXED, "fp64": ntf.PREC_F64}[arm]
+    fdt = torch.float64 if arm == "fp64" else torch.float32
+    H = [torch.from_numpy(h).to(dev, dtype=fdt) for h in H0]
+    X = Xd.to(fdt) if Xd.dtype != fdt else Xd
+    return ntf.NtfAdmm(X, H, opts=ntf.AdmmOptions(inner_iters=T, precision=prec)), H
+
+
+def time_steps(torch, solver, steps, warmup):
+    for _ in range(warmup):
+        solver.step()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        solver.step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def time_passes(torch, solver, reps):
+    """Average duration of each MTTKRP kernel launched on its own (HIP events
+    on the stream the library launches on: torch's current stream)."""
+    s = torch.cuda.current_stream()
+    out = {}
+    for name, which in (("pass1", 0), ("mode2", 1), ("pass3", 2)):
+        solver.launch_pass(which)          # warm
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            solver.launch_pass(which)
+        e1.record(s)
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps   # ms
+    return out
+
+
+def cpu_baseline(X64, H0, T, sample_slabs):
+    """The FP64 oracle (as it stands) on the host: one outer iteration over the
+    first `sample_slabs` mode-1 slabs of the same tensor, scaled to the full
+    tensor by the slab ratio (MTTKRP work is linear in I)."""
+    from oracle import ntf_oracle as orc
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        cores = os.cpu_count() or 1
+    I = X64.shape[0]
+    S = min(I, sample_slabs)
+    Xs = np.ascontiguousarray(X64[:S], dtype=np.float64)
+    st = orc.init_state([H0[0][:S].astype(np.float64), H0[1].astype(np.float64),
+                         H0[2].astype(np.float64)])
+    t0 = time.perf_counter()
+    orc.outer_step(Xs, st, orc.Opts(inner_iters=T))
+    dt = time.perf_counter() - t0
+    full = dt * I / S
+    return {"value": 1.0 / full, "unit": "outer_iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 outer iteration (T={T}) of the FP64 oracle on the first {S} of {I} "
+                      f"mode-1 slabs ({dt:.1f} s), scaled by {I}/{S}",
+            "seconds_measured": dt}
+
+
+def time_to_target(torch, ntf, Xd, H0, T, arms, dev, ref_arm="fp64", max_outer=3000, every=10,
+                   tol=1e-4):
+    """Time for each arm to reach (RFE - RFE*)/RFE* <= tol.  RFE* is the RFE
+    the reference arm converges to (|dRFE|/RFE < 1e-9 over `every` steps, or
+    the cap).  Step time is measured with HIP events; fits are untimed."""
+    res = {}
+    ref, H = make_solver(ntf, torch, Xd, H0, ref_arm, T, dev)
+    prev = None
+    it = 0
+    while it < max_outer:
+        ref.run(every, stats=False)
+        it += every
+        r = ref.fit()
+        if prev is not None and abs(prev - r) < 1e-9 * r:
+            break
+        prev = r
+    rfe_star = ref.fit()
+    ref.close()
+    del ref, H
+    torch.cuda.empty_cache()
+    res["rfe_star"] = rfe_star
+    res["rfe_star_source"] = f"{ref_arm} GPU run to |dRFE|/RFE < 1e-9 ({it} outer iterations)"
+    s = torch.cuda.current_stream()
+    for arm in arms:
+        solver, H = make_solver(ntf, torch, Xd, H0, arm, T, dev)
+        solver.step()                        # graph capture, untimed
+        torch.cuda.synchronize()
+        total_ms, it = 0.0, 1
+        hit = None
+        r = solver.fit()
+        trace = [(it, 0.0, r)]
+        while it < max_outer:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(every):
+                solver.step()
+            e1.record(s)
+            torch.cuda.synchronize()
+            total_ms += e0.elapsed_time(e1)
+            it += every
+            r = solver.fit()
+            trace.append((it, total_ms, r))
+            if (r - rfe_star) / rfe_star <= tol:
+                hit = (it, total_ms, r)
+                break
+        res[arm] = {"reached": hit is not None, "outer_iters": hit[0] if hit else None,
+                    "seconds": hit[1] / 1e3 if hit else None, "rfe": r,
+                    "rel_to_star": (r - rfe_star) / rfe_star, "trace_tail": trace[-3:]}
+        solver.close()
+        del solver, H
+        torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--pass-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-slabs", type=int, default=0)
+    ap.add_argument("--ttt", action="store_true", help="also measure time to rel fit 1e-4")
+    ap.add_argument("--single-arm", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import ntf_synth
+    import paper_1409_2383_amd as ntf
+    ntf.library_path()
+    dev = torch.device("cuda:0")
+    wl = WORKLOADS[args.workload]
+    dims, F, T = wl["dims"], wl["F"], wl["T"]
+    seed = ntf_synth.config_seed(wl["config"])
+    log(f"[bench] generating {dims} F={F} ({wl['dist']}, {wl['snr']} dB) seed {seed}")
+    t0 = time.perf_counter()
+    x_dt = np.float64 if wl["arms"][0] == "fp64" else np.float32
+    pt = ntf_synth.planted(dims, F, seed, dist=wl["dist"], snr_db=wl["snr"], clip=wl["clip"],
+                           dtype=x_dt)
+    H0 = ntf_synth.init_factors(dims, F, seed, dtype=np.float64)
+    Xd = torch.from_numpy(pt.X).to(dev)
+    log(f"[bench] data ready in {time.perf_counter() - t0:.1f} s")
+
+    arms = wl["arms"][:1] if args.single_arm else wl["arms"]
+    results = {}
+    for arm in arms:
+        solver, H = make_solver(ntf, torch, Xd, H0, arm, T, dev)
+        ms, wall = time_steps(torch, solver, args.steps, args.warmup)
+        passes = time_passes(torch, solver, args.pass_reps)
+        nbytes = solver.plan_info()
+        results[arm] = {"ms_per_step": ms, "wall_s": wall, "outer_iters_per_s": 1e3 / ms,
+                        "pass_ms": passes, "pass_bytes": nbytes,
+                        "pass_gbs": {k: nbytes[k] / (passes[k] * 1e-3) / 1e9 for k in passes}}
+        log(f"[bench] {arm}: {ms:.3f} ms/step, passes {passes}")
+        solver.close()
+        del solver, H
+        torch.cuda.empty_cache()
+
+    head = arms[0]
+    r = results[head]
+    dom = max(("pass1", "pass3"), key=lambda k: r["pass_ms"][k])
+    achieved = r["pass_gbs"][dom]
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{head}_{dom}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tj = json.load(fh)
+        if tj.get("src_hash") == src_hash():
+            traffic = tj.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                "algorithmic_bytes_per_launch": r["pass_bytes"][dom],
+                "avg_launch_ms": r["pass_ms"][dom]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        slabs = args.cpu_sample_slabs or {"c1": 40, "c2": 100, "c3": 100}[args.workload]
+        log(f"[bench] CPU oracle baseline on {slabs} slabs")
+        cpu = cpu_baseline(pt.X, H0, T, slabs)
+
+    ttt = None
+    if args.ttt and args.workload == "c3":
+        log("[bench] time to rel fit 1e-4")
+        ttt = time_to_target(torch, ntf, Xd, H0, T, ("mixed", "fp32"), dev)
+
+    dtype = {"mixed": "bf16", "fp32": "f32", "fp64": "f64"}[head]
+    line = {
+        "metric": "NTF outer iters/s + MTTKRP GB/s (% HBM peak), mixed vs FP32 at rel fit 1e-4",
+        "value": r["outer_iters_per_s"], "unit": "outer_iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, dims))} dense, F={F} planted {wl['dist']} "
+                               f"factors, {wl['snr']:.0f} dB, T={T} inner iters, {head} arm",
+                   "dims": list(dims), "F": F, "inner_iters": T, "arm": head},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "arms": results,
+    }
+    if ttt is not None:
+        line["time_to_rel_fit_1e-4"] = ttt
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * ntf_admm.h -- C ABI of the gfx950 (MI355X) ADMoM non-negative CP
+ * factorisation library, libntf_admm.so.
+ *
+ * Method: Liavas & Sidiropoulos, "Parallel algorithms for constrained tensor
+ * factorization via the alternating direction method of multipliers".
+ * The problem is eq. Problem_NTF (Section II): given a dense 3-way tensor X
+ * and a rank F, find A, B, C >= 0 minimising 1/2 ||X - [A,B,C]||_F^2.  One
+ * outer iteration is one ADMoM iteration (eq. ADMoM_NTF): the three factors
+ * are updated in Gauss-Seidel order A, B, C (eq. ADMM_NTF_ALS_C), each by
+ *
+ *   W   = X^(n) (Khatri-Rao of the other two factors)            (MTTKRP)
+ *   G   = Hadamard product of the other factors' Grams          (Section IV-A)
+ *   L   = chol(G + rho I)                                         (FP64)
+ *   T times:  Ht^T = (W + rho (H + U)) (G + rho I)^{-1}
+ *             H    = max(0, Ht^T - U),   U += H - Ht^T            (eq. ADMoM_NTF)
+ *
+ * with H the non-negative auxiliary factor (the paper's A-tilde) and U the
+ * scaled dual, U = -Y / rho.  The paper runs T = 1 (footnote to eq.
+ * ADMM_NTF_ALS_C); T is a parameter here.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers unless stated otherwise; the
+ *    caller allocates and owns them.  The library allocates no device memory:
+ *    every temporary lives in a caller-provided workspace whose size the
+ *    matching *_workspace_bytes function returns.
+ *  - Tensors are dense, C order [I][J][K] (k fastest).  Factor matrices are
+ *    row-major [d_n][F].
+ *  - `stream` is a hipStream_t (NULL = the default stream); all device work is
+ *    enqueued on it in order.  Functions documented as synchronising wait for
+ *    the stream before returning.
+ *  - Errors are returned as ntf_status codes; nothing is printed and nothing
+ *    aborts.  On error nothing has been enqueued unless stated otherwise.
+ *  - Device pointers must be 16-byte aligned.
+ */
+#ifndef NTF_ADMM_H
+#define NTF_ADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NTF_OK = 0,
+  NTF_NOT_CONVERGED = 1,   /* informational: run() hit its cap before the stop test held */
+  NTF_E_INVAL = -1,        /* bad sizes, null/misaligned pointers, inconsistent options */
+  NTF_E_WORKSPACE = -2,    /* workspace smaller than *_workspace_bytes */
+  NTF_E_HIP = -3,          /* a HIP runtime call failed; see ntf_admm_last_error */
+  NTF_E_NUMERIC = -4,      /* G + rho I not positive definite, or NaN/Inf met on device */
+  NTF_E_UNSUPPORTED = -5   /* valid request outside what this build implements */
+} ntf_status;
+
+typedef enum {
+  NTF_PREC_F32 = 0,         /* X float32; MTTKRP on FP32 MFMA; Gram, Cholesky, solves FP64; H,U float32 */
+  NTF_PREC_BF16_MIXED = 1,  /* X float32 + bfloat16 copy with a power-of-two scale per mode-1 slab;
+                               MTTKRP on BF16 MFMA with FP32 accumulation; Gram FP32;
+                               Cholesky and solves FP64; H,U float32 */
+  NTF_PREC_F64 = 3          /* X float64; everything FP64 (MFMA f64); H,U float64 */
+} ntf_precision;
+
+typedef enum {
+  NTF_RHO_TRACE = 0,        /* rho_n = trace(G_n)/F at every update of mode n */
+  NTF_RHO_FIXED = 1,        /* rho_n = rho0 */
+  NTF_RHO_ADAPTIVE = 2      /* residual balancing, Section IV-D (eq. varying_penalty_rule),
+                               applied after every outer iteration, starting from rho0 */
+} ntf_rho_policy;
+
+/* The problem, as Section II states it. */
+typedef struct {
+  int64_t dims[3];          /* I, J, K >= 1 */
+  int32_t F;                /* rank, 1..64 */
+  int32_t x_dtype;          /* 0 = float32 (F32, BF16_MIXED), 1 = float64 (F64) */
+  const void *X;            /* device, [I][J][K]; BORROWED read-only, must outlive the context */
+  void *H[3];               /* device in/out, [d_n][F]: initial factors in, factors out.
+                               float32, or float64 for NTF_PREC_F64 */
+  void *U[3];               /* device in/out, [d_n][F], same dtype: scaled duals (zero = cold start) */
+} ntf_problem;
+
+typedef struct {
+  int32_t inner_iters;      /* T >= 1: inner ADMoM iterations per mode update (row-wise cap) */
+  int32_t rho_policy;       /* ntf_rho_policy */
+  double rho0;              /* initial / fixed penalty, > 0 (Section VI-A uses 1) */
+  double mu, tau_incr, tau_decr;   /* residual balancing (Section VI-A: 8, 4, 2) */
+  double inner_eps_abs, inner_eps_rel; /* row-wise inner early stop: the Section IV-C test
+                               written for one row (sqrt(F) in place of sqrt(I F));
+                               both 0 = always run T iterations */
+  double stop_eps_abs, stop_eps_rel;   /* outer stop test of Section IV-C on every mode,
+                               used by ntf_admm_run; both 0 = no outer test */
+  int32_t precision;        /* ntf_precision */
+  int32_t factor_source;    /* 0: later modes use the projected H (default);
+                               1: they use the unconstrained primal Ht^T, as the paper does */
+  int32_t rescale_dual_on_rho_change; /* 1: U *= rho_old/rho_new when rho changes (keeps the
+                               unscaled dual Y fixed); forced on for NTF_RHO_ADAPTIVE */
+  int32_t paper_init;       /* 1: auxiliary and dual variables start at zero and the given
+                               factors seed the primal (Section VI-A); needs factor_source 1 */
+  int32_t reserved[4];      /* must be zero */
+} ntf_opts;
+
+/* Statistics of the most recent outer iteration (Section IV-C quantities). */
+typedef struct {
+  int64_t outer;            /* outer iterations completed since init */
+  double rho[3];            /* penalty used by the last update of each mode */
+  double prim[3];           /* ||H_n - Ht_n^T||_F after the last inner iteration */
+  double dual[3];           /* rho_n ||H_n^new - H_n^old||_F over the whole mode update */
+  double norm_h[3];         /* ||H_n||_F */
+  double norm_p[3];         /* ||Ht_n^T||_F */
+  double norm_y[3];         /* rho_n ||U_n||_F = ||Y_n||_F */
+  double inner_iters_mean[3]; /* mean inner iterations per row in the last update */
+  double rfe_cheap;         /* RFE from ||X||^2 - 2<W_3,H_3> + sum(G1*G2*G3); monitoring only */
+  int32_t numeric_error;    /* non-zero if a non-PD system or NaN/Inf was met */
+  int32_t converged;        /* Section IV-C stop test held for all modes (needs stop_eps_* > 0) */
+} ntf_stats;
+
+typedef struct ntf_admm_ctx ntf_admm_ctx;
+
+/* ------------------------------------------------------------------ solver */
+
+/* Workspace bytes ntf_admm_init needs for this problem and options; 0 if the
+ * arguments are invalid.  Host-only, no device work. */
+size_t ntf_admm_workspace_bytes(const ntf_problem *prob, const ntf_opts *opts);
+
+/* Validate, carve the workspace, build the bfloat16 copy of X if the
+ * precision asks for it (Section II data, stored as two bf16 layouts), compute
+ * ||X||^2 and the initial Grams, and factor G_1 + rho I.  The context keeps
+ * the pointers in `prob`; `workspace` (device, >= ntf_admm_workspace_bytes)
+ * is borrowed for the life of the context.  Synchronises the stream. */
+ntf_status ntf_admm_init(ntf_admm_ctx **out, const ntf_problem *prob, const ntf_opts *opts,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/* One outer iteration (modes 1, 2, 3 in Gauss-Seidel order, eqs. ADMoM_NTF and
+ * ADMM_NTF_ALS_C).  The first call captures the iteration into a HIP graph;
+ * later calls replay it.  If `stats` is non-NULL the call synchronises and
+ * fills it; otherwise it only enqueues. */
+ntf_status ntf_admm_step(ntf_admm_ctx *ctx, ntf_stats *stats);
+
+/* Up to `max_outer` outer iterations.  With opts.stop_eps_abs or stop_eps_rel > 0 the
+ * run stops early once the Section IV-C test holds on every mode (checked
+ * every `check_every` iterations, >= 1; each check synchronises) and returns
+ * NTF_OK, else NTF_NOT_CONVERGED.  With both eps zero it enqueues all
+ * iterations and returns NTF_OK.  `stats` as in ntf_admm_step. */
+ntf_status ntf_admm_run(ntf_admm_ctx *ctx, int32_t max_outer, int32_t check_every, ntf_stats *stats);
+
+/* Direct relative fit error ||X - [H1,H2,H3]||_F / ||X||_F (Section VI-A),
+ * the model formed and the error accumulated in FP64 over the original X.
+ * Synchronises; result to host *rfe. */
+ntf_status ntf_admm_fit(ntf_admm_ctx *ctx, double *rfe);
+
+/* Checkpoint support.  The complete solver state (eq. ADMoM_NTF's Z plus the
+ * penalties, Section IV-C/D) is H and U, which live in the caller's buffers,
+ * and a context-internal part: per-mode penalties and residual totals, the
+ * outer count and, with factor_source 1, the primal factors.
+ * ntf_admm_state_bytes gives the size of that internal part; get_state
+ * synchronises and copies it to host memory `buf`; set_state loads it into a
+ * context created for the same problem and options and recomputes the Grams
+ * from the current H buffers exactly as the solver forms them, so that
+ * run(a+b) and run(a); get_state; set_state; run(b) give bitwise identical
+ * results.  Both return NTF_E_INVAL if `bytes` is not the state size. */
+size_t ntf_admm_state_bytes(const ntf_admm_ctx *ctx);
+ntf_status ntf_admm_get_state(ntf_admm_ctx *ctx, void *buf, size_t bytes);
+ntf_status ntf_admm_set_state(ntf_admm_ctx *ctx, const void *buf, size_t bytes);
+
+/* W_n (the MTTKRP of mode n, 0-based) with the context's precision and
+ * kernels, from the current factors, into `W_out` (device, float64 [d_n][F]).
+ * Stream-ordered, does not change the solver state. */
+ntf_status ntf_admm_mttkrp(ntf_admm_ctx *ctx, int32_t mode, double *W_out);
+
+/* Measurement hook: enqueue exactly one MTTKRP kernel with the current
+ * factors and nothing else -- pass 0: mode-1 partials plus the k-contracted
+ * intermediate T = X x_3 C (streams X); pass 1: mode-2 partials from T;
+ * pass 2: mode-3 partials (streams X).  Stream-ordered; writes only scratch
+ * (T and the partials), never the solver state. */
+ntf_status ntf_admm_launch_pass(ntf_admm_ctx *ctx, int32_t pass);
+
+ntf_status ntf_admm_destroy(ntf_admm_ctx *ctx);
+const char *ntf_admm_last_error(const ntf_admm_ctx *ctx);
+const char *ntf_status_str(ntf_status s);
+
+/* ------------------------------------------------------ kernel-level calls */
+
+/* One mode update on its own (Section IV, one line of eq. ADMM_NTF_ALS_C with
+ * the projection and dual update): given W [rows][F] (float64) and G [F][F]
+ * (float64, symmetric PSD), factor G + rho I in FP64 on the device, then run
+ * up to T inner iterations per row on H, U (in/out, [rows][F], dtype 0 =
+ * float32, 1 = float64).  rho <= 0 selects trace(G)/F.  Row-wise early stop
+ * as in ntf_opts.eps_*.  `iters_out` (device int32 [rows], may be NULL)
+ * receives the iterations each row ran; `Ht_out` (device, same dtype as H,
+ * may be NULL) the last Ht^T.  Stream-ordered. */
+size_t ntf_inner_workspace_bytes(int64_t rows, int32_t F);
+ntf_status ntf_inner_update(const double *W, void *H, void *U, int64_t rows, int32_t F, int32_t dtype,
+                            const double *G, double rho, int32_t T, double eps_abs, double eps_rel,
+                            int32_t *iters_out, void *Ht_out, void *workspace, size_t ws_bytes,
+                            void *stream);
+
+/* Gram matrix H^T H of a [rows][F] factor (dtype 0 = float32, 1 = float64),
+ * accumulated in FP64, into G_out (device float64 [F][F]).  Stream-ordered. */
+size_t ntf_gram_workspace_bytes(int64_t rows, int32_t F);
+ntf_status ntf_gram(const void *H, int64_t rows, int32_t F, int32_t dtype, double *G_out,
+                    void *workspace, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTF_ADMM_H */

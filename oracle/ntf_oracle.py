@@ -328,7 +328,10 @@ def outer_step(X: np.ndarray, st: State, opts: Opts) -> List[dict]:
     infos = [mode_update(X, st, n, opts) for n in range(3)]
     if opts.rho_policy == RHO_ADAPTIVE:
         for n in range(3):
-            st.rho[n] = _adapt_rho(st.rho[n], infos[n]["prim"], infos[n]["dual"], opts)
+            new = _adapt_rho(st.rho[n], infos[n]["prim"], infos[n]["dual"], opts)
+            if new != st.rho[n]:
+                st.U[n] = st.U[n] * (st.rho[n] / new)   # the unscaled dual Y = -rho U is the state
+            st.rho[n] = new
     st.outer += 1
     return infos
 
@@ -496,3 +499,28 @@ def quantize_slabs_bf16(X: np.ndarray):
             s[i] = math.ldexp(1.0, e - 1)
         Xq[i] = _round_bf16((X[i].astype(np.float64) / s[i]).astype(np.float32)).astype(np.float64)
     return Xq, s
+
+
+def mttkrp_mixed(X: np.ndarray, factors: Sequence[np.ndarray], n: int) -> np.ndarray:
+    """MTTKRP with the operand rounding of the mixed-precision recipe (the
+    method itself is unchanged): X is replaced by its per-slab bfloat16 copy
+    s_i * Xq[i]; modes 1 and 2 contract against bfloat16(C) with the other
+    factor in float32; mode 3 contracts against Khatri-Rao rows formed in
+    float32 as (s_i * A[i,:]) * B[j,:] and rounded to bfloat16.  Accumulation
+    is exact up to float64 rounding."""
+    Xq, s = quantize_slabs_bf16(X)
+    A, B, C = (np.asarray(f, dtype=np.float32) for f in factors)
+    Xs = Xq * s[:, None, None]
+    if n == 0:
+        Cb = _round_bf16(C).astype(np.float64)
+        return mttkrp(Xs, [A.astype(np.float64), B.astype(np.float64), Cb], 0)
+    if n == 1:
+        Cb = _round_bf16(C).astype(np.float64)
+        return mttkrp(Xs, [A.astype(np.float64), B.astype(np.float64), Cb], 1)
+    # mode 3: KR[(i,j), f] = bf16(fl32(fl32(s_i A[i,f]) B[j,f]))
+    I, J = A.shape[0], B.shape[0]
+    sA = (s.astype(np.float32)[:, None] * A).astype(np.float32)
+    KR = (sA[:, None, :] * B[None, :, :]).astype(np.float32)          # [I, J, F], float32 products
+    KRb = _round_bf16(KR).astype(np.float64).reshape(I * J, -1)
+    Xflat = Xq.reshape(I * J, -1)                                      # rows (i, j), columns k
+    return Xflat.T @ KRb

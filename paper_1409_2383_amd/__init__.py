@@ -1,0 +1,232 @@
+"""MI355X (gfx950) ADMoM non-negative CP factorisation.
+
+Thin Python front end of libntf_admm.so.  PyTorch provides device memory and
+the stream; every step of the method runs in the library's HIP kernels.  The
+names follow the paper (Liavas & Sidiropoulos): H_n are the non-negative
+factors (A-tilde, B-tilde, C-tilde), U_n the scaled duals (-Y_n / rho_n).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import (PREC_BF16_MIXED, PREC_F32, PREC_F64, RHO_ADAPTIVE, RHO_FIXED, RHO_TRACE,
+                   NtfError)
+
+__all__ = ["NtfAdmm", "AdmmOptions", "inner_update", "gram", "PREC_F32", "PREC_BF16_MIXED",
+           "PREC_F64", "RHO_TRACE", "RHO_FIXED", "RHO_ADAPTIVE", "NtfError", "library_path"]
+
+
+def library_path() -> str:
+    _lib.lib()
+    return _lib.LIB_PATH
+
+
+@dataclass
+class AdmmOptions:
+    inner_iters: int = 1
+    rho_policy: int = RHO_TRACE
+    rho0: float = 1.0
+    mu: float = 8.0
+    tau_incr: float = 4.0
+    tau_decr: float = 2.0
+    inner_eps_abs: float = 0.0
+    inner_eps_rel: float = 0.0
+    stop_eps_abs: float = 0.0
+    stop_eps_rel: float = 0.0
+    precision: int = PREC_F32
+    factor_source: int = 0
+    rescale_dual_on_rho_change: int = 0
+    paper_init: int = 0
+
+    def to_c(self) -> _lib.Opts:
+        o = _lib.Opts()
+        for name, _ in _lib.Opts._fields_:
+            if name == "reserved":
+                continue
+            setattr(o, name, getattr(self, name))
+        return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class NtfAdmm:
+    """ADMoM NTF solver bound to one tensor and one set of factor buffers.
+
+    X: CUDA tensor [I, J, K], float32 (F32 / BF16_MIXED) or float64 (F64), C order.
+    H: three CUDA tensors [d_n, F] (float32, or float64 for F64): initial
+       factors, updated in place.  U: three duals of the same shape (zeros if
+       omitted).  The workspace is a torch uint8 tensor owned by this object.
+    """
+
+    def __init__(self, X, H: Sequence, U: Optional[Sequence] = None,
+                 opts: Optional[AdmmOptions] = None, stream=None):
+        torch = _torch()
+        self.opts = opts or AdmmOptions()
+        fdt = torch.float64 if self.opts.precision == PREC_F64 else torch.float32
+        if not X.is_cuda or not X.is_contiguous() or X.dim() != 3:
+            raise ValueError("X must be a contiguous 3-way CUDA tensor")
+        if X.dtype != fdt:
+            raise ValueError(f"X must be {fdt} for this precision")
+        F = H[0].shape[1]
+        self.X = X
+        self.H = list(H)
+        for n in range(3):
+            h = self.H[n]
+            if (not h.is_cuda or h.dtype != fdt or not h.is_contiguous()
+                    or tuple(h.shape) != (X.shape[n], F)):
+                raise ValueError(f"H[{n}] must be a contiguous CUDA {fdt} tensor of shape "
+                                 f"({X.shape[n]}, {F})")
+        self.U = list(U) if U is not None else [torch.zeros_like(h) for h in self.H]
+        for n in range(3):
+            if self.U[n].shape != self.H[n].shape or self.U[n].dtype != fdt or not self.U[n].is_contiguous():
+                raise ValueError(f"U[{n}] must match H[{n}]")
+        self.F = F
+        self.stream = stream
+        L = _lib.lib()
+        pr = _lib.Problem()
+        for n in range(3):
+            pr.dims[n] = X.shape[n]
+            pr.H[n] = _ptr(self.H[n])
+            pr.U[n] = _ptr(self.U[n])
+        pr.F = F
+        pr.x_dtype = 1 if self.opts.precision == PREC_F64 else 0
+        pr.X = _ptr(X)
+        self._prob = pr
+        self._copts = self.opts.to_c()
+        nbytes = L.ntf_admm_workspace_bytes(ctypes.byref(pr), ctypes.byref(self._copts))
+        if nbytes == 0:
+            ctx = ctypes.c_void_p()
+            st = L.ntf_admm_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
+                                 None, 0, _stream_handle(stream))
+            _lib.check(st, "ntf_admm_init")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
+        ctx = ctypes.c_void_p()
+        st = L.ntf_admm_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
+                             ctypes.c_void_p(_ptr(self.workspace)), nbytes, _stream_handle(stream))
+        _lib.check(st, "ntf_admm_init", None)
+        self._ctx = ctx
+
+    # -- solver
+    def step(self, stats: bool = False):
+        L = _lib.lib()
+        if stats:
+            s = _lib.Stats()
+            _lib.check(L.ntf_admm_step(self._ctx, ctypes.byref(s)), "ntf_admm_step", self._ctx)
+            return s.as_dict()
+        _lib.check(L.ntf_admm_step(self._ctx, None), "ntf_admm_step", self._ctx)
+        return None
+
+    def run(self, max_outer: int, check_every: int = 1, stats: bool = True):
+        L = _lib.lib()
+        s = _lib.Stats()
+        st = L.ntf_admm_run(self._ctx, int(max_outer), int(check_every),
+                            ctypes.byref(s) if stats else None)
+        _lib.check(st, "ntf_admm_run", self._ctx, ok=(_lib.NTF_OK, _lib.NTF_NOT_CONVERGED))
+        out = s.as_dict() if stats else {}
+        out["status"] = st
+        return out
+
+    def fit(self) -> float:
+        r = ctypes.c_double()
+        _lib.check(_lib.lib().ntf_admm_fit(self._ctx, ctypes.byref(r)), "ntf_admm_fit", self._ctx)
+        return r.value
+
+    def mttkrp(self, mode: int):
+        torch = _torch()
+        W = torch.empty((self.X.shape[mode], self.F), dtype=torch.float64, device=self.X.device)
+        _lib.check(_lib.lib().ntf_admm_mttkrp(self._ctx, int(mode), ctypes.c_void_p(_ptr(W))),
+                   "ntf_admm_mttkrp", self._ctx)
+        return W
+
+    def launch_pass(self, which: int):
+        """Enqueue one MTTKRP kernel only (0: pass 1, 1: mode 2 from T, 2: pass 3)."""
+        _lib.check(_lib.lib().ntf_admm_launch_pass(self._ctx, int(which)), "ntf_admm_launch_pass",
+                   self._ctx)
+
+    def plan_info(self) -> dict:
+        """Algorithmic bytes of each MTTKRP kernel launch (see bench.py)."""
+        I, J, K = self.X.shape
+        es = self.X.element_size()
+        F = self.F
+        x_bytes = I * J * K * (2 if self.opts.precision == PREC_BF16_MIXED else es)
+        t_bytes = I * J * F * (8 if self.opts.precision == PREC_F64 else 4)
+        return {"pass1": x_bytes + t_bytes, "mode2": t_bytes, "pass3": x_bytes}
+
+    def get_state(self) -> bytes:
+        L = _lib.lib()
+        n = L.ntf_admm_state_bytes(self._ctx)
+        buf = ctypes.create_string_buffer(n)
+        _lib.check(L.ntf_admm_get_state(self._ctx, buf, n), "ntf_admm_get_state", self._ctx)
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        L = _lib.lib()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _lib.check(L.ntf_admm_set_state(self._ctx, buf, len(blob)), "ntf_admm_set_state", self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _lib.lib().ntf_admm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def inner_update(W, H, U, G, rho: float = 0.0, T: int = 1, eps_abs: float = 0.0,
+                 eps_rel: float = 0.0, want_iters: bool = False, want_ht: bool = False,
+                 stream=None):
+    """One mode update on given W (float64 [rows,F]) and G (float64 [F,F]):
+    Cholesky of G + rho I on the device, then up to T inner iterations per row
+    on H, U (in place).  rho <= 0 selects trace(G)/F."""
+    torch = _torch()
+    rows, F = H.shape
+    dtype = 1 if H.dtype == torch.float64 else 0
+    L = _lib.lib()
+    nb = L.ntf_inner_workspace_bytes(rows, F)
+    ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=H.device)
+    iters = torch.zeros(rows, dtype=torch.int32, device=H.device) if want_iters else None
+    ht = torch.empty_like(H) if want_ht else None
+    st = L.ntf_inner_update(_ptr(W), _ptr(H), _ptr(U), rows, F, dtype, _ptr(G), float(rho), int(T),
+                            float(eps_abs), float(eps_rel),
+                            ctypes.c_void_p(_ptr(iters)) if iters is not None else None,
+                            ctypes.c_void_p(_ptr(ht)) if ht is not None else None,
+                            ctypes.c_void_p(_ptr(ws)), nb, _stream_handle(stream))
+    _lib.check(st, "ntf_inner_update")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return iters, ht
+
+
+def gram(H, stream=None):
+    """H^T H accumulated in FP64 on the device."""
+    torch = _torch()
+    rows, F = H.shape
+    dtype = 1 if H.dtype == torch.float64 else 0
+    L = _lib.lib()
+    nb = L.ntf_gram_workspace_bytes(rows, F)
+    ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=H.device)
+    G = torch.empty((F, F), dtype=torch.float64, device=H.device)
+    st = L.ntf_gram(_ptr(H), rows, F, dtype, _ptr(G), ctypes.c_void_p(_ptr(ws)), nb,
+                    _stream_handle(stream))
+    _lib.check(st, "ntf_gram")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return G

@@ -1,0 +1,793 @@
+// MTTKRP kernels for gfx950: the three matricised-tensor-times-Khatri-Rao
+// products of one ADMoM iteration (eq. ADMM_NTF_ALS_C), computed from one copy
+// of the dense tensor X [I][J][K] (k fastest) in two streaming passes.
+//
+//   pass 1:  T[i,j,:] = sum_k X[i,j,k] C[k,:]         (MFMA, contraction over k)
+//            W1[i,:]  = sum_j B[j,:] * T[i,j,:]       (fused epilogue, per-tile partials)
+//   mode 2:  W2[j,:]  = sum_i A_new[i,:] * T[i,j,:]   (T re-read; X is not)
+//   pass 3:  W3[k,:]  = sum_{i,j} X[i,j,k] A_new[i,:] * B_new[j,:]
+//                                                    (MFMA, contraction over (i,j);
+//                                                     Khatri-Rao rows built per tile in LDS)
+//
+// Modes 1 and 2 both contract C^k over k (the update of B uses A^{k+1} and C^k),
+// so the k-contraction T is shared by them: two passes over X per outer
+// iteration instead of three.  The Khatri-Rao matrix is never materialised:
+// pass 1 keeps C in LDS, pass 3 builds 64 Khatri-Rao rows at a time in LDS.
+//
+// All partial sums are written to fixed slots and reduced later in a fixed
+// order, so results are bitwise reproducible.
+#include "ntf_device.h"
+#include "ntf_launch.h"
+
+#include <algorithm>
+
+namespace ntf {
+
+// ---------------------------------------------------------------- set-up
+
+// bfloat16 copies of X with a power-of-two scale per mode-1 slab:
+//   s_i = 2^(e-1) where max|X[i]| = m * 2^e, m in [0.5, 1)  (so max|X[i]|/s_i in [1,2));
+//   Xr  [I][J][Kp]      row-major, k padded with zeros to Kp (multiple of 32);
+//   Xj8 [I][JG][Kp3][8] groups of 8 consecutive j interleaved innermost, zero padded.
+__global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ X, int64_t J, int64_t K,
+                                                  int64_t Kp, int64_t JG, int64_t Kp3,
+                                                  __bf16* __restrict__ Xr, __bf16* __restrict__ Xj8,
+                                                  float* __restrict__ scale) {
+  const int64_t i = blockIdx.x;
+  const float* Xi = X + i * J * K;
+  const int64_t n = J * K;
+  float m = 0.f;
+  for (int64_t t = threadIdx.x; t < n; t += 256) m = fmaxf(m, fabsf(Xi[t]));
+  __shared__ float red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  m = red[0];
+  float s = 1.f;
+  if (m > 0.f && isfinite(m)) {
+    int e;
+    (void)frexpf(m, &e);
+    s = ldexpf(1.f, e - 1);
+  }
+  if (threadIdx.x == 0) scale[i] = s;
+  const float inv = 1.f / s;  // exact: s is a power of two
+  __bf16* Xri = Xr + i * J * Kp;
+  for (int64_t t = threadIdx.x; t < J * Kp; t += 256) {
+    const int64_t j = t / Kp, k = t - j * Kp;
+    const float v = (k < K) ? Xi[j * K + k] * inv : 0.f;
+    Xri[t] = (__bf16)v;
+  }
+  __bf16* Xji = Xj8 + i * JG * Kp3 * 8;
+  for (int64_t t = threadIdx.x; t < JG * Kp3 * 8; t += 256) {
+    const int64_t e = t & 7, rest = t >> 3;
+    const int64_t jg = rest / Kp3, k = rest - jg * Kp3;
+    const int64_t j = jg * 8 + e;
+    const float v = (j < J && k < K) ? Xi[j * K + k] * inv : 0.f;
+    Xji[t] = (__bf16)v;
+  }
+}
+
+// sum of squares, FP64 accumulation, fixed-order two-level reduction
+template <typename XT>
+__global__ __launch_bounds__(256) void k_sumsq_part(const XT* __restrict__ X, int64_t n,
+                                                    double* __restrict__ part) {
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += stride) {
+    const double v = (double)X[t];
+    acc += v * v;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(64) void k_sum_parts(const double* __restrict__ part, int nparts,
+                                                  double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += part[p];
+    *out = s;
+  }
+}
+
+// ---------------------------------------------------------------- pass 1
+
+// Work item = (slab i, chunk of 16*MT consecutive j), all of k, owned by ONE
+// wave; the four waves of a block take four items at a time and share C in
+// LDS (loaded once per block when it fits, which it does for K*F up to
+// 600*64 in FP32 and 1200*64 in bf16).  Each wave streams its rows of X with
+// 16-byte loads that are the MFMA A operands, keeping U k-steps of loads in
+// flight, and contracts them against all FT 16-column tiles of the rank.
+// The epilogue stores T and reduces this item's share of
+// W1[i,:] = sum_j B[j,:] * T[i,j,:] across the wave into P1[i][chunk][:].
+//
+// FP32/FP64: C in LDS as [k/4][FP][4] so one 16-byte read gives the B
+// operands of the four MFMAs whose contraction slots match the 16-byte X load
+// (lane group g holds k = kb + 4g + c in element c).
+template <typename T, int FT, int MT>
+__global__ __launch_bounds__(256) void k_pass1(const T* __restrict__ X, int I, int J, int K, int F,
+                                               const T* __restrict__ Hb, const T* __restrict__ Hc,
+                                               T* __restrict__ Tout, T* __restrict__ P1, int nch,
+                                               int KC, int vec) {
+  typedef Mfma<T> M;
+  typedef typename M::acc_t acc_t;
+  constexpr int FP = FT * 16;
+  constexpr int R = 16 * MT;
+  constexpr int U = 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Cs = reinterpret_cast<T*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
+  const int64_t nitems = (int64_t)I * nch;
+  const int nkc = (K + KC - 1) / KC;
+  const int64_t nblock_iters = (nitems + 4LL * gridDim.x - 1) / (4LL * gridDim.x);
+  for (int64_t bi = 0; bi < nblock_iters; ++bi) {
+    const int64_t item = (bi * gridDim.x + blockIdx.x) * 4 + wave;
+    const bool has = item < nitems;
+    const int i = has ? (int)(item / nch) : 0;
+    const int ch = has ? (int)(item - (int64_t)i * nch) : 0;
+    const int j0 = ch * R;
+    acc_t acc[MT][FT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = M::zero();
+    for (int kc = 0; kc < nkc; ++kc) {
+      const int kbeg = kc * KC, kend = min(K, kbeg + KC);
+      if (nkc > 1 || bi == 0) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < KC * FP; idx += 256) {
+          const int kk = idx / FP, f = idx - kk * FP, k = kbeg + kk;
+          const T v = (k < kend && f < F) ? Hc[(int64_t)k * F + f] : T(0);
+          Cs[((kk >> 2) * FP + f) * 4 + (kk & 3)] = v;
+        }
+        __syncthreads();
+      }
+      if (!has) continue;
+      const T* xrow[MT];
+      bool rowok[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int j = j0 + mt * 16 + n;
+        rowok[mt] = j < J;
+        xrow[mt] = X + ((int64_t)i * J + (rowok[mt] ? j : 0)) * K + 4 * g;
+      }
+      T xv[U][MT][4];
+      auto load_step = [&](int kb, T (&dst)[MT][4]) {
+        const int valid = kend - (kb + 4 * g);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          if (rowok[mt] && valid > 0) {
+            load4<T>(xrow[mt] + kb, valid, vec != 0, dst[mt]);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) dst[mt][c] = T(0);
+          }
+        }
+      };
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (kbeg + 16 * u < kend) load_step(kbeg + 16 * u, xv[u]);
+      for (int kb = kbeg; kb < kend; kb += 16 * U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int kbu = kb + 16 * u;
+          if (kbu < kend) {
+            const T* cbase = Cs + ((((kbu - kbeg) >> 2) + g) * FP + n) * 4;
+#pragma unroll
+            for (int ft = 0; ft < FT; ++ft) {
+              T cv[4];
+              Vec4Load<T>::load(cbase + ft * 64, cv);
+#pragma unroll
+              for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                  acc[mt][ft] = M::mma(xv[u][mt][c], cv[c], acc[mt][ft]);
+            }
+            if (kbu + 16 * U < kend) load_step(kbu + 16 * U, xv[u]);
+          }
+        }
+      }
+    }
+    if (!has) continue;
+    // epilogue: store T, reduce this item's share of W1[i,:]
+    T part[FT];
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) part[ft] = T(0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int j = j0 + mt * 16 + M::row(g, ii);
+          const int f = ft * 16 + n;
+          if (j < J && f < F) {
+            const T v = acc[mt][ft][ii];
+            Tout[((int64_t)i * J + j) * F + f] = v;
+            part[ft] += Hb[(int64_t)j * F + f] * v;
+          }
+        }
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+      part[ft] += __shfl_xor(part[ft], 16);
+      part[ft] += __shfl_xor(part[ft], 32);
+      const int f = ft * 16 + n;
+      if (g == 0 && f < F) P1[((int64_t)i * nch + ch) * F + f] = part[ft];
+    }
+  }
+}
+
+// BF16: X from the row-major bfloat16 copy (Kp a multiple of 32, zero
+// padded); C transposed in LDS as bf16 [FP][KC+8] so lane (n,g) reads
+// C[kb+8g .. kb+8g+7][ft*16+n] with one 16-byte load.  The slab scale s_i is
+// applied to the FP32 accumulator in the epilogue (exact, power of two).
+template <int FT, int MT>
+__global__ __launch_bounds__(256) void k_pass1_bf16(const __bf16* __restrict__ Xr,
+                                                    const float* __restrict__ scale, int I, int J,
+                                                    int K, int Kp, int F, const float* __restrict__ Hb,
+                                                    const float* __restrict__ Hc,
+                                                    float* __restrict__ Tout, float* __restrict__ P1,
+                                                    int nch, int KC) {
+  constexpr int FP = FT * 16;
+  constexpr int R = 16 * MT;
+  constexpr int U = 4;
+  const int KCS = KC + 8;  // LDS row stride (elements); 16-byte multiple since KC % 32 == 0
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* Cs = reinterpret_cast<__bf16*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
+  const int64_t nitems = (int64_t)I * nch;
+  const int nkc = (Kp + KC - 1) / KC;
+  const int64_t nblock_iters = (nitems + 4LL * gridDim.x - 1) / (4LL * gridDim.x);
+  for (int64_t bi = 0; bi < nblock_iters; ++bi) {
+    const int64_t item = (bi * gridDim.x + blockIdx.x) * 4 + wave;
+    const bool has = item < nitems;
+    const int i = has ? (int)(item / nch) : 0;
+    const int ch = has ? (int)(item - (int64_t)i * nch) : 0;
+    const int j0 = ch * R;
+    f32x4 acc[MT][FT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < nkc; ++kc) {
+      const int kbeg = kc * KC, kend = min(Kp, kbeg + KC);
+      if (nkc > 1 || bi == 0) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < KC * FP; idx += 256) {
+          const int kk = idx / FP, f = idx - kk * FP, k = kbeg + kk;
+          const float v = (k < K && f < F) ? Hc[(int64_t)k * F + f] : 0.f;
+          Cs[f * KCS + kk] = (__bf16)v;
+        }
+        __syncthreads();
+      }
+      if (!has) continue;
+      const __bf16* xrow[MT];
+      bool rowok[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int j = j0 + mt * 16 + n;
+        rowok[mt] = j < J;
+        xrow[mt] = Xr + ((int64_t)i * J + (rowok[mt] ? j : 0)) * Kp + 8 * g;
+      }
+      bf16x8 xv[U][MT];
+      auto load_step = [&](int kb, bf16x8 (&dst)[MT]) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          if (rowok[mt]) {
+            dst[mt] = *reinterpret_cast<const bf16x8*>(xrow[mt] + kb);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[mt][e] = (__bf16)0.f;
+          }
+        }
+      };
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (kbeg + 32 * u < kend) load_step(kbeg + 32 * u, xv[u]);
+      const __bf16* cb = Cs + n * KCS + 8 * g;
+      for (int kb = kbeg; kb < kend; kb += 32 * U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int kbu = kb + 32 * u;
+          if (kbu < kend) {
+#pragma unroll
+            for (int ft = 0; ft < FT; ++ft) {
+              const bf16x8 cv = *reinterpret_cast<const bf16x8*>(cb + ft * 16 * KCS + (kbu - kbeg));
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][mt], cv, acc[mt][ft]);
+            }
+            if (kbu + 32 * U < kend) load_step(kbu + 32 * U, xv[u]);
+          }
+        }
+      }
+    }
+    if (!has) continue;
+    const float s = scale[i];
+    float part[FT];
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int j = j0 + mt * 16 + 4 * g + ii;
+          const int f = ft * 16 + n;
+          if (j < J && f < F) {
+            const float v = s * acc[mt][ft][ii];
+            Tout[((int64_t)i * J + j) * F + f] = v;
+            part[ft] += Hb[(int64_t)j * F + f] * v;
+          }
+        }
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+      part[ft] += __shfl_xor(part[ft], 16);
+      part[ft] += __shfl_xor(part[ft], 32);
+      const int f = ft * 16 + n;
+      if (g == 0 && f < F) P1[((int64_t)i * nch + ch) * F + f] = part[ft];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- mode 2 from T
+
+// P2[ic][j][f] = sum_{i in chunk ic} A[i][f] * T[i][j][f]; one thread per (j,f),
+// coalesced over the contiguous (j,f) index of each slab of T.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mode2(const T* __restrict__ Tin, const T* __restrict__ Ha,
+                                               int I, int64_t JF, int F, int ich,
+                                               T* __restrict__ P2) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= JF) return;
+  const int f = (int)(idx % F);
+  const int ic = blockIdx.y;
+  const int i0 = ic * ich, i1 = min(I, i0 + ich);
+  T acc = T(0);
+  for (int i = i0; i < i1; ++i) acc += Ha[(int64_t)i * F + f] * Tin[(int64_t)i * JF + idx];
+  P2[(int64_t)ic * JF + idx] = acc;
+}
+
+// ---------------------------------------------------------------- pass 3, FP32 / FP64
+
+// Block = nw waves; wave w covers k in [kw0, kw0+64) with four MFMA instances
+// c = 0..3 whose result row m holds k = kw0 + 4m + c (the 16-byte X load of
+// lane (n,g) covers k = kw0 + 4n .. +3 of row r0 + g).  Rows r = i*J + j of the
+// block's chunk are contracted 64 at a time; their Khatri-Rao rows
+// KR[r][f] = A[i][f] * B[j][f] are built in LDS (double buffered: the next
+// 64 rows are built while the current ones are contracted, one barrier per
+// 64 rows) and shared by all waves.  X loads run two steps ahead.
+template <typename T, int FT>
+__global__ __launch_bounds__(512) void k_pass3(const T* __restrict__ X, int64_t IJ, int J, int K,
+                                               int F, const T* __restrict__ Ha,
+                                               const T* __restrict__ Hb, T* __restrict__ P3,
+                                               int64_t rpc, int vec) {
+  typedef Mfma<T> M;
+  typedef typename M::acc_t acc_t;
+  constexpr int FP = FT * 16;
+  constexpr int KRS = FP + ((FT % 2 == 0) ? 16 : 0);  // LDS row stride: 4 lane groups on distinct banks
+  __shared__ __align__(16) T KRs[2][64 * KRS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int kw0 = (blockIdx.y * nw + wave) * 64;
+  const int64_t rbeg = (int64_t)blockIdx.x * rpc;
+  const int64_t rend = min(IJ, rbeg + rpc);
+  const int nep = (int)((rend - rbeg + 63) >> 6);
+  acc_t acc[4][FT];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) acc[c][ft] = M::zero();
+  const int kl = kw0 + 4 * n;           // first k of this lane's 16-byte load
+  const int valid = K - kl;
+  const bool kact = kw0 < K;
+  auto build = [&](int e, int buf) {
+    const int64_t r0 = rbeg + 64LL * e;
+    for (int idx = threadIdx.x; idx < 64 * FP; idx += blockDim.x) {
+      const int rr = idx / FP, f = idx - rr * FP;
+      const int64_t r = r0 + rr;
+      T v = T(0);
+      if (r < rend && f < F) {
+        const int64_t i = r / J, j = r - i * J;
+        v = Ha[i * F + f] * Hb[j * F + f];
+      }
+      KRs[buf][rr * KRS + f] = v;
+    }
+  };
+  auto load = [&](int64_t r, T (&dst)[4]) {
+    if (kact && r < rend && valid > 0) {
+      load4<T>(X + r * K + kl, valid, vec != 0, dst);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dst[c] = T(0);
+    }
+  };
+  if (nep > 0) build(0, 0);
+  __syncthreads();
+  for (int e = 0; e < nep; ++e) {
+    const int64_t r0 = rbeg + 64LL * e;
+    if (e + 1 < nep) build(e + 1, (e + 1) & 1);
+    if (kact) {
+      const T* kbuf = KRs[e & 1];
+      T xv[2][4];
+      load(r0 + g, xv[0]);
+      load(r0 + 4 + g, xv[1]);
+#pragma unroll
+      for (int st = 0; st < 16; ++st) {
+        const T* kb = kbuf + (4 * st + g) * KRS + n;
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) {
+          const T b = kb[ft * 16];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c][ft] = M::mma(xv[st & 1][c], b, acc[c][ft]);
+        }
+        if (st + 2 < 16) load(r0 + 4 * (st + 2) + g, xv[st & 1]);
+      }
+    }
+    __syncthreads();
+  }
+  if (!kact) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int k = kw0 + 4 * M::row(g, ii) + c;
+        const int f = ft * 16 + n;
+        if (k < K && f < F) P3[((int64_t)blockIdx.x * K + k) * F + f] = acc[c][ft][ii];
+      }
+}
+
+// ---------------------------------------------------------------- pass 3, BF16
+
+// X from the j-interleaved copy Xj8[q][k][e] (q = i*JG + jg, row j = 8jg + e):
+// lane (n,g) loads the 8 rows of group q0 + 4s + g at k = kt + n with one
+// 16-byte read, which is exactly the A operand of v_mfma_f32_16x16x32_bf16
+// (contraction over 32 rows, result rows = 16 consecutive k).  The
+// Khatri-Rao rows s_i * A[i][f] * B[j][f] of 64 rows (8 groups) are built in
+// LDS as bf16, transposed [FP][72], so the B operand is again one 16-byte
+// read; the next 64 rows are built, and their X loads issued, while the
+// current ones are contracted (one barrier per 64 rows).
+template <int FT>
+__global__ __launch_bounds__(512) void k_pass3_bf16(const __bf16* __restrict__ Xj8,
+                                                    const float* __restrict__ scale, int64_t IQ,
+                                                    int J, int JG, int K, int Kp3, int F,
+                                                    const float* __restrict__ Ha,
+                                                    const float* __restrict__ Hb,
+                                                    float* __restrict__ P3, int64_t gpc) {
+  constexpr int FP = FT * 16;
+  constexpr int KRP = 72;
+  __shared__ __align__(16) __bf16 KRt[2][FP * KRP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int kw0 = (blockIdx.y * nw + wave) * 64;
+  const int64_t qbeg = (int64_t)blockIdx.x * gpc;
+  const int64_t qend = min(IQ, qbeg + gpc);
+  const int nep = (int)((qend - qbeg + 7) >> 3);
+  const bool kact = kw0 < Kp3;
+  f32x4 acc[4][FT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto build = [&](int e, int buf) {
+    const int64_t q0 = qbeg + 8LL * e;
+    for (int idx = threadIdx.x; idx < 64 * FP; idx += blockDim.x) {
+      const int f = idx >> 6, rr = idx & 63;
+      const int64_t q = q0 + (rr >> 3);
+      float v = 0.f;
+      if (q < qend && f < F) {
+        const int64_t i = q / JG, jg = q - i * JG;
+        const int64_t j = jg * 8 + (rr & 7);
+        if (j < J) v = scale[i] * Ha[i * F + f] * Hb[j * F + f];
+      }
+      KRt[buf][f * KRP + rr] = (__bf16)v;
+    }
+  };
+  auto load = [&](int e, bf16x8 (&dst)[2][4]) {
+    const int64_t q0 = qbeg + 8LL * e;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int64_t q = q0 + 4 * s + g;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int kt = kw0 + mt * 16;
+        if (kact && q < qend && kt < Kp3) {
+          dst[s][mt] = *reinterpret_cast<const bf16x8*>(Xj8 + (q * Kp3 + kt + n) * 8);
+        } else {
+#pragma unroll
+          for (int e2 = 0; e2 < 8; ++e2) dst[s][mt][e2] = (__bf16)0.f;
+        }
+      }
+    }
+  };
+  bf16x8 xa[2][4], xb[2][4];
+  if (nep > 0) {
+    load(0, xa);
+    build(0, 0);
+  }
+  __syncthreads();
+  for (int e = 0; e < nep; ++e) {
+    if (e + 1 < nep) {
+      load(e + 1, xb);
+      build(e + 1, (e + 1) & 1);
+    }
+    if (kact) {
+      const __bf16* kr = KRt[e & 1];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) {
+          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(kr + (ft * 16 + n) * KRP + s * 32 + 8 * g);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) acc[mt][ft] = mma_bf16(xa[s][mt], bv, acc[mt][ft]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) xa[s][mt] = xb[s][mt];
+  }
+  if (!kact) return;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int k = kw0 + mt * 16 + 4 * g + ii;
+        const int f = ft * 16 + n;
+        if (k < K && f < F) P3[((int64_t)blockIdx.x * K + k) * F + f] = acc[mt][ft][ii];
+      }
+}
+
+// ---------------------------------------------------------------- partial reduction
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_reduce_partials(const PT* __restrict__ part,
+                                                         int64_t pstride, int64_t rowstride,
+                                                         int nparts, int64_t rows, int F,
+                                                         double* __restrict__ W) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= rows * F) return;
+  const int64_t r = idx / F, f = idx - r * F;
+  double s = 0.0;
+#pragma unroll 8
+  for (int p = 0; p < nparts; ++p) s += (double)part[p * pstride + r * rowstride + f];
+  W[idx] = s;
+}
+
+// ---------------------------------------------------------------- planning and launchers
+
+size_t elem_size(int prec) { return prec == PREC_F64 ? 8 : 4; }
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+static const size_t kLdsBudget = 150 * 1024;
+
+bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
+  if (F < 1 || F > 64) return false;
+  p = Plan();
+  p.prec = prec;
+  p.I = dims[0];
+  p.J = dims[1];
+  p.K = dims[2];
+  p.F = F;
+  p.FT = (F + 15) / 16;
+  p.FP = p.FT * 16;
+  p.vec = (p.K % 4) == 0;
+  const int cus = cu_count > 0 ? cu_count : 256;
+  // pass 1: one wave per (slab, 16*MT rows) item, four waves per block
+  if (prec == PREC_BF16) {
+    p.MT1 = 4;
+  } else {
+    // MFMA-bound in FP32 at large F: pick the row tile with the least padding
+    const int64_t pad1 = cdiv(p.J, 16) * 16, pad2 = cdiv(p.J, 32) * 32;
+    p.MT1 = (pad2 - p.J) <= (pad1 - p.J) + p.J / 16 ? 2 : 1;
+  }
+  p.R1 = 16 * p.MT1;
+  p.nch1 = (int)cdiv(p.J, p.R1);
+  p.ntiles1 = p.I * p.nch1;
+  if (prec == PREC_BF16) {
+    p.Kp = rup(p.K, 32);
+    p.JG = cdiv(p.J, 8);
+    p.Kp3 = rup(p.K, 16);
+    int64_t kc = p.Kp;
+    while ((size_t)p.FP * (kc + 8) * 2 > kLdsBudget) kc = rup(kc / 2, 32);
+    p.KC1 = (int)kc;
+    p.lds1 = (size_t)p.FP * (kc + 8) * 2;
+  } else {
+    const size_t es = elem_size(prec);
+    int64_t kc = rup(p.K, 16);
+    while ((size_t)p.FP * kc * es > kLdsBudget) kc = rup(kc / 2, 16);
+    p.KC1 = (int)kc;
+    p.lds1 = (size_t)p.FP * kc * es;
+  }
+  int occ = (int)std::min<size_t>(8, (160 * 1024) / std::max<size_t>(p.lds1 + 512, 1));
+  if (occ < 1) occ = 1;
+  p.grid1 = (int)std::min<int64_t>(cdiv(p.ntiles1, 4), (int64_t)cus * occ);
+  // mode 2 from T
+  p.ich2 = 16;
+  p.nich2 = (int)cdiv(p.I, p.ich2);
+  // pass 3: k split into 64-column wave tiles, at most 8 waves per block,
+  // balanced over ceil(tiles/8) k-groups; about two blocks per CU
+  const int64_t kspan = (prec == PREC_BF16) ? p.Kp3 : p.K;
+  const int ktiles = (int)cdiv(kspan, 64);
+  p.nkg3 = (int)cdiv(ktiles, 8);
+  p.nw3 = (int)cdiv(ktiles, p.nkg3);
+  const int64_t units = (prec == PREC_BF16) ? p.I * p.JG : p.I * p.J;  // groups or rows
+  const int64_t epoch = (prec == PREC_BF16) ? 8 : 64;
+  int64_t nrc = std::max<int64_t>(1, 2LL * cus / p.nkg3);
+  nrc = std::min<int64_t>(nrc, cdiv(units, epoch));
+  p.rpc3 = rup(cdiv(units, nrc), epoch);
+  p.nrc3 = (int)cdiv(units, p.rpc3);
+  // inner sweep
+  int FL = 4;
+  while (FL < F) FL <<= 1;
+  p.FL = FL;
+  p.rpb = 1024 / FL;
+  for (int m = 0; m < 3; ++m) p.nblk_inner[m] = (int)cdiv(dims[m], p.rpb);
+  p.nprep = (int)std::max<int64_t>(1, std::min<int64_t>(16, cdiv((int64_t)F * F, 256)));
+  return true;
+}
+
+hipError_t launch_quantize(const float* X, const Plan& p, __bf16* Xr, __bf16* Xj8, float* scale,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_quantize, dim3((unsigned)p.I), dim3(256), 0, s, X, p.J, p.K, p.Kp, p.JG,
+                     p.Kp3, Xr, Xj8, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const void* X, int x_is_f64, int64_t n, double* partial, int nparts,
+                        double* out, hipStream_t s) {
+  if (x_is_f64)
+    hipLaunchKernelGGL(k_sumsq_part<double>, dim3(nparts), dim3(256), 0, s, (const double*)X, n,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_sumsq_part<float>, dim3(nparts), dim3(256), 0, s, (const float*)X, n,
+                       partial);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, partial, nparts, out);
+  return hipGetLastError();
+}
+
+template <typename T, int FT, int MT>
+static hipError_t pass1_t(const Plan& p, const void* X, const void* Hb, const void* Hc, void* Tout,
+                          void* P1, hipStream_t s) {
+  auto kern = k_pass1<T, FT, MT>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)p.lds1);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(256), p.lds1, s, (const T*)X, (int)p.I, (int)p.J,
+                     (int)p.K, p.F, (const T*)Hb, (const T*)Hc, (T*)Tout, (T*)P1, p.nch1, p.KC1,
+                     p.vec ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename T, int FT>
+static hipError_t pass1_mt(const Plan& p, const void* X, const void* Hb, const void* Hc, void* Tout,
+                           void* P1, hipStream_t s) {
+  if (p.MT1 == 2) return pass1_t<T, FT, 2>(p, X, Hb, Hc, Tout, P1, s);
+  return pass1_t<T, FT, 1>(p, X, Hb, Hc, Tout, P1, s);
+}
+
+template <int FT>
+static hipError_t pass1_bf16(const Plan& p, const __bf16* Xr, const float* scale, const void* Hb,
+                             const void* Hc, void* Tout, void* P1, hipStream_t s) {
+  auto kern = k_pass1_bf16<FT, 4>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)p.lds1);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(256), p.lds1, s, Xr, scale, (int)p.I, (int)p.J,
+                     (int)p.K, (int)p.Kp, p.F, (const float*)Hb, (const float*)Hc, (float*)Tout,
+                     (float*)P1, p.nch1, p.KC1);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass1(const Plan& p, const void* X, const __bf16* Xr, const float* scale,
+                        const void* Hb, const void* Hc, void* Tout, void* P1, hipStream_t s) {
+  if (p.prec == PREC_BF16) {
+    switch (p.FT) {
+      case 1: return pass1_bf16<1>(p, Xr, scale, Hb, Hc, Tout, P1, s);
+      case 2: return pass1_bf16<2>(p, Xr, scale, Hb, Hc, Tout, P1, s);
+      case 3: return pass1_bf16<3>(p, Xr, scale, Hb, Hc, Tout, P1, s);
+      default: return pass1_bf16<4>(p, Xr, scale, Hb, Hc, Tout, P1, s);
+    }
+  }
+  if (p.prec == PREC_F64) {
+    switch (p.FT) {
+      case 1: return pass1_mt<double, 1>(p, X, Hb, Hc, Tout, P1, s);
+      case 2: return pass1_mt<double, 2>(p, X, Hb, Hc, Tout, P1, s);
+      case 3: return pass1_mt<double, 3>(p, X, Hb, Hc, Tout, P1, s);
+      default: return pass1_mt<double, 4>(p, X, Hb, Hc, Tout, P1, s);
+    }
+  }
+  switch (p.FT) {
+    case 1: return pass1_mt<float, 1>(p, X, Hb, Hc, Tout, P1, s);
+    case 2: return pass1_mt<float, 2>(p, X, Hb, Hc, Tout, P1, s);
+    case 3: return pass1_mt<float, 3>(p, X, Hb, Hc, Tout, P1, s);
+    default: return pass1_mt<float, 4>(p, X, Hb, Hc, Tout, P1, s);
+  }
+}
+
+hipError_t launch_mode2(const Plan& p, const void* Tin, const void* Ha, void* P2, hipStream_t s) {
+  const int64_t JF = p.J * p.F;
+  dim3 grid((unsigned)cdiv(JF, 256), (unsigned)p.nich2);
+  if (p.prec == PREC_F64)
+    hipLaunchKernelGGL(k_mode2<double>, grid, dim3(256), 0, s, (const double*)Tin,
+                       (const double*)Ha, (int)p.I, JF, p.F, p.ich2, (double*)P2);
+  else
+    hipLaunchKernelGGL(k_mode2<float>, grid, dim3(256), 0, s, (const float*)Tin, (const float*)Ha,
+                       (int)p.I, JF, p.F, p.ich2, (float*)P2);
+  return hipGetLastError();
+}
+
+template <typename T, int FT>
+static void pass3_t(const Plan& p, const void* X, const void* Ha, const void* Hb, void* P3,
+                    hipStream_t s) {
+  hipLaunchKernelGGL((k_pass3<T, FT>), dim3(p.nrc3, p.nkg3), dim3(64 * p.nw3), 0, s, (const T*)X,
+                     p.I * p.J, (int)p.J, (int)p.K, p.F, (const T*)Ha, (const T*)Hb, (T*)P3,
+                     p.rpc3, p.vec ? 1 : 0);
+}
+
+template <int FT>
+static void pass3_bf16(const Plan& p, const __bf16* Xj8, const float* scale, const void* Ha,
+                       const void* Hb, void* P3, hipStream_t s) {
+  hipLaunchKernelGGL((k_pass3_bf16<FT>), dim3(p.nrc3, p.nkg3), dim3(64 * p.nw3), 0, s, Xj8, scale,
+                     p.I * p.JG, (int)p.J, (int)p.JG, (int)p.K, (int)p.Kp3, p.F, (const float*)Ha,
+                     (const float*)Hb, (float*)P3, p.rpc3);
+}
+
+hipError_t launch_pass3(const Plan& p, const void* X, const __bf16* Xj8, const float* scale,
+                        const void* Ha, const void* Hb, void* P3, hipStream_t s) {
+  if (p.prec == PREC_BF16) {
+    switch (p.FT) {
+      case 1: pass3_bf16<1>(p, Xj8, scale, Ha, Hb, P3, s); break;
+      case 2: pass3_bf16<2>(p, Xj8, scale, Ha, Hb, P3, s); break;
+      case 3: pass3_bf16<3>(p, Xj8, scale, Ha, Hb, P3, s); break;
+      default: pass3_bf16<4>(p, Xj8, scale, Ha, Hb, P3, s); break;
+    }
+  } else if (p.prec == PREC_F64) {
+    switch (p.FT) {
+      case 1: pass3_t<double, 1>(p, X, Ha, Hb, P3, s); break;
+      case 2: pass3_t<double, 2>(p, X, Ha, Hb, P3, s); break;
+      case 3: pass3_t<double, 3>(p, X, Ha, Hb, P3, s); break;
+      default: pass3_t<double, 4>(p, X, Ha, Hb, P3, s); break;
+    }
+  } else {
+    switch (p.FT) {
+      case 1: pass3_t<float, 1>(p, X, Ha, Hb, P3, s); break;
+      case 2: pass3_t<float, 2>(p, X, Ha, Hb, P3, s); break;
+      case 3: pass3_t<float, 3>(p, X, Ha, Hb, P3, s); break;
+      default: pass3_t<float, 4>(p, X, Ha, Hb, P3, s); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const void* part, int part_is_f64, int64_t pstride,
+                                  int64_t rowstride, int nparts, int64_t rows, int F, double* W,
+                                  hipStream_t s) {
+  const unsigned grid = (unsigned)cdiv(rows * F, 256);
+  if (part_is_f64)
+    hipLaunchKernelGGL(k_reduce_partials<double>, dim3(grid), dim3(256), 0, s,
+                       (const double*)part, pstride, rowstride, nparts, rows, F, W);
+  else
+    hipLaunchKernelGGL(k_reduce_partials<float>, dim3(grid), dim3(256), 0, s, (const float*)part,
+                       pstride, rowstride, nparts, rows, F, W);
+  return hipGetLastError();
+}
+
+}  // namespace ntf

@@ -1,0 +1,752 @@
+// C-ABI host layer of libntf_admm.so: validation, workspace carving, the
+// per-outer-iteration launch sequence (captured once into a HIP graph with a
+// side branch for the small F x F work), statistics, fit and checkpointing.
+//
+// One outer iteration (eq. ADMoM_NTF; modes in the Gauss-Seidel order of
+// eq. ADMM_NTF_ALS_C) is enqueued as
+//
+//   main stream                          side stream
+//   pass 1  (W1 partials + T)            prep 1: Gram_3 <- partials; chol(G1 + rho I)
+//   inner 1  <------------------------- (join)
+//   mode 2 from T                        prep 2: Gram_1 <- partials; chol(G2 + rho I)
+//   inner 2  <------------------------- (join)
+//   pass 3  (W3 partials)                prep 3: Gram_2 <- partials; chol(G3 + rho I)
+//   inner 3  <------------------------- (join)
+//
+// so every Cholesky overlaps an MTTKRP pass.  The fused inner kernel of mode n
+// leaves the Gram partials of its new factor for the next prepare step.
+#include "../../include/ntf_admm.h"
+#include "ntf_launch.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+using namespace ntf;
+
+namespace {
+
+struct DevState {
+  double rho[3][2];      // [mode][0] rho of the last update, [1] rho of the update before
+  double resid[3][8];    // residual totals of the last update of each mode
+  double fin[10];        // statistics scratch (mode-3 residual totals, cheap fit terms)
+  double xnorm2;         // ||X||_F^2
+  double fit[2];         // direct fit: squared error, squared norm
+  int fresh[3];          // resid[m] not yet used by the penalty rule
+  int flag;              // numeric error bits
+  unsigned counter[4];   // last-block tickets of the prepare kernels
+};
+
+struct Layout {
+  size_t state = 0, T = 0, P1 = 0, P2 = 0, P3 = 0, W[3] = {0, 0, 0}, prim[3] = {0, 0, 0},
+         gram[3] = {0, 0, 0}, linv[3] = {0, 0, 0}, gpart = 0, rpart = 0, sumsq = 0, fitpart = 0,
+         xr = 0, xj8 = 0, scale = 0, total = 0;
+};
+
+const int kSumsqParts = 1024;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  }
+};
+
+int cu_count() {
+  static int cached = 0;
+  if (cached == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cached = n;
+    else
+      cached = 256;
+  }
+  return cached;
+}
+
+Layout make_layout(const Plan& p, const ntf_opts& o) {
+  Layout L;
+  Carver c;
+  const size_t es = elem_size(p.prec);
+  const int64_t F = p.F;
+  L.state = c.take(sizeof(DevState));
+  L.T = c.take((size_t)(p.I * p.J * F) * es);
+  L.P1 = c.take((size_t)(p.I * p.nch1 * F) * es);
+  L.P2 = c.take((size_t)((int64_t)p.nich2 * p.J * F) * es);
+  L.P3 = c.take((size_t)((int64_t)p.nrc3 * p.K * F) * es);
+  const int64_t d[3] = {p.I, p.J, p.K};
+  int maxblk = 1;
+  for (int m = 0; m < 3; ++m) {
+    L.W[m] = c.take((size_t)(d[m] * F) * 8);
+    L.prim[m] = (o.factor_source == 1) ? c.take((size_t)(d[m] * F) * es) : 0;
+    L.gram[m] = c.take((size_t)(F * F) * 8);
+    L.linv[m] = c.take((size_t)(F * F) * 8);
+    if (p.nblk_inner[m] > maxblk) maxblk = p.nblk_inner[m];
+  }
+  L.gpart = c.take((size_t)maxblk * F * F * 8);
+  L.rpart = c.take((size_t)maxblk * 8 * 8);
+  L.sumsq = c.take((size_t)kSumsqParts * 8);
+  L.fitpart = c.take((size_t)fit_parts(p) * 2 * 8);
+  if (p.prec == PREC_BF16) {
+    L.xr = c.take((size_t)(p.I * p.J * p.Kp) * 2);
+    L.xj8 = c.take((size_t)(p.I * p.JG * p.Kp3 * 8) * 2);
+    L.scale = c.take((size_t)p.I * 4);
+  }
+  L.total = c.off;
+  return L;
+}
+
+}  // namespace
+
+struct ntf_admm_ctx {
+  ntf_problem prob;
+  ntf_opts opts;
+  Plan plan;
+  Layout lay;
+  char* ws = nullptr;
+  hipStream_t s0 = nullptr, s1 = nullptr;  // caller's stream, side stream
+  hipStream_t sc = nullptr;                 // internal stream the graph is captured on
+  hipEvent_t ev_fork = nullptr, ev_inner[3] = {nullptr, nullptr, nullptr},
+             ev_prep[3] = {nullptr, nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool use_graph = true;
+  int64_t outer = 0;
+  DevState* host_state = nullptr;  // pinned
+  std::string err;
+
+  template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+  DevState* dstate() { return at<DevState>(lay.state); }
+  int hf64() const { return plan.prec == PREC_F64 ? 1 : 0; }
+  const void* feed(int m) const {
+    return (opts.factor_source == 1) ? (const void*)(ws + lay.prim[m]) : (const void*)prob.H[m];
+  }
+};
+
+#define NTF_HIP(ctx, call)                                                             \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      if (ctx) (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);        \
+      return NTF_E_HIP;                                                                \
+    }                                                                                  \
+  } while (0)
+
+static ntf_status validate(const ntf_problem* pr, const ntf_opts* o, std::string* why) {
+  auto fail = [&](const char* m) {
+    if (why) *why = m;
+    return NTF_E_INVAL;
+  };
+  if (!pr || !o) return fail("null problem or options");
+  for (int m = 0; m < 3; ++m)
+    if (pr->dims[m] < 1 || pr->dims[m] > (int64_t)1 << 31) return fail("dims must be in [1, 2^31]");
+  if (pr->F < 1 || pr->F > 64) return fail("F must be in [1, 64]");
+  if (o->precision != NTF_PREC_F32 && o->precision != NTF_PREC_BF16_MIXED &&
+      o->precision != NTF_PREC_F64)
+    return fail("unknown precision");
+  if ((o->precision == NTF_PREC_F64) != (pr->x_dtype == 1)) return fail("x_dtype does not match precision");
+  if (pr->x_dtype != 0 && pr->x_dtype != 1) return fail("x_dtype must be 0 or 1");
+  if (!pr->X) return fail("null X");
+  if (((uintptr_t)pr->X) & 15) return fail("X not 16-byte aligned");
+  for (int m = 0; m < 3; ++m) {
+    if (!pr->H[m] || !pr->U[m]) return fail("null factor or dual");
+    if ((((uintptr_t)pr->H[m]) | ((uintptr_t)pr->U[m])) & 15) return fail("factor/dual not 16-byte aligned");
+  }
+  if (o->inner_iters < 1) return fail("inner_iters must be >= 1");
+  if (o->rho_policy < 0 || o->rho_policy > 2) return fail("unknown rho_policy");
+  if (!(o->rho0 > 0.0)) return fail("rho0 must be > 0");
+  if (o->rho_policy == NTF_RHO_ADAPTIVE && !(o->mu > 1.0 && o->tau_incr > 1.0 && o->tau_decr > 1.0))
+    return fail("mu, tau_incr, tau_decr must be > 1");
+  if (o->inner_eps_abs < 0 || o->inner_eps_rel < 0 || o->stop_eps_abs < 0 || o->stop_eps_rel < 0)
+    return fail("tolerances must be >= 0");
+  if (o->factor_source != 0 && o->factor_source != 1) return fail("factor_source must be 0 or 1");
+  if (o->paper_init && o->factor_source != 1) return fail("paper_init needs factor_source 1");
+  for (int q = 0; q < 4; ++q)
+    if (o->reserved[q] != 0) return fail("reserved fields must be zero");
+  const int64_t I = pr->dims[0], J = pr->dims[1], K = pr->dims[2];
+  if (I * J > ((int64_t)1 << 40) || I * J * K > ((int64_t)1 << 46)) return fail("tensor too large");
+  return NTF_OK;
+}
+
+extern "C" {
+
+const char* ntf_status_str(ntf_status s) {
+  switch (s) {
+    case NTF_OK: return "ok";
+    case NTF_NOT_CONVERGED: return "not converged";
+    case NTF_E_INVAL: return "invalid argument";
+    case NTF_E_WORKSPACE: return "workspace too small";
+    case NTF_E_HIP: return "HIP runtime error";
+    case NTF_E_NUMERIC: return "numeric failure (non-PD system or NaN/Inf)";
+    case NTF_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+static thread_local std::string g_init_err;  // why the last failed init on this thread failed
+
+const char* ntf_admm_last_error(const ntf_admm_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_init_err.c_str();
+}
+
+size_t ntf_admm_workspace_bytes(const ntf_problem* prob, const ntf_opts* opts) {
+  if (validate(prob, opts, nullptr) != NTF_OK) return 0;
+  Plan p;
+  if (!make_plan(p, opts->precision, prob->dims, prob->F, 256)) return 0;
+  return make_layout(p, *opts).total;
+}
+
+}  // extern "C"
+
+// Grams of the three current factors, with mode 3's partials left in place for
+// the first prepare step, exactly as the inner kernel would have left them.
+static ntf_status compute_grams(ntf_admm_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t d[3] = {p.I, p.J, p.K};
+  const int gf32 = (p.prec == PREC_BF16) ? 1 : 0;
+  double* gpart = c->at<double>(c->lay.gpart);
+  for (int m = 0; m < 3; ++m) {
+    NTF_HIP(c, launch_gram_part(c->feed(m), c->hf64(), d[m], p.F, p.rpb, gf32, gpart, c->s0));
+    NTF_HIP(c, launch_reduce_partials(gpart, 1, (int64_t)p.F * p.F, p.F, p.nblk_inner[m], p.F, p.F,
+                                      c->at<double>(c->lay.gram[m]), c->s0));
+  }
+  // leave mode 3's partials (the buffer already holds them) and zero residual partials
+  NTF_HIP(c, launch_fill(c->at<double>(c->lay.rpart), (int64_t)p.nblk_inner[2] * 8, 0.0, c->s0));
+  return NTF_OK;
+}
+
+static void prep_args(ntf_admm_ctx* c, int m, PrepArgs& a) {
+  // prepare mode m: reduce the partials of mode (m+2)%3 (the one updated last)
+  const Plan& p = c->plan;
+  const int src = (m + 2) % 3;
+  const int oth = (m + 1) % 3;  // the other Gram in G_m besides gram[src]
+  DevState* ds = c->dstate();
+  a = PrepArgs();
+  a.F = p.F;
+  a.gram_part = c->at<double>(c->lay.gpart);
+  a.nparts = p.nblk_inner[src];
+  a.gram_dst = c->at<double>(c->lay.gram[src]);
+  a.resid_part = c->at<double>(c->lay.rpart);
+  a.resid_dst = ds->resid[src];
+  a.fresh_dst = &ds->fresh[src];
+  a.gram_a = c->at<double>(c->lay.gram[src]);
+  a.gram_b = c->at<double>(c->lay.gram[oth]);
+  a.policy = c->opts.rho_policy;
+  a.rho0 = c->opts.rho0;
+  a.mu = c->opts.mu;
+  a.tau_incr = c->opts.tau_incr;
+  a.tau_decr = c->opts.tau_decr;
+  a.rho_state = ds->rho[m];
+  a.resid_mode = ds->resid[m];
+  a.fresh_mode = &ds->fresh[m];
+  a.Linv = c->at<double>(c->lay.linv[m]);
+  a.flag = &ds->flag;
+  a.counter = &ds->counter[m];
+}
+
+static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
+  const Plan& p = c->plan;
+  const int64_t d[3] = {p.I, p.J, p.K};
+  DevState* ds = c->dstate();
+  a = InnerArgs();
+  a.part_f64 = c->hf64();
+  if (m == 0) {
+    a.part = c->ws + c->lay.P1;
+    a.pstride = p.F;
+    a.rowstride = (int64_t)p.nch1 * p.F;
+    a.nparts = p.nch1;
+  } else if (m == 1) {
+    a.part = c->ws + c->lay.P2;
+    a.pstride = p.J * p.F;
+    a.rowstride = p.F;
+    a.nparts = p.nich2;
+  } else {
+    a.part = c->ws + c->lay.P3;
+    a.pstride = p.K * p.F;
+    a.rowstride = p.F;
+    a.nparts = p.nrc3;
+  }
+  a.Wout = c->at<double>(c->lay.W[m]);
+  a.H = c->prob.H[m];
+  a.U = c->prob.U[m];
+  a.Pout = (c->opts.factor_source == 1) ? (void*)(c->ws + c->lay.prim[m]) : nullptr;
+  a.h_f64 = c->hf64();
+  a.rows = d[m];
+  a.F = p.F;
+  a.FL = p.FL;
+  a.Linv = c->at<double>(c->lay.linv[m]);
+  a.rho = ds->rho[m];
+  a.rescale = (c->opts.rescale_dual_on_rho_change || c->opts.rho_policy == NTF_RHO_ADAPTIVE) ? 1 : 0;
+  a.T = c->opts.inner_iters;
+  a.eps_abs = c->opts.inner_eps_abs;
+  a.eps_rel = c->opts.inner_eps_rel;
+  a.gram_from_primal = (c->opts.factor_source == 1) ? 1 : 0;
+  a.gram_f32 = (p.prec == PREC_BF16) ? 1 : 0;
+  a.gram_part = c->at<double>(c->lay.gpart);
+  a.resid_part = c->at<double>(c->lay.rpart);
+  a.flag = &ds->flag;
+}
+
+// Enqueue one outer iteration on `ms` with the prepare kernels on s1.
+static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
+  const Plan& p = c->plan;
+  const __bf16* xr = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xr) : nullptr;
+  const __bf16* xj8 = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xj8) : nullptr;
+  const float* scale = p.prec == PREC_BF16 ? c->at<float>(c->lay.scale) : nullptr;
+  void* T = c->ws + c->lay.T;
+  PrepArgs pa;
+  InnerArgs ia;
+  // mode 1 (A): prepare on the side while pass 1 streams X
+  NTF_HIP(c, hipEventRecord(c->ev_fork, ms));
+  NTF_HIP(c, hipStreamWaitEvent(c->s1, c->ev_fork, 0));
+  prep_args(c, 0, pa);
+  NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
+  NTF_HIP(c, hipEventRecord(c->ev_prep[0], c->s1));
+  NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, ms));
+  NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[0], 0));
+  inner_args(c, 0, ia);
+  NTF_HIP(c, launch_inner(ia, p.nblk_inner[0], ms));
+  // mode 2 (B)
+  NTF_HIP(c, hipEventRecord(c->ev_inner[0], ms));
+  NTF_HIP(c, hipStreamWaitEvent(c->s1, c->ev_inner[0], 0));
+  prep_args(c, 1, pa);
+  NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
+  NTF_HIP(c, hipEventRecord(c->ev_prep[1], c->s1));
+  NTF_HIP(c, launch_mode2(p, T, c->feed(0), c->ws + c->lay.P2, ms));
+  NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[1], 0));
+  inner_args(c, 1, ia);
+  NTF_HIP(c, launch_inner(ia, p.nblk_inner[1], ms));
+  // mode 3 (C)
+  NTF_HIP(c, hipEventRecord(c->ev_inner[1], ms));
+  NTF_HIP(c, hipStreamWaitEvent(c->s1, c->ev_inner[1], 0));
+  prep_args(c, 2, pa);
+  NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
+  NTF_HIP(c, hipEventRecord(c->ev_prep[2], c->s1));
+  NTF_HIP(c, launch_pass3(p, c->prob.X, xj8, scale, c->feed(0), c->feed(1), c->ws + c->lay.P3, ms));
+  NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[2], 0));
+  inner_args(c, 2, ia);
+  NTF_HIP(c, launch_inner(ia, p.nblk_inner[2], ms));
+  return NTF_OK;
+}
+
+static ntf_status launch_outer(ntf_admm_ctx* c) {
+  if (!c->use_graph) {
+    ntf_status st = enqueue_outer(c, c->s0);
+    if (st == NTF_OK) c->outer++;
+    return st;
+  }
+  if (!c->gexec) {
+    NTF_HIP(c, hipStreamBeginCapture(c->sc, hipStreamCaptureModeThreadLocal));
+    ntf_status st = enqueue_outer(c, c->sc);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->sc, &g);
+    if (st != NTF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    NTF_HIP(c, e);
+    c->graph = g;
+    NTF_HIP(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  }
+  NTF_HIP(c, hipGraphLaunch(c->gexec, c->s0));
+  c->outer++;
+  return NTF_OK;
+}
+
+static ntf_status fill_stats(ntf_admm_ctx* c, ntf_stats* st) {
+  const Plan& p = c->plan;
+  DevState* ds = c->dstate();
+  NTF_HIP(c, launch_finish(p.F, c->at<double>(c->lay.gpart), c->at<double>(c->lay.rpart),
+                           p.nblk_inner[2], c->at<double>(c->lay.gram[0]),
+                           c->at<double>(c->lay.gram[1]), c->at<double>(c->lay.W[2]),
+                           c->prob.H[2], c->hf64(), p.K, ds->fin, c->s0));
+  NTF_HIP(c, hipMemcpyAsync(c->host_state, ds, sizeof(DevState), hipMemcpyDeviceToHost, c->s0));
+  NTF_HIP(c, hipStreamSynchronize(c->s0));
+  const DevState& h = *c->host_state;
+  std::memset(st, 0, sizeof(*st));
+  st->outer = c->outer;
+  const int64_t d[3] = {p.I, p.J, p.K};
+  bool conv = true;
+  for (int m = 0; m < 3; ++m) {
+    const double* r = (m == 2) ? h.fin : h.resid[m];
+    const double rho = h.rho[m][0];
+    st->rho[m] = rho;
+    st->prim[m] = std::sqrt(r[0]);
+    st->dual[m] = rho * std::sqrt(r[1]);
+    st->norm_h[m] = std::sqrt(r[2]);
+    st->norm_p[m] = std::sqrt(r[3]);
+    st->norm_y[m] = rho * std::sqrt(r[4]);
+    st->inner_iters_mean[m] = r[5] / (double)d[m];
+    const double sq = std::sqrt((double)d[m] * p.F) * c->opts.stop_eps_abs;
+    if (st->prim[m] > sq + c->opts.stop_eps_rel * std::fmax(st->norm_p[m], st->norm_h[m])) conv = false;
+    if (st->dual[m] > sq + c->opts.stop_eps_rel * st->norm_y[m]) conv = false;
+  }
+  const double e2 = h.xnorm2 - 2.0 * h.fin[8] + h.fin[9];
+  st->rfe_cheap = h.xnorm2 > 0 ? std::sqrt(std::fmax(e2, 0.0) / h.xnorm2) : 0.0;
+  st->numeric_error = h.flag;
+  st->converged = (c->opts.stop_eps_abs > 0 || c->opts.stop_eps_rel > 0) && conv ? 1 : 0;
+  if (c->outer == 0) st->converged = 0;
+  return h.flag ? NTF_E_NUMERIC : NTF_OK;
+}
+
+extern "C" {
+
+ntf_status ntf_admm_init(ntf_admm_ctx** out, const ntf_problem* prob, const ntf_opts* opts,
+                         void* workspace, size_t ws_bytes, void* stream) {
+  if (!out) return NTF_E_INVAL;
+  *out = nullptr;
+  std::string why;
+  ntf_status vs = validate(prob, opts, &why);
+  g_init_err = why;
+  if (vs != NTF_OK) return vs;
+  ntf_admm_ctx* c = new (std::nothrow) ntf_admm_ctx();
+  if (!c) return NTF_E_HIP;
+  c->prob = *prob;
+  c->opts = *opts;
+  if (!make_plan(c->plan, opts->precision, prob->dims, prob->F, cu_count())) {
+    delete c;
+    return NTF_E_UNSUPPORTED;
+  }
+  c->lay = make_layout(c->plan, c->opts);
+  if (!workspace || ((uintptr_t)workspace & 255)) {
+    delete c;
+    return NTF_E_INVAL;
+  }
+  if (ws_bytes < c->lay.total) {
+    delete c;
+    return NTF_E_WORKSPACE;
+  }
+  c->ws = reinterpret_cast<char*>(workspace);
+  c->s0 = reinterpret_cast<hipStream_t>(stream);
+  const char* ng = std::getenv("NTF_NO_GRAPH");
+  c->use_graph = !(ng && ng[0] == '1');
+  ntf_status st = [&]() -> ntf_status {
+    NTF_HIP(c, hipStreamCreateWithFlags(&c->s1, hipStreamNonBlocking));
+    NTF_HIP(c, hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking));
+    NTF_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    for (int m = 0; m < 3; ++m) {
+      NTF_HIP(c, hipEventCreateWithFlags(&c->ev_inner[m], hipEventDisableTiming));
+      NTF_HIP(c, hipEventCreateWithFlags(&c->ev_prep[m], hipEventDisableTiming));
+    }
+    NTF_HIP(c, hipHostMalloc((void**)&c->host_state, sizeof(DevState), hipHostMallocDefault));
+    const Plan& p = c->plan;
+    // state block
+    DevState init;
+    std::memset(&init, 0, sizeof(init));
+    for (int m = 0; m < 3; ++m) init.rho[m][0] = init.rho[m][1] = c->opts.rho0;
+    *c->host_state = init;
+    NTF_HIP(c, hipMemcpyAsync(c->dstate(), c->host_state, sizeof(DevState), hipMemcpyHostToDevice, c->s0));
+    // bfloat16 copies
+    if (p.prec == PREC_BF16)
+      NTF_HIP(c, launch_quantize((const float*)prob->X, p, c->at<__bf16>(c->lay.xr),
+                                 c->at<__bf16>(c->lay.xj8), c->at<float>(c->lay.scale), c->s0));
+    NTF_HIP(c, launch_sumsq(prob->X, prob->x_dtype, p.I * p.J * p.K, c->at<double>(c->lay.sumsq),
+                            kSumsqParts, &c->dstate()->xnorm2, c->s0));
+    // paper initialisation: the given factors seed the primal; auxiliary and duals start at zero
+    const int64_t d[3] = {p.I, p.J, p.K};
+    const size_t es = elem_size(p.prec);
+    if (c->opts.factor_source == 1) {
+      for (int m = 0; m < 3; ++m) {
+        NTF_HIP(c, hipMemcpyAsync(c->ws + c->lay.prim[m], prob->H[m], (size_t)(d[m] * p.F) * es,
+                                  hipMemcpyDeviceToDevice, c->s0));
+        if (c->opts.paper_init) {
+          NTF_HIP(c, hipMemsetAsync(prob->H[m], 0, (size_t)(d[m] * p.F) * es, c->s0));
+          NTF_HIP(c, hipMemsetAsync(prob->U[m], 0, (size_t)(d[m] * p.F) * es, c->s0));
+        }
+      }
+    }
+    ntf_status g = compute_grams(c);
+    if (g != NTF_OK) return g;
+    NTF_HIP(c, hipStreamSynchronize(c->s0));
+    return NTF_OK;
+  }();
+  if (st != NTF_OK) {
+    g_init_err = c->err;
+    ntf_admm_destroy(c);
+    return st;
+  }
+  *out = c;
+  return NTF_OK;
+}
+
+ntf_status ntf_admm_step(ntf_admm_ctx* c, ntf_stats* stats) {
+  if (!c) return NTF_E_INVAL;
+  ntf_status st = launch_outer(c);
+  if (st != NTF_OK) return st;
+  if (stats) return fill_stats(c, stats);
+  return NTF_OK;
+}
+
+ntf_status ntf_admm_run(ntf_admm_ctx* c, int32_t max_outer, int32_t check_every, ntf_stats* stats) {
+  if (!c || max_outer < 0) return NTF_E_INVAL;
+  const bool test = c->opts.stop_eps_abs > 0 || c->opts.stop_eps_rel > 0;
+  if (test && check_every < 1) return NTF_E_INVAL;
+  ntf_stats local;
+  for (int32_t it = 0; it < max_outer; ++it) {
+    ntf_status st = launch_outer(c);
+    if (st != NTF_OK) return st;
+    if (test && ((it + 1) % check_every == 0 || it + 1 == max_outer)) {
+      st = fill_stats(c, stats ? stats : &local);
+      if (st != NTF_OK) return st;
+      if ((stats ? stats : &local)->converged) return NTF_OK;
+    }
+  }
+  if (stats && !test) {
+    ntf_status st = fill_stats(c, stats);
+    if (st != NTF_OK) return st;
+  }
+  return test ? NTF_NOT_CONVERGED : NTF_OK;
+}
+
+ntf_status ntf_admm_fit(ntf_admm_ctx* c, double* rfe) {
+  if (!c || !rfe) return NTF_E_INVAL;
+  const Plan& p = c->plan;
+  DevState* ds = c->dstate();
+  NTF_HIP(c, launch_fit(p, c->prob.X, c->prob.x_dtype, c->prob.H[0], c->prob.H[1], c->prob.H[2],
+                        c->hf64(), c->at<double>(c->lay.fitpart), ds->fit, c->s0, nullptr));
+  double h[2];
+  NTF_HIP(c, hipMemcpyAsync(h, ds->fit, sizeof(h), hipMemcpyDeviceToHost, c->s0));
+  NTF_HIP(c, hipStreamSynchronize(c->s0));
+  *rfe = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+  return NTF_OK;
+}
+
+size_t ntf_admm_state_bytes(const ntf_admm_ctx* c) {
+  if (!c) return 0;
+  size_t b = sizeof(DevState) + sizeof(int64_t);
+  if (c->opts.factor_source == 1) {
+    const int64_t d[3] = {c->plan.I, c->plan.J, c->plan.K};
+    for (int m = 0; m < 3; ++m) b += (size_t)(d[m] * c->plan.F) * elem_size(c->plan.prec);
+  }
+  return b;
+}
+
+ntf_status ntf_admm_get_state(ntf_admm_ctx* c, void* buf, size_t bytes) {
+  if (!c || !buf || bytes != ntf_admm_state_bytes(c)) return NTF_E_INVAL;
+  char* o = reinterpret_cast<char*>(buf);
+  // The last mode's residuals are still partials; fold their totals into the
+  // snapshot (fin[0..7]) so it is self-contained (the penalty rule reads them).
+  const Plan& p = c->plan;
+  NTF_HIP(c, launch_finish(p.F, c->at<double>(c->lay.gpart), c->at<double>(c->lay.rpart),
+                           p.nblk_inner[2], c->at<double>(c->lay.gram[0]),
+                           c->at<double>(c->lay.gram[1]), c->at<double>(c->lay.W[2]),
+                           c->prob.H[2], c->hf64(), p.K, c->dstate()->fin, c->s0));
+  NTF_HIP(c, hipStreamSynchronize(c->s0));
+  NTF_HIP(c, hipMemcpy(o, c->dstate(), sizeof(DevState), hipMemcpyDeviceToHost));
+  std::memcpy(o + sizeof(DevState), &c->outer, sizeof(int64_t));
+  size_t off = sizeof(DevState) + sizeof(int64_t);
+  if (c->opts.factor_source == 1) {
+    const int64_t d[3] = {c->plan.I, c->plan.J, c->plan.K};
+    for (int m = 0; m < 3; ++m) {
+      const size_t nb = (size_t)(d[m] * c->plan.F) * elem_size(c->plan.prec);
+      NTF_HIP(c, hipMemcpy(o + off, c->ws + c->lay.prim[m], nb, hipMemcpyDeviceToHost));
+      off += nb;
+    }
+  }
+  return NTF_OK;
+}
+
+ntf_status ntf_admm_set_state(ntf_admm_ctx* c, const void* buf, size_t bytes) {
+  if (!c || !buf || bytes != ntf_admm_state_bytes(c)) return NTF_E_INVAL;
+  const char* in = reinterpret_cast<const char*>(buf);
+  DevState s;
+  std::memcpy(&s, in, sizeof(DevState));
+  std::memcpy(&c->outer, in + sizeof(DevState), sizeof(int64_t));
+  for (int q = 0; q < 4; ++q) s.counter[q] = 0;
+  s.flag = 0;
+  *c->host_state = s;
+  NTF_HIP(c, hipMemcpyAsync(c->dstate(), c->host_state, sizeof(DevState), hipMemcpyHostToDevice, c->s0));
+  size_t off = sizeof(DevState) + sizeof(int64_t);
+  if (c->opts.factor_source == 1) {
+    const int64_t d[3] = {c->plan.I, c->plan.J, c->plan.K};
+    for (int m = 0; m < 3; ++m) {
+      const size_t nb = (size_t)(d[m] * c->plan.F) * elem_size(c->plan.prec);
+      NTF_HIP(c, hipMemcpyAsync(c->ws + c->lay.prim[m], in + off, nb, hipMemcpyHostToDevice, c->s0));
+      off += nb;
+    }
+  }
+  ntf_status g = compute_grams(c);
+  if (g != NTF_OK) return g;
+  // the last mode's residual totals become its first partial (the rest are zero)
+  NTF_HIP(c, hipMemcpyAsync(c->at<double>(c->lay.rpart), c->host_state->fin, 8 * sizeof(double),
+                            hipMemcpyHostToDevice, c->s0));
+  NTF_HIP(c, hipStreamSynchronize(c->s0));
+  return NTF_OK;
+}
+
+ntf_status ntf_admm_mttkrp(ntf_admm_ctx* c, int32_t mode, double* W_out) {
+  if (!c || !W_out || mode < 0 || mode > 2) return NTF_E_INVAL;
+  const Plan& p = c->plan;
+  const __bf16* xr = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xr) : nullptr;
+  const __bf16* xj8 = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xj8) : nullptr;
+  const float* scale = p.prec == PREC_BF16 ? c->at<float>(c->lay.scale) : nullptr;
+  void* T = c->ws + c->lay.T;
+  const int pf64 = c->hf64();
+  if (mode == 0 || mode == 1)
+    NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, c->s0));
+  if (mode == 0)
+    NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P1, pf64, p.F, (int64_t)p.nch1 * p.F, p.nch1,
+                                      p.I, p.F, W_out, c->s0));
+  if (mode == 1) {
+    NTF_HIP(c, launch_mode2(p, T, c->feed(0), c->ws + c->lay.P2, c->s0));
+    NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P2, pf64, p.J * p.F, p.F, p.nich2, p.J, p.F,
+                                      W_out, c->s0));
+  }
+  if (mode == 2) {
+    NTF_HIP(c, launch_pass3(p, c->prob.X, xj8, scale, c->feed(0), c->feed(1), c->ws + c->lay.P3, c->s0));
+    NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P3, pf64, p.K * p.F, p.F, p.nrc3, p.K, p.F,
+                                      W_out, c->s0));
+  }
+  return NTF_OK;
+}
+
+ntf_status ntf_admm_launch_pass(ntf_admm_ctx* c, int32_t pass) {
+  if (!c || pass < 0 || pass > 2) return NTF_E_INVAL;
+  const Plan& p = c->plan;
+  const __bf16* xr = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xr) : nullptr;
+  const __bf16* xj8 = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xj8) : nullptr;
+  const float* scale = p.prec == PREC_BF16 ? c->at<float>(c->lay.scale) : nullptr;
+  void* T = c->ws + c->lay.T;
+  if (pass == 0)
+    NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, c->s0));
+  else if (pass == 1)
+    NTF_HIP(c, launch_mode2(p, T, c->feed(0), c->ws + c->lay.P2, c->s0));
+  else
+    NTF_HIP(c, launch_pass3(p, c->prob.X, xj8, scale, c->feed(0), c->feed(1), c->ws + c->lay.P3, c->s0));
+  return NTF_OK;
+}
+
+ntf_status ntf_admm_destroy(ntf_admm_ctx* c) {
+  if (!c) return NTF_E_INVAL;
+  if (c->s0 || c->s1) {
+    (void)hipStreamSynchronize(c->s0);
+    if (c->s1) (void)hipStreamSynchronize(c->s1);
+  }
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  for (int m = 0; m < 3; ++m) {
+    if (c->ev_inner[m]) (void)hipEventDestroy(c->ev_inner[m]);
+    if (c->ev_prep[m]) (void)hipEventDestroy(c->ev_prep[m]);
+  }
+  if (c->s1) (void)hipStreamDestroy(c->s1);
+  if (c->sc) (void)hipStreamDestroy(c->sc);
+  if (c->host_state) (void)hipHostFree(c->host_state);
+  delete c;
+  return NTF_OK;
+}
+
+// ---------------------------------------------------------------- kernel-level calls
+
+size_t ntf_gram_workspace_bytes(int64_t rows, int32_t F) {
+  if (rows < 1 || F < 1 || F > 64) return 0;
+  const int64_t nparts = (rows + 63) / 64;
+  return align_up((size_t)nparts * F * F * 8, 256);
+}
+
+ntf_status ntf_gram(const void* H, int64_t rows, int32_t F, int32_t dtype, double* G_out,
+                    void* workspace, size_t ws_bytes, void* stream) {
+  if (!H || !G_out || rows < 1 || F < 1 || F > 64 || (dtype != 0 && dtype != 1) || !workspace)
+    return NTF_E_INVAL;
+  if (ws_bytes < ntf_gram_workspace_bytes(rows, F)) return NTF_E_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t nparts = (rows + 63) / 64;
+  double* part = reinterpret_cast<double*>(workspace);
+  if (launch_gram_part(H, dtype, rows, F, 64, 0, part, s) != hipSuccess) return NTF_E_HIP;
+  if (launch_reduce_partials(part, 1, (int64_t)F * F, F, (int)nparts, F, F, G_out, s) != hipSuccess)
+    return NTF_E_HIP;
+  return NTF_OK;
+}
+
+namespace {
+struct InnerWs {
+  size_t state, ones, linv, gpart, rpart, total;
+};
+InnerWs inner_ws(int64_t rows, int F) {
+  int FL = 4;
+  while (FL < F) FL <<= 1;
+  const int rpb = 1024 / FL;
+  const int64_t nblk = (rows + rpb - 1) / rpb;
+  Carver c;
+  InnerWs w;
+  w.state = c.take(sizeof(DevState));
+  w.ones = c.take((size_t)F * F * 8);
+  w.linv = c.take((size_t)F * F * 8);
+  w.gpart = c.take((size_t)nblk * F * F * 8);
+  w.rpart = c.take((size_t)nblk * 8 * 8);
+  w.total = c.off;
+  return w;
+}
+}  // namespace
+
+size_t ntf_inner_workspace_bytes(int64_t rows, int32_t F) {
+  if (rows < 1 || F < 1 || F > 64) return 0;
+  return inner_ws(rows, F).total;
+}
+
+ntf_status ntf_inner_update(const double* W, void* H, void* U, int64_t rows, int32_t F,
+                            int32_t dtype, const double* G, double rho, int32_t T, double eps_abs,
+                            double eps_rel, int32_t* iters_out, void* Ht_out, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  if (!W || !H || !U || !G || rows < 1 || F < 1 || F > 64 || (dtype != 0 && dtype != 1) || T < 1 ||
+      !workspace || eps_abs < 0 || eps_rel < 0)
+    return NTF_E_INVAL;
+  const InnerWs w = inner_ws(rows, F);
+  if (ws_bytes < w.total) return NTF_E_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>(workspace);
+  DevState* ds = reinterpret_cast<DevState*>(base + w.state);
+  // zeroed state (rho/prev = given rho or 0 for trace), ones for the Hadamard partner
+  if (launch_fill(reinterpret_cast<double*>(ds), sizeof(DevState) / 8, 0.0, s) != hipSuccess) return NTF_E_HIP;
+  if (launch_fill(reinterpret_cast<double*>(base + w.ones), (int64_t)F * F, 1.0, s) != hipSuccess) return NTF_E_HIP;
+  PrepArgs pa;
+  pa.F = F;
+  pa.gram_a = G;
+  pa.gram_b = reinterpret_cast<double*>(base + w.ones);
+  pa.policy = rho > 0 ? 1 : 0;
+  pa.rho0 = rho > 0 ? rho : 1.0;
+  pa.rho_state = ds->rho[0];
+  pa.Linv = reinterpret_cast<double*>(base + w.linv);
+  pa.flag = &ds->flag;
+  pa.counter = &ds->counter[0];
+  if (launch_prep(pa, 1, s) != hipSuccess) return NTF_E_HIP;
+  int FL = 4;
+  while (FL < F) FL <<= 1;
+  InnerArgs ia;
+  ia.part = W;
+  ia.part_f64 = 1;
+  ia.pstride = 0;
+  ia.rowstride = F;
+  ia.nparts = 1;
+  ia.H = H;
+  ia.U = U;
+  ia.Pout = Ht_out;
+  ia.h_f64 = dtype;
+  ia.rows = rows;
+  ia.F = F;
+  ia.FL = FL;
+  ia.Linv = pa.Linv;
+  ia.rho = ds->rho[0];
+  ia.T = T;
+  ia.eps_abs = eps_abs;
+  ia.eps_rel = eps_rel;
+  ia.iters_out = iters_out;
+  ia.gram_part = reinterpret_cast<double*>(base + w.gpart);
+  ia.resid_part = reinterpret_cast<double*>(base + w.rpart);
+  ia.flag = &ds->flag;
+  const int rpb = 1024 / FL;
+  if (launch_inner(ia, (int)((rows + rpb - 1) / rpb), s) != hipSuccess) return NTF_E_HIP;
+  return NTF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Device-side helpers shared by the gfx950 kernels of libntf_admm.
+//
+// MFMA operand/result layouts (one wave of 64 lanes, lane l, n = l % 16,
+// g = l / 16), as used by every contraction kernel here:
+//   v_mfma_f32_16x16x4_f32 / v_mfma_f64_16x16x4_f64 (D = A[16x4] B[4x16] + C):
+//     lane supplies A[n][g] and B[g][n];
+//     f32 result: element i of the lane's 4 holds D[4g + i][n];
+//     f64 result: element i holds D[g + 4i][n].
+//   v_mfma_f32_16x16x32_bf16 (A 16x32, B 32x16, 8 bf16 per lane):
+//     lane supplies A[n][8g .. 8g+7] and B[8g .. 8g+7][n];
+//     result element i holds D[4g + i][n].
+// The contraction index of one instruction may be permuted freely as long as
+// A and B use the same permutation; the kernels use that to turn 16-byte
+// vector loads into operands.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ntf {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename T> struct Mfma;
+
+template <> struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of the 16x16 result held in accumulator element i by lane group g
+  static __device__ __forceinline__ int row(int g, int i) { return 4 * g + i; }
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+};
+
+template <> struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int i) { return g + 4 * i; }
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+};
+
+static __device__ __forceinline__ f32x4 mma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Four consecutive elements starting at p (p + 3 must be in bounds when full).
+template <typename T> struct Vec4Load;
+template <> struct Vec4Load<float> {
+  static __device__ __forceinline__ void load(const float* p, float (&v)[4]) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  }
+};
+template <> struct Vec4Load<double> {
+  static __device__ __forceinline__ void load(const double* p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+};
+
+template <typename T>
+static __device__ __forceinline__ void load4(const T* p, int valid, bool vec, T (&v)[4]) {
+  if (vec && valid >= 4) {
+    Vec4Load<T>::load(p, v);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = (c < valid) ? p[c] : T(0);
+  }
+}
+
+// Reduce across the `width` lanes of an aligned lane group (width a power of 2, <= 64).
+template <typename T>
+static __device__ __forceinline__ T group_sum(T v, int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, width);
+  return v;
+}
+
+}  // namespace ntf

@@ -1,0 +1,129 @@
+// Host-side launch interface between the NTF kernels and the C-ABI layer.
+// Internal to libntf_admm.so; not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ntf {
+
+enum Prec { PREC_F32 = 0, PREC_BF16 = 1, PREC_F64 = 3 };
+
+// Launch geometry of the three MTTKRP kernels and the inner sweep for one
+// problem shape; fixed at context creation.
+struct Plan {
+  int prec = 0;
+  int64_t I = 0, J = 0, K = 0;
+  int F = 0, FT = 0, FP = 0;      // rank, 16-column MFMA tiles, padded rank
+  bool vec = true;                // K % 4 == 0: 16-byte row loads of the FP32/FP64 tensor
+  // bfloat16 copies: row-major [I][J][Kp] and j-interleaved [I][JG][Kp3][8]
+  int64_t Kp = 0, JG = 0, Kp3 = 0;
+  // pass 1 (mode-1 MTTKRP plus the k-contracted intermediate T = X x_3 C)
+  int MT1 = 1, R1 = 16, nch1 = 0, KC1 = 0, grid1 = 0;  // 16*MT1 rows per wave item
+  int64_t ntiles1 = 0;
+  size_t lds1 = 0;
+  // mode 2 from T
+  int ich2 = 16, nich2 = 0;
+  // pass 3 (mode-3 MTTKRP): waves per block, k-groups, row chunks
+  int nw3 = 0, nkg3 = 0, nrc3 = 0;
+  int64_t rpc3 = 0;               // rows (FP32/FP64) or 8-row groups (BF16) per chunk
+  // inner sweep: lanes per row, rows per 1024-thread block, blocks per mode
+  int FL = 0, rpb = 0;
+  int nblk_inner[3] = {0, 0, 0};
+  int nprep = 1;                  // blocks of the prepare kernel
+};
+
+size_t elem_size(int prec);       // bytes of an X / factor element for a precision
+
+// Fill `p` for a problem; returns false if unsupported.
+bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count);
+
+// ---- set-up
+hipError_t launch_quantize(const float* X, const Plan& p, __bf16* Xr, __bf16* Xj8, float* scale,
+                           hipStream_t s);
+hipError_t launch_sumsq(const void* X, int x_is_f64, int64_t n, double* partial, int nparts,
+                        double* out, hipStream_t s);
+
+// ---- MTTKRP
+// pass 1: Tout [I*J][F] (T elem = float, or double for F64) and P1 [I][nch1][F]
+hipError_t launch_pass1(const Plan& p, const void* X, const __bf16* Xr, const float* scale,
+                        const void* Hb, const void* Hc, void* Tout, void* P1, hipStream_t s);
+// mode 2 from T: P2 [nich2][J][F]
+hipError_t launch_mode2(const Plan& p, const void* Tin, const void* Ha, void* P2, hipStream_t s);
+// pass 3: P3 [nrc3][K][F]
+hipError_t launch_pass3(const Plan& p, const void* X, const __bf16* Xj8, const float* scale,
+                        const void* Ha, const void* Hb, void* P3, hipStream_t s);
+// W[rows][F] (double) = sum over partials, fixed order
+hipError_t launch_reduce_partials(const void* part, int part_is_f64, int64_t pstride,
+                                  int64_t rowstride, int nparts, int64_t rows, int F, double* W,
+                                  hipStream_t s);
+
+// ---- ADMM
+struct InnerArgs {
+  const void* part = nullptr;     // MTTKRP partials (float or double)
+  int part_f64 = 0;
+  int64_t pstride = 0, rowstride = 0;
+  int nparts = 0;
+  double* Wout = nullptr;         // may be null
+  void* H = nullptr;
+  void* U = nullptr;
+  void* Pout = nullptr;           // last Ht^T (may be null)
+  int h_f64 = 0;
+  int64_t rows = 0;
+  int F = 0, FL = 0;
+  const double* Linv = nullptr;   // [F][F] inverse of the Cholesky factor
+  const double* rho = nullptr;    // device: [0] rho for this update, [1] rho of the previous update
+  int rescale = 0;
+  int T = 1;
+  double eps_abs = 0.0, eps_rel = 0.0;
+  int32_t* iters_out = nullptr;   // may be null
+  int gram_from_primal = 0;       // Gram partial of Ht^T instead of H
+  int gram_f32 = 0;               // accumulate the Gram partial in FP32 (mixed precision)
+  double* gram_part = nullptr;    // [nblk][F][F]
+  double* resid_part = nullptr;   // [nblk][8]
+  int* flag = nullptr;
+};
+hipError_t launch_inner(const InnerArgs& a, int nblk, hipStream_t s);
+
+struct PrepArgs {
+  int F = 0;
+  const double* gram_part = nullptr;  // partials of the mode just updated (nullptr: none)
+  int nparts = 0;
+  double* gram_dst = nullptr;         // its reduced Gram [F][F]
+  const double* resid_part = nullptr; // its residual partials [nparts][8]
+  double* resid_dst = nullptr;        // its residual totals [8]
+  int* fresh_dst = nullptr;           // set to 1 when resid_dst is written
+  const double* gram_a = nullptr;     // G = gram_a (*) gram_b for the mode being prepared
+  const double* gram_b = nullptr;
+  int policy = 0;
+  double rho0 = 1, mu = 8, tau_incr = 4, tau_decr = 2;
+  double* rho_state = nullptr;        // [0] rho (in/out), [1] previous rho (out)
+  const double* resid_mode = nullptr; // residual totals of the mode being prepared
+  int* fresh_mode = nullptr;
+  double* Linv = nullptr;             // out [F][F]
+  int* flag = nullptr;
+  unsigned* counter = nullptr;        // last-block ticket, zero on entry, left zero
+  // optional cheap fit (after the third mode): <W3,H3> and sum(G1*G2*G3)
+  const double* W3 = nullptr;
+  const void* H3 = nullptr;
+  int h_f64 = 0;
+  int64_t K = 0;
+  const double* gram_c = nullptr;     // third Gram for sum(G1*G2*G3)
+  double* fit_out = nullptr;          // [2]
+};
+hipError_t launch_prep(const PrepArgs& a, int nblk, hipStream_t s);
+
+// Gram partials: ceil(rows/rpp) partials [p][F][F] of rows [p*rpp, (p+1)*rpp)
+hipError_t launch_gram_part(const void* H, int h_f64, int64_t rows, int F, int64_t rpp,
+                            int gram_f32, double* part, hipStream_t s);
+hipError_t launch_fit(const Plan& p, const void* X, int x_f64, const void* H1, const void* H2,
+                      const void* H3, int h_f64, double* part, double* out, hipStream_t s,
+                      int* nparts_out);
+int fit_parts(const Plan& p);
+hipError_t launch_finish(int F, const double* gram_part, const double* resid_part, int nparts,
+                         const double* g0, const double* g1, const double* W3, const void* H3,
+                         int h_f64, int64_t K, double* out, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+}  // namespace ntf
