@@ -96,7 +96,9 @@ typedef struct {
                                unscaled dual Y fixed); forced on for NTF_RHO_ADAPTIVE */
   int32_t paper_init;       /* 1: auxiliary and dual variables start at zero and the given
                                factors seed the primal (Section VI-A); needs factor_source 1 */
-  int32_t reserved[4];      /* must be zero */
+  int32_t warm_hidden;      /* > 0: reserve workspace for a learned warm start with this many
+                               hidden units (see ntf_admm_set_warmstart); 0 = none */
+  int32_t reserved[3];      /* must be zero */
 } ntf_opts;
 
 /* Statistics of the most recent outer iteration (Section IV-C quantities). */
@@ -110,6 +112,7 @@ typedef struct {
   double norm_y[3];         /* rho_n ||U_n||_F = ||Y_n||_F */
   double inner_iters_mean[3]; /* mean inner iterations per row in the last update */
   double rfe_cheap;         /* RFE from ||X||^2 - 2<W_3,H_3> + sum(G1*G2*G3); monitoring only */
+  int64_t warm_taken[3];    /* rows whose inner sweep started from the network's prediction */
   int32_t numeric_error;    /* non-zero if a non-PD system or NaN/Inf was met */
   int32_t converged;        /* Section IV-C stop test held for all modes (needs stop_eps_* > 0) */
 } ntf_stats;
@@ -177,6 +180,76 @@ ntf_status ntf_admm_launch_pass(ntf_admm_ctx *ctx, int32_t pass);
 ntf_status ntf_admm_destroy(ntf_admm_ctx *ctx);
 const char *ntf_admm_last_error(const ntf_admm_ctx *ctx);
 const char *ntf_status_str(ntf_status s);
+
+/* ------------------------------------------- learned warm start (not in the paper)
+ *
+ * A 3-layer MLP with ReLU after every layer maps one row's NNLS problem
+ * min_{h>=0} 1/2 h^T G h - w^T h (the fixed point of the inner sweep for that
+ * row, Section IV) to a starting point.  Row inputs (D = F(F+1)/2 + F floats):
+ * the upper triangle of G/rho, row by row, then w/||w||; the network predicts
+ * h rho/||w||.  Parameters are one flat vector
+ *   [W1 hidden*D, b1 hidden, W2 hidden*hidden, b2 hidden, W3 F*hidden, b3 F]
+ * with y = relu(W x + b) per layer (weights row-major [out][in]). */
+typedef struct {
+  int32_t F;                /* rank the network serves, 1..64 */
+  int32_t hidden;           /* hidden units per layer, 1..1024 */
+  int32_t dtype;            /* 0 = float32 parameters, 1 = float16 */
+  int32_t reserved;         /* must be zero */
+  const void *params;       /* device, flat parameter vector (borrowed) */
+} ntf_mlp;
+
+/* Number of parameters of the network for rank F and `hidden` units. */
+size_t ntf_mlp_param_count(int32_t F, int32_t hidden);
+
+/* Row inputs X_out [rows][D] (float32) and output scales scale_out [rows]
+ * (||w_i||/rho) from G [F][F] and W [rows][F] (float64, device). */
+ntf_status ntf_mlp_features(const double *G, const double *W, int64_t rows, int32_t F, double rho,
+                            float *X_out, float *scale_out, void *stream);
+
+/* Forward pass on `batch` rows: Y [batch][F]; `act` [2][batch][hidden]
+ * float32 receives the two hidden activations (needed by the backward pass). */
+ntf_status ntf_mlp_forward(const ntf_mlp *net, const float *X, int64_t batch, float *Y, float *act,
+                           void *stream);
+
+/* Gradient of sum(dY * Y) with respect to the parameters of a float32
+ * network, into grad (flat, overwritten).  `work` holds (2*hidden + F)*batch
+ * floats of scratch.  FP32 throughout; every sum has a fixed order. */
+ntf_status ntf_mlp_backward(const ntf_mlp *net, const float *X, const float *act, const float *Y,
+                            const float *dY, int64_t batch, float *grad, float *work, void *stream);
+
+/* dY = (Y - T)/batch and the loss 1/(2 batch) sum (Y - T)^2 into loss_dev[0]
+ * (device double); part_dev holds 64 doubles of scratch. */
+ntf_status ntf_mlp_mse(const float *Y, const float *T, int64_t batch, int32_t F, float *dY,
+                       double *loss_dev, double *part_dev, void *stream);
+
+/* One Adam step (bias-corrected, `step` >= 1) on n parameters; if params_f16
+ * is non-NULL it receives the updated parameters as float16. */
+ntf_status ntf_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t step, void *params_f16,
+                        void *stream);
+
+/* dst[r][:] = src[idx[r]][:] for r < n (minibatch gather; idx device int64). */
+ntf_status ntf_gather_rows(const float *src, const int64_t *idx, int64_t n, int32_t cols,
+                           float *dst, void *stream);
+
+/* Training targets T_out [rows][F] = h* / scale for converged rows h*
+ * (float64) and the scales of ntf_mlp_features. */
+ntf_status ntf_mlp_targets(const double *Hstar, const float *scale, int64_t rows, int32_t F,
+                           float *T_out, void *stream);
+
+/* The NNLS problems mode `mode` would solve from the current factors: W_out
+ * [d_n][F] (its MTTKRP), G_out [F][F] (the Gram Hadamard product) and
+ * rho_out[0] = trace(G)/F, all float64 device buffers.  Stream-ordered; does
+ * not change the solver state.  Used to generate warm-start training pairs. */
+ntf_status ntf_admm_mode_problem(ntf_admm_ctx *ctx, int32_t mode, double *W_out, double *G_out,
+                                 double *rho_out);
+
+/* Use `net` (rank ctx's F, hidden <= opts.warm_hidden) to warm-start every
+ * mode update: after G and W are formed, each row starts from the network's
+ * candidate if its NNLS KKT violation ||min(h, hG - w)|| is smaller than the
+ * previous iterate's, otherwise from the previous iterate (the fallback).
+ * NULL disables.  The next step re-captures the iteration graph. */
+ntf_status ntf_admm_set_warmstart(ntf_admm_ctx *ctx, const ntf_mlp *net);
 
 /* ------------------------------------------------------ kernel-level calls */
 

@@ -40,6 +40,7 @@ class AdmmOptions:
     factor_source: int = 0
     rescale_dual_on_rho_change: int = 0
     paper_init: int = 0
+    warm_hidden: int = 0
 
     def to_c(self) -> _lib.Opts:
         o = _lib.Opts()

@@ -54,7 +54,8 @@ class Opts(ctypes.Structure):
         ("factor_source", c_int32),
         ("rescale_dual_on_rho_change", c_int32),
         ("paper_init", c_int32),
-        ("reserved", c_int32 * 4),
+        ("warm_hidden", c_int32),
+        ("reserved", c_int32 * 3),
     ]
 
 
@@ -69,6 +70,7 @@ class Stats(ctypes.Structure):
         ("norm_y", c_double * 3),
         ("inner_iters_mean", c_double * 3),
         ("rfe_cheap", c_double),
+        ("warm_taken", c_int64 * 3),
         ("numeric_error", c_int32),
         ("converged", c_int32),
     ]
@@ -79,6 +81,16 @@ class Stats(ctypes.Structure):
             v = getattr(self, name)
             out[name] = list(v) if hasattr(v, "__len__") else v
         return out
+
+
+class Mlp(ctypes.Structure):
+    _fields_ = [
+        ("F", c_int32),
+        ("hidden", c_int32),
+        ("dtype", c_int32),
+        ("reserved", c_int32),
+        ("params", c_void_p),
+    ]
 
 
 # (name, restype, argtypes) of every exported function
@@ -102,6 +114,18 @@ SIGNATURES = [
                                    c_size_t, c_void_p]),
     ("ntf_gram_workspace_bytes", c_size_t, [c_int64, c_int32]),
     ("ntf_gram", c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("ntf_admm_set_warmstart", c_int32, [c_void_p, POINTER(Mlp)]),
+    ("ntf_mlp_param_count", c_size_t, [c_int32, c_int32]),
+    ("ntf_mlp_features", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_double, c_void_p, c_void_p, c_void_p]),
+    ("ntf_mlp_forward", c_int32, [POINTER(Mlp), c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    ("ntf_mlp_backward", c_int32, [POINTER(Mlp), c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
+                                   c_void_p, c_void_p]),
+    ("ntf_mlp_mse", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("ntf_mlp_adam", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, c_int32, c_void_p, c_void_p]),
+    ("ntf_gather_rows", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
+    ("ntf_mlp_targets", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
+    ("ntf_admm_mode_problem", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
 ]
 
 _LIB = None

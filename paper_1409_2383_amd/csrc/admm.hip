@@ -16,15 +16,15 @@ namespace ntf {
 
 // ---------------------------------------------------------------- inner sweep
 
-// Block of 1024 threads; each row of the factor owns FL consecutive lanes
-// (FL = next power of two >= F, so a row never straddles a wave) and lane f
-// of a row holds h_f, u_f, w_f in FP64 registers for the whole sweep.  Both
-// triangular applications are lane-parallel mat-vecs against Linv (zero
-// padded to FL x FL) held in LDS twice, row-major and transposed, so every
-// step reads consecutive banks; the right-hand side of a row is broadcast
-// from lane to lane (v_readlane when a row fills the wave, ds_bpermute
-// otherwise), so the T iterations need no block barrier and every wave leaves
-// the loop as soon as all of its rows have met the stop test.
+// Block of 256 threads.  A row of the factor lives on FL consecutive lanes
+// (FL = next power of two >= F, so a row never straddles a wave), and every
+// lane group carries RPL rows at once: lane f holds h_f, u_f, w_f of RPL rows
+// in FP64 registers for the whole sweep.  Both triangular applications are
+// lane-parallel mat-vecs against Linv (zero padded to FL x FL) in LDS, held
+// row-major and transposed so every step reads consecutive banks; each Linv
+// element read from LDS serves the RPL rows of the lane.  The right-hand
+// sides are exchanged through LDS (broadcast reads), two barriers per
+// inner iteration.
 struct InnerK {
   const void* part;
   int part_f64;
@@ -48,170 +48,278 @@ struct InnerK {
 };
 
 template <int FL>
-static __device__ __forceinline__ double lane_bcast(double v, int g) {
-  if constexpr (FL == 64) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), g);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), g);
-    return __hiloint2double(hi, lo);
-  } else {
-    return __shfl(v, g, FL);
-  }
-}
+static constexpr int inner_rpl() { return FL >= 32 ? 2 : 1; }
 
-// y_f = sum_g M[g][f] * v_g  over the FL lanes of a row (M in LDS, FL x FL)
-template <int FL>
-static __device__ __forceinline__ double row_matvec(const double* __restrict__ M, double v, int f) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+// out[q] = sum_g M[g*FL + f] * V[q*BS + g] for the RPL rows of a lane, with
+// the LDS reads of chunk c+1 issued before the FMAs of chunk c (register
+// double buffering), so LDS latency overlaps arithmetic.
+template <int FL, int RPL, int BS>
+static __device__ __forceinline__ void lane_matvec(const double* __restrict__ M,
+                                                   const double* __restrict__ V, int f,
+                                                   double (&out)[RPL]) {
+  constexpr int C = FL < 8 ? FL : 8;
+  constexpr int NC = FL / C;
+  double ma[C], va[RPL][C], mb[C], vb[RPL][C];
 #pragma unroll
-  for (int g = 0; g < FL; g += 4) {
-    a0 += M[(g + 0) * FL + f] * lane_bcast<FL>(v, g + 0);
-    if (g + 1 < FL) a1 += M[(g + 1) * FL + f] * lane_bcast<FL>(v, g + 1);
-    if (g + 2 < FL) a2 += M[(g + 2) * FL + f] * lane_bcast<FL>(v, g + 2);
-    if (g + 3 < FL) a3 += M[(g + 3) * FL + f] * lane_bcast<FL>(v, g + 3);
+  for (int q = 0; q < RPL; ++q) out[q] = 0.0;
+  auto ld = [&](int c, double (&m)[C], double (&v)[RPL][C]) {
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      m[t] = M[(c * C + t) * FL + f];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) v[q][t] = V[q * BS + c * C + t];
+    }
+  };
+  auto fm = [&](const double (&m)[C], const double (&v)[RPL][C]) {
+#pragma unroll
+    for (int t = 0; t < C; ++t)
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) out[q] += m[t] * v[q][t];
+  };
+  ld(0, ma, va);
+  if constexpr (NC == 1) {
+    fm(ma, va);
+  } else {
+    // NC is even here; a rolled loop keeps the compiler from hoisting every
+    // chunk's loads (which would blow the register budget)
+#pragma unroll 1
+    for (int c = 0; c < NC; c += 2) {
+      ld(c + 1, mb, vb);
+      fm(ma, va);
+      if (c + 2 < NC) ld(c + 2, ma, va);
+      fm(mb, vb);
+    }
   }
-  return (a0 + a1) + (a2 + a3);
 }
+template <int FL>
+static constexpr int inner_rows_per_block() { return (256 / FL) * inner_rpl<FL>(); }
 
 template <typename HT, int FL>
-__global__ __launch_bounds__(1024) void k_inner(InnerK a) {
+__global__ __launch_bounds__(256) void k_inner(InnerK a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int RPB = 1024 / FL;
+  constexpr int RPL = inner_rpl<FL>();
+  constexpr int NG = 256 / FL;             // lane groups per block
+  constexpr int RPB = NG * RPL;            // rows per block
+  constexpr int BS = FL + 1;               // padded row stride of the exchange buffers
   const int F = a.F;
   double* Ls = reinterpret_cast<double*>(smem_raw);   // Ls[g][f]  = Linv[g][f]
   double* LTs = Ls + FL * FL;                         // LTs[g][f] = Linv[f][g]
-  double* hs = LTs + FL * FL;                         // [RPB][FL] Gram staging
-  __shared__ double red[16][8];
+  double* xb = LTs + FL * FL;                         // [RPB][BS] exchange (b, then y)
+  __shared__ double red[4][8];
 
   const int tid = threadIdx.x;
-  const int rl = tid / FL, f = tid - rl * FL;
-  const int64_t row = (int64_t)blockIdx.x * RPB + rl;
-  const bool active = (row < a.rows) && (f < F);
+  const int grp = tid / FL, f = tid - grp * FL;
+  const int64_t row0 = (int64_t)blockIdx.x * RPB;
 
-  for (int e = tid; e < FL * FL; e += 1024) {
-    const int r = e / FL, c = e - r * FL;
-    const double v = (r < F && c < F) ? a.Linv[r * F + c] : 0.0;
-    Ls[e] = v;
-    LTs[c * FL + r] = v;
+  {
+    // all loads first, then the LDS writes (no serialised load-wait chain)
+    constexpr int PER = (FL * FL + 255) / 256;
+    double lv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      const int r = e / FL, c = e - r * FL;
+      lv[q] = (e < FL * FL && r < F && c < F) ? a.Linv[r * F + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      if (e < FL * FL) {
+        const int r = e / FL, c = e - r * FL;
+        Ls[e] = lv[q];
+        LTs[c * FL + r] = lv[q];
+      }
+    }
   }
   const double rho = a.rho[0];
   const double uscale = (a.rescale && a.rho[1] > 0.0) ? a.rho[1] / rho : 1.0;
 
-  double w = 0.0, h = 0.0, u = 0.0;
-  if (active) {
-    const int64_t off = row * a.rowstride + f;
-    if (a.part_f64) {
-      const double* p = reinterpret_cast<const double*>(a.part) + off;
+  // row q of this lane group is block row grp*RPL + q
+  double w[RPL], h[RPL], u[RPL], x[RPL], h0[RPL];
+  bool act[RPL], done[RPL];
+  int iters[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int64_t row = row0 + grp * RPL + q;
+    act[q] = (row < a.rows) && (f < F);
+    done[q] = row >= a.rows;
+    iters[q] = 0;
+    w[q] = h[q] = u[q] = x[q] = 0.0;
+    if (act[q]) {
+      const int64_t off = row * a.rowstride + f;
+      double sw = 0.0;
+      if (a.part_f64) {
+        const double* p = reinterpret_cast<const double*>(a.part) + off;
 #pragma unroll 8
-      for (int q = 0; q < a.nparts; ++q) w += p[q * a.pstride];
-    } else {
-      const float* p = reinterpret_cast<const float*>(a.part) + off;
+        for (int t = 0; t < a.nparts; ++t) sw += p[t * a.pstride];
+      } else {
+        const float* p = reinterpret_cast<const float*>(a.part) + off;
 #pragma unroll 8
-      for (int q = 0; q < a.nparts; ++q) w += (double)p[q * a.pstride];
+        for (int t = 0; t < a.nparts; ++t) sw += (double)p[t * a.pstride];
+      }
+      w[q] = sw;
+      if (a.Wout) a.Wout[row * F + f] = sw;
+      h[q] = (double)reinterpret_cast<const HT*>(a.H)[row * F + f];
+      u[q] = (double)reinterpret_cast<const HT*>(a.U)[row * F + f] * uscale;
     }
-    if (a.Wout) a.Wout[row * F + f] = w;
-    h = (double)reinterpret_cast<const HT*>(a.H)[row * F + f];
-    u = (double)reinterpret_cast<const HT*>(a.U)[row * F + f] * uscale;
+    h0[q] = h[q];
   }
-  const double h0 = h;
-  double x = 0.0;
-  bool row_done = (row >= a.rows);
-  int iters = 0;
   const bool early = (a.eps_abs > 0.0) || (a.eps_rel > 0.0);
   const double sqF = sqrt((double)F);
-  __syncthreads();
+  __shared__ int any_active;
+  double* yb = xb + RPB * BS;   // second exchange buffer: b and y never share one
 
   for (int t = 0; t < a.T; ++t) {
-    if (early && !__any(!row_done)) break;   // wave-uniform
-    const double b = active ? w + rho * (h + u) : 0.0;
-    const double y = row_matvec<FL>(LTs, b, f);       // y = L^{-1} b
-    const double xn = row_matvec<FL>(Ls, y, f);       // x = L^{-T} y
-    if (!row_done) {
-      const double v = xn - u;
+    if (early) {
+      if (tid == 0) any_active = 0;
+      __syncthreads();
+      bool mine = false;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) mine |= !done[q];
+      if (mine) any_active = 1;
+      __syncthreads();
+      if (!any_active) break;
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) xb[(grp * RPL + q) * BS + f] = act[q] ? w[q] + rho * (h[q] + u[q]) : 0.0;
+    __syncthreads();
+    double y[RPL];
+    lane_matvec<FL, RPL, BS>(LTs, xb + grp * RPL * BS, f, y);      // y = L^{-1} b
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) yb[(grp * RPL + q) * BS + f] = y[q];
+    __syncthreads();
+    double xn[RPL];
+    lane_matvec<FL, RPL, BS>(Ls, yb + grp * RPL * BS, f, xn);      // x = L^{-T} y
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      if (done[q]) continue;
+      const double v = xn[q] - u[q];
       const double hn = (v > 0.0) ? v : 0.0;
       const double un = hn - v;
-      const double dh = hn - h;
-      h = active ? hn : 0.0;
-      u = active ? un : 0.0;
-      x = active ? xn : 0.0;
-      ++iters;
+      const double dh = hn - h[q];
+      h[q] = act[q] ? hn : 0.0;
+      u[q] = act[q] ? un : 0.0;
+      x[q] = act[q] ? xn[q] : 0.0;
+      ++iters[q];
       if (early) {
-        const double sp = group_sum((h - x) * (h - x), FL);
-        const double sx = group_sum(x * x, FL);
-        const double sh = group_sum(h * h, FL);
-        const double sd = group_sum(active ? dh * dh : 0.0, FL);
-        const double su = group_sum(u * u, FL);
+        const double sp = group_sum((h[q] - x[q]) * (h[q] - x[q]), FL);
+        const double sx = group_sum(x[q] * x[q], FL);
+        const double sh = group_sum(h[q] * h[q], FL);
+        const double sd = group_sum(act[q] ? dh * dh : 0.0, FL);
+        const double su = group_sum(u[q] * u[q], FL);
         const double tol_p = sqF * a.eps_abs + a.eps_rel * fmax(sqrt(sx), sqrt(sh));
         const double tol_d = sqF * a.eps_abs + a.eps_rel * rho * sqrt(su);
-        if (sqrt(sp) <= tol_p && rho * sqrt(sd) <= tol_d) row_done = true;
+        if (sqrt(sp) <= tol_p && rho * sqrt(sd) <= tol_d) done[q] = true;
       }
     }
   }
+  __syncthreads();
 
-  if (active) {
-    if (!isfinite(x) || !isfinite(w)) atomicOr(a.flag, 1);
-    HT* Hp = reinterpret_cast<HT*>(a.H);
-    HT* Up = reinterpret_cast<HT*>(a.U);
-    Hp[row * F + f] = (HT)h;
-    Up[row * F + f] = (HT)u;
-    if (a.Pout) reinterpret_cast<HT*>(a.Pout)[row * F + f] = (HT)x;
-    if (a.iters_out && f == 0) a.iters_out[row] = iters;
+  double qs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int64_t row = row0 + grp * RPL + q;
+    if (act[q]) {
+      if (!isfinite(x[q]) || !isfinite(w[q])) atomicOr(a.flag, 1);
+      reinterpret_cast<HT*>(a.H)[row * F + f] = (HT)h[q];
+      reinterpret_cast<HT*>(a.U)[row * F + f] = (HT)u[q];
+      if (a.Pout) reinterpret_cast<HT*>(a.Pout)[row * F + f] = (HT)x[q];
+      if (a.iters_out && f == 0) a.iters_out[row] = iters[q];
+      const double hv = (double)(HT)h[q], xv = (double)(HT)x[q], uv = (double)(HT)u[q];
+      qs[0] += (hv - xv) * (hv - xv);
+      qs[1] += (hv - h0[q]) * (hv - h0[q]);
+      qs[2] += hv * hv;
+      qs[3] += xv * xv;
+      qs[4] += uv * uv;
+      if (f == 0) qs[5] += (double)iters[q];
+    }
   }
-
   // residual partials of this block: ||h-x||^2, ||h-h0||^2, ||h||^2, ||x||^2, ||u||^2, iterations
   {
-    double q[6];
-    const double hv = (double)(HT)h, xv = (double)(HT)x, uv = (double)(HT)u;
-    q[0] = active ? (hv - xv) * (hv - xv) : 0.0;
-    q[1] = active ? (hv - h0) * (hv - h0) : 0.0;
-    q[2] = active ? hv * hv : 0.0;
-    q[3] = active ? xv * xv : 0.0;
-    q[4] = active ? uv * uv : 0.0;
-    q[5] = (active && f == 0) ? (double)iters : 0.0;
     const int wave = tid >> 6;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const double sum = group_sum(q[k], 64);
+      const double sum = group_sum(qs[k], 64);
       if ((tid & 63) == 0) red[wave][k] = sum;
     }
     __syncthreads();
     if (tid < 6) {
-      double sum = 0.0;
-      for (int wv = 0; wv < 16; ++wv) sum += red[wv][tid];
+      const double sum = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
       a.resid_part[(int64_t)blockIdx.x * 8 + tid] = sum;
     }
     if (tid == 6 || tid == 7) a.resid_part[(int64_t)blockIdx.x * 8 + tid] = 0.0;
   }
-
-  // Gram partial of this block's rows (of the stored factor values)
+  // Gram partial of this block's rows (of the stored factor values), rows in order
   {
-    const double src = a.gram_from_primal ? x : h;
-    hs[rl * FL + f] = active ? (double)(HT)src : 0.0;
-    __syncthreads();
-    const int nrow = (int)min((int64_t)RPB, a.rows - (int64_t)blockIdx.x * RPB);
-    for (int e = tid; e < F * F; e += 1024) {
-      const int r = e / F, c = e - r * F;
-      double sum;
-      if (a.gram_f32) {
-        float sf = 0.f;
-        for (int q2 = 0; q2 < nrow; ++q2) sf += (float)hs[q2 * FL + r] * (float)hs[q2 * FL + c];
-        sum = sf;
-      } else {
-        sum = 0.0;
-        for (int q2 = 0; q2 < nrow; ++q2) sum += hs[q2 * FL + r] * hs[q2 * FL + c];
-      }
-      a.gram_part[(int64_t)blockIdx.x * F * F + e] = sum;
+    double* hs = xb;  // [RPB][BS]
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const double src = a.gram_from_primal ? x[q] : h[q];
+      hs[(grp * RPL + q) * BS + f] = act[q] ? (double)(HT)src : 0.0;
     }
+    __syncthreads();
+    const int nrow = (int)min((int64_t)RPB, a.rows - row0);
+    // thread (ti,tj) owns entries (ti+16p, tj+16q); each entry is summed over
+    // the block's rows in row order (the order the standalone Gram partials use)
+    constexpr int NBT = (FL + 15) / 16;
+    const int ti = tid >> 4, tj = tid & 15;
+    double acc[NBT][NBT];
+    float accf[NBT][NBT];
+#pragma unroll
+    for (int p = 0; p < NBT; ++p)
+#pragma unroll
+      for (int q = 0; q < NBT; ++q) {
+        acc[p][q] = 0.0;
+        accf[p][q] = 0.f;
+      }
+    for (int r2 = 0; r2 < nrow; ++r2) {
+      double vi[NBT], vj[NBT];
+#pragma unroll
+      for (int p = 0; p < NBT; ++p) {
+        vi[p] = (ti + 16 * p < FL) ? hs[r2 * BS + ti + 16 * p] : 0.0;
+        vj[p] = (tj + 16 * p < FL) ? hs[r2 * BS + tj + 16 * p] : 0.0;
+      }
+      if (a.gram_f32) {
+#pragma unroll
+        for (int p = 0; p < NBT; ++p)
+#pragma unroll
+          for (int q = 0; q < NBT; ++q) accf[p][q] += (float)vi[p] * (float)vj[q];
+      } else {
+#pragma unroll
+        for (int p = 0; p < NBT; ++p)
+#pragma unroll
+          for (int q = 0; q < NBT; ++q) acc[p][q] += vi[p] * vj[q];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < NBT; ++p)
+#pragma unroll
+      for (int q = 0; q < NBT; ++q) {
+        const int r = ti + 16 * p, c = tj + 16 * q;
+        if (r < F && c < F)
+          a.gram_part[(int64_t)blockIdx.x * F * F + r * F + c] = a.gram_f32 ? (double)accf[p][q] : acc[p][q];
+      }
   }
 }
 
 template <typename HT, int FL>
 static hipError_t inner_launch(const InnerK& k, int nblk, hipStream_t s) {
-  const size_t lds = (size_t)(2 * FL * FL + 1024) * sizeof(double);
+  const size_t lds = (size_t)(2 * FL * FL + 2 * inner_rows_per_block<FL>() * (FL + 1)) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_inner<HT, FL>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_inner<HT, FL>), dim3(nblk), dim3(1024), lds, s, k);
+  hipLaunchKernelGGL((k_inner<HT, FL>), dim3(nblk), dim3(256), lds, s, k);
   return hipGetLastError();
+}
+
+int inner_rows_per_block(int FL) {
+  switch (FL) {
+    case 4: return inner_rows_per_block<4>();
+    case 8: return inner_rows_per_block<8>();
+    case 16: return inner_rows_per_block<16>();
+    case 32: return inner_rows_per_block<32>();
+    default: return inner_rows_per_block<64>();
+  }
 }
 
 template <typename HT>
@@ -279,6 +387,8 @@ struct PrepK {
   const double* resid_mode;
   int* fresh_mode;
   double* Linv;
+  double* G_out;
+  int* taken;
   int* flag;
   unsigned* counter;
   const double* W3;
@@ -289,25 +399,42 @@ struct PrepK {
   double* fit_out;
 };
 
+// Totals of the 8 residual partial columns over nparts partials, grouped
+// fixed order (32 groups of 256 threads); used by the prepare and statistics
+// kernels so both give bitwise identical totals.
+static __device__ void resid_totals(const double* __restrict__ part, int nparts,
+                                    double* __restrict__ out) {
+  __shared__ double rr[32][8];
+  const int c = threadIdx.x & 7, pg = threadIdx.x >> 3;
+  rr[pg][c] = group_partial(part + c, 8, nparts, pg, 32);
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    double t = rr[0][threadIdx.x];
+    for (int q = 1; q < 32; ++q) t += rr[q][threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   const int F = a.F;
   const int tid = threadIdx.x;
   __shared__ int is_last;
   if (a.gram_part) {
+    // grouped fixed-order reduction (the same order as launch_reduce_partials
+    // with 4 groups): block b reduces entries b*64 .. b*64+63
+    __shared__ double gred[4][64];
     const int nent = F * F;
-    for (int e = blockIdx.x * 256 + tid; e < nent; e += gridDim.x * 256) {
-      double s = 0.0;
-#pragma unroll 8
-      for (int p = 0; p < a.nparts; ++p) s += a.gram_part[(int64_t)p * nent + e];
-      a.gram_dst[e] = s;
+    const int el = tid & 63, pg = tid >> 6;
+    for (int e0 = blockIdx.x * 64; e0 < nent; e0 += gridDim.x * 64) {
+      const int e = e0 + el;
+      gred[pg][el] = (e < nent) ? group_partial(a.gram_part + e, nent, a.nparts, pg, 4) : 0.0;
+      __syncthreads();
+      if (pg == 0 && e < nent) a.gram_dst[e] = ((gred[0][el] + gred[1][el]) + gred[2][el]) + gred[3][el];
+      __syncthreads();
     }
-    if (blockIdx.x == 0 && tid < 8) {
-      double s = 0.0;
-#pragma unroll 8
-      for (int p = 0; p < a.nparts; ++p) s += a.resid_part[(int64_t)p * 8 + tid];
-      a.resid_dst[tid] = s;
-    }
+    if (blockIdx.x == 0) resid_totals(a.resid_part, a.nparts, a.resid_dst);
     __threadfence();
     __syncthreads();
     if (tid == 0) {
@@ -332,11 +459,29 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   __shared__ double rho_sh;
   __shared__ int bad_sh;
 
-  for (int e = tid; e < F * F; e += 256) {
-    const int r = e / F, c = e - r * F;
-    Gs[r * 65 + c] = a.gram_a[e] * a.gram_b[e];
+  {
+    double ga[NB * NB], gb[NB * NB];
+#pragma unroll
+    for (int q = 0; q < NB * NB; ++q) {
+      const int e = tid + 256 * q;
+      ga[q] = (e < F * F) ? a.gram_a[e] : 0.0;
+      gb[q] = (e < F * F) ? a.gram_b[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NB * NB; ++q) {
+      const int e = tid + 256 * q;
+      if (e < F * F) {
+        const int r = e / F, c = e - r * F;
+        const double gv = ga[q] * gb[q];
+        Gs[r * 65 + c] = gv;
+        if (a.G_out) a.G_out[e] = gv;
+      }
+    }
   }
-  if (tid == 0) bad_sh = 0;
+  if (tid == 0) {
+    bad_sh = 0;
+    if (a.taken) *a.taken = 0;
+  }
   __syncthreads();
 
   // penalty
@@ -345,6 +490,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
     double rho;
     if (a.policy == 0) {
       double tr = 0.0;
+#pragma unroll 8
       for (int f = 0; f < F; ++f) tr += Gs[f * 65 + f];
       rho = tr / F;
       if (!(rho > 0.0) || !isfinite(rho)) rho = a.rho0;
@@ -497,6 +643,8 @@ hipError_t launch_prep(const PrepArgs& pa, int nblk, hipStream_t s) {
   k.resid_mode = pa.resid_mode;
   k.fresh_mode = pa.fresh_mode;
   k.Linv = pa.Linv;
+  k.G_out = pa.G_out;
+  k.taken = pa.taken;
   k.flag = pa.flag;
   k.counter = pa.counter;
   k.W3 = pa.W3;
@@ -527,22 +675,27 @@ __global__ __launch_bounds__(256) void k_finish(int F, const double* __restrict_
                                                 const double* __restrict__ W3, const void* H3,
                                                 int h_f64, int64_t K, double* __restrict__ out) {
   __shared__ double sred[256];
+  __shared__ double gred[4][64];
   const int tid = threadIdx.x;
-  if (tid < 8) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += resid_part[(int64_t)p * 8 + tid];
-    out[tid] = s;
-  }
+  resid_totals(resid_part, nparts, out);
   double s1 = 0.0, s2 = 0.0;
   for (int64_t e = tid; e < K * F; e += 256) {
     const double hv = h_f64 ? reinterpret_cast<const double*>(H3)[e]
                             : (double)reinterpret_cast<const float*>(H3)[e];
     s1 += W3[e] * hv;
   }
-  for (int e = tid; e < F * F; e += 256) {
-    double g2 = 0.0;
-    for (int p = 0; p < nparts; ++p) g2 += gram_part[(int64_t)p * F * F + e];
-    s2 += g0[e] * g1[e] * g2;
+  {
+    const int el = tid & 63, pg = tid >> 6;
+    for (int e0 = 0; e0 < F * F; e0 += 64) {
+      const int e = e0 + el;
+      gred[pg][el] = (e < F * F) ? group_partial(gram_part + e, (int64_t)F * F, nparts, pg, 4) : 0.0;
+      __syncthreads();
+      if (pg == 0 && e < F * F) {
+        const double g2 = ((gred[0][el] + gred[1][el]) + gred[2][el]) + gred[3][el];
+        s2 += g0[e] * g1[e] * g2;
+      }
+      __syncthreads();
+    }
   }
   sred[tid] = s1;
   __syncthreads();

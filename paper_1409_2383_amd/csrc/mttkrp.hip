@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64) void k_sum_parts(const double* __restrict__ par
 // operands of the four MFMAs whose contraction slots match the 16-byte X load
 // (lane group g holds k = kb + 4g + c in element c).
 template <typename T, int FT, int MT>
-__global__ __launch_bounds__(256) void k_pass1(const T* __restrict__ X, int I, int J, int K, int F,
+__global__ __launch_bounds__(512) void k_pass1(const T* __restrict__ X, int I, int J, int K, int F,
                                                const T* __restrict__ Hb, const T* __restrict__ Hc,
                                                T* __restrict__ Tout, T* __restrict__ P1, int nch,
                                                int KC, int vec) {
@@ -128,9 +128,10 @@ __global__ __launch_bounds__(256) void k_pass1(const T* __restrict__ X, int I, i
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
   const int64_t nitems = (int64_t)I * nch;
   const int nkc = (K + KC - 1) / KC;
-  const int64_t nblock_iters = (nitems + 4LL * gridDim.x - 1) / (4LL * gridDim.x);
+  const int nwb = blockDim.x >> 6;
+  const int64_t nblock_iters = (nitems + (int64_t)nwb * gridDim.x - 1) / ((int64_t)nwb * gridDim.x);
   for (int64_t bi = 0; bi < nblock_iters; ++bi) {
-    const int64_t item = (bi * gridDim.x + blockIdx.x) * 4 + wave;
+    const int64_t item = (bi * gridDim.x + blockIdx.x) * nwb + wave;
     const bool has = item < nitems;
     const int i = has ? (int)(item / nch) : 0;
     const int ch = has ? (int)(item - (int64_t)i * nch) : 0;
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_pass1(const T* __restrict__ X, int I, i
       const int kbeg = kc * KC, kend = min(K, kbeg + KC);
       if (nkc > 1 || bi == 0) {
         __syncthreads();
-        for (int idx = threadIdx.x; idx < KC * FP; idx += 256) {
+        for (int idx = threadIdx.x; idx < KC * FP; idx += blockDim.x) {
           const int kk = idx / FP, f = idx - kk * FP, k = kbeg + kk;
           const T v = (k < kend && f < F) ? Hc[(int64_t)k * F + f] : T(0);
           Cs[((kk >> 2) * FP + f) * 4 + (kk & 3)] = v;
@@ -158,41 +159,51 @@ __global__ __launch_bounds__(256) void k_pass1(const T* __restrict__ X, int I, i
       for (int mt = 0; mt < MT; ++mt) {
         const int j = j0 + mt * 16 + n;
         rowok[mt] = j < J;
-        xrow[mt] = X + ((int64_t)i * J + (rowok[mt] ? j : 0)) * K + 4 * g;
+        xrow[mt] = X + ((int64_t)i * J + (rowok[mt] ? j : 0)) * K + 8 * g;
       }
-      T xv[U][MT][4];
-      auto load_step = [&](int kb, T (&dst)[MT][4]) {
-        const int valid = kend - (kb + 4 * g);
+      // super step = 32 k: lane group g loads k = kb+8g .. kb+8g+7 of each of
+      // its rows (two 16-byte loads, h = 0, 1); MFMA (h,c) contracts slot g
+      // at k = kb + 8g + 4h + c
+      T xv[U][2][MT][4];
+      auto load_step = [&](int kb, T (&dst)[2][MT][4]) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          if (rowok[mt] && valid > 0) {
-            load4<T>(xrow[mt] + kb, valid, vec != 0, dst[mt]);
-          } else {
+        for (int h = 0; h < 2; ++h) {
+          const int valid = kend - (kb + 8 * g + 4 * h);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) dst[mt][c] = T(0);
+          for (int mt = 0; mt < MT; ++mt) {
+            if (rowok[mt] && valid > 0) {
+              load4<T>(xrow[mt] + kb + 4 * h, valid, vec != 0, dst[h][mt]);
+            } else {
+#pragma unroll
+              for (int c = 0; c < 4; ++c) dst[h][mt][c] = T(0);
+            }
           }
         }
       };
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (kbeg + 16 * u < kend) load_step(kbeg + 16 * u, xv[u]);
-      for (int kb = kbeg; kb < kend; kb += 16 * U) {
+        if (kbeg + 32 * u < kend) load_step(kbeg + 32 * u, xv[u]);
+      for (int kb = kbeg; kb < kend; kb += 32 * U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int kbu = kb + 16 * u;
+          const int kbu = kb + 32 * u;
           if (kbu < kend) {
-            const T* cbase = Cs + ((((kbu - kbeg) >> 2) + g) * FP + n) * 4;
+            // every MFMA of the super step runs: slots past K hold zeros in X and C
 #pragma unroll
-            for (int ft = 0; ft < FT; ++ft) {
-              T cv[4];
-              Vec4Load<T>::load(cbase + ft * 64, cv);
+            for (int h = 0; h < 2; ++h) {
+              const T* cbase = Cs + ((((kbu - kbeg) >> 2) + 2 * g + h) * FP + n) * 4;
 #pragma unroll
-              for (int c = 0; c < 4; ++c)
+              for (int ft = 0; ft < FT; ++ft) {
+                T cv[4];
+                Vec4Load<T>::load(cbase + ft * 64, cv);
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                  acc[mt][ft] = M::mma(xv[u][mt][c], cv[c], acc[mt][ft]);
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                  for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][ft] = M::mma(xv[u][h][mt][c], cv[c], acc[mt][ft]);
+              }
             }
-            if (kbu + 16 * U < kend) load_step(kbu + 16 * U, xv[u]);
+            if (kbu + 32 * U < kend) load_step(kbu + 32 * U, xv[u]);
           }
         }
       }
@@ -227,11 +238,14 @@ __global__ __launch_bounds__(256) void k_pass1(const T* __restrict__ X, int I, i
 }
 
 // BF16: X from the row-major bfloat16 copy (Kp a multiple of 32, zero
-// padded); C transposed in LDS as bf16 [FP][KC+8] so lane (n,g) reads
-// C[kb+8g .. kb+8g+7][ft*16+n] with one 16-byte load.  The slab scale s_i is
-// applied to the FP32 accumulator in the epilogue (exact, power of two).
+// padded); C transposed in LDS as bf16 [FP][KC+8].  A super step covers 64 k:
+// lane (n,g) loads 32 contiguous bytes of its row (k = kb+16g .. kb+16g+15,
+// so every wave load covers whole 128-byte lines) and feeds them to two MFMAs,
+// h = 0, 1, whose contraction slot of lane group g holds k = kb+16g+8h+e; the
+// matching B operands are one 32-byte LDS read per rank tile.  The slab scale
+// s_i is applied to the FP32 accumulator in the epilogue (exact).
 template <int FT, int MT>
-__global__ __launch_bounds__(256) void k_pass1_bf16(const __bf16* __restrict__ Xr,
+__global__ __launch_bounds__(512) void k_pass1_bf16(const __bf16* __restrict__ Xr,
                                                     const float* __restrict__ scale, int I, int J,
                                                     int K, int Kp, int F, const float* __restrict__ Hb,
                                                     const float* __restrict__ Hc,
@@ -239,16 +253,17 @@ __global__ __launch_bounds__(256) void k_pass1_bf16(const __bf16* __restrict__ X
                                                     int nch, int KC) {
   constexpr int FP = FT * 16;
   constexpr int R = 16 * MT;
-  constexpr int U = 4;
+  constexpr int U = 2;
   const int KCS = KC + 8;  // LDS row stride (elements); 16-byte multiple since KC % 32 == 0
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __bf16* Cs = reinterpret_cast<__bf16*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
   const int64_t nitems = (int64_t)I * nch;
   const int nkc = (Kp + KC - 1) / KC;
-  const int64_t nblock_iters = (nitems + 4LL * gridDim.x - 1) / (4LL * gridDim.x);
+  const int nwb = blockDim.x >> 6;
+  const int64_t nblock_iters = (nitems + (int64_t)nwb * gridDim.x - 1) / ((int64_t)nwb * gridDim.x);
   for (int64_t bi = 0; bi < nblock_iters; ++bi) {
-    const int64_t item = (bi * gridDim.x + blockIdx.x) * 4 + wave;
+    const int64_t item = (bi * gridDim.x + blockIdx.x) * nwb + wave;
     const bool has = item < nitems;
     const int i = has ? (int)(item / nch) : 0;
     const int ch = has ? (int)(item - (int64_t)i * nch) : 0;
@@ -259,10 +274,12 @@ __global__ __launch_bounds__(256) void k_pass1_bf16(const __bf16* __restrict__ X
 #pragma unroll
       for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < nkc; ++kc) {
+      // KC is a multiple of 64 (whole super steps, zero filled past K in LDS);
+      // X rows end at Kp (a multiple of 32), so loads are masked per lane
       const int kbeg = kc * KC, kend = min(Kp, kbeg + KC);
       if (nkc > 1 || bi == 0) {
         __syncthreads();
-        for (int idx = threadIdx.x; idx < KC * FP; idx += 256) {
+        for (int idx = threadIdx.x; idx < KC * FP; idx += blockDim.x) {
           const int kk = idx / FP, f = idx - kk * FP, k = kbeg + kk;
           const float v = (k < K && f < F) ? Hc[(int64_t)k * F + f] : 0.f;
           Cs[f * KCS + kk] = (__bf16)v;
@@ -276,36 +293,42 @@ __global__ __launch_bounds__(256) void k_pass1_bf16(const __bf16* __restrict__ X
       for (int mt = 0; mt < MT; ++mt) {
         const int j = j0 + mt * 16 + n;
         rowok[mt] = j < J;
-        xrow[mt] = Xr + ((int64_t)i * J + (rowok[mt] ? j : 0)) * Kp + 8 * g;
+        xrow[mt] = Xr + ((int64_t)i * J + (rowok[mt] ? j : 0)) * Kp + 16 * g;
       }
-      bf16x8 xv[U][MT];
-      auto load_step = [&](int kb, bf16x8 (&dst)[MT]) {
+      bf16x8 xv[U][2][MT];
+      auto load_step = [&](int kb, bf16x8 (&dst)[2][MT]) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          if (rowok[mt]) {
-            dst[mt] = *reinterpret_cast<const bf16x8*>(xrow[mt] + kb);
-          } else {
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) dst[mt][e] = (__bf16)0.f;
+          for (int mt = 0; mt < MT; ++mt) {
+            if (rowok[mt] && kb + 16 * g + 8 * h < kend) {
+              dst[h][mt] = *reinterpret_cast<const bf16x8*>(xrow[mt] + kb + 8 * h);
+            } else {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
+            }
           }
-        }
       };
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (kbeg + 32 * u < kend) load_step(kbeg + 32 * u, xv[u]);
-      const __bf16* cb = Cs + n * KCS + 8 * g;
-      for (int kb = kbeg; kb < kend; kb += 32 * U) {
+        if (kbeg + 64 * u < kend) load_step(kbeg + 64 * u, xv[u]);
+      const __bf16* cb = Cs + n * KCS + 16 * g;
+      for (int kb = kbeg; kb < kend; kb += 64 * U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int kbu = kb + 32 * u;
+          const int kbu = kb + 64 * u;
           if (kbu < kend) {
 #pragma unroll
             for (int ft = 0; ft < FT; ++ft) {
-              const bf16x8 cv = *reinterpret_cast<const bf16x8*>(cb + ft * 16 * KCS + (kbu - kbeg));
+              const __bf16* cp = cb + ft * 16 * KCS + (kbu - kbeg);
+              const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(cp);
+              const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(cp + 8);
 #pragma unroll
-              for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][mt], cv, acc[mt][ft]);
+              for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], c0, acc[mt][ft]);
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], c1, acc[mt][ft]);
             }
-            if (kbu + 32 * U < kend) load_step(kbu + 32 * U, xv[u]);
+            if (kbu + 64 * U < kend) load_step(kbu + 64 * U, xv[u]);
           }
         }
       }
@@ -335,6 +358,143 @@ __global__ __launch_bounds__(256) void k_pass1_bf16(const __bf16* __restrict__ X
       part[ft] += __shfl_xor(part[ft], 32);
       const int f = ft * 16 + n;
       if (g == 0 && f < F) P1[((int64_t)i * nch + ch) * F + f] = part[ft];
+    }
+  }
+}
+
+// BF16 pass 1, streaming form (C fits in LDS, loaded once per block): each
+// wave walks its items (i, chunk) as one continuous sequence of 64-k super
+// steps, so its U-deep load pipeline never drains at item boundaries; the
+// epilogue of an item (T store and W1 partial) runs between two super steps
+// while the loads of the next item are already in flight.
+template <int FT, int MT>
+__global__ __launch_bounds__(512) void k_pass1_bf16s(const __bf16* __restrict__ Xr,
+                                                     const float* __restrict__ scale, int I, int J,
+                                                     int K, int Kp, int F,
+                                                     const float* __restrict__ Hb,
+                                                     const float* __restrict__ Hc,
+                                                     float* __restrict__ Tout,
+                                                     float* __restrict__ P1, int nch, int KC) {
+  constexpr int FP = FT * 16;
+  constexpr int R = 16 * MT;
+  constexpr int U = 4;
+  const int KCS = KC + 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* Cs = reinterpret_cast<__bf16*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
+  for (int idx = threadIdx.x; idx < KC * FP; idx += blockDim.x) {
+    const int kk = idx / FP, f = idx - kk * FP;
+    const float v = (kk < K && f < F) ? Hc[(int64_t)kk * F + f] : 0.f;
+    Cs[f * KCS + kk] = (__bf16)v;
+  }
+  __syncthreads();
+  const int64_t nitems = (int64_t)I * nch;
+  const int nwb = blockDim.x >> 6;
+  const int64_t stride = (int64_t)gridDim.x * nwb;
+  const int64_t first = (int64_t)blockIdx.x * nwb + wave;
+  if (first >= nitems) return;
+  const int64_t myitems = (nitems - first + stride - 1) / stride;
+  const int nsteps = (Kp + 63) / 64;
+  const int64_t total = myitems * nsteps;
+
+  // load cursor
+  int64_t l_item = first;
+  int l_kb = 0;
+  const __bf16* l_row[MT];
+  bool l_ok[MT];
+  auto set_rows = [&](int64_t item) {
+    const int i = (int)(item / nch), ch = (int)(item - (int64_t)i * nch);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int j = ch * R + mt * 16 + n;
+      l_ok[mt] = j < J;
+      l_row[mt] = Xr + ((int64_t)i * J + (l_ok[mt] ? j : 0)) * Kp + 16 * g;
+    }
+  };
+  set_rows(l_item);
+  bf16x8 xv[U][2][MT];
+  auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (l_ok[mt] && l_kb + 16 * g + 8 * h < Kp) {
+          dst[h][mt] = *reinterpret_cast<const bf16x8*>(l_row[mt] + l_kb + 8 * h);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
+        }
+      }
+    l_kb += 64;
+    if (l_kb >= Kp) {
+      l_kb = 0;
+      l_item += stride;
+      if (l_item < nitems) set_rows(l_item);
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (u < total) load_next(xv[u]);
+
+  f32x4 acc[MT][FT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int64_t c_item = first;
+  int c_step = 0;
+  const __bf16* cb = Cs + n * KCS + 16 * g;
+  for (int64_t s0 = 0; s0 < total; s0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t sidx = s0 + u;
+      if (sidx < total) {
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) {
+          const __bf16* cp = cb + ft * 16 * KCS + c_step * 64;
+          const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(cp);
+          const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(cp + 8);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], c0, acc[mt][ft]);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], c1, acc[mt][ft]);
+        }
+        if (sidx + U < total) load_next(xv[u]);
+        if (++c_step == nsteps) {
+          // epilogue of item c_item
+          const int i = (int)(c_item / nch), ch = (int)(c_item - (int64_t)i * nch);
+          const int j0 = ch * R;
+          const float sc = scale[i];
+          float part[FT];
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+              for (int ii = 0; ii < 4; ++ii) {
+                const int j = j0 + mt * 16 + 4 * g + ii;
+                const int f = ft * 16 + n;
+                if (j < J && f < F) {
+                  const float v = sc * acc[mt][ft][ii];
+                  Tout[((int64_t)i * J + j) * F + f] = v;
+                  part[ft] += Hb[(int64_t)j * F + f] * v;
+                }
+              }
+              acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft) {
+            part[ft] += __shfl_xor(part[ft], 16);
+            part[ft] += __shfl_xor(part[ft], 32);
+            const int f = ft * 16 + n;
+            if (g == 0 && f < F) P1[((int64_t)i * nch + ch) * F + f] = part[ft];
+          }
+          c_step = 0;
+          c_item += stride;
+        }
+      }
     }
   }
 }
@@ -451,94 +611,89 @@ __global__ __launch_bounds__(512) void k_pass3(const T* __restrict__ X, int64_t 
 // ---------------------------------------------------------------- pass 3, BF16
 
 // X from the j-interleaved copy Xj8[q][k][e] (q = i*JG + jg, row j = 8jg + e):
-// lane (n,g) loads the 8 rows of group q0 + 4s + g at k = kt + n with one
+// lane (n,g) loads the 8 rows of group jg0 + 4s + g at k = kt + n with one
 // 16-byte read, which is exactly the A operand of v_mfma_f32_16x16x32_bf16
-// (contraction over 32 rows, result rows = 16 consecutive k).  The
-// Khatri-Rao rows s_i * A[i][f] * B[j][f] of 64 rows (8 groups) are built in
-// LDS as bf16, transposed [FP][72], so the B operand is again one 16-byte
-// read; the next 64 rows are built, and their X loads issued, while the
-// current ones are contracted (one barrier per 64 rows).
+// (contraction over 32 rows, result rows = 16 consecutive k).  A block owns a
+// range of slabs; per slab (or chunk of JCG groups of a slab, when a whole slab
+// does not fit) it builds the Khatri-Rao rows s_i * A[i][f] * B[j][f] of the
+// slab in LDS as bf16, transposed [FP][8*JCG+8], with coalesced loads of B,
+// so the B operand is again one 16-byte read; X loads of the slab are issued
+// before the build and run U steps ahead.
 template <int FT>
-__global__ __launch_bounds__(512) void k_pass3_bf16(const __bf16* __restrict__ Xj8,
-                                                    const float* __restrict__ scale, int64_t IQ,
+__global__ __launch_bounds__(768) void k_pass3_bf16(const __bf16* __restrict__ Xj8,
+                                                    const float* __restrict__ scale, int I,
                                                     int J, int JG, int K, int Kp3, int F,
                                                     const float* __restrict__ Ha,
                                                     const float* __restrict__ Hb,
-                                                    float* __restrict__ P3, int64_t gpc) {
+                                                    float* __restrict__ P3, int spb, int JCG) {
   constexpr int FP = FT * 16;
-  constexpr int KRP = 72;
-  __shared__ __align__(16) __bf16 KRt[2][FP * KRP];
+  constexpr int U = 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* KRt = reinterpret_cast<__bf16*>(smem_raw);
+  const int KRL = 32 * ((JCG + 3) / 4);  // rows per chunk rounded up to whole MFMA steps
+  const int KRP = KRL + 8;               // LDS row stride (elements), 16-byte multiple
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
   const int nw = blockDim.x >> 6;
   const int kw0 = (blockIdx.y * nw + wave) * 64;
-  const int64_t qbeg = (int64_t)blockIdx.x * gpc;
-  const int64_t qend = min(IQ, qbeg + gpc);
-  const int nep = (int)((qend - qbeg + 7) >> 3);
   const bool kact = kw0 < Kp3;
+  const int ibeg = blockIdx.x * spb, iend = min(I, ibeg + spb);
+  const int nchunk = (JG + JCG - 1) / JCG;
   f32x4 acc[4][FT];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
-  auto build = [&](int e, int buf) {
-    const int64_t q0 = qbeg + 8LL * e;
-    for (int idx = threadIdx.x; idx < 64 * FP; idx += blockDim.x) {
-      const int f = idx >> 6, rr = idx & 63;
-      const int64_t q = q0 + (rr >> 3);
-      float v = 0.f;
-      if (q < qend && f < F) {
-        const int64_t i = q / JG, jg = q - i * JG;
-        const int64_t j = jg * 8 + (rr & 7);
-        if (j < J) v = scale[i] * Ha[i * F + f] * Hb[j * F + f];
+  for (int i = ibeg; i < iend; ++i) {
+    for (int cj = 0; cj < nchunk; ++cj) {
+      const int jg0 = cj * JCG, ng = min(JCG, JG - jg0);
+      const int nsteps = (ng + 3) >> 2;
+      const __bf16* xq = Xj8 + ((int64_t)i * JG + jg0) * Kp3 * 8;
+      bf16x8 xv[U][4];
+      auto load = [&](int st, bf16x8 (&dst)[4]) {
+        const int gq = 4 * st + g;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const int kt = kw0 + mt * 16;
+          if (kact && gq < ng && kt < Kp3) {
+            dst[mt] = *reinterpret_cast<const bf16x8*>(xq + ((int64_t)gq * Kp3 + kt + n) * 8);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[mt][e] = (__bf16)0.f;
+          }
+        }
+      };
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (u < nsteps) load(u, xv[u]);
+      __syncthreads();  // previous chunk's MFMAs are done with KRt
+      const float si = scale[i];
+      for (int idx = threadIdx.x; idx < KRL * FP; idx += blockDim.x) {
+        const int rr = idx / FP, f = idx - rr * FP;
+        const int j = jg0 * 8 + rr;
+        float v = 0.f;
+        if (rr < 8 * ng && j < J && f < F) v = si * Ha[(int64_t)i * F + f] * Hb[(int64_t)j * F + f];
+        KRt[f * KRP + rr] = (__bf16)v;
       }
-      KRt[buf][f * KRP + rr] = (__bf16)v;
-    }
-  };
-  auto load = [&](int e, bf16x8 (&dst)[2][4]) {
-    const int64_t q0 = qbeg + 8LL * e;
+      __syncthreads();
+      if (kact) {
+        const __bf16* kr = KRt + n * KRP + 8 * g;
+        for (int st0 = 0; st0 < nsteps; st0 += U) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int64_t q = q0 + 4 * s + g;
+          for (int u = 0; u < U; ++u) {
+            const int st = st0 + u;
+            if (st < nsteps) {
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) {
-        const int kt = kw0 + mt * 16;
-        if (kact && q < qend && kt < Kp3) {
-          dst[s][mt] = *reinterpret_cast<const bf16x8*>(Xj8 + (q * Kp3 + kt + n) * 8);
-        } else {
+              for (int ft = 0; ft < FT; ++ft) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(kr + ft * 16 * KRP + st * 32);
 #pragma unroll
-          for (int e2 = 0; e2 < 8; ++e2) dst[s][mt][e2] = (__bf16)0.f;
+                for (int mt = 0; mt < 4; ++mt) acc[mt][ft] = mma_bf16(xv[u][mt], bv, acc[mt][ft]);
+              }
+              if (st + U < nsteps) load(st + U, xv[u]);
+            }
+          }
         }
       }
     }
-  };
-  bf16x8 xa[2][4], xb[2][4];
-  if (nep > 0) {
-    load(0, xa);
-    build(0, 0);
-  }
-  __syncthreads();
-  for (int e = 0; e < nep; ++e) {
-    if (e + 1 < nep) {
-      load(e + 1, xb);
-      build(e + 1, (e + 1) & 1);
-    }
-    if (kact) {
-      const __bf16* kr = KRt[e & 1];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-#pragma unroll
-        for (int ft = 0; ft < FT; ++ft) {
-          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(kr + (ft * 16 + n) * KRP + s * 32 + 8 * g);
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) acc[mt][ft] = mma_bf16(xa[s][mt], bv, acc[mt][ft]);
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) xa[s][mt] = xb[s][mt];
   }
   if (!kact) return;
 #pragma unroll
@@ -555,18 +710,30 @@ __global__ __launch_bounds__(512) void k_pass3_bf16(const __bf16* __restrict__ X
 
 // ---------------------------------------------------------------- partial reduction
 
-template <typename PT>
-__global__ __launch_bounds__(256) void k_reduce_partials(const PT* __restrict__ part,
-                                                         int64_t pstride, int64_t rowstride,
-                                                         int nparts, int64_t rows, int F,
-                                                         double* __restrict__ W) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= rows * F) return;
-  const int64_t r = idx / F, f = idx - r * F;
+// Fixed-order grouped reduction: partial p goes to group p % G, each group
+// sums its partials in increasing p, and the G group sums are added in
+// increasing group order.  Block = 64 elements x G groups.
+template <typename PT, int G>
+__global__ __launch_bounds__(64 * G) void k_reduce_grouped(const PT* __restrict__ part,
+                                                           int64_t pstride, int64_t rowstride,
+                                                           int nparts, int64_t rows, int F,
+                                                           double* __restrict__ W) {
+  __shared__ double red[G][64];
+  const int el = threadIdx.x & 63, pg = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + el;
   double s = 0.0;
-#pragma unroll 8
-  for (int p = 0; p < nparts; ++p) s += (double)part[p * pstride + r * rowstride + f];
-  W[idx] = s;
+  if (e < rows * F) {
+    const int64_t r = e / F, f = e - r * F;
+    s = group_partial(part + r * rowstride + f, pstride, nparts, pg, G);
+  }
+  red[pg][el] = s;
+  __syncthreads();
+  if (pg == 0 && e < rows * F) {
+    double t = red[0][el];
+#pragma unroll
+    for (int q = 1; q < G; ++q) t += red[q][el];
+    W[e] = t;
+  }
 }
 
 // ---------------------------------------------------------------- planning and launchers
@@ -576,7 +743,7 @@ size_t elem_size(int prec) { return prec == PREC_F64 ? 8 : 4; }
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
-static const size_t kLdsBudget = 150 * 1024;
+static const size_t kLdsBudget = 158 * 1024;
 
 bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   if (F < 1 || F > 64) return false;
@@ -592,7 +759,7 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   const int cus = cu_count > 0 ? cu_count : 256;
   // pass 1: one wave per (slab, 16*MT rows) item, four waves per block
   if (prec == PREC_BF16) {
-    p.MT1 = 4;
+    p.MT1 = 2;
   } else {
     // MFMA-bound in FP32 at large F: pick the row tile with the least padding
     const int64_t pad1 = cdiv(p.J, 16) * 16, pad2 = cdiv(p.J, 32) * 32;
@@ -605,42 +772,56 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
     p.Kp = rup(p.K, 32);
     p.JG = cdiv(p.J, 8);
     p.Kp3 = rup(p.K, 16);
-    int64_t kc = p.Kp;
-    while ((size_t)p.FP * (kc + 8) * 2 > kLdsBudget) kc = rup(kc / 2, 32);
+    int64_t kc = rup(p.Kp, 64);
+    while ((size_t)p.FP * (kc + 8) * 2 > kLdsBudget) kc = rup(kc / 2, 64);
     p.KC1 = (int)kc;
     p.lds1 = (size_t)p.FP * (kc + 8) * 2;
   } else {
     const size_t es = elem_size(prec);
-    int64_t kc = rup(p.K, 16);
-    while ((size_t)p.FP * kc * es > kLdsBudget) kc = rup(kc / 2, 16);
+    int64_t kc = rup(p.K, 32);
+    while ((size_t)p.FP * kc * es > kLdsBudget) kc = rup(kc / 2, 32);
     p.KC1 = (int)kc;
     p.lds1 = (size_t)p.FP * kc * es;
   }
   int occ = (int)std::min<size_t>(8, (160 * 1024) / std::max<size_t>(p.lds1 + 512, 1));
   if (occ < 1) occ = 1;
-  p.grid1 = (int)std::min<int64_t>(cdiv(p.ntiles1, 4), (int64_t)cus * occ);
+  p.grid1 = (int)std::min<int64_t>(cdiv(p.ntiles1, 8), (int64_t)cus * occ);
   // mode 2 from T
   p.ich2 = 16;
   p.nich2 = (int)cdiv(p.I, p.ich2);
-  // pass 3: k split into 64-column wave tiles, at most 8 waves per block,
-  // balanced over ceil(tiles/8) k-groups; about two blocks per CU
+  // pass 3: k split into 64-column wave tiles.  FP32/FP64: at most 8 waves per
+  // block, balanced over ceil(tiles/8) k-groups, row chunks for about two
+  // blocks per CU.  BF16: up to 12 waves per block, blocks own whole slabs
+  // (or slab chunks of JCG 8-row groups whose Khatri-Rao rows fit in LDS).
   const int64_t kspan = (prec == PREC_BF16) ? p.Kp3 : p.K;
   const int ktiles = (int)cdiv(kspan, 64);
-  p.nkg3 = (int)cdiv(ktiles, 8);
-  p.nw3 = (int)cdiv(ktiles, p.nkg3);
-  const int64_t units = (prec == PREC_BF16) ? p.I * p.JG : p.I * p.J;  // groups or rows
-  const int64_t epoch = (prec == PREC_BF16) ? 8 : 64;
-  int64_t nrc = std::max<int64_t>(1, 2LL * cus / p.nkg3);
-  nrc = std::min<int64_t>(nrc, cdiv(units, epoch));
-  p.rpc3 = rup(cdiv(units, nrc), epoch);
-  p.nrc3 = (int)cdiv(units, p.rpc3);
+  if (prec == PREC_BF16) {
+    p.nkg3 = (int)cdiv(ktiles, 12);
+    p.nw3 = (int)cdiv(ktiles, p.nkg3);
+    int64_t jcg = p.JG;
+    auto lds_of = [&](int64_t q) { return (size_t)p.FP * (32 * cdiv(q, 4) + 8) * 2; };
+    while (lds_of(jcg) > kLdsBudget) jcg = cdiv(jcg, 2);
+    p.jcg3 = (int)jcg;
+    p.lds3 = lds_of(jcg);
+    const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(p.I, (int64_t)cus / p.nkg3));
+    p.rpc3 = cdiv(p.I, nblk);          // slabs per block
+    p.nrc3 = (int)cdiv(p.I, p.rpc3);
+  } else {
+    p.nkg3 = (int)cdiv(ktiles, 8);
+    p.nw3 = (int)cdiv(ktiles, p.nkg3);
+    const int64_t units = p.I * p.J;
+    int64_t nrc = std::max<int64_t>(1, 2LL * cus / p.nkg3);
+    nrc = std::min<int64_t>(nrc, cdiv(units, 64));
+    p.rpc3 = rup(cdiv(units, nrc), 64);
+    p.nrc3 = (int)cdiv(units, p.rpc3);
+  }
   // inner sweep
   int FL = 4;
   while (FL < F) FL <<= 1;
   p.FL = FL;
-  p.rpb = 1024 / FL;
+  p.rpb = inner_rows_per_block(FL);
   for (int m = 0; m < 3; ++m) p.nblk_inner[m] = (int)cdiv(dims[m], p.rpb);
-  p.nprep = (int)std::max<int64_t>(1, std::min<int64_t>(16, cdiv((int64_t)F * F, 256)));
+  p.nprep = (int)std::max<int64_t>(1, cdiv((int64_t)F * F, 64));
   return true;
 }
 
@@ -670,7 +851,7 @@ static hipError_t pass1_t(const Plan& p, const void* X, const void* Hb, const vo
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)p.lds1);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(256), p.lds1, s, (const T*)X, (int)p.I, (int)p.J,
+  hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(512), p.lds1, s, (const T*)X, (int)p.I, (int)p.J,
                      (int)p.K, p.F, (const T*)Hb, (const T*)Hc, (T*)Tout, (T*)P1, p.nch1, p.KC1,
                      p.vec ? 1 : 0);
   return hipGetLastError();
@@ -686,11 +867,21 @@ static hipError_t pass1_mt(const Plan& p, const void* X, const void* Hb, const v
 template <int FT>
 static hipError_t pass1_bf16(const Plan& p, const __bf16* Xr, const float* scale, const void* Hb,
                              const void* Hc, void* Tout, void* P1, hipStream_t s) {
-  auto kern = k_pass1_bf16<FT, 4>;
+  if (p.KC1 >= p.Kp) {
+    auto kern = k_pass1_bf16s<FT, 2>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds1);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(512), p.lds1, s, Xr, scale, (int)p.I, (int)p.J,
+                       (int)p.K, (int)p.Kp, p.F, (const float*)Hb, (const float*)Hc, (float*)Tout,
+                       (float*)P1, p.nch1, p.KC1);
+    return hipGetLastError();
+  }
+  auto kern = k_pass1_bf16<FT, 2>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)p.lds1);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(256), p.lds1, s, Xr, scale, (int)p.I, (int)p.J,
+  hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(512), p.lds1, s, Xr, scale, (int)p.I, (int)p.J,
                      (int)p.K, (int)p.Kp, p.F, (const float*)Hb, (const float*)Hc, (float*)Tout,
                      (float*)P1, p.nch1, p.KC1);
   return hipGetLastError();
@@ -743,21 +934,26 @@ static void pass3_t(const Plan& p, const void* X, const void* Ha, const void* Hb
 }
 
 template <int FT>
-static void pass3_bf16(const Plan& p, const __bf16* Xj8, const float* scale, const void* Ha,
-                       const void* Hb, void* P3, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass3_bf16<FT>), dim3(p.nrc3, p.nkg3), dim3(64 * p.nw3), 0, s, Xj8, scale,
-                     p.I * p.JG, (int)p.J, (int)p.JG, (int)p.K, (int)p.Kp3, p.F, (const float*)Ha,
-                     (const float*)Hb, (float*)P3, p.rpc3);
+static hipError_t pass3_bf16(const Plan& p, const __bf16* Xj8, const float* scale, const void* Ha,
+                             const void* Hb, void* P3, hipStream_t s) {
+  auto kern = k_pass3_bf16<FT>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)p.lds3);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(p.nrc3, p.nkg3), dim3(64 * p.nw3), p.lds3, s, Xj8, scale,
+                     (int)p.I, (int)p.J, (int)p.JG, (int)p.K, (int)p.Kp3, p.F, (const float*)Ha,
+                     (const float*)Hb, (float*)P3, (int)p.rpc3, p.jcg3);
+  return hipGetLastError();
 }
 
 hipError_t launch_pass3(const Plan& p, const void* X, const __bf16* Xj8, const float* scale,
                         const void* Ha, const void* Hb, void* P3, hipStream_t s) {
   if (p.prec == PREC_BF16) {
     switch (p.FT) {
-      case 1: pass3_bf16<1>(p, Xj8, scale, Ha, Hb, P3, s); break;
-      case 2: pass3_bf16<2>(p, Xj8, scale, Ha, Hb, P3, s); break;
-      case 3: pass3_bf16<3>(p, Xj8, scale, Ha, Hb, P3, s); break;
-      default: pass3_bf16<4>(p, Xj8, scale, Ha, Hb, P3, s); break;
+      case 1: return pass3_bf16<1>(p, Xj8, scale, Ha, Hb, P3, s);
+      case 2: return pass3_bf16<2>(p, Xj8, scale, Ha, Hb, P3, s);
+      case 3: return pass3_bf16<3>(p, Xj8, scale, Ha, Hb, P3, s);
+      default: return pass3_bf16<4>(p, Xj8, scale, Ha, Hb, P3, s);
     }
   } else if (p.prec == PREC_F64) {
     switch (p.FT) {
@@ -779,14 +975,23 @@ hipError_t launch_pass3(const Plan& p, const void* X, const __bf16* Xj8, const f
 
 hipError_t launch_reduce_partials(const void* part, int part_is_f64, int64_t pstride,
                                   int64_t rowstride, int nparts, int64_t rows, int F, double* W,
-                                  hipStream_t s) {
-  const unsigned grid = (unsigned)cdiv(rows * F, 256);
-  if (part_is_f64)
-    hipLaunchKernelGGL(k_reduce_partials<double>, dim3(grid), dim3(256), 0, s,
-                       (const double*)part, pstride, rowstride, nparts, rows, F, W);
-  else
-    hipLaunchKernelGGL(k_reduce_partials<float>, dim3(grid), dim3(256), 0, s, (const float*)part,
-                       pstride, rowstride, nparts, rows, F, W);
+                                  hipStream_t s, int groups) {
+  const unsigned grid = (unsigned)cdiv(rows * F, 64);
+  if (groups == 4) {
+    if (part_is_f64)
+      hipLaunchKernelGGL((k_reduce_grouped<double, 4>), dim3(grid), dim3(256), 0, s,
+                         (const double*)part, pstride, rowstride, nparts, rows, F, W);
+    else
+      hipLaunchKernelGGL((k_reduce_grouped<float, 4>), dim3(grid), dim3(256), 0, s,
+                         (const float*)part, pstride, rowstride, nparts, rows, F, W);
+  } else {
+    if (part_is_f64)
+      hipLaunchKernelGGL((k_reduce_grouped<double, 16>), dim3(grid), dim3(1024), 0, s,
+                         (const double*)part, pstride, rowstride, nparts, rows, F, W);
+    else
+      hipLaunchKernelGGL((k_reduce_grouped<float, 16>), dim3(grid), dim3(1024), 0, s,
+                         (const float*)part, pstride, rowstride, nparts, rows, F, W);
+  }
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -40,12 +41,15 @@ struct DevState {
   int fresh[3];          // resid[m] not yet used by the penalty rule
   int flag;              // numeric error bits
   unsigned counter[4];   // last-block tickets of the prepare kernels
+  int warm_taken[3];     // rows started from the network in the last update of each mode
+  int pad_;
 };
 
 struct Layout {
   size_t state = 0, T = 0, P1 = 0, P2 = 0, P3 = 0, W[3] = {0, 0, 0}, prim[3] = {0, 0, 0},
          gram[3] = {0, 0, 0}, linv[3] = {0, 0, 0}, gpart = 0, rpart = 0, sumsq = 0, fitpart = 0,
-         xr = 0, xj8 = 0, scale = 0, total = 0;
+         xr = 0, xj8 = 0, scale = 0, wx = 0, wy = 0, wact = 0, wscale = 0, wG[3] = {0, 0, 0},
+         total = 0;
 };
 
 const int kSumsqParts = 1024;
@@ -96,11 +100,21 @@ Layout make_layout(const Plan& p, const ntf_opts& o) {
   L.gpart = c.take((size_t)maxblk * F * F * 8);
   L.rpart = c.take((size_t)maxblk * 8 * 8);
   L.sumsq = c.take((size_t)kSumsqParts * 8);
-  L.fitpart = c.take((size_t)fit_parts(p) * 2 * 8);
+  // fit partials; also scratch for ntf_admm_mode_problem (two Grams + partials)
+  L.fitpart = c.take(std::max<size_t>((size_t)fit_parts(p) * 2, (size_t)(2 + maxblk) * F * F) * 8);
   if (p.prec == PREC_BF16) {
     L.xr = c.take((size_t)(p.I * p.J * p.Kp) * 2);
     L.xj8 = c.take((size_t)(p.I * p.JG * p.Kp3 * 8) * 2);
     L.scale = c.take((size_t)p.I * 4);
+  }
+  if (o.warm_hidden > 0) {
+    const int64_t rmax = std::max(p.I, std::max(p.J, p.K));
+    const int64_t D = F * (F + 1) / 2 + F;
+    L.wx = c.take((size_t)(rmax * D) * 4);
+    L.wy = c.take((size_t)(rmax * F) * 4);
+    L.wact = c.take((size_t)(2 * rmax * o.warm_hidden) * 4);
+    L.wscale = c.take((size_t)rmax * 4);
+    for (int m = 0; m < 3; ++m) L.wG[m] = c.take((size_t)(F * F) * 8);
   }
   L.total = c.off;
   return L;
@@ -123,6 +137,8 @@ struct ntf_admm_ctx {
   bool use_graph = true;
   int64_t outer = 0;
   DevState* host_state = nullptr;  // pinned
+  bool warm_on = false;
+  ntf_mlp warm{};
   std::string err;
 
   template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -171,8 +187,9 @@ static ntf_status validate(const ntf_problem* pr, const ntf_opts* o, std::string
     return fail("tolerances must be >= 0");
   if (o->factor_source != 0 && o->factor_source != 1) return fail("factor_source must be 0 or 1");
   if (o->paper_init && o->factor_source != 1) return fail("paper_init needs factor_source 1");
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 3; ++q)
     if (o->reserved[q] != 0) return fail("reserved fields must be zero");
+  if (o->warm_hidden < 0 || o->warm_hidden > 1024) return fail("warm_hidden must be in [0, 1024]");
   const int64_t I = pr->dims[0], J = pr->dims[1], K = pr->dims[2];
   if (I * J > ((int64_t)1 << 40) || I * J * K > ((int64_t)1 << 46)) return fail("tensor too large");
   return NTF_OK;
@@ -218,7 +235,7 @@ static ntf_status compute_grams(ntf_admm_ctx* c) {
   for (int m = 0; m < 3; ++m) {
     NTF_HIP(c, launch_gram_part(c->feed(m), c->hf64(), d[m], p.F, p.rpb, gf32, gpart, c->s0));
     NTF_HIP(c, launch_reduce_partials(gpart, 1, (int64_t)p.F * p.F, p.F, p.nblk_inner[m], p.F, p.F,
-                                      c->at<double>(c->lay.gram[m]), c->s0));
+                                      c->at<double>(c->lay.gram[m]), c->s0, 4));
   }
   // leave mode 3's partials (the buffer already holds them) and zero residual partials
   NTF_HIP(c, launch_fill(c->at<double>(c->lay.rpart), (int64_t)p.nblk_inner[2] * 8, 0.0, c->s0));
@@ -250,6 +267,8 @@ static void prep_args(ntf_admm_ctx* c, int m, PrepArgs& a) {
   a.resid_mode = ds->resid[m];
   a.fresh_mode = &ds->fresh[m];
   a.Linv = c->at<double>(c->lay.linv[m]);
+  a.G_out = c->warm_on ? c->at<double>(c->lay.wG[m]) : nullptr;
+  a.taken = &ds->warm_taken[m];
   a.flag = &ds->flag;
   a.counter = &ds->counter[m];
 }
@@ -259,24 +278,15 @@ static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
   const int64_t d[3] = {p.I, p.J, p.K};
   DevState* ds = c->dstate();
   a = InnerArgs();
-  a.part_f64 = c->hf64();
-  if (m == 0) {
-    a.part = c->ws + c->lay.P1;
-    a.pstride = p.F;
-    a.rowstride = (int64_t)p.nch1 * p.F;
-    a.nparts = p.nch1;
-  } else if (m == 1) {
-    a.part = c->ws + c->lay.P2;
-    a.pstride = p.J * p.F;
+  {
+    // W_m was reduced from the MTTKRP partials by the grouped reduction
+    a.part = c->ws + c->lay.W[m];
+    a.part_f64 = 1;
+    a.pstride = 0;
     a.rowstride = p.F;
-    a.nparts = p.nich2;
-  } else {
-    a.part = c->ws + c->lay.P3;
-    a.pstride = p.K * p.F;
-    a.rowstride = p.F;
-    a.nparts = p.nrc3;
+    a.nparts = 1;
   }
-  a.Wout = c->at<double>(c->lay.W[m]);
+  a.Wout = nullptr;
   a.H = c->prob.H[m];
   a.U = c->prob.U[m];
   a.Pout = (c->opts.factor_source == 1) ? (void*)(c->ws + c->lay.prim[m]) : nullptr;
@@ -297,6 +307,27 @@ static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
   a.flag = &ds->flag;
 }
 
+// Learned warm start of mode m (after its W and its prepare step): row
+// inputs, network forward, and the per-row KKT judge that writes the chosen
+// starting point into H_m, U_m.
+static ntf_status enqueue_warm(ntf_admm_ctx* c, int m, hipStream_t ms) {
+  const Plan& p = c->plan;
+  const int64_t d[3] = {p.I, p.J, p.K};
+  DevState* ds = c->dstate();
+  float* X = c->at<float>(c->lay.wx);
+  float* Y = c->at<float>(c->lay.wy);
+  float* sc = c->at<float>(c->lay.wscale);
+  const double* G = c->at<double>(c->lay.wG[m]);
+  const double* W = c->at<double>(c->lay.W[m]);
+  NTF_HIP(c, mlp_features(G, W, d[m], p.F, ds->rho[m], 0.0, X, sc, ms));
+  NTF_HIP(c, mlp_forward(c->warm.params, c->warm.dtype, p.F, c->warm.hidden, X, d[m], Y,
+                         c->at<float>(c->lay.wact), ms));
+  const int rescale = (c->opts.rescale_dual_on_rho_change || c->opts.rho_policy == NTF_RHO_ADAPTIVE) ? 1 : 0;
+  NTF_HIP(c, mlp_judge(Y, sc, G, W, c->prob.H[m], c->prob.U[m], c->hf64(), d[m], p.F, p.FL,
+                       ds->rho[m], rescale, &ds->warm_taken[m], ms));
+  return NTF_OK;
+}
+
 // Enqueue one outer iteration on `ms` with the prepare kernels on s1.
 static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   const Plan& p = c->plan;
@@ -313,7 +344,13 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
   NTF_HIP(c, hipEventRecord(c->ev_prep[0], c->s1));
   NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, ms));
+  NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P1, c->hf64(), p.F, (int64_t)p.nch1 * p.F,
+                                    p.nch1, p.I, p.F, c->at<double>(c->lay.W[0]), ms, 16));
   NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[0], 0));
+  if (c->warm_on) {
+    ntf_status w = enqueue_warm(c, 0, ms);
+    if (w != NTF_OK) return w;
+  }
   inner_args(c, 0, ia);
   NTF_HIP(c, launch_inner(ia, p.nblk_inner[0], ms));
   // mode 2 (B)
@@ -323,7 +360,13 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
   NTF_HIP(c, hipEventRecord(c->ev_prep[1], c->s1));
   NTF_HIP(c, launch_mode2(p, T, c->feed(0), c->ws + c->lay.P2, ms));
+  NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P2, c->hf64(), p.J * p.F, p.F, p.nich2, p.J, p.F,
+                                    c->at<double>(c->lay.W[1]), ms, 16));
   NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[1], 0));
+  if (c->warm_on) {
+    ntf_status w = enqueue_warm(c, 1, ms);
+    if (w != NTF_OK) return w;
+  }
   inner_args(c, 1, ia);
   NTF_HIP(c, launch_inner(ia, p.nblk_inner[1], ms));
   // mode 3 (C)
@@ -333,7 +376,13 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
   NTF_HIP(c, hipEventRecord(c->ev_prep[2], c->s1));
   NTF_HIP(c, launch_pass3(p, c->prob.X, xj8, scale, c->feed(0), c->feed(1), c->ws + c->lay.P3, ms));
+  NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P3, c->hf64(), p.K * p.F, p.F, p.nrc3, p.K, p.F,
+                                    c->at<double>(c->lay.W[2]), ms, 16));
   NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[2], 0));
+  if (c->warm_on) {
+    ntf_status w = enqueue_warm(c, 2, ms);
+    if (w != NTF_OK) return w;
+  }
   inner_args(c, 2, ia);
   NTF_HIP(c, launch_inner(ia, p.nblk_inner[2], ms));
   return NTF_OK;
@@ -394,6 +443,7 @@ static ntf_status fill_stats(ntf_admm_ctx* c, ntf_stats* st) {
   const double e2 = h.xnorm2 - 2.0 * h.fin[8] + h.fin[9];
   st->rfe_cheap = h.xnorm2 > 0 ? std::sqrt(std::fmax(e2, 0.0) / h.xnorm2) : 0.0;
   st->numeric_error = h.flag;
+  for (int m = 0; m < 3; ++m) st->warm_taken[m] = h.warm_taken[m];
   st->converged = (c->opts.stop_eps_abs > 0 || c->opts.stop_eps_rel > 0) && conv ? 1 : 0;
   if (c->outer == 0) st->converged = 0;
   return h.flag ? NTF_E_NUMERIC : NTF_OK;
@@ -596,16 +646,16 @@ ntf_status ntf_admm_mttkrp(ntf_admm_ctx* c, int32_t mode, double* W_out) {
     NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, c->s0));
   if (mode == 0)
     NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P1, pf64, p.F, (int64_t)p.nch1 * p.F, p.nch1,
-                                      p.I, p.F, W_out, c->s0));
+                                      p.I, p.F, W_out, c->s0, 16));
   if (mode == 1) {
     NTF_HIP(c, launch_mode2(p, T, c->feed(0), c->ws + c->lay.P2, c->s0));
     NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P2, pf64, p.J * p.F, p.F, p.nich2, p.J, p.F,
-                                      W_out, c->s0));
+                                      W_out, c->s0, 16));
   }
   if (mode == 2) {
     NTF_HIP(c, launch_pass3(p, c->prob.X, xj8, scale, c->feed(0), c->feed(1), c->ws + c->lay.P3, c->s0));
     NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P3, pf64, p.K * p.F, p.F, p.nrc3, p.K, p.F,
-                                      W_out, c->s0));
+                                      W_out, c->s0, 16));
   }
   return NTF_OK;
 }
@@ -646,6 +696,116 @@ ntf_status ntf_admm_destroy(ntf_admm_ctx* c) {
   return NTF_OK;
 }
 
+ntf_status ntf_admm_mode_problem(ntf_admm_ctx* c, int32_t mode, double* W_out, double* G_out,
+                                 double* rho_out) {
+  if (!c || mode < 0 || mode > 2 || !W_out || !G_out || !rho_out) return NTF_E_INVAL;
+  const Plan& p = c->plan;
+  const int64_t d[3] = {p.I, p.J, p.K};
+  ntf_status st = ntf_admm_mttkrp(c, mode, W_out);
+  if (st != NTF_OK) return st;
+  // Grams of the two other factors, in the fit-partial scratch buffer
+  double* tmp = c->at<double>(c->lay.fitpart);
+  double* Ga = tmp;
+  double* Gb = tmp + (size_t)p.F * p.F;
+  double* part = tmp + 2 * (size_t)p.F * p.F;
+  const int a = (mode + 1) % 3, b = (mode + 2) % 3;
+  const int gf32 = (p.prec == PREC_BF16) ? 1 : 0;
+  NTF_HIP(c, launch_gram_part(c->feed(a), c->hf64(), d[a], p.F, p.rpb, gf32, part, c->s0));
+  NTF_HIP(c, launch_reduce_partials(part, 1, (int64_t)p.F * p.F, p.F, p.nblk_inner[a], p.F, p.F, Ga,
+                                    c->s0, 4));
+  NTF_HIP(c, launch_gram_part(c->feed(b), c->hf64(), d[b], p.F, p.rpb, gf32, part, c->s0));
+  NTF_HIP(c, launch_reduce_partials(part, 1, (int64_t)p.F * p.F, p.F, p.nblk_inner[b], p.F, p.F, Gb,
+                                    c->s0, 4));
+  NTF_HIP(c, hadamard_rho(Ga, Gb, p.F, c->opts.rho0, G_out, rho_out, c->s0));
+  return NTF_OK;
+}
+
+ntf_status ntf_mlp_targets(const double* Hstar, const float* scale, int64_t rows, int32_t F,
+                           float* T_out, void* stream) {
+  if (!Hstar || !scale || !T_out || rows < 1 || F < 1 || F > 64) return NTF_E_INVAL;
+  return mlp_targets(Hstar, scale, rows, F, T_out, (hipStream_t)stream) == hipSuccess ? NTF_OK
+                                                                                       : NTF_E_HIP;
+}
+
+ntf_status ntf_admm_set_warmstart(ntf_admm_ctx* c, const ntf_mlp* net) {
+  if (!c) return NTF_E_INVAL;
+  if (net) {
+    if (net->F != c->plan.F || net->hidden < 1 || net->hidden > c->opts.warm_hidden ||
+        (net->dtype != 0 && net->dtype != 1) || !net->params || net->reserved != 0) {
+      c->err = "warm start network does not match the context (rank, hidden <= warm_hidden, dtype)";
+      return NTF_E_INVAL;
+    }
+    c->warm = *net;
+    c->warm_on = true;
+  } else {
+    c->warm_on = false;
+  }
+  // the iteration graph changes: capture it again on the next step
+  if (c->gexec) {
+    NTF_HIP(c, hipStreamSynchronize(c->s0));
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return NTF_OK;
+}
+
+size_t ntf_mlp_param_count(int32_t F, int32_t hidden) {
+  if (F < 1 || F > 64 || hidden < 1 || hidden > 1024) return 0;
+  return mlp_param_count(F, hidden);
+}
+
+static bool mlp_ok(const ntf_mlp* n) {
+  return n && n->F >= 1 && n->F <= 64 && n->hidden >= 1 && n->hidden <= 1024 &&
+         (n->dtype == 0 || n->dtype == 1) && n->params && n->reserved == 0;
+}
+
+ntf_status ntf_mlp_features(const double* G, const double* W, int64_t rows, int32_t F, double rho,
+                            float* X_out, float* scale_out, void* stream) {
+  if (!G || !W || !X_out || !scale_out || rows < 1 || F < 1 || F > 64 || !(rho > 0)) return NTF_E_INVAL;
+  return mlp_features(G, W, rows, F, nullptr, rho, X_out, scale_out, (hipStream_t)stream) == hipSuccess
+             ? NTF_OK : NTF_E_HIP;
+}
+
+ntf_status ntf_mlp_forward(const ntf_mlp* net, const float* X, int64_t batch, float* Y, float* act,
+                           void* stream) {
+  if (!mlp_ok(net) || !X || !Y || !act || batch < 1) return NTF_E_INVAL;
+  return mlp_forward(net->params, net->dtype, net->F, net->hidden, X, batch, Y, act,
+                     (hipStream_t)stream) == hipSuccess ? NTF_OK : NTF_E_HIP;
+}
+
+ntf_status ntf_mlp_backward(const ntf_mlp* net, const float* X, const float* act, const float* Y,
+                            const float* dY, int64_t batch, float* grad, float* work, void* stream) {
+  if (!mlp_ok(net) || net->dtype != 0 || !X || !act || !Y || !dY || !grad || !work || batch < 1)
+    return NTF_E_INVAL;
+  return mlp_backward((const float*)net->params, net->F, net->hidden, X, act, Y, dY, batch, grad,
+                      work, (hipStream_t)stream) == hipSuccess ? NTF_OK : NTF_E_HIP;
+}
+
+ntf_status ntf_mlp_mse(const float* Y, const float* T, int64_t batch, int32_t F, float* dY,
+                       double* loss_dev, double* part_dev, void* stream) {
+  if (!Y || !T || !dY || !loss_dev || !part_dev || batch < 1 || F < 1) return NTF_E_INVAL;
+  return mlp_mse(Y, T, batch, F, dY, part_dev, loss_dev, (hipStream_t)stream) == hipSuccess
+             ? NTF_OK : NTF_E_HIP;
+}
+
+ntf_status ntf_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t step, void* params_f16,
+                        void* stream) {
+  if (!params || !grad || !m || !v || n < 1 || step < 1 || !(lr > 0)) return NTF_E_INVAL;
+  return mlp_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step, params_f16,
+                  (hipStream_t)stream) == hipSuccess ? NTF_OK : NTF_E_HIP;
+}
+
+ntf_status ntf_gather_rows(const float* src, const int64_t* idx, int64_t n, int32_t cols,
+                           float* dst, void* stream) {
+  if (!src || !idx || !dst || n < 1 || cols < 1) return NTF_E_INVAL;
+  return gather_rows(src, idx, n, cols, dst, (hipStream_t)stream) == hipSuccess ? NTF_OK : NTF_E_HIP;
+}
+
 // ---------------------------------------------------------------- kernel-level calls
 
 size_t ntf_gram_workspace_bytes(int64_t rows, int32_t F) {
@@ -663,7 +823,7 @@ ntf_status ntf_gram(const void* H, int64_t rows, int32_t F, int32_t dtype, doubl
   const int64_t nparts = (rows + 63) / 64;
   double* part = reinterpret_cast<double*>(workspace);
   if (launch_gram_part(H, dtype, rows, F, 64, 0, part, s) != hipSuccess) return NTF_E_HIP;
-  if (launch_reduce_partials(part, 1, (int64_t)F * F, F, (int)nparts, F, F, G_out, s) != hipSuccess)
+  if (launch_reduce_partials(part, 1, (int64_t)F * F, F, (int)nparts, F, F, G_out, s, 4) != hipSuccess)
     return NTF_E_HIP;
   return NTF_OK;
 }
@@ -675,7 +835,7 @@ struct InnerWs {
 InnerWs inner_ws(int64_t rows, int F) {
   int FL = 4;
   while (FL < F) FL <<= 1;
-  const int rpb = 1024 / FL;
+  const int rpb = inner_rows_per_block(FL);
   const int64_t nblk = (rows + rpb - 1) / rpb;
   Carver c;
   InnerWs w;
@@ -744,7 +904,7 @@ ntf_status ntf_inner_update(const double* W, void* H, void* U, int64_t rows, int
   ia.gram_part = reinterpret_cast<double*>(base + w.gpart);
   ia.resid_part = reinterpret_cast<double*>(base + w.rpart);
   ia.flag = &ds->flag;
-  const int rpb = 1024 / FL;
+  const int rpb = inner_rows_per_block(FL);
   if (launch_inner(ia, (int)((rows + rpb - 1) / rpb), s) != hipSuccess) return NTF_E_HIP;
   return NTF_OK;
 }

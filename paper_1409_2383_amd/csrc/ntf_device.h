@@ -81,4 +81,15 @@ static __device__ __forceinline__ T group_sum(T v, int width) {
   return v;
 }
 
+// Sum of the partials p = g, g+G, g+2G, ... < nparts of one element, in
+// increasing p (one group of the fixed-order grouped reductions).
+template <typename PT>
+static __device__ __forceinline__ double group_partial(const PT* __restrict__ base, int64_t pstride,
+                                                       int nparts, int g, int G) {
+  double s = 0.0;
+#pragma unroll 4
+  for (int p = g; p < nparts; p += G) s += (double)base[(int64_t)p * pstride];
+  return s;
+}
+
 }  // namespace ntf

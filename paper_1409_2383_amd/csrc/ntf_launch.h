@@ -27,8 +27,10 @@ struct Plan {
   int ich2 = 16, nich2 = 0;
   // pass 3 (mode-3 MTTKRP): waves per block, k-groups, row chunks
   int nw3 = 0, nkg3 = 0, nrc3 = 0;
-  int64_t rpc3 = 0;               // rows (FP32/FP64) or 8-row groups (BF16) per chunk
-  // inner sweep: lanes per row, rows per 1024-thread block, blocks per mode
+  int64_t rpc3 = 0;               // rows (FP32/FP64) or slabs (BF16) per block
+  int jcg3 = 0;                   // BF16: 8-row groups per Khatri-Rao chunk in LDS
+  size_t lds3 = 0;
+  // inner sweep: lanes per row, rows per block, blocks per mode
   int FL = 0, rpb = 0;
   int nblk_inner[3] = {0, 0, 0};
   int nprep = 1;                  // blocks of the prepare kernel
@@ -55,9 +57,10 @@ hipError_t launch_mode2(const Plan& p, const void* Tin, const void* Ha, void* P2
 hipError_t launch_pass3(const Plan& p, const void* X, const __bf16* Xj8, const float* scale,
                         const void* Ha, const void* Hb, void* P3, hipStream_t s);
 // W[rows][F] (double) = sum over partials, fixed order
+// (fixed grouped order: partial p to group p % groups, groups = 4 or 16)
 hipError_t launch_reduce_partials(const void* part, int part_is_f64, int64_t pstride,
                                   int64_t rowstride, int nparts, int64_t rows, int F, double* W,
-                                  hipStream_t s);
+                                  hipStream_t s, int groups);
 
 // ---- ADMM
 struct InnerArgs {
@@ -85,6 +88,7 @@ struct InnerArgs {
   int* flag = nullptr;
 };
 hipError_t launch_inner(const InnerArgs& a, int nblk, hipStream_t s);
+int inner_rows_per_block(int FL);     // rows one inner-sweep block handles
 
 struct PrepArgs {
   int F = 0;
@@ -102,6 +106,8 @@ struct PrepArgs {
   const double* resid_mode = nullptr; // residual totals of the mode being prepared
   int* fresh_mode = nullptr;
   double* Linv = nullptr;             // out [F][F]
+  double* G_out = nullptr;            // optional out: G of the mode being prepared [F][F]
+  int* taken = nullptr;               // warm-start counter of the mode being prepared (zeroed)
   int* flag = nullptr;
   unsigned* counter = nullptr;        // last-block ticket, zero on entry, left zero
   // optional cheap fit (after the third mode): <W3,H3> and sum(G1*G2*G3)
@@ -125,5 +131,28 @@ hipError_t launch_finish(int F, const double* gram_part, const double* resid_par
                          const double* g0, const double* g1, const double* W3, const void* H3,
                          int h_f64, int64_t K, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+// ---- learned warm start (mlp.hip)
+size_t mlp_param_count(int F, int Hd);
+hipError_t mlp_forward(const void* params, int f16, int F, int Hd, const float* X, int64_t B,
+                       float* Y, float* act, hipStream_t s);
+hipError_t mlp_backward(const float* P, int F, int Hd, const float* X, const float* act,
+                        const float* Y, const float* dY, int64_t B, float* grad, float* work,
+                        hipStream_t s);
+hipError_t mlp_mse(const float* Y, const float* T, int64_t B, int F, float* dY, double* part,
+                   double* loss, hipStream_t s);
+hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                    float b2, float eps, int step, void* p16, hipStream_t s);
+hipError_t mlp_features(const double* G, const double* W, int64_t rows, int F,
+                        const double* rho_p, double rho_v, float* X, float* scale, hipStream_t s);
+hipError_t gather_rows(const float* src, const int64_t* idx, int64_t n, int cols, float* dst,
+                       hipStream_t s);
+hipError_t mlp_targets(const double* Hs, const float* scale, int64_t rows, int F, float* T,
+                       hipStream_t s);
+hipError_t hadamard_rho(const double* Ga, const double* Gb, int F, double rho0, double* G,
+                        double* rho, hipStream_t s);
+hipError_t mlp_judge(const float* Y, const float* scale, const double* G, const double* W, void* H,
+                     void* U, int h_f64, int64_t rows, int F, int FL, const double* rho_p,
+                     int rescale, int* taken, hipStream_t s);
 
 }  // namespace ntf
