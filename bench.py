@@ -92,9 +92,10 @@ def time_passes(torch, solver, reps):
     return out
 
 
-def cpu_baseline(X64, H0, T, sample_slabs):
-    """The FP64 oracle (as it stands) on the host: one outer iteration over the
-    first `sample_slabs` mode-1 slabs of the same tensor, scaled to the full
+def cpu_baseline(X, H0, T, sample_slabs, min_seconds=10.0, max_iters=5):
+    """The FP64 oracle (as it stands) on the host: outer iterations over the
+    first `sample_slabs` mode-1 slabs of the same tensor (all of them by
+    default), repeated until `min_seconds` have passed, scaled to the full
     tensor by the slab ratio (MTTKRP work is linear in I)."""
     from oracle import ntf_oracle as orc
     try:
@@ -102,19 +103,41 @@ def cpu_baseline(X64, H0, T, sample_slabs):
         cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
     except Exception:
         cores = os.cpu_count() or 1
-    I = X64.shape[0]
-    S = min(I, sample_slabs)
-    Xs = np.ascontiguousarray(X64[:S], dtype=np.float64)
+    I = X.shape[0]
+    S = min(I, sample_slabs) if sample_slabs > 0 else I
+    Xs = np.ascontiguousarray(X[:S], dtype=np.float64)
     st = orc.init_state([H0[0][:S].astype(np.float64), H0[1].astype(np.float64),
                          H0[2].astype(np.float64)])
+    opts = orc.Opts(inner_iters=T)
+    n = 0
     t0 = time.perf_counter()
-    orc.outer_step(Xs, st, orc.Opts(inner_iters=T))
-    dt = time.perf_counter() - t0
-    full = dt * I / S
-    return {"value": 1.0 / full, "unit": "outer_iters/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 outer iteration (T={T}) of the FP64 oracle on the first {S} of {I} "
-                      f"mode-1 slabs ({dt:.1f} s), scaled by {I}/{S}",
+    while True:
+        orc.outer_step(Xs, st, opts)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or n >= max_iters:
+            break
+    per_iter = dt / n * I / S
+    where = f"all {I}" if S == I else f"the first {S} of {I}"
+    return {"value": 1.0 / per_iter, "unit": "outer_iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} outer iteration(s) (T={T}) of the FP64 oracle on {where} mode-1 slabs "
+                      f"of the same tensor ({dt:.1f} s)" + ("" if S == I else f", scaled by {I}/{S}"),
             "seconds_measured": dt}
+
+
+def copy_calibration(torch, dev, mib, reps=3):
+    """Launches a plain elementwise copy-type kernel (negation: reads and writes
+    exactly `mib` MiB each) so that hardware byte counters taken in the same
+    run can be scaled against a known transfer."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: {reps} x neg over {mib} MiB")
+    del src, dst
 
 
 def time_to_target(torch, ntf, Xd, H0, T, arms, dev, ref_arm="fp64", max_outer=3000, every=10,
@@ -141,13 +164,18 @@ def time_to_target(torch, ntf, Xd, H0, T, arms, dev, ref_arm="fp64", max_outer=3
     res["rfe_star_source"] = f"{ref_arm} GPU run to |dRFE|/RFE < 1e-9 ({it} outer iterations)"
     s = torch.cuda.current_stream()
     for arm in arms:
-        solver, H = make_solver(ntf, torch, Xd, H0, arm, T, dev)
-        solver.step()                        # graph capture, untimed
         torch.cuda.synchronize()
-        total_ms, it = 0.0, 1
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        solver, H = make_solver(ntf, torch, Xd, H0, arm, T, dev)   # includes BF16 quantization
+        solver.step()                                               # and the graph capture
+        e1.record(s)
+        torch.cuda.synchronize()
+        init_ms = e0.elapsed_time(e1)
+        total_ms, it = init_ms, 1
         hit = None
         r = solver.fit()
-        trace = [(it, 0.0, r)]
+        trace = [(it, total_ms, r)]
         while it < max_outer:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
@@ -163,12 +191,108 @@ def time_to_target(torch, ntf, Xd, H0, T, arms, dev, ref_arm="fp64", max_outer=3
                 hit = (it, total_ms, r)
                 break
         res[arm] = {"reached": hit is not None, "outer_iters": hit[0] if hit else None,
+                    "init_and_first_step_ms": init_ms,
                     "seconds": hit[1] / 1e3 if hit else None, "rfe": r,
                     "rel_to_star": (r - rfe_star) / rfe_star, "trace_tail": trace[-3:]}
         solver.close()
         del solver, H
         torch.cuda.empty_cache()
     return res
+
+
+PASS_KERNELS = {"pass1": "k_pass1", "mode2": "k_mode2", "pass3": "k_pass3"}
+
+
+def _counter_means(path):
+    import collections
+    import csv
+    agg = collections.defaultdict(list)
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
+
+
+def write_traffic(fetch_csv, write_csv, calib_mib, workload, arm, pass_bytes, cmd):
+    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch) into HBM bytes per launch of each MTTKRP kernel.  Each counter is
+    scaled by what it reads for the copy-calibration kernel, which reads and
+    writes exactly `calib_mib` MiB per launch."""
+    fetch, write = _counter_means(fetch_csv), _counter_means(write_csv)
+
+    def find(tab, needle, counter):
+        hits = [(v, k[0]) for k, v in tab.items() if needle in k[0] and k[1] == counter]
+        if len(hits) != 1:
+            raise SystemExit(f"expected one kernel matching {needle!r} for {counter}, got {len(hits)}")
+        return hits[0][0][0], hits[0][1]
+    kib = calib_mib * 1024.0
+    f_cal, _ = find(fetch, "neg_kernel", "FETCH_SIZE")
+    w_cal, _ = find(write, "neg_kernel", "WRITE_SIZE")
+    f_scale, w_scale = f_cal / kib, w_cal / kib
+    tag = src_hash()
+    lines = [f"# HBM traffic per launch, {workload} {arm} arm", "",
+             "Commands (run from the repository root, NTF_NO_GRAPH=1):", "",
+             "    " + cmd.replace("COUNTER", "FETCH_SIZE").replace("OUT", "pmc_fetch"),
+             "    " + cmd.replace("COUNTER", "WRITE_SIZE").replace("OUT", "pmc_write"), "",
+             f"Copy calibration (elementwise negation, {calib_mib} MiB read + {calib_mib} MiB "
+             f"written per launch): FETCH_SIZE reads {f_cal:.0f} KiB (scale {f_scale:.4f}), "
+             f"WRITE_SIZE reads {w_cal:.0f} KiB (scale {w_scale:.4f}).", "",
+             "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | algorithmic bytes "
+             "| traffic / algorithmic |", "|---|---|---|---|---|---|"]
+    out = {}
+    for name, needle in PASS_KERNELS.items():
+        fk, full = find(fetch, needle, "FETCH_SIZE")
+        wk, _ = find(write, needle, "WRITE_SIZE")
+        nbytes = fk * 1024.0 / f_scale + wk * 1024.0 / w_scale
+        out[name] = {"kernel": full, "fetch_kib": fk, "write_kib": wk, "bytes_per_launch": nbytes,
+                     "algorithmic_bytes": pass_bytes[name], "src_hash": tag,
+                     "fetch_scale": f_scale, "write_scale": w_scale}
+        lines.append(f"| {name} (`{full[:48]}`) | {fk:.0f} | {wk:.0f} | {nbytes / 1e9:.4f} GB | "
+                     f"{pass_bytes[name] / 1e9:.4f} GB | {nbytes / pass_bytes[name]:.3f} |")
+        with open(os.path.join(ROOT, "profiles", f"traffic_{workload}_{arm}_{name}.json"), "w") as fh:
+            json.dump(out[name], fh, indent=1)
+    lines += ["", f"Source hash of the kernels measured: `{tag}`.", ""]
+    with open(os.path.join(ROOT, "profiles", f"traffic_{workload}_{arm}.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    return out
+
+
+def write_kernel_stats(stats_csv, workload, arm, cmd):
+    """Short text summary of a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    lines = [f"# Kernel time, {workload} {arm} arm", "", "Command (from /tmp, TMPDIR=/tmp):", "",
+             "    " + cmd, "", "| kernel | calls | average us | min us | max us | share % |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{r['Name'][:64]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    lines += ["", f"Source hash of the kernels measured: `{src_hash()}`.", ""]
+    with open(os.path.join(ROOT, "profiles", f"kernels_{workload}_{arm}.md"), "w") as fh:
+        fh.write("\n".join(lines))
+
+
+def summarize(args):
+    wl = WORKLOADS[args.workload]
+    arm = wl["arms"][0]
+    if args.write_kernel_stats:
+        cmd = (f"rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- python3 "
+               f"<repo>/bench.py --workload {args.workload} --steps 20 --warmup 3 --pass-reps 20 "
+               f"--no-cpu-baseline --single-arm")
+        write_kernel_stats(args.write_kernel_stats, args.workload, arm, cmd)
+    if args.write_traffic:
+        import paper_1409_2383_amd as ntf
+        if args.copy_calib_mib <= 0:
+            raise SystemExit("--write-traffic needs --copy-calib-mib (the size the runs used)")
+        prec = {"fp32": ntf.PREC_F32, "mixed": ntf.PREC_BF16_MIXED, "fp64": ntf.PREC_F64}[arm]
+        nb = ntf.pass_bytes(wl["dims"], wl["F"], prec, 8 if arm == "fp64" else 4)
+        cmd = (f"timeout -s KILL 180 rocprofv3 --pmc COUNTER --output-format csv -d gpurun_out/OUT "
+               f"-o run -- python3 bench.py --workload {args.workload} --steps 2 --warmup 1 "
+               f"--pass-reps 3 --no-cpu-baseline --single-arm --copy-calib-mib {args.copy_calib_mib}")
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.copy_calib_mib,
+                      args.workload, arm, nb, cmd)
 
 
 def main():
@@ -179,10 +303,19 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-slabs", type=int, default=0)
+    ap.add_argument("--cpu-sample-slabs", type=int, default=0, help="0 = all slabs")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also launch a known-size copy kernel (for byte-counter scaling)")
     ap.add_argument("--ttt", action="store_true", help="also measure time to rel fit 1e-4")
     ap.add_argument("--single-arm", action="store_true")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs into profiles/ and exit")
+    ap.add_argument("--write-kernel-stats", metavar="STATS_CSV",
+                    help="summarise a rocprofv3 --kernel-trace --stats run into profiles/ and exit")
     args = ap.parse_args()
+    if args.write_traffic or args.write_kernel_stats:
+        summarize(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, "
               "'How the path would shard'); run with --gpus 1", file=sys.stderr)
@@ -220,6 +353,9 @@ def main():
         del solver, H
         torch.cuda.empty_cache()
 
+    if args.copy_calib_mib > 0:
+        copy_calibration(torch, dev, args.copy_calib_mib)
+
     head = arms[0]
     r = results[head]
     dom = max(("pass1", "pass3"), key=lambda k: r["pass_ms"][k])
@@ -238,8 +374,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        slabs = args.cpu_sample_slabs or {"c1": 40, "c2": 100, "c3": 100}[args.workload]
-        log(f"[bench] CPU oracle baseline on {slabs} slabs")
+        slabs = args.cpu_sample_slabs
+        log(f"[bench] CPU oracle baseline on {slabs or 'all'} slabs")
         cpu = cpu_baseline(pt.X, H0, T, slabs)
 
     ttt = None

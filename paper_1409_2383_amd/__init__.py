@@ -161,13 +161,8 @@ class NtfAdmm:
                    self._ctx)
 
     def plan_info(self) -> dict:
-        """Algorithmic bytes of each MTTKRP kernel launch (see bench.py)."""
-        I, J, K = self.X.shape
-        es = self.X.element_size()
-        F = self.F
-        x_bytes = I * J * K * (2 if self.opts.precision == PREC_BF16_MIXED else es)
-        t_bytes = I * J * F * (8 if self.opts.precision == PREC_F64 else 4)
-        return {"pass1": x_bytes + t_bytes, "mode2": t_bytes, "pass3": x_bytes}
+        """Algorithmic bytes of each MTTKRP kernel launch."""
+        return pass_bytes(tuple(self.X.shape), self.F, self.opts.precision, self.X.element_size())
 
     def get_state(self) -> bytes:
         L = _lib.lib()
@@ -231,3 +226,16 @@ def gram(H, stream=None):
     _lib.check(st, "ntf_gram")
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     return G
+
+
+def pass_bytes(dims, F: int, precision: int, x_elem_bytes: int = 4) -> dict:
+    """Algorithmic HBM bytes of one launch of each MTTKRP kernel: the tensor
+    copy the kernel streams (BF16 in the mixed-precision mode, else X itself)
+    and the I x J x F intermediate X x_3 H_3 that the first pass writes and the
+    mode-2 kernel reads.  Factor reads (at most a few MB, L2-resident) are
+    not counted."""
+    I, J, K = dims
+    x_bytes = I * J * K * (2 if precision == PREC_BF16_MIXED else x_elem_bytes)
+    t_bytes = I * J * F * (8 if precision == PREC_F64 else 4)
+    return {"pass1": x_bytes + t_bytes, "mode2": t_bytes, "pass3": x_bytes}
+
