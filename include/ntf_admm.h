@@ -273,6 +273,105 @@ size_t ntf_gram_workspace_bytes(int64_t rows, int32_t F);
 ntf_status ntf_gram(const void *H, int64_t rows, int32_t F, int32_t dtype, double *G_out,
                     void *workspace, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------- batched */
+
+/* Many independent problems of uneven shapes factorised together: one
+ * persistent kernel per outer iteration runs every problem's three mode
+ * updates (eq. ADMoM_NTF, Gauss-Seidel order of eq. ADMM_NTF_ALS_C) from one
+ * global work list, and each outer iteration is one replay of a captured HIP
+ * graph.  Every problem is the single-problem method of Section IV with its
+ * own F, G, rho and Cholesky factor; problems share nothing but the launch.
+ *
+ * Precision is NTF_PREC_BF16_MIXED only: at init the library writes two
+ * bfloat16 copies of each X with a power-of-two scale per mode-1 slab
+ * ([I][J][Kp], k fastest, and [I][K][Jp], j fastest; Kp, Jp = K, J rounded
+ * up to 32), then the MTTKRPs run on BF16 MFMA with FP32 accumulation (the
+ * mode-3 product scales each slab's result by the row of H_1 instead of
+ * forming Khatri-Rao rows), Grams in FP32 per row block summed in FP64, and
+ * Cholesky and solves in FP64.  Options used: inner_iters, rho_policy
+ * (TRACE or FIXED), rho0, inner_eps_abs/rel, rescale_dual_on_rho_change;
+ * factor_source, paper_init, warm_hidden and the outer stop test must be 0.
+ * Every problem: x_dtype 0, float32 H and U, F in 1..64, and its work items
+ * must fit the LDS (contraction lengths up to about 1000 at F = 64, larger at
+ * smaller F); otherwise init returns NTF_E_UNSUPPORTED. */
+typedef struct ntf_batch_ctx ntf_batch_ctx;
+
+/* Tile choice of one bucket of MTTKRP work items, as the autotuner reports
+ * and accepts it. */
+typedef struct {
+  int32_t kind;            /* 1 = the pass for modes 1 and 2 (contraction over k),
+                              3 = the pass for mode 3 (contraction over j) */
+  int32_t ft;              /* ceil(F / 16): 16-column MFMA tiles of the rank */
+  int32_t qbucket;         /* contraction length: 0 <= 128, 1 <= 256, 2 <= 512, 3 larger */
+  int32_t mt;              /* 16-row MFMA tiles per wave step, 1 or 2 */
+  int64_t item_elems;      /* target tensor elements per work item (whole slabs, >= 1 slab) */
+  double us;               /* autotuner: measured microseconds of the bucket's items, else 0 */
+} ntf_batch_tile;
+
+typedef struct {
+  int32_t n_problems;
+  int32_t grid;            /* persistent blocks (resident blocks per CU x CUs) */
+  int32_t lds_bytes;       /* dynamic LDS per block */
+  int32_t n_items;         /* work items per outer iteration */
+  int64_t items_by_kind[9];/* pass 1, prep 1, inner 1, prep 2, mode 2, inner 2, prep 3, pass 3, inner 3 */
+  int64_t x_bytes;         /* bytes of one BF16 copy of all tensors (unpadded) */
+  int64_t t_bytes;         /* bytes of all I x J x F intermediates */
+} ntf_batch_info;
+
+/* Workspace bytes for these problems and options (0 and *why on error). */
+size_t ntf_batch_workspace_bytes(const ntf_problem *probs, int32_t n, const ntf_opts *opts);
+
+/* Validates, carves the workspace (device, 256-byte aligned, caller-owned),
+ * writes the BF16 copies and the initial Grams, picks default tiles and
+ * captures the iteration graph.  `probs` is host memory [n], copied; every X
+ * is borrowed and must outlive the context.  Synchronising. */
+ntf_status ntf_batch_init(ntf_batch_ctx **out, const ntf_problem *probs, int32_t n,
+                          const ntf_opts *opts, void *workspace, size_t ws_bytes, void *stream);
+
+/* n_outer outer iterations of every problem (graph replays on the stream).
+ * Stream-ordered; errors found on the device are reported by ntf_batch_sync. */
+ntf_status ntf_batch_step(ntf_batch_ctx *ctx, int32_t n_outer);
+
+/* Waits for the stream; returns NTF_E_NUMERIC if a non-PD system or NaN/Inf
+ * was met (bits 1, 2) or a dependency wait timed out (bit 8) since init.
+ * `flags_out` (host, may be NULL) receives the bits. */
+ntf_status ntf_batch_sync(ntf_batch_ctx *ctx, int32_t *flags_out);
+
+/* Relative fit error ||X - [H1,H2,H3]||_F / ||X||_F of every problem from the
+ * FP32 tensors and current factors, FP64 accumulation; rfe_host is host
+ * memory [n].  Synchronising. */
+ntf_status ntf_batch_fit(ntf_batch_ctx *ctx, double *rfe_host);
+
+/* MTTKRP of mode `mode` (0..2) of problem `prob` from the current factors
+ * (the batched kernels' BF16 arithmetic, no factor update) into W_out
+ * (device float64 [d_mode][F]).  Runs the pass work of all problems.
+ * Stream-ordered. */
+ntf_status ntf_batch_mttkrp(ntf_batch_ctx *ctx, int32_t prob, int32_t mode, double *W_out);
+
+/* Launches the work items of one kind for all problems on their own, without
+ * dependencies: kind 0 = pass for modes 1 and 2, 4 = mode 2 from T, 7 = pass
+ * for mode 3.  Leaves the factors unchanged.  For timing.  Stream-ordered. */
+ntf_status ntf_batch_launch_kind(ntf_batch_ctx *ctx, int32_t kind);
+
+/* Times `candidates` tile choices per bucket present in the batch (pass-only
+ * launches, reps each, HIP events), keeps the fastest, rebuilds the work list
+ * and re-captures the graph.  Writes the chosen tiles to out (host, up to cap
+ * entries; *n_out = entries written).  Factors are unchanged.  Synchronising. */
+ntf_status ntf_batch_autotune(ntf_batch_ctx *ctx, int32_t reps, ntf_batch_tile *out, int32_t cap,
+                              int32_t *n_out);
+
+/* Applies tile choices (e.g. from an autotuner cache) to the matching
+ * buckets; others keep theirs.  Rebuilds the work list and re-captures the
+ * graph.  Synchronising. */
+ntf_status ntf_batch_set_tiles(ntf_batch_ctx *ctx, const ntf_batch_tile *tiles, int32_t n);
+
+/* The current tile choices (host out, up to cap entries). */
+ntf_status ntf_batch_get_tiles(ntf_batch_ctx *ctx, ntf_batch_tile *out, int32_t cap, int32_t *n_out);
+
+ntf_status ntf_batch_info_get(ntf_batch_ctx *ctx, ntf_batch_info *out);
+const char *ntf_batch_last_error(const ntf_batch_ctx *ctx);
+ntf_status ntf_batch_destroy(ntf_batch_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

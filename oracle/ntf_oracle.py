@@ -176,6 +176,10 @@ class Opts:
     eps_rel: float = 0.0
     factor_source: int = 0               # 0: later modes use projected H; 1: the primal (paper)
     rescale_dual_on_rho_change: bool = False   # keep Y = -rho U fixed when rho changes
+    # operand rounding of the MTTKRP (the mixed-precision recipe; not in the
+    # paper): "exact", or bfloat16 operands as in mttkrp_mixed with mode 3 in
+    # Khatri-Rao ("bf16_kr") or factored ("bf16_factored") form
+    mttkrp_operands: str = "exact"
 
 
 @dataclass
@@ -289,7 +293,10 @@ def mode_update(X: np.ndarray, st: State, n: int, opts: Opts) -> dict:
     projection and dual update of eq. ADMoM_NTF)."""
     feed = st.P if opts.factor_source == 1 else st.H
     factors = [feed[0], feed[1], feed[2]]
-    W = mttkrp(X, factors, n)
+    if opts.mttkrp_operands == "exact":
+        W = mttkrp(X, factors, n)
+    else:
+        W = mttkrp_mixed(X, factors, n, mode3="factored" if opts.mttkrp_operands == "bf16_factored" else "kr")
     G = gram_hadamard(factors, n)
     if opts.rho_policy == RHO_TRACE:
         rho = rho_trace(G, opts.rho0)
@@ -501,13 +508,17 @@ def quantize_slabs_bf16(X: np.ndarray):
     return Xq, s
 
 
-def mttkrp_mixed(X: np.ndarray, factors: Sequence[np.ndarray], n: int) -> np.ndarray:
+def mttkrp_mixed(X: np.ndarray, factors: Sequence[np.ndarray], n: int, mode3: str = "kr") -> np.ndarray:
     """MTTKRP with the operand rounding of the mixed-precision recipe (the
     method itself is unchanged): X is replaced by its per-slab bfloat16 copy
     s_i * Xq[i]; modes 1 and 2 contract against bfloat16(C) with the other
-    factor in float32; mode 3 contracts against Khatri-Rao rows formed in
-    float32 as (s_i * A[i,:]) * B[j,:] and rounded to bfloat16.  Accumulation
+    factor in float32.  Mode 3, mode3="kr": against Khatri-Rao rows formed in
+    float32 as (s_i * A[i,:]) * B[j,:] and rounded to bfloat16; mode3=
+    "factored": against bfloat16(B) with A in float32 applied per slab
+    (W3[k,:] = sum_i s_i A[i,:] * sum_j Xq[i,j,k] bf16(B[j,:])).  Accumulation
     is exact up to float64 rounding."""
+    if mode3 not in ("kr", "factored"):
+        raise ValueError("mode3 must be 'kr' or 'factored'")
     Xq, s = quantize_slabs_bf16(X)
     A, B, C = (np.asarray(f, dtype=np.float32) for f in factors)
     Xs = Xq * s[:, None, None]
@@ -517,6 +528,9 @@ def mttkrp_mixed(X: np.ndarray, factors: Sequence[np.ndarray], n: int) -> np.nda
     if n == 1:
         Cb = _round_bf16(C).astype(np.float64)
         return mttkrp(Xs, [A.astype(np.float64), B.astype(np.float64), Cb], 1)
+    if mode3 == "factored":
+        Bb = _round_bf16(B).astype(np.float64)
+        return mttkrp(Xs, [A.astype(np.float64), Bb, C.astype(np.float64)], 2)
     # mode 3: KR[(i,j), f] = bf16(fl32(fl32(s_i A[i,f]) B[j,f]))
     I, J = A.shape[0], B.shape[0]
     sA = (s.astype(np.float32)[:, None] * A).astype(np.float32)

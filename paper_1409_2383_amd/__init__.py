@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import (PREC_BF16_MIXED, PREC_F32, PREC_F64, RHO_ADAPTIVE, RHO_FIXED, RHO_TRACE,
                    NtfError)
 
-__all__ = ["NtfAdmm", "AdmmOptions", "inner_update", "gram", "PREC_F32", "PREC_BF16_MIXED",
+__all__ = ["NtfAdmm", "NtfBatch", "AdmmOptions", "inner_update", "gram", "PREC_F32", "PREC_BF16_MIXED",
            "PREC_F64", "RHO_TRACE", "RHO_FIXED", "RHO_ADAPTIVE", "NtfError", "library_path"]
 
 
@@ -238,4 +238,146 @@ def pass_bytes(dims, F: int, precision: int, x_elem_bytes: int = 4) -> dict:
     x_bytes = I * J * K * (2 if precision == PREC_BF16_MIXED else x_elem_bytes)
     t_bytes = I * J * F * (8 if precision == PREC_F64 else 4)
     return {"pass1": x_bytes + t_bytes, "mode2": t_bytes, "pass3": x_bytes}
+
+
+class NtfBatch:
+    """Many independent NTF problems of uneven shapes, factorised together:
+    one persistent kernel per outer iteration over a global work list, each
+    outer iteration one replay of a captured HIP graph (mixed precision only:
+    BF16 MTTKRP with FP32 accumulation, FP32 Grams, FP64 Cholesky/solves).
+
+    Xs: CUDA float32 tensors [I, J, K]; Hs: per problem three CUDA float32
+    factors [d_n, F] (updated in place); Us: duals (zeros if omitted).
+    """
+
+    KIND_PASS1, KIND_MODE2, KIND_PASS3 = 0, 4, 7
+
+    def __init__(self, Xs: Sequence, Hs: Sequence[Sequence], Us=None,
+                 opts: Optional[AdmmOptions] = None, stream=None):
+        torch = _torch()
+        self.opts = opts or AdmmOptions(precision=PREC_BF16_MIXED)
+        if self.opts.precision != PREC_BF16_MIXED:
+            raise ValueError("the batched solver runs in PREC_BF16_MIXED only")
+        n = len(Xs)
+        if n < 1 or len(Hs) != n:
+            raise ValueError("need one factor triple per tensor")
+        self.X, self.H = list(Xs), [list(h) for h in Hs]
+        self.U = [list(u) for u in Us] if Us is not None else \
+            [[torch.zeros_like(h) for h in hs] for hs in self.H]
+        probs = (_lib.Problem * n)()
+        for p in range(n):
+            X, H, U = self.X[p], self.H[p], self.U[p]
+            if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 3 or not X.is_contiguous():
+                raise ValueError(f"X[{p}] must be a contiguous 3-way CUDA float32 tensor")
+            F = H[0].shape[1]
+            for m in range(3):
+                for t, nm in ((H[m], "H"), (U[m], "U")):
+                    if (not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous()
+                            or tuple(t.shape) != (X.shape[m], F)):
+                        raise ValueError(f"{nm}[{p}][{m}] must be contiguous CUDA float32 "
+                                         f"({X.shape[m]}, {F})")
+                probs[p].dims[m] = X.shape[m]
+                probs[p].H[m] = _ptr(H[m])
+                probs[p].U[m] = _ptr(U[m])
+            probs[p].F = F
+            probs[p].x_dtype = 0
+            probs[p].X = _ptr(X)
+        self.n = n
+        self.Fs = [h[0].shape[1] for h in self.H]
+        self._probs = probs
+        self._copts = self.opts.to_c()
+        L = _lib.lib()
+        nbytes = L.ntf_batch_workspace_bytes(probs, n, ctypes.byref(self._copts))
+        if nbytes == 0:
+            ctx = ctypes.c_void_p()
+            _lib.check(L.ntf_batch_init(ctypes.byref(ctx), probs, n, ctypes.byref(self._copts), None, 0,
+                                        _stream_handle(stream)), "ntf_batch_init", None, batch=True)
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.X[0].device)
+        ctx = ctypes.c_void_p()
+        _lib.check(L.ntf_batch_init(ctypes.byref(ctx), probs, n, ctypes.byref(self._copts),
+                                    ctypes.c_void_p(_ptr(self.workspace)), nbytes,
+                                    _stream_handle(stream)), "ntf_batch_init", None, batch=True)
+        self._ctx = ctx
+
+    def _check(self, st, where):
+        return _lib.check(st, where, self._ctx, batch=True)
+
+    def step(self, n_outer: int = 1):
+        self._check(_lib.lib().ntf_batch_step(self._ctx, int(n_outer)), "ntf_batch_step")
+
+    def sync(self) -> int:
+        flags = ctypes.c_int32(0)
+        st = _lib.lib().ntf_batch_sync(self._ctx, ctypes.byref(flags))
+        self._check(st, "ntf_batch_sync")
+        return flags.value
+
+    def fit(self):
+        import numpy as np
+        out = (ctypes.c_double * self.n)()
+        self._check(_lib.lib().ntf_batch_fit(self._ctx, out), "ntf_batch_fit")
+        return np.array(out[:], dtype=np.float64)
+
+    def mttkrp(self, prob: int, mode: int):
+        torch = _torch()
+        rows = self.X[prob].shape[mode]
+        W = torch.empty((rows, self.Fs[prob]), dtype=torch.float64, device=self.X[prob].device)
+        self._check(_lib.lib().ntf_batch_mttkrp(self._ctx, int(prob), int(mode), _ptr(W)),
+                    "ntf_batch_mttkrp")
+        return W
+
+    def launch_kind(self, kind: int):
+        self._check(_lib.lib().ntf_batch_launch_kind(self._ctx, int(kind)), "ntf_batch_launch_kind")
+
+    @staticmethod
+    def _tiles_to_list(arr, n):
+        return [{"kind": t.kind, "ft": t.ft, "qbucket": t.qbucket, "mt": t.mt,
+                 "item_elems": t.item_elems, "us": t.us} for t in arr[:n]]
+
+    def autotune(self, reps: int = 3, cache_path: Optional[str] = None):
+        """Times tile candidates per bucket, keeps the fastest; with a cache
+        file, writes the choices there (JSON) for set_tiles on a later run."""
+        cap = 64
+        arr = (_lib.BatchTile * cap)()
+        nout = ctypes.c_int32(0)
+        self._check(_lib.lib().ntf_batch_autotune(self._ctx, int(reps), arr, cap, ctypes.byref(nout)),
+                    "ntf_batch_autotune")
+        tiles = self._tiles_to_list(arr, nout.value)
+        if cache_path:
+            import json
+            with open(cache_path, "w") as fh:
+                json.dump(tiles, fh, indent=1)
+        return tiles
+
+    def set_tiles(self, tiles):
+        arr = (_lib.BatchTile * max(1, len(tiles)))()
+        for i, t in enumerate(tiles):
+            for k in ("kind", "ft", "qbucket", "mt", "item_elems", "us"):
+                setattr(arr[i], k, t.get(k, 0))
+        self._check(_lib.lib().ntf_batch_set_tiles(self._ctx, arr, len(tiles)), "ntf_batch_set_tiles")
+
+    def tiles(self):
+        cap = 64
+        arr = (_lib.BatchTile * cap)()
+        nout = ctypes.c_int32(0)
+        self._check(_lib.lib().ntf_batch_get_tiles(self._ctx, arr, cap, ctypes.byref(nout)),
+                    "ntf_batch_get_tiles")
+        return self._tiles_to_list(arr, nout.value)
+
+    def info(self) -> dict:
+        i = _lib.BatchInfo()
+        self._check(_lib.lib().ntf_batch_info_get(self._ctx, ctypes.byref(i)), "ntf_batch_info_get")
+        return {"n_problems": i.n_problems, "grid": i.grid, "lds_bytes": i.lds_bytes,
+                "n_items": i.n_items, "items_by_kind": list(i.items_by_kind),
+                "x_bytes": i.x_bytes, "t_bytes": i.t_bytes}
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _lib.lib().ntf_batch_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 

@@ -93,6 +93,29 @@ class Mlp(ctypes.Structure):
     ]
 
 
+class BatchTile(ctypes.Structure):
+    _fields_ = [
+        ("kind", c_int32),
+        ("ft", c_int32),
+        ("qbucket", c_int32),
+        ("mt", c_int32),
+        ("item_elems", c_int64),
+        ("us", c_double),
+    ]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_problems", c_int32),
+        ("grid", c_int32),
+        ("lds_bytes", c_int32),
+        ("n_items", c_int32),
+        ("items_by_kind", c_int64 * 9),
+        ("x_bytes", c_int64),
+        ("t_bytes", c_int64),
+    ]
+
+
 # (name, restype, argtypes) of every exported function
 SIGNATURES = [
     ("ntf_status_str", c_char_p, [c_int32]),
@@ -126,6 +149,20 @@ SIGNATURES = [
     ("ntf_gather_rows", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     ("ntf_mlp_targets", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     ("ntf_admm_mode_problem", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    ("ntf_batch_workspace_bytes", c_size_t, [POINTER(Problem), c_int32, POINTER(Opts)]),
+    ("ntf_batch_init", c_int32, [POINTER(c_void_p), POINTER(Problem), c_int32, POINTER(Opts), c_void_p,
+                                 c_size_t, c_void_p]),
+    ("ntf_batch_step", c_int32, [c_void_p, c_int32]),
+    ("ntf_batch_sync", c_int32, [c_void_p, POINTER(c_int32)]),
+    ("ntf_batch_fit", c_int32, [c_void_p, POINTER(c_double)]),
+    ("ntf_batch_mttkrp", c_int32, [c_void_p, c_int32, c_int32, c_void_p]),
+    ("ntf_batch_launch_kind", c_int32, [c_void_p, c_int32]),
+    ("ntf_batch_autotune", c_int32, [c_void_p, c_int32, POINTER(BatchTile), c_int32, POINTER(c_int32)]),
+    ("ntf_batch_set_tiles", c_int32, [c_void_p, POINTER(BatchTile), c_int32]),
+    ("ntf_batch_get_tiles", c_int32, [c_void_p, POINTER(BatchTile), c_int32, POINTER(c_int32)]),
+    ("ntf_batch_info_get", c_int32, [c_void_p, POINTER(BatchInfo)]),
+    ("ntf_batch_last_error", c_char_p, [c_void_p]),
+    ("ntf_batch_destroy", c_int32, [c_void_p]),
 ]
 
 _LIB = None
@@ -157,8 +194,9 @@ class NtfError(RuntimeError):
         super().__init__(f"{where}: {msg} ({status})" + (f": {detail}" if detail else ""))
 
 
-def check(status: int, where: str, ctx=None, ok=(NTF_OK,)):
+def check(status: int, where: str, ctx=None, ok=(NTF_OK,), batch=False):
     if status not in ok:
-        detail = lib().ntf_admm_last_error(ctx).decode(errors="replace")
+        err = lib().ntf_batch_last_error if batch else lib().ntf_admm_last_error
+        detail = err(ctx).decode(errors="replace")
         raise NtfError(status, where, detail)
     return status

@@ -9,297 +9,17 @@
 //                             v = ht - u;  h = max(0, v);  u = h - v.
 // The system matrix is common to all rows (Appendix B), so it is factored
 // once per mode update; the rows are then independent.
-#include "ntf_device.h"
+#include "admm_body.h"
 #include "ntf_launch.h"
 
 namespace ntf {
 
 // ---------------------------------------------------------------- inner sweep
 
-// Block of 256 threads.  A row of the factor lives on FL consecutive lanes
-// (FL = next power of two >= F, so a row never straddles a wave), and every
-// lane group carries RPL rows at once: lane f holds h_f, u_f, w_f of RPL rows
-// in FP64 registers for the whole sweep.  Both triangular applications are
-// lane-parallel mat-vecs against Linv (zero padded to FL x FL) in LDS, held
-// row-major and transposed so every step reads consecutive banks; each Linv
-// element read from LDS serves the RPL rows of the lane.  The right-hand
-// sides are exchanged through LDS (broadcast reads), two barriers per
-// inner iteration.
-struct InnerK {
-  const void* part;
-  int part_f64;
-  int64_t pstride, rowstride;
-  int nparts;
-  double* Wout;
-  void* H;
-  void* U;
-  void* Pout;
-  int64_t rows;
-  int F;
-  const double* Linv;
-  const double* rho;
-  int rescale, T;
-  double eps_abs, eps_rel;
-  int32_t* iters_out;
-  int gram_from_primal, gram_f32;
-  double* gram_part;
-  double* resid_part;
-  int* flag;
-};
-
-template <int FL>
-static constexpr int inner_rpl() { return FL >= 32 ? 2 : 1; }
-
-// out[q] = sum_g M[g*FL + f] * V[q*BS + g] for the RPL rows of a lane, with
-// the LDS reads of chunk c+1 issued before the FMAs of chunk c (register
-// double buffering), so LDS latency overlaps arithmetic.
-template <int FL, int RPL, int BS>
-static __device__ __forceinline__ void lane_matvec(const double* __restrict__ M,
-                                                   const double* __restrict__ V, int f,
-                                                   double (&out)[RPL]) {
-  constexpr int C = FL < 8 ? FL : 8;
-  constexpr int NC = FL / C;
-  double ma[C], va[RPL][C], mb[C], vb[RPL][C];
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) out[q] = 0.0;
-  auto ld = [&](int c, double (&m)[C], double (&v)[RPL][C]) {
-#pragma unroll
-    for (int t = 0; t < C; ++t) {
-      m[t] = M[(c * C + t) * FL + f];
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) v[q][t] = V[q * BS + c * C + t];
-    }
-  };
-  auto fm = [&](const double (&m)[C], const double (&v)[RPL][C]) {
-#pragma unroll
-    for (int t = 0; t < C; ++t)
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) out[q] += m[t] * v[q][t];
-  };
-  ld(0, ma, va);
-  if constexpr (NC == 1) {
-    fm(ma, va);
-  } else {
-    // NC is even here; a rolled loop keeps the compiler from hoisting every
-    // chunk's loads (which would blow the register budget)
-#pragma unroll 1
-    for (int c = 0; c < NC; c += 2) {
-      ld(c + 1, mb, vb);
-      fm(ma, va);
-      if (c + 2 < NC) ld(c + 2, ma, va);
-      fm(mb, vb);
-    }
-  }
-}
-template <int FL>
-static constexpr int inner_rows_per_block() { return (256 / FL) * inner_rpl<FL>(); }
-
 template <typename HT, int FL>
 __global__ __launch_bounds__(256) void k_inner(InnerK a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int RPL = inner_rpl<FL>();
-  constexpr int NG = 256 / FL;             // lane groups per block
-  constexpr int RPB = NG * RPL;            // rows per block
-  constexpr int BS = FL + 1;               // padded row stride of the exchange buffers
-  const int F = a.F;
-  double* Ls = reinterpret_cast<double*>(smem_raw);   // Ls[g][f]  = Linv[g][f]
-  double* LTs = Ls + FL * FL;                         // LTs[g][f] = Linv[f][g]
-  double* xb = LTs + FL * FL;                         // [RPB][BS] exchange (b, then y)
-  __shared__ double red[4][8];
-
-  const int tid = threadIdx.x;
-  const int grp = tid / FL, f = tid - grp * FL;
-  const int64_t row0 = (int64_t)blockIdx.x * RPB;
-
-  {
-    // all loads first, then the LDS writes (no serialised load-wait chain)
-    constexpr int PER = (FL * FL + 255) / 256;
-    double lv[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q;
-      const int r = e / FL, c = e - r * FL;
-      lv[q] = (e < FL * FL && r < F && c < F) ? a.Linv[r * F + c] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q;
-      if (e < FL * FL) {
-        const int r = e / FL, c = e - r * FL;
-        Ls[e] = lv[q];
-        LTs[c * FL + r] = lv[q];
-      }
-    }
-  }
-  const double rho = a.rho[0];
-  const double uscale = (a.rescale && a.rho[1] > 0.0) ? a.rho[1] / rho : 1.0;
-
-  // row q of this lane group is block row grp*RPL + q
-  double w[RPL], h[RPL], u[RPL], x[RPL], h0[RPL];
-  bool act[RPL], done[RPL];
-  int iters[RPL];
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int64_t row = row0 + grp * RPL + q;
-    act[q] = (row < a.rows) && (f < F);
-    done[q] = row >= a.rows;
-    iters[q] = 0;
-    w[q] = h[q] = u[q] = x[q] = 0.0;
-    if (act[q]) {
-      const int64_t off = row * a.rowstride + f;
-      double sw = 0.0;
-      if (a.part_f64) {
-        const double* p = reinterpret_cast<const double*>(a.part) + off;
-#pragma unroll 8
-        for (int t = 0; t < a.nparts; ++t) sw += p[t * a.pstride];
-      } else {
-        const float* p = reinterpret_cast<const float*>(a.part) + off;
-#pragma unroll 8
-        for (int t = 0; t < a.nparts; ++t) sw += (double)p[t * a.pstride];
-      }
-      w[q] = sw;
-      if (a.Wout) a.Wout[row * F + f] = sw;
-      h[q] = (double)reinterpret_cast<const HT*>(a.H)[row * F + f];
-      u[q] = (double)reinterpret_cast<const HT*>(a.U)[row * F + f] * uscale;
-    }
-    h0[q] = h[q];
-  }
-  const bool early = (a.eps_abs > 0.0) || (a.eps_rel > 0.0);
-  const double sqF = sqrt((double)F);
-  __shared__ int any_active;
-  double* yb = xb + RPB * BS;   // second exchange buffer: b and y never share one
-
-  for (int t = 0; t < a.T; ++t) {
-    if (early) {
-      if (tid == 0) any_active = 0;
-      __syncthreads();
-      bool mine = false;
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) mine |= !done[q];
-      if (mine) any_active = 1;
-      __syncthreads();
-      if (!any_active) break;
-    }
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) xb[(grp * RPL + q) * BS + f] = act[q] ? w[q] + rho * (h[q] + u[q]) : 0.0;
-    __syncthreads();
-    double y[RPL];
-    lane_matvec<FL, RPL, BS>(LTs, xb + grp * RPL * BS, f, y);      // y = L^{-1} b
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) yb[(grp * RPL + q) * BS + f] = y[q];
-    __syncthreads();
-    double xn[RPL];
-    lane_matvec<FL, RPL, BS>(Ls, yb + grp * RPL * BS, f, xn);      // x = L^{-T} y
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      if (done[q]) continue;
-      const double v = xn[q] - u[q];
-      const double hn = (v > 0.0) ? v : 0.0;
-      const double un = hn - v;
-      const double dh = hn - h[q];
-      h[q] = act[q] ? hn : 0.0;
-      u[q] = act[q] ? un : 0.0;
-      x[q] = act[q] ? xn[q] : 0.0;
-      ++iters[q];
-      if (early) {
-        const double sp = group_sum((h[q] - x[q]) * (h[q] - x[q]), FL);
-        const double sx = group_sum(x[q] * x[q], FL);
-        const double sh = group_sum(h[q] * h[q], FL);
-        const double sd = group_sum(act[q] ? dh * dh : 0.0, FL);
-        const double su = group_sum(u[q] * u[q], FL);
-        const double tol_p = sqF * a.eps_abs + a.eps_rel * fmax(sqrt(sx), sqrt(sh));
-        const double tol_d = sqF * a.eps_abs + a.eps_rel * rho * sqrt(su);
-        if (sqrt(sp) <= tol_p && rho * sqrt(sd) <= tol_d) done[q] = true;
-      }
-    }
-  }
-  __syncthreads();
-
-  double qs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int64_t row = row0 + grp * RPL + q;
-    if (act[q]) {
-      if (!isfinite(x[q]) || !isfinite(w[q])) atomicOr(a.flag, 1);
-      reinterpret_cast<HT*>(a.H)[row * F + f] = (HT)h[q];
-      reinterpret_cast<HT*>(a.U)[row * F + f] = (HT)u[q];
-      if (a.Pout) reinterpret_cast<HT*>(a.Pout)[row * F + f] = (HT)x[q];
-      if (a.iters_out && f == 0) a.iters_out[row] = iters[q];
-      const double hv = (double)(HT)h[q], xv = (double)(HT)x[q], uv = (double)(HT)u[q];
-      qs[0] += (hv - xv) * (hv - xv);
-      qs[1] += (hv - h0[q]) * (hv - h0[q]);
-      qs[2] += hv * hv;
-      qs[3] += xv * xv;
-      qs[4] += uv * uv;
-      if (f == 0) qs[5] += (double)iters[q];
-    }
-  }
-  // residual partials of this block: ||h-x||^2, ||h-h0||^2, ||h||^2, ||x||^2, ||u||^2, iterations
-  {
-    const int wave = tid >> 6;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const double sum = group_sum(qs[k], 64);
-      if ((tid & 63) == 0) red[wave][k] = sum;
-    }
-    __syncthreads();
-    if (tid < 6) {
-      const double sum = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-      a.resid_part[(int64_t)blockIdx.x * 8 + tid] = sum;
-    }
-    if (tid == 6 || tid == 7) a.resid_part[(int64_t)blockIdx.x * 8 + tid] = 0.0;
-  }
-  // Gram partial of this block's rows (of the stored factor values), rows in order
-  {
-    double* hs = xb;  // [RPB][BS]
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      const double src = a.gram_from_primal ? x[q] : h[q];
-      hs[(grp * RPL + q) * BS + f] = act[q] ? (double)(HT)src : 0.0;
-    }
-    __syncthreads();
-    const int nrow = (int)min((int64_t)RPB, a.rows - row0);
-    // thread (ti,tj) owns entries (ti+16p, tj+16q); each entry is summed over
-    // the block's rows in row order (the order the standalone Gram partials use)
-    constexpr int NBT = (FL + 15) / 16;
-    const int ti = tid >> 4, tj = tid & 15;
-    double acc[NBT][NBT];
-    float accf[NBT][NBT];
-#pragma unroll
-    for (int p = 0; p < NBT; ++p)
-#pragma unroll
-      for (int q = 0; q < NBT; ++q) {
-        acc[p][q] = 0.0;
-        accf[p][q] = 0.f;
-      }
-    for (int r2 = 0; r2 < nrow; ++r2) {
-      double vi[NBT], vj[NBT];
-#pragma unroll
-      for (int p = 0; p < NBT; ++p) {
-        vi[p] = (ti + 16 * p < FL) ? hs[r2 * BS + ti + 16 * p] : 0.0;
-        vj[p] = (tj + 16 * p < FL) ? hs[r2 * BS + tj + 16 * p] : 0.0;
-      }
-      if (a.gram_f32) {
-#pragma unroll
-        for (int p = 0; p < NBT; ++p)
-#pragma unroll
-          for (int q = 0; q < NBT; ++q) accf[p][q] += (float)vi[p] * (float)vj[q];
-      } else {
-#pragma unroll
-        for (int p = 0; p < NBT; ++p)
-#pragma unroll
-          for (int q = 0; q < NBT; ++q) acc[p][q] += vi[p] * vj[q];
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < NBT; ++p)
-#pragma unroll
-      for (int q = 0; q < NBT; ++q) {
-        const int r = ti + 16 * p, c = tj + 16 * q;
-        if (r < F && c < F)
-          a.gram_part[(int64_t)blockIdx.x * F * F + r * F + c] = a.gram_f32 ? (double)accf[p][q] : acc[p][q];
-      }
-  }
+  inner_body<HT, FL>(a, (int64_t)blockIdx.x, smem_raw);
 }
 
 template <typename HT, int FL>
@@ -371,34 +91,6 @@ hipError_t launch_inner(const InnerArgs& ia, int nblk, hipStream_t s) {
 // Cholesky and the triangular inverse use 256 threads on a 16 x 16 grid, thread
 // (ti,tj) owning elements (ti+16a, tj+16b) in registers; each elimination step
 // broadcasts one column (or row) through LDS, one barrier per step.
-struct PrepK {
-  int F;
-  const double* gram_part;
-  int nparts;
-  double* gram_dst;
-  const double* resid_part;
-  double* resid_dst;
-  int* fresh_dst;
-  const double* gram_a;
-  const double* gram_b;
-  int policy;
-  double rho0, mu, tau_incr, tau_decr;
-  double* rho_state;
-  const double* resid_mode;
-  int* fresh_mode;
-  double* Linv;
-  double* G_out;
-  int* taken;
-  int* flag;
-  unsigned* counter;
-  const double* W3;
-  const void* H3;
-  int h_f64;
-  int64_t K;
-  const double* gram_c;
-  double* fit_out;
-};
-
 // Totals of the 8 residual partial columns over nparts partials, grouped
 // fixed order (32 groups of 256 threads); used by the prepare and statistics
 // kernels so both give bitwise identical totals.
@@ -451,176 +143,8 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   } else if (blockIdx.x != 0) {
     return;
   }
-
-  __shared__ double Gs[64 * 65];
-  __shared__ double rowbuf[2][128];
-  __shared__ double colbuf[2][64];
-  __shared__ double sred[256];
-  __shared__ double rho_sh;
-  __shared__ int bad_sh;
-
-  {
-    double ga[NB * NB], gb[NB * NB];
-#pragma unroll
-    for (int q = 0; q < NB * NB; ++q) {
-      const int e = tid + 256 * q;
-      ga[q] = (e < F * F) ? a.gram_a[e] : 0.0;
-      gb[q] = (e < F * F) ? a.gram_b[e] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < NB * NB; ++q) {
-      const int e = tid + 256 * q;
-      if (e < F * F) {
-        const int r = e / F, c = e - r * F;
-        const double gv = ga[q] * gb[q];
-        Gs[r * 65 + c] = gv;
-        if (a.G_out) a.G_out[e] = gv;
-      }
-    }
-  }
-  if (tid == 0) {
-    bad_sh = 0;
-    if (a.taken) *a.taken = 0;
-  }
-  __syncthreads();
-
-  // penalty
-  if (tid == 0) {
-    const double rho_prev = a.rho_state[0];
-    double rho;
-    if (a.policy == 0) {
-      double tr = 0.0;
-#pragma unroll 8
-      for (int f = 0; f < F; ++f) tr += Gs[f * 65 + f];
-      rho = tr / F;
-      if (!(rho > 0.0) || !isfinite(rho)) rho = a.rho0;
-    } else if (a.policy == 1) {
-      rho = a.rho0;
-    } else {
-      rho = rho_prev > 0.0 ? rho_prev : a.rho0;
-      if (a.fresh_mode && *a.fresh_mode) {
-        const double prim = sqrt(a.resid_mode[0]);
-        const double dual = rho * sqrt(a.resid_mode[1]);
-        if (prim > a.mu * dual) rho = rho * a.tau_incr;
-        else if (dual > a.mu * prim) rho = rho / a.tau_decr;
-        *a.fresh_mode = 0;
-      }
-    }
-    a.rho_state[1] = (rho_prev > 0.0) ? rho_prev : rho;
-    a.rho_state[0] = rho;
-    rho_sh = rho;
-  }
-  __syncthreads();
-  const double rho = rho_sh;
-
-  // One elimination sweep over the augmented matrix [G + rho I | I]: row k is
-  // divided by sqrt(a_kk) and a_ik / a_kk times the unscaled row k is
-  // subtracted from every row i > k.  The left block becomes L^T and the
-  // right block L^{-1} (L the Cholesky factor), i.e. the factorisation and
-  // the triangular inverse in F steps.  Thread (ti,tj) owns rows ti+16a and
-  // columns tj+16b of both blocks; row k and column k are broadcast through
-  // LDS (double buffered, one barrier per step).
-  const int ti = tid >> 4, tj = tid & 15;
-  double rl[NB][NB], rr[NB][NB];
-#pragma unroll
-  for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-    for (int ib = 0; ib < NB; ++ib) {
-      const int i = ti + 16 * ia, j = tj + 16 * ib;
-      double v;
-      if (i < F && j < F) v = Gs[i * 65 + j] + ((i == j) ? rho : 0.0);
-      else v = (i == j) ? 1.0 : 0.0;
-      rl[ia][ib] = v;
-      rr[ia][ib] = (i == j) ? 1.0 : 0.0;
-    }
-#pragma unroll
-  for (int kb = 0; kb < NB; ++kb) {
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = 16 * kb + kk;
-      if (k >= F) break;
-      const int buf = k & 1;
-      if (ti == kk) {
-#pragma unroll
-        for (int ib = 0; ib < NB; ++ib) {
-          rowbuf[buf][tj + 16 * ib] = rl[kb][ib];
-          rowbuf[buf][64 + tj + 16 * ib] = rr[kb][ib];
-        }
-      }
-      if (tj == kk) {
-#pragma unroll
-        for (int ia = 0; ia < NB; ++ia) colbuf[buf][ti + 16 * ia] = rl[ia][kb];
-      }
-      __syncthreads();
-      double akk = rowbuf[buf][k];
-      if (!(akk > 0.0) || !isfinite(akk)) {
-        if (tid == 0) bad_sh = 1;
-        akk = 1.0;
-      }
-      const double inv = 1.0 / akk;
-      const double sc = 1.0 / sqrt(akk);
-      double rkl[NB], rkr[NB];
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        rkl[ib] = rowbuf[buf][tj + 16 * ib];
-        rkr[ib] = rowbuf[buf][64 + tj + 16 * ib];
-      }
-#pragma unroll
-      for (int ia = 0; ia < NB; ++ia) {
-        const int i = ti + 16 * ia;
-        if (i == k) {
-#pragma unroll
-          for (int ib = 0; ib < NB; ++ib) {
-            rl[ia][ib] = rkl[ib] * sc;
-            rr[ia][ib] = rkr[ib] * sc;
-          }
-        } else if (i > k && i < F) {
-          const double m = colbuf[buf][i] * inv;
-#pragma unroll
-          for (int ib = 0; ib < NB; ++ib) {
-            rl[ia][ib] -= m * rkl[ib];
-            rr[ia][ib] -= m * rkr[ib];
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  const bool bad = bad_sh != 0;
-#pragma unroll
-  for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-    for (int ib = 0; ib < NB; ++ib) {
-      const int i = ti + 16 * ia, j = tj + 16 * ib;
-      if (i < F && j < F) a.Linv[i * F + j] = bad ? 0.0 : (j <= i ? rr[ia][ib] : 0.0);
-    }
-  if (bad && tid == 0) atomicOr(a.flag, 2);
-
-  // optional cheap fit terms: <W3, H3> and sum(G1 * G2 * G3)
-  if (a.fit_out) {
-    double s1 = 0.0, s2 = 0.0;
-    const int64_t nkf = a.K * F;
-    for (int64_t e = tid; e < nkf; e += 256) {
-      const double hv = a.h_f64 ? reinterpret_cast<const double*>(a.H3)[e]
-                                : (double)reinterpret_cast<const float*>(a.H3)[e];
-      s1 += a.W3[e] * hv;
-    }
-    for (int e = tid; e < F * F; e += 256) s2 += a.gram_a[e] * a.gram_b[e] * a.gram_c[e];
-    sred[tid] = s1;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) sred[tid] += sred[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) a.fit_out[0] = sred[0];
-    __syncthreads();
-    sred[tid] = s2;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) sred[tid] += sred[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) a.fit_out[1] = sred[0];
-  }
+  __shared__ double prep_lds[kPrepLdsDoubles];
+  prep_body<NB>(a, prep_lds);
 }
 
 hipError_t launch_prep(const PrepArgs& pa, int nblk, hipStream_t s) {

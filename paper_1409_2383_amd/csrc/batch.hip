@@ -1,0 +1,700 @@
+// Batched ADMoM NTF for gfx950: one persistent kernel runs one outer
+// iteration (eq. ADMoM_NTF, modes in the Gauss-Seidel order of eq.
+// ADMM_NTF_ALS_C) of every problem of a batch of independent tensors of
+// uneven shapes.
+//
+// Work items (problem, kind, index) sit in one global list; blocks take
+// tickets from an atomic counter and run the item of their ticket.  Per
+// problem and outer iteration the kinds depend on each other as
+//
+//   P1 (slab groups) --------------+--> IN1 (row blocks) --+--> M2 --> IN2 --+--> P3 --> IN3
+//   PREP1 -------------------------+                       +--> PREP2 ---^   +--> PREP3 --^
+//
+// (PREPn: G_n = Gram (*) Gram of the other two modes, rho, L^{-1}; INn: the
+// fused inner sweep of mode n; P1: T = X x_3 H3 and the W1 rows; M2: W2
+// from T and the new H1; P3: W3 partials from the new H1 and H2).  The list
+// is sorted so that every item depends only on items with smaller tickets,
+// and a block waits (thread 0 polls the problem's completion counters) only
+// on such items.  A waiting block's dependencies are therefore held by
+// running blocks or already done, and the lowest held ticket never waits:
+// the kernel cannot deadlock, whatever the number of resident blocks.  Every
+// wait is also bounded (flag bit 8 when a bound is hit).
+//
+// MTTKRP arithmetic: BF16 operands, FP32 MFMA accumulation, the power-of-two
+// slab scale of X applied to each slab's FP32 result.
+//   P1: T[i,j,:] = s_i sum_k Xq[i,j,k] bf16(H3[k,:]);  W1[i,:] = sum_j H2[j,:] * T[i,j,:]
+//   M2: W2[j,:]  = sum_i H1[i,:] * T[i,j,:]                      (FP64 accumulation)
+//   P3: W3[k,:]  = sum_i s_i H1[i,:] * (sum_j Xq[i,j,k] bf16(H2[j,:]))
+// P3 reads a second BF16 copy with j fastest ([I][K][Jp]), so that its
+// contraction is contiguous like P1's; the Khatri-Rao factor of mode 3 is
+// applied in factored form (the H1 row scales each slab's result), so no
+// Khatri-Rao row is formed at all.
+#include "admm_body.h"
+#include "batch.h"
+#include "ntf_launch.h"
+
+#include <algorithm>
+
+namespace ntf {
+
+static __host__ __device__ __forceinline__ int rup_i(int x, int a) { return (x + a - 1) / a * a; }
+
+size_t batch_lds_p1(const BProb& p) {
+  const int FP = p.FT * 16, KCS = rup_i(p.Kp, 64) + 8;
+  return (size_t)FP * KCS * 2 + (size_t)4 * p.spi1 * FP * 4;
+}
+size_t batch_lds_p3(const BProb& p) {
+  const int FP = p.FT * 16, JCS = rup_i(p.Jp, 64) + 8;
+  return (size_t)FP * JCS * 2;
+}
+// The batched kernel runs the inner sweep with one row per lane group
+// (256 / FL rows per block), which keeps its register budget within two
+// resident blocks per compute unit; latency is hidden by the other items.
+int batch_inner_rows(int FL) { return 256 / FL; }
+size_t batch_lds_inner(int FL) {
+  return (size_t)(2 * FL * FL + 2 * batch_inner_rows(FL) * (FL + 1)) * sizeof(double);
+}
+size_t batch_lds_prep() { return (size_t)kPrepLdsDoubles * sizeof(double); }
+
+// ---------------------------------------------------------------- pass 1 item
+
+// Slabs s0 .. s0+ns-1 of one problem.  H3^T (BF16) sits in LDS; each wave
+// walks its 16*MT-row tiles (slab-major, tiles wave, wave+4, ...) as one
+// continuous sequence of 64-element super steps with U steps of loads in
+// flight, so its pipeline does not drain between tiles.  A lane's 32-byte
+// load covers contraction elements 16g .. 16g+15 of a super step; the two
+// MFMAs of the step take the first and second 8 (the contraction order
+// inside an instruction is free as long as both operands agree).
+template <int FT, int MT>
+__device__ __forceinline__ void p1_item(const BProb& P, int idx, unsigned char* lds) {
+  constexpr int FP = FT * 16;
+  constexpr int R = 16 * MT;
+  constexpr int U = 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+  const int J = P.J, K = P.K, F = P.F, Kp = P.Kp;
+  const int KC = rup_i(Kp, 64), KCS = KC + 8;
+  __bf16* Cs = reinterpret_cast<__bf16*>(lds);
+  const int s0 = idx * P.spi1;
+  const int ns = min(P.I, s0 + P.spi1) - s0;
+  float* w1p = reinterpret_cast<float*>(lds + (size_t)FP * KCS * 2);   // [4][ns][FP]
+  const float* __restrict__ Hb = P.H[1];
+  const float* __restrict__ Hc = P.H[2];
+  for (int e = tid; e < KC * FP; e += 256) {
+    const int kk = e / FP, f = e - kk * FP;
+    const float v = (kk < K && f < F) ? Hc[(int64_t)kk * F + f] : 0.f;
+    Cs[f * KCS + kk] = (__bf16)v;
+  }
+  for (int e = tid; e < 4 * ns * FP; e += 256) w1p[e] = 0.f;
+  __syncthreads();
+
+  const int nrg = (J + R - 1) / R;
+  const int ntiles = ns * nrg;
+  const int myt = ntiles > wave ? (ntiles - wave + 3) / 4 : 0;
+  const int nsteps = KC / 64;
+  const int total = myt * nsteps;
+  if (total > 0) {
+    int l_t = wave, l_kb = 0;
+    const __bf16* l_row[MT];
+    bool l_ok[MT];
+    auto set_rows = [&](int t) {
+      const int sl = t / nrg, rg = t - sl * nrg;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int j = rg * R + mt * 16 + n;
+        l_ok[mt] = j < J;
+        l_row[mt] = P.Xr + ((int64_t)(s0 + sl) * J + (l_ok[mt] ? j : 0)) * Kp + 16 * g;
+      }
+    };
+    set_rows(l_t);
+    bf16x8 xv[U][2][MT];
+    auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          if (l_ok[mt] && l_kb + 16 * g + 8 * h < Kp) {
+            dst[h][mt] = *reinterpret_cast<const bf16x8*>(l_row[mt] + l_kb + 8 * h);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
+          }
+        }
+      l_kb += 64;
+      if (l_kb >= Kp) {
+        l_kb = 0;
+        l_t += 4;
+        if (l_t < ntiles) set_rows(l_t);
+      }
+    };
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < total) load_next(xv[u]);
+
+    f32x4 acc[MT][FT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float wrun[FT];
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) wrun[ft] = 0.f;
+    int cur_sl = -1;
+    auto flush = [&]() {
+      if (cur_sl >= 0 && g == 0) {
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) w1p[(wave * ns + cur_sl) * FP + ft * 16 + n] = wrun[ft];
+      }
+    };
+    int c_t = wave, c_step = 0;
+    const __bf16* cb = Cs + n * KCS + 16 * g;
+    for (int s = 0; s < total; s += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int sidx = s + u;
+        if (sidx < total) {
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft) {
+            const __bf16* cp = cb + ft * 16 * KCS + c_step * 64;
+            const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(cp);
+            const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(cp + 8);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], c0, acc[mt][ft]);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], c1, acc[mt][ft]);
+          }
+          if (sidx + U < total) load_next(xv[u]);
+          if (++c_step == nsteps) {
+            const int sl = c_t / nrg, rg = c_t - sl * nrg;
+            const int i = s0 + sl;
+            const float sc = P.scale[i];
+            if (sl != cur_sl) {
+              flush();
+              cur_sl = sl;
+#pragma unroll
+              for (int ft = 0; ft < FT; ++ft) wrun[ft] = 0.f;
+            }
+            float part[FT];
+#pragma unroll
+            for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+              for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) {
+                  const int j = rg * R + mt * 16 + 4 * g + ii;
+                  const int f = ft * 16 + n;
+                  if (j < J && f < F) {
+                    const float v = sc * acc[mt][ft][ii];
+                    P.T[((int64_t)i * J + j) * F + f] = v;
+                    part[ft] += Hb[(int64_t)j * F + f] * v;
+                  }
+                }
+                acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+              }
+#pragma unroll
+            for (int ft = 0; ft < FT; ++ft) {
+              part[ft] += __shfl_xor(part[ft], 16);
+              part[ft] += __shfl_xor(part[ft], 32);
+              wrun[ft] += part[ft];
+            }
+            c_step = 0;
+            c_t += 4;
+          }
+        }
+      }
+    }
+    flush();
+  }
+  __syncthreads();
+  // W1 rows of this item's slabs: the four waves' partials in wave order
+  for (int e = tid; e < ns * F; e += 256) {
+    const int sl = e / F, f = e - sl * F;
+    double w = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < 4; ++wv) w += (double)w1p[(wv * ns + sl) * FP + f];
+    P.W[0][(int64_t)(s0 + sl) * F + f] = w;
+  }
+}
+
+// ---------------------------------------------------------------- pass 3 item
+
+// Slabs s0 .. s0+ns-1 of one problem, from the j-fastest copy.  H2^T (BF16)
+// sits in LDS.  Each wave owns 16*MT-row groups of k (rg = wave, wave+4, ..)
+// and, for each, streams the slabs of the item: the FP32 result of a slab is
+// scaled by s_i * H1[i,:] and added to the group's total, which is written
+// to this item's partial of W3 at the end.
+template <int FT, int MT>
+__device__ __forceinline__ void p3_item(const BProb& P, int idx, unsigned char* lds) {
+  constexpr int FP = FT * 16;
+  constexpr int R = 16 * MT;
+  constexpr int U = 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+  const int J = P.J, K = P.K, F = P.F, Jp = P.Jp;
+  const int JC = rup_i(Jp, 64), JCS = JC + 8;
+  __bf16* Bs = reinterpret_cast<__bf16*>(lds);
+  const float* __restrict__ Ha = P.H[0];
+  const float* __restrict__ Hb = P.H[1];
+  for (int e = tid; e < JC * FP; e += 256) {
+    const int jj = e / FP, f = e - jj * FP;
+    const float v = (jj < J && f < F) ? Hb[(int64_t)jj * F + f] : 0.f;
+    Bs[f * JCS + jj] = (__bf16)v;
+  }
+  __syncthreads();
+  const int s0 = idx * P.spi3;
+  const int ns = min(P.I, s0 + P.spi3) - s0;
+  const int nrg = (K + R - 1) / R;
+  const int myrg = nrg > wave ? (nrg - wave + 3) / 4 : 0;
+  const int nsteps = JC / 64;
+  const int total = myrg * ns * nsteps;
+  if (total == 0) return;   // (wave-uniform; the caller's barrier follows the item)
+
+  int l_rgc = 0, l_sl = 0, l_kb = 0;
+  const __bf16* l_row[MT];
+  bool l_ok[MT];
+  auto set_rows = [&]() {
+    const int rg = wave + 4 * l_rgc;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int k = rg * R + mt * 16 + n;
+      l_ok[mt] = k < K;
+      l_row[mt] = P.Xt + ((int64_t)(s0 + l_sl) * K + (l_ok[mt] ? k : 0)) * Jp + 16 * g;
+    }
+  };
+  set_rows();
+  bf16x8 xv[U][2][MT];
+  auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (l_ok[mt] && l_kb + 16 * g + 8 * h < Jp) {
+          dst[h][mt] = *reinterpret_cast<const bf16x8*>(l_row[mt] + l_kb + 8 * h);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
+        }
+      }
+    l_kb += 64;
+    if (l_kb >= Jp) {
+      l_kb = 0;
+      if (++l_sl == ns) {
+        l_sl = 0;
+        ++l_rgc;
+      }
+      if (l_rgc < myrg) set_rows();
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (u < total) load_next(xv[u]);
+
+  f32x4 acc[MT][FT], tot[MT][FT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+      acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+      tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  int c_step = 0, c_sl = 0, c_rgc = 0;
+  const __bf16* bb = Bs + n * JCS + 16 * g;
+  for (int s = 0; s < total; s += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int sidx = s + u;
+      if (sidx < total) {
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) {
+          const __bf16* bp = bb + ft * 16 * JCS + c_step * 64;
+          const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(bp);
+          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(bp + 8);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], b0, acc[mt][ft]);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], b1, acc[mt][ft]);
+        }
+        if (sidx + U < total) load_next(xv[u]);
+        if (++c_step == nsteps) {
+          // end of a slab: scale by s_i * H1[i, f] and accumulate
+          const int i = s0 + c_sl;
+          const float sc = P.scale[i];
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft) {
+            const int f = ft * 16 + n;
+            const float coef = (f < F) ? sc * Ha[(int64_t)i * F + f] : 0.f;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+              for (int ii = 0; ii < 4; ++ii) tot[mt][ft][ii] += coef * acc[mt][ft][ii];
+              acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+          }
+          c_step = 0;
+          if (++c_sl == ns) {
+            // end of a row group: write this item's partial rows
+            const int rg = wave + 4 * c_rgc;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+              for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) {
+                  const int k = rg * R + mt * 16 + 4 * g + ii;
+                  const int f = ft * 16 + n;
+                  if (k < K && f < F) P.W3p[((int64_t)idx * K + k) * F + f] = tot[mt][ft][ii];
+                }
+                tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+              }
+            c_sl = 0;
+            ++c_rgc;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- mode-2 item
+
+// W2 rows j0 .. j0+63: one thread per (j, f), summing over all slabs i in
+// order (FP64), reads of T coalesced over the contiguous (j, f) index.
+__device__ __forceinline__ void m2_item(const BProb& P, int idx) {
+  const int I = P.I, J = P.J, F = P.F;
+  const int j0 = idx * 64;
+  const int E = min(64, J - j0) * F;
+  const int64_t JF = (int64_t)J * F;
+  const float* __restrict__ A = P.H[0];
+  const float* __restrict__ Tb = P.T + (int64_t)j0 * F;
+  for (int e = threadIdx.x; e < E; e += 256) {
+    const int f = e % F;
+    double s = 0.0;
+    int i = 0;
+    for (; i + 4 <= I; i += 4) {
+      float t[4], a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        t[q] = Tb[(int64_t)(i + q) * JF + e];
+        a[q] = A[(int64_t)(i + q) * F + f];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += (double)a[q] * (double)t[q];
+    }
+    for (; i < I; ++i) s += (double)A[(int64_t)i * F + f] * (double)Tb[(int64_t)i * JF + e];
+    P.W[1][(int64_t)j0 * F + e] = s;
+  }
+}
+
+// ---------------------------------------------------------------- ADMM items
+
+template <int FL>
+__device__ __forceinline__ void inner_item(const BProb& P, const BatchK& a, int m, int idx,
+                                           unsigned char* lds) {
+  InnerK k;
+  if (m == 2) {   // W3 = the pass-3 partials, summed in item order per element
+    k.part = P.W3p;
+    k.part_f64 = 0;
+    k.pstride = (int64_t)P.K * P.F;
+    k.nparts = P.n_p3;
+  } else {
+    k.part = P.W[m];
+    k.part_f64 = 1;
+    k.pstride = 0;
+    k.nparts = 1;
+  }
+  k.rowstride = P.F;
+  k.Wout = nullptr;
+  k.H = P.H[m];
+  k.U = P.U[m];
+  k.Pout = nullptr;
+  k.rows = (m == 0) ? P.I : (m == 1) ? P.J : P.K;
+  k.F = P.F;
+  k.Linv = P.Linv;
+  k.rho = P.rho + 2 * m;
+  k.rescale = a.rescale;
+  k.T = a.T;
+  k.eps_abs = a.eps_abs;
+  k.eps_rel = a.eps_rel;
+  k.iters_out = nullptr;
+  k.gram_from_primal = 0;
+  k.gram_f32 = 1;
+  k.gram_part = P.gpart;
+  k.resid_part = nullptr;
+  k.flag = a.flag;
+  inner_body<float, FL, 1, 4, 1>(k, idx, lds);
+}
+
+template <int NB>
+__device__ __forceinline__ void prep_item(const BProb& P, const BatchK& a, int m,
+                                          unsigned char* lds) {
+  PrepK k{};
+  k.F = P.F;
+  k.gram_part = nullptr;
+  k.gram_a = P.gram[m == 0 ? 1 : 0];
+  k.gram_b = P.gram[m == 2 ? 1 : 2];
+  k.policy = a.policy;
+  k.rho0 = a.rho0;
+  k.rho_state = P.rho + 2 * m;
+  k.Linv = P.Linv;
+  k.flag = a.flag;
+  prep_body<NB>(k, reinterpret_cast<double*>(lds));
+}
+
+// One function per item family, each loading the fields of the problem's
+// descriptor it uses (read-only for the launch: through the constant address
+// space, into scalar registers), so no descriptor field stays live across
+// the families.
+typedef __attribute__((address_space(4))) const BProb ConstProb;
+static __device__ __forceinline__ BProb load_prob(const BProb* probs, int p) {
+  static_assert(sizeof(BProb) % 4 == 0, "descriptor must be whole words");
+  typedef __attribute__((address_space(4))) const unsigned ConstWord;
+  ConstWord* src = (ConstWord*)(probs + p);
+  BProb out;
+  unsigned* dst = reinterpret_cast<unsigned*>(&out);
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(BProb) / 4); ++q) dst[q] = src[q];
+  return out;
+}
+
+__device__ __forceinline__ void run_p1(const BProb* probs, int p, int idx,
+                                                 unsigned char* lds) {
+  const BProb P = load_prob(probs, p);
+  switch (P.FT * 4 + P.mt1) {
+    case 1 * 4 + 1: p1_item<1, 1>(P, idx, lds); break;
+    case 1 * 4 + 2: p1_item<1, 2>(P, idx, lds); break;
+    case 2 * 4 + 1: p1_item<2, 1>(P, idx, lds); break;
+    case 2 * 4 + 2: p1_item<2, 2>(P, idx, lds); break;
+    case 3 * 4 + 1: p1_item<3, 1>(P, idx, lds); break;
+    case 3 * 4 + 2: p1_item<3, 2>(P, idx, lds); break;
+    case 4 * 4 + 1: p1_item<4, 1>(P, idx, lds); break;
+    default: p1_item<4, 2>(P, idx, lds); break;
+  }
+}
+
+__device__ __forceinline__ void run_p3(const BProb* probs, int p, int idx,
+                                                 unsigned char* lds) {
+  const BProb P = load_prob(probs, p);
+  switch (P.FT * 4 + P.mt3) {
+    case 1 * 4 + 1: p3_item<1, 1>(P, idx, lds); break;
+    case 1 * 4 + 2: p3_item<1, 2>(P, idx, lds); break;
+    case 2 * 4 + 1: p3_item<2, 1>(P, idx, lds); break;
+    case 2 * 4 + 2: p3_item<2, 2>(P, idx, lds); break;
+    case 3 * 4 + 1: p3_item<3, 1>(P, idx, lds); break;
+    case 3 * 4 + 2: p3_item<3, 2>(P, idx, lds); break;
+    case 4 * 4 + 1: p3_item<4, 1>(P, idx, lds); break;
+    default: p3_item<4, 2>(P, idx, lds); break;
+  }
+}
+
+__device__ __forceinline__ void run_m2(const BProb* probs, int p, int idx) {
+  const BProb P = load_prob(probs, p);
+  m2_item(P, idx);
+}
+
+__device__ __forceinline__ void run_inner(const BProb* probs, int p, const BatchK& a,
+                                                    int m, int idx, unsigned char* lds) {
+  const BProb P = load_prob(probs, p);
+  switch (P.FL) {
+    case 4: inner_item<4>(P, a, m, idx, lds); break;
+    case 8: inner_item<8>(P, a, m, idx, lds); break;
+    case 16: inner_item<16>(P, a, m, idx, lds); break;
+    case 32: inner_item<32>(P, a, m, idx, lds); break;
+    default: inner_item<64>(P, a, m, idx, lds); break;
+  }
+}
+
+__device__ __forceinline__ void run_prep(const BProb* probs, int p, const BatchK& a,
+                                                   int m, unsigned char* lds) {
+  const BProb P = load_prob(probs, p);
+  switch (P.NB) {
+    case 1: prep_item<1>(P, a, m, lds); break;
+    case 2: prep_item<2>(P, a, m, lds); break;
+    case 3: prep_item<3>(P, a, m, lds); break;
+    default: prep_item<4>(P, a, m, lds); break;
+  }
+}
+
+// Dependencies of an item kind: (kind, count that must be done) pairs.
+__device__ __forceinline__ int item_deps(int kind, const ConstProb* P, int (&dk)[2], int (&need)[2]) {
+  switch (kind) {
+    case BK_IN1: dk[0] = BK_P1; need[0] = P->n_p1; dk[1] = BK_PREP1; need[1] = 1; return 2;
+    case BK_PREP2: dk[0] = BK_IN1; need[0] = P->n_in[0]; return 1;
+    case BK_M2: dk[0] = BK_P1; need[0] = P->n_p1; dk[1] = BK_IN1; need[1] = P->n_in[0]; return 2;
+    case BK_IN2: dk[0] = BK_M2; need[0] = P->n_m2; dk[1] = BK_PREP2; need[1] = 1; return 2;
+    case BK_PREP3: dk[0] = BK_IN2; need[0] = P->n_in[1]; return 1;
+    case BK_P3: dk[0] = BK_IN2; need[0] = P->n_in[1]; return 1;
+    case BK_IN3: dk[0] = BK_P3; need[0] = P->n_p3; dk[1] = BK_PREP3; need[1] = 1; return 2;
+    default: return 0;
+  }
+}
+
+// Bounded wait: gives up (flag bit 8) after spin_limit polls, and at once
+// when an earlier wait of the launch has given up.
+__device__ __forceinline__ void wait_count(int* c, int need, const BatchK& a) {
+  long long spins = 0;
+  while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > a.spin_limit ||
+        (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8)) {
+      atomicOr(a.flag, 8);
+      break;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch(BatchK a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ unsigned s_ticket;
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) s_ticket = atomicAdd(a.head, 1u);
+    __syncthreads();
+    // (readfirstlane: the ticket is block-uniform, so the item, the problem
+    // descriptor and everything derived from them live in scalar registers)
+    const unsigned t = __builtin_amdgcn_readfirstlane(s_ticket);
+    __syncthreads();
+    if (t >= (unsigned)a.n_items) break;
+    const uint2 it = a.items[t];
+    const int p = __builtin_amdgcn_readfirstlane((int)it.x);
+    const int kind = __builtin_amdgcn_readfirstlane((int)(it.y >> 24));
+    const int idx = __builtin_amdgcn_readfirstlane((int)(it.y & 0xffffffu));
+    const ConstProb* P = (const ConstProb*)(a.probs) + p;
+    int* ctr = a.ctr + (int64_t)p * kCtrPerProb;
+    if (!a.nodeps) {
+      if (tid == 0) {
+        int dk[2], need[2];
+        const int nd = item_deps(kind, P, dk, need);
+        for (int q = 0; q < nd; ++q) wait_count(&ctr[dk[q]], need[q], a);
+      }
+      __syncthreads();
+      __threadfence();   // acquire: the producers' writes are visible to every wave
+    }
+    switch (kind) {
+      case BK_P1: run_p1(a.probs, p, idx, lds); break;
+      case BK_P3: run_p3(a.probs, p, idx, lds); break;
+      case BK_M2: run_m2(a.probs, p, idx); break;
+      case BK_PREP1: run_prep(a.probs, p, a, 0, lds); break;
+      case BK_PREP2: run_prep(a.probs, p, a, 1, lds); break;
+      case BK_PREP3: run_prep(a.probs, p, a, 2, lds); break;
+      default: {   // inner sweep of mode m; the last block of the mode forms its Gram
+        const int m = (kind == BK_IN1) ? 0 : (kind == BK_IN2) ? 1 : 2;
+        run_inner(a.probs, p, a, m, idx, lds);
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+          const int tk = atomicAdd(&ctr[kArriveIn + m], 1);
+          s_last = (tk == P->n_in[m] - 1) ? 1 : 0;
+        }
+        __syncthreads();
+        if (s_last) {
+          __threadfence();
+          const int F = P->F, nb = P->n_in[m];
+          const double* gp = P->gpart;
+          double* gm = P->gram[m];
+          for (int e = tid; e < F * F; e += 256) {
+            double s = 0.0;
+            for (int b = 0; b < nb; ++b) s += gp[(int64_t)b * F * F + e];
+            gm[e] = s;
+          }
+        }
+        break;
+      }
+    }
+    // release: every wave's writes of this item are visible before the count moves
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) atomicAdd(&ctr[kind], 1);
+  }
+}
+
+hipError_t launch_batch(const BatchK& k, int grid, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_batch,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(256), lds, s, k);
+  return hipGetLastError();
+}
+
+int batch_occupancy(size_t lds) {
+  if (hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess)
+    return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, 256, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+__global__ __launch_bounds__(256) void k_zero_ints(int* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s) {
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- set-up
+
+// One block per slab: the power-of-two scale (max|X[i]|/s_i in [1,2)), the
+// k-fastest copy [J][Kp] and, through 32 x 32 LDS tiles, the j-fastest copy
+// [K][Jp]; padding is zero.
+__global__ __launch_bounds__(256) void k_bquant(const float* __restrict__ X, int J, int K, int Kp,
+                                                int Jp, __bf16* __restrict__ Xr,
+                                                __bf16* __restrict__ Xt, float* __restrict__ scale) {
+  const int64_t i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float* Xi = X + i * J * K;
+  const int64_t n = (int64_t)J * K;
+  float m = 0.f;
+  for (int64_t t = tid; t < n; t += 256) m = fmaxf(m, fabsf(Xi[t]));
+  __shared__ float red[256];
+  __shared__ float tile[32][33];
+  red[tid] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  m = red[0];
+  float s = 1.f;
+  if (m > 0.f && isfinite(m)) {
+    int e;
+    (void)frexpf(m, &e);
+    s = ldexpf(1.f, e - 1);
+  }
+  if (tid == 0) scale[i] = s;
+  const float inv = 1.f / s;   // exact: s is a power of two
+  __bf16* Xri = Xr + i * J * Kp;
+  for (int64_t t = tid; t < (int64_t)J * Kp; t += 256) {
+    const int64_t j = t / Kp, k = t - j * Kp;
+    Xri[t] = (__bf16)((k < K) ? Xi[j * K + k] * inv : 0.f);
+  }
+  __bf16* Xti = Xt + i * K * Jp;
+  const int tr = tid >> 5, tc = tid & 31;
+  for (int j0 = 0; j0 < Jp; j0 += 32)
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + tr + 8 * q, k = k0 + tc;
+        tile[tr + 8 * q][tc] = (j < J && k < K) ? Xi[(int64_t)j * K + k] * inv : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + tr + 8 * q, j = j0 + tc;
+        if (k < K) Xti[(int64_t)k * Jp + j] = (__bf16)tile[tc][tr + 8 * q];
+      }
+    }
+}
+
+hipError_t launch_batch_quantize(const float* X, int I, int J, int K, int Kp, int Jp, __bf16* Xr,
+                                 __bf16* Xt, float* scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_bquant, dim3(I), dim3(256), 0, s, X, J, K, Kp, Jp, Xr, Xt, scale);
+  return hipGetLastError();
+}
+
+}  // namespace ntf

@@ -61,7 +61,9 @@ def _c_sizeof(struct_name):
 
 
 @pytest.mark.parametrize("cname,pyname", [("ntf_problem", "Problem"), ("ntf_opts", "Opts"),
-                                          ("ntf_stats", "Stats")])
+                                          ("ntf_stats", "Stats"), ("ntf_mlp", "Mlp"),
+                                          ("ntf_batch_tile", "BatchTile"),
+                                          ("ntf_batch_info", "BatchInfo")])
 def test_struct_layouts_match(cname, pyname):
     from paper_1409_2383_amd import _lib
     assert _c_sizeof(cname) == ctypes.sizeof(getattr(_lib, pyname))

@@ -333,3 +333,48 @@ def test_slab_quantisation_against_torch_bfloat16():
         assert math.log2(s[i]) == int(math.log2(s[i]))
         ref = torch.from_numpy(X[i] / np.float32(s[i])).to(torch.bfloat16).to(torch.float64).numpy()
         np.testing.assert_array_equal(Xq[i], ref)
+
+
+def test_mixed_mttkrp_reduces_to_exact_on_bfloat16_values():
+    # With every operand that the recipe rounds already a bfloat16 value (X a
+    # small-integer tensor, the rounded factors multiples of 1/8 in [0, 2]),
+    # the mixed-precision MTTKRP is the exact one.  The factor that the
+    # factored mode-3 form keeps in float32 (A) is left arbitrary: rounding it
+    # by mistake would move the result by ~1e-3.
+    rng = np.random.default_rng(121)
+    I, J, K, F = 6, 5, 7, 3
+    X = rng.integers(0, 9, (I, J, K)).astype(np.float32)
+    A = rng.random((I, F)).astype(np.float32).astype(np.float64)
+    B = (rng.integers(0, 17, (J, F)) / 8.0)
+    C = (rng.integers(0, 17, (K, F)) / 8.0)
+    fac = [A, B, C]
+    X64 = X.astype(np.float64)
+    for n in (0, 1):
+        for m3 in ("kr", "factored"):
+            np.testing.assert_allclose(orc.mttkrp_mixed(X, fac, n, mode3=m3), orc.mttkrp(X64, fac, n),
+                                       rtol=1e-14, atol=0)
+    np.testing.assert_allclose(orc.mttkrp_mixed(X, fac, 2, mode3="factored"), orc.mttkrp(X64, fac, 2),
+                               rtol=1e-14, atol=0)
+    # the Khatri-Rao form rounds the products A[i,f] B[j,f]: not exact here
+    kr = orc.mttkrp_mixed(X, fac, 2, mode3="kr")
+    assert np.max(np.abs(kr - orc.mttkrp(X64, fac, 2))) > 1e-6 * np.max(np.abs(kr))
+
+
+def test_mixed_mttkrp_factored_brute_force():
+    # the factored mode-3 rounding written out element by element
+    rng = np.random.default_rng(122)
+    I, J, K, F = 3, 4, 5, 2
+    X = (rng.random((I, J, K)) * 3.0).astype(np.float32)
+    A, B, C = (rng.random((d, F)) for d in (I, J, K))
+    Xq, s = orc.quantize_slabs_bf16(X)
+    Bb = orc._round_bf16(B.astype(np.float32)).astype(np.float64)
+    A32 = A.astype(np.float32).astype(np.float64)
+    W = np.zeros((K, F))
+    for k in range(K):
+        for f in range(F):
+            tot = 0.0
+            for i in range(I):
+                inner = sum(Xq[i, j, k] * Bb[j, f] for j in range(J))
+                tot += s[i] * A32[i, f] * inner
+            W[k, f] = tot
+    np.testing.assert_allclose(orc.mttkrp_mixed(X, [A, B, C], 2, mode3="factored"), W, rtol=1e-12)
