@@ -32,6 +32,9 @@ WORKLOADS = {
                arms=("fp32", "mixed")),
     "c3": dict(dims=(1000, 800, 600), F=64, dist="exponential", snr=30.0, clip=False, T=10,
                config=3, arms=("mixed", "fp32")),
+    # batched: n tensors, every mode uniform on [lo, hi], F uniform on 5..40
+    "c5": dict(n=256, lo=50, hi=500, ranks=tuple(range(5, 41)), dist="uniform", snr=20.0,
+               clip=False, T=10, config=5, arms=("mixed",)),
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -295,6 +298,135 @@ def summarize(args):
                       args.workload, arm, nb, cmd)
 
 
+def _gen_tensor(args):
+    import ntf_synth
+    dims, F, seed, snr = args
+    pt = ntf_synth.planted(dims, F, seed, snr_db=snr, dtype=np.float32)
+    H0 = ntf_synth.init_factors(dims, F, seed, dtype=np.float32)
+    return pt.X, H0
+
+
+def bench_batched(args):
+    """Batched workload: many planted tensors of uneven shapes factorised
+    together (one persistent kernel per outer iteration).  value = problem
+    outer iterations per second over the whole batch."""
+    import multiprocessing as mp
+    import torch
+    import ntf_synth
+    import paper_1409_2383_amd as ntf
+    ntf.library_path()
+    dev = torch.device("cuda:0")
+    wl = WORKLOADS[args.workload]
+    n = args.batch_n or wl["n"]
+    base = ntf_synth.config_seed(wl["config"])
+    shapes = ntf_synth.batch_shapes(n, base, wl["lo"], wl["hi"], wl["ranks"])
+    jobs = [(dims, F, ntf_synth.config_seed(wl["config"], t), wl["snr"]) for t, (dims, F) in enumerate(shapes)]
+    log(f"[bench] generating {n} tensors (modes {wl['lo']}..{wl['hi']}, F 5..40)")
+    t0 = time.perf_counter()
+    Xs, Hs = [], []
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for t, (X, H0) in enumerate(pool.imap(_gen_tensor, jobs, chunksize=1)):
+            Xs.append(torch.from_numpy(X).to(dev))
+            Hs.append([torch.from_numpy(h).to(dev) for h in H0])
+            if (t + 1) % 64 == 0:
+                log(f"[bench] {t + 1}/{n} tensors on the device ({time.perf_counter() - t0:.0f} s)")
+    T = wl["T"]
+    opts = ntf.AdmmOptions(inner_iters=T, precision=ntf.PREC_BF16_MIXED)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b = ntf.NtfBatch(Xs, Hs, opts=opts)
+    init_s = time.perf_counter() - t1
+    tiles = None
+    if not args.no_tune:
+        t1 = time.perf_counter()
+        tiles = b.autotune(reps=2)
+        log(f"[bench] autotuned {len(tiles)} buckets in {time.perf_counter() - t1:.1f} s")
+    info = b.info()
+    log(f"[bench] batch ready: {info}")
+    s = torch.cuda.current_stream()
+    b.step(args.warmup)
+    b.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    b.step(args.steps)
+    e1.record(s)
+    flags = b.sync()
+    ms = e0.elapsed_time(e1) / args.steps
+    # pass-only launches of the whole batch (the persistent kernel with one kind)
+    pass_ms = {}
+    for name, kind in (("pass1", b.KIND_PASS1), ("mode2", b.KIND_MODE2), ("pass3", b.KIND_PASS3)):
+        b.launch_kind(kind)
+        torch.cuda.synchronize()
+        e0.record(s)
+        for _ in range(args.pass_reps):
+            b.launch_kind(kind)
+        e1.record(s)
+        torch.cuda.synchronize()
+        pass_ms[name] = e0.elapsed_time(e1) / args.pass_reps
+    nbytes = {"pass1": info["x_bytes"] + info["t_bytes"], "mode2": info["t_bytes"],
+              "pass3": info["x_bytes"]}
+    gbs = {k: nbytes[k] / (pass_ms[k] * 1e-3) / 1e9 for k in pass_ms}
+    prof = b.profile()          # one more outer iteration, instrumented per item kind
+    fits = b.fit()
+    dom = max(("pass1", "pass3"), key=lambda k: pass_ms[k])
+    roofline = {"bound": "hbm", "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs[dom] / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_batch ({dom} items only)",
+                "algorithmic_bytes_per_launch": nbytes[dom], "avg_launch_ms": pass_ms[dom]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_batched(jobs, T, shapes)
+    b.close()
+    line = {
+        "metric": "NTF outer iters/s + MTTKRP GB/s (% HBM peak), mixed vs FP32 at rel fit 1e-4",
+        "value": n * 1e3 / ms, "unit": "problem_outer_iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"batch of {n} planted tensors, modes uniform {wl['lo']}-{wl['hi']}, "
+                               f"F uniform 5-40, {wl['snr']:.0f} dB, T={T}, BF16 MTTKRP",
+                   "n_tensors": n, "inner_iters": T},
+        "roofline": roofline, "cpu_baseline": cpu,
+        "batch": {"init_s": init_s, "info": info, "tiles": tiles, "pass_ms": pass_ms, "pass_gbs": gbs,
+                  "flags": flags, "rfe_after": {"min": float(fits.min()), "median": float(np.median(fits)),
+                                                "max": float(fits.max())},
+                  "outer_iters_done": args.warmup + args.steps + 1,
+                  "profile_one_iteration": prof},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_batched(jobs, T, shapes, min_seconds=10.0):
+    """The FP64 oracle on the host: one outer iteration per tensor over the
+    first tensors of the batch (regenerated from their seeds) until
+    min_seconds of oracle time have passed, scaled to the whole batch by
+    MTTKRP work (sum of I J K F)."""
+    from oracle import ntf_oracle as orc
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        cores = os.cpu_count() or 1
+    work = [d[0] * d[1] * d[2] * F for d, F in shapes]
+    done, used, dt = 0.0, 0, 0.0
+    for job in jobs:
+        X, H0 = _gen_tensor(job)
+        X64 = X.astype(np.float64)
+        st = orc.init_state([h.astype(np.float64) for h in H0])
+        t0 = time.perf_counter()
+        orc.outer_step(X64, st, orc.Opts(inner_iters=T))
+        dt += time.perf_counter() - t0
+        done += work[used]
+        used += 1
+        if dt >= min_seconds:
+            break
+    per_batch_iter = dt * sum(work) / done
+    return {"value": len(shapes) / per_batch_iter, "unit": "problem_outer_iters/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"1 outer iteration (T={T}) of the FP64 oracle on each of the first {used} tensors "
+                      f"({dt:.1f} s), scaled to all {len(shapes)} by sum(I J K F)",
+            "seconds_measured": dt}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +444,8 @@ def main():
                     help="summarise two rocprofv3 --pmc runs into profiles/ and exit")
     ap.add_argument("--write-kernel-stats", metavar="STATS_CSV",
                     help="summarise a rocprofv3 --kernel-trace --stats run into profiles/ and exit")
+    ap.add_argument("--batch-n", type=int, default=0, help="batched workload: number of tensors")
+    ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the autotuner")
     args = ap.parse_args()
     if args.write_traffic or args.write_kernel_stats:
         summarize(args)
@@ -321,6 +455,9 @@ def main():
               "'How the path would shard'); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c5":
+        bench_batched(args)
+        return
     import torch
     import ntf_synth
     import paper_1409_2383_amd as ntf

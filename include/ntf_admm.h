@@ -368,6 +368,13 @@ ntf_status ntf_batch_set_tiles(ntf_batch_ctx *ctx, const ntf_batch_tile *tiles, 
 /* The current tile choices (host out, up to cap entries). */
 ntf_status ntf_batch_get_tiles(ntf_batch_ctx *ctx, ntf_batch_tile *out, int32_t cap, int32_t *n_out);
 
+/* Runs one outer iteration (not from the graph) with per-item wall-clock
+ * timing and returns, per work-item kind (the order of items_by_kind), the
+ * summed microseconds blocks spent running items (busy_us), waiting for their
+ * dependencies (wait_us), and the item count; host arrays [9].  The
+ * iteration updates the factors like ntf_batch_step.  Synchronising. */
+ntf_status ntf_batch_profile(ntf_batch_ctx *ctx, double *busy_us, double *wait_us, int64_t *items);
+
 ntf_status ntf_batch_info_get(ntf_batch_ctx *ctx, ntf_batch_info *out);
 const char *ntf_batch_last_error(const ntf_batch_ctx *ctx);
 ntf_status ntf_batch_destroy(ntf_batch_ctx *ctx);

@@ -363,6 +363,16 @@ class NtfBatch:
                     "ntf_batch_get_tiles")
         return self._tiles_to_list(arr, nout.value)
 
+    KIND_NAMES = ("pass1", "prep1", "inner1", "prep2", "mode2", "inner2", "prep3", "pass3", "inner3")
+
+    def profile(self) -> dict:
+        """One instrumented outer iteration: per item kind, summed block time
+        busy and waiting (microseconds) and the item count."""
+        busy, wait, items = (ctypes.c_double * 9)(), (ctypes.c_double * 9)(), (ctypes.c_int64 * 9)()
+        self._check(_lib.lib().ntf_batch_profile(self._ctx, busy, wait, items), "ntf_batch_profile")
+        return {k: {"busy_us": busy[q], "wait_us": wait[q], "items": items[q]}
+                for q, k in enumerate(self.KIND_NAMES)}
+
     def info(self) -> dict:
         i = _lib.BatchInfo()
         self._check(_lib.lib().ntf_batch_info_get(self._ctx, ctypes.byref(i)), "ntf_batch_info_get")

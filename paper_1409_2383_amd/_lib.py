@@ -161,6 +161,7 @@ SIGNATURES = [
     ("ntf_batch_set_tiles", c_int32, [c_void_p, POINTER(BatchTile), c_int32]),
     ("ntf_batch_get_tiles", c_int32, [c_void_p, POINTER(BatchTile), c_int32, POINTER(c_int32)]),
     ("ntf_batch_info_get", c_int32, [c_void_p, POINTER(BatchInfo)]),
+    ("ntf_batch_profile", c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),
     ("ntf_batch_last_error", c_char_p, [c_void_p]),
     ("ntf_batch_destroy", c_int32, [c_void_p]),
 ]

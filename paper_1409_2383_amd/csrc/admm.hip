@@ -19,7 +19,7 @@ namespace ntf {
 template <typename HT, int FL>
 __global__ __launch_bounds__(256) void k_inner(InnerK a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  inner_body<HT, FL>(a, (int64_t)blockIdx.x, smem_raw);
+  inner_body<HT, FL>(a, (int64_t)blockIdx.x, smem_raw, (int)threadIdx.x);
 }
 
 template <typename HT, int FL>
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
     return;
   }
   __shared__ double prep_lds[kPrepLdsDoubles];
-  prep_body<NB>(a, prep_lds);
+  prep_body<NB>(a, prep_lds, tid);
 }
 
 hipError_t launch_prep(const PrepArgs& pa, int nblk, hipStream_t s) {

@@ -91,7 +91,8 @@ static constexpr int inner_rows_per_block() { return (256 / FL) * inner_rpl<FL>(
 // a smaller register footprint: CH = mat-vec chunk, GF = 1 fixes the Gram
 // partial to FP32 (-1: a.gram_f32 decides at run time).
 template <typename HT, int FL, int RPL = inner_rpl<FL>(), int CH = 8, int GF = -1>
-__device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigned char* smem_raw) {
+__device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigned char* smem_raw,
+                                           const int tid) {
   constexpr int NG = 256 / FL;             // lane groups per block
   constexpr int RPB = NG * RPL;            // rows per block
   constexpr int BS = FL + 1;               // padded row stride of the exchange buffers
@@ -101,7 +102,6 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
   double* xb = LTs + FL * FL;                         // [RPB][BS] exchange (b, then y)
   __shared__ double red[4][8];
 
-  const int tid = threadIdx.x;
   const int grp = tid / FL, f = tid - grp * FL;
   const int64_t row0 = bid * RPB;
 
@@ -343,9 +343,8 @@ constexpr int kPrepLdsDoubles = 64 * 65 + 256 + 128 + 256 + 2;
 // holds kPrepLdsDoubles doubles.  Also called per work item by the batched
 // persistent kernel.
 template <int NB>
-__device__ __forceinline__ void prep_body(const PrepK& a, double* lds) {
+__device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int tid) {
   const int F = a.F;
-  const int tid = threadIdx.x;
   double* Gs = lds;                                   // [64][65]
   double (*rowbuf)[128] = reinterpret_cast<double (*)[128]>(lds + 64 * 65);
   double (*colbuf)[64] = reinterpret_cast<double (*)[64]>(lds + 64 * 65 + 256);

@@ -68,6 +68,7 @@ struct BatchK {
   int policy;            // 0 trace, 1 fixed
   double rho0;
   long long spin_limit;  // polls before a wait gives up (flag bit 8)
+  unsigned long long* prof;  // null, or [BK_NKINDS][3]: wall-clock ticks busy, waiting, items
 };
 
 // LDS bytes a problem's items need.
@@ -78,6 +79,7 @@ int batch_inner_rows(int FL);      // inner-sweep rows per work item
 size_t batch_lds_prep();
 
 hipError_t launch_batch(const BatchK& k, int grid, size_t lds, hipStream_t s);
+constexpr int kProfWords = BK_NKINDS * 3;
 int batch_occupancy(size_t lds);   // resident blocks per CU at this LDS size (0 on error)
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s);
 // BF16 copies [I][J][Kp] and [I][K][Jp] of one FP32 problem with slab scales

@@ -39,6 +39,12 @@ namespace ntf {
 
 static __host__ __device__ __forceinline__ int rup_i(int x, int a) { return (x + a - 1) / a * a; }
 
+// Problem descriptors are read-only for a whole launch: the kernel reads them
+// through the constant address space (scalar loads into scalar registers),
+// by reference, never as a local copy (a copy indexed at run time would live
+// in scratch memory).
+typedef __attribute__((address_space(4))) const BProb ConstProb;
+
 size_t batch_lds_p1(const BProb& p) {
   const int FP = p.FT * 16, KCS = rup_i(p.Kp, 64) + 8;
   return (size_t)FP * KCS * 2 + (size_t)4 * p.spi1 * FP * 4;
@@ -66,11 +72,11 @@ size_t batch_lds_prep() { return (size_t)kPrepLdsDoubles * sizeof(double); }
 // MFMAs of the step take the first and second 8 (the contraction order
 // inside an instruction is free as long as both operands agree).
 template <int FT, int MT>
-__device__ __forceinline__ void p1_item(const BProb& P, int idx, unsigned char* lds) {
+__device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned char* lds, const int tid) {
   constexpr int FP = FT * 16;
   constexpr int R = 16 * MT;
   constexpr int U = 4;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+  const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
   const int J = P.J, K = P.K, F = P.F, Kp = P.Kp;
   const int KC = rup_i(Kp, 64), KCS = KC + 8;
   __bf16* Cs = reinterpret_cast<__bf16*>(lds);
@@ -225,11 +231,11 @@ __device__ __forceinline__ void p1_item(const BProb& P, int idx, unsigned char* 
 // scaled by s_i * H1[i,:] and added to the group's total, which is written
 // to this item's partial of W3 at the end.
 template <int FT, int MT>
-__device__ __forceinline__ void p3_item(const BProb& P, int idx, unsigned char* lds) {
+__device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned char* lds, const int tid) {
   constexpr int FP = FT * 16;
   constexpr int R = 16 * MT;
   constexpr int U = 4;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+  const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
   const int J = P.J, K = P.K, F = P.F, Jp = P.Jp;
   const int JC = rup_i(Jp, 64), JCS = JC + 8;
   __bf16* Bs = reinterpret_cast<__bf16*>(lds);
@@ -359,14 +365,14 @@ __device__ __forceinline__ void p3_item(const BProb& P, int idx, unsigned char* 
 
 // W2 rows j0 .. j0+63: one thread per (j, f), summing over all slabs i in
 // order (FP64), reads of T coalesced over the contiguous (j, f) index.
-__device__ __forceinline__ void m2_item(const BProb& P, int idx) {
+__device__ __forceinline__ void m2_item(const ConstProb& P, int idx, const int tid) {
   const int I = P.I, J = P.J, F = P.F;
   const int j0 = idx * 64;
   const int E = min(64, J - j0) * F;
   const int64_t JF = (int64_t)J * F;
   const float* __restrict__ A = P.H[0];
   const float* __restrict__ Tb = P.T + (int64_t)j0 * F;
-  for (int e = threadIdx.x; e < E; e += 256) {
+  for (int e = tid; e < E; e += 256) {
     const int f = e % F;
     double s = 0.0;
     int i = 0;
@@ -388,8 +394,8 @@ __device__ __forceinline__ void m2_item(const BProb& P, int idx) {
 // ---------------------------------------------------------------- ADMM items
 
 template <int FL>
-__device__ __forceinline__ void inner_item(const BProb& P, const BatchK& a, int m, int idx,
-                                           unsigned char* lds) {
+__device__ __forceinline__ void inner_item(const ConstProb& P, const BatchK& a, int m, int idx,
+                                           unsigned char* lds, const int tid) {
   InnerK k;
   if (m == 2) {   // W3 = the pass-3 partials, summed in item order per element
     k.part = P.W3p;
@@ -397,15 +403,16 @@ __device__ __forceinline__ void inner_item(const BProb& P, const BatchK& a, int 
     k.pstride = (int64_t)P.K * P.F;
     k.nparts = P.n_p3;
   } else {
-    k.part = P.W[m];
+    k.part = (m == 0) ? P.W[0] : P.W[1];
     k.part_f64 = 1;
     k.pstride = 0;
     k.nparts = 1;
   }
   k.rowstride = P.F;
   k.Wout = nullptr;
-  k.H = P.H[m];
-  k.U = P.U[m];
+  // (selects, not P.H[m]: a run-time index would put the descriptor in scratch)
+  k.H = (m == 0) ? P.H[0] : (m == 1) ? P.H[1] : P.H[2];
+  k.U = (m == 0) ? P.U[0] : (m == 1) ? P.U[1] : P.U[2];
   k.Pout = nullptr;
   k.rows = (m == 0) ? P.I : (m == 1) ? P.J : P.K;
   k.F = P.F;
@@ -421,96 +428,88 @@ __device__ __forceinline__ void inner_item(const BProb& P, const BatchK& a, int 
   k.gram_part = P.gpart;
   k.resid_part = nullptr;
   k.flag = a.flag;
-  inner_body<float, FL, 1, 4, 1>(k, idx, lds);
+  inner_body<float, FL, 1, 4, 1>(k, idx, lds, tid);
 }
 
 template <int NB>
-__device__ __forceinline__ void prep_item(const BProb& P, const BatchK& a, int m,
-                                          unsigned char* lds) {
+__device__ __forceinline__ void prep_item(const ConstProb& P, const BatchK& a, int m,
+                                          unsigned char* lds, const int tid) {
   PrepK k{};
   k.F = P.F;
   k.gram_part = nullptr;
-  k.gram_a = P.gram[m == 0 ? 1 : 0];
-  k.gram_b = P.gram[m == 2 ? 1 : 2];
+  k.gram_a = (m == 0) ? P.gram[1] : P.gram[0];
+  k.gram_b = (m == 2) ? P.gram[1] : P.gram[2];
   k.policy = a.policy;
   k.rho0 = a.rho0;
   k.rho_state = P.rho + 2 * m;
   k.Linv = P.Linv;
   k.flag = a.flag;
-  prep_body<NB>(k, reinterpret_cast<double*>(lds));
+  prep_body<NB>(k, reinterpret_cast<double*>(lds), tid);
 }
 
 // One function per item family, each loading the fields of the problem's
 // descriptor it uses (read-only for the launch: through the constant address
 // space, into scalar registers), so no descriptor field stays live across
 // the families.
-typedef __attribute__((address_space(4))) const BProb ConstProb;
-static __device__ __forceinline__ BProb load_prob(const BProb* probs, int p) {
-  static_assert(sizeof(BProb) % 4 == 0, "descriptor must be whole words");
-  typedef __attribute__((address_space(4))) const unsigned ConstWord;
-  ConstWord* src = (ConstWord*)(probs + p);
-  BProb out;
-  unsigned* dst = reinterpret_cast<unsigned*>(&out);
-#pragma unroll
-  for (int q = 0; q < (int)(sizeof(BProb) / 4); ++q) dst[q] = src[q];
-  return out;
+static __device__ __forceinline__ const ConstProb& load_prob(const BProb* probs, int p) {
+  return ((const ConstProb*)probs)[p];
 }
 
 __device__ __forceinline__ void run_p1(const BProb* probs, int p, int idx,
-                                                 unsigned char* lds) {
-  const BProb P = load_prob(probs, p);
+                                                 unsigned char* lds, const int tid) {
+  const ConstProb& P = load_prob(probs, p);
   switch (P.FT * 4 + P.mt1) {
-    case 1 * 4 + 1: p1_item<1, 1>(P, idx, lds); break;
-    case 1 * 4 + 2: p1_item<1, 2>(P, idx, lds); break;
-    case 2 * 4 + 1: p1_item<2, 1>(P, idx, lds); break;
-    case 2 * 4 + 2: p1_item<2, 2>(P, idx, lds); break;
-    case 3 * 4 + 1: p1_item<3, 1>(P, idx, lds); break;
-    case 3 * 4 + 2: p1_item<3, 2>(P, idx, lds); break;
-    case 4 * 4 + 1: p1_item<4, 1>(P, idx, lds); break;
-    default: p1_item<4, 2>(P, idx, lds); break;
+    case 1 * 4 + 1: p1_item<1, 1>(P, idx, lds, tid); break;
+    case 1 * 4 + 2: p1_item<1, 2>(P, idx, lds, tid); break;
+    case 2 * 4 + 1: p1_item<2, 1>(P, idx, lds, tid); break;
+    case 2 * 4 + 2: p1_item<2, 2>(P, idx, lds, tid); break;
+    case 3 * 4 + 1: p1_item<3, 1>(P, idx, lds, tid); break;
+    case 3 * 4 + 2: p1_item<3, 2>(P, idx, lds, tid); break;
+    case 4 * 4 + 1: p1_item<4, 1>(P, idx, lds, tid); break;
+    default: p1_item<4, 2>(P, idx, lds, tid); break;
   }
 }
 
 __device__ __forceinline__ void run_p3(const BProb* probs, int p, int idx,
-                                                 unsigned char* lds) {
-  const BProb P = load_prob(probs, p);
+                                                 unsigned char* lds, const int tid) {
+  const ConstProb& P = load_prob(probs, p);
   switch (P.FT * 4 + P.mt3) {
-    case 1 * 4 + 1: p3_item<1, 1>(P, idx, lds); break;
-    case 1 * 4 + 2: p3_item<1, 2>(P, idx, lds); break;
-    case 2 * 4 + 1: p3_item<2, 1>(P, idx, lds); break;
-    case 2 * 4 + 2: p3_item<2, 2>(P, idx, lds); break;
-    case 3 * 4 + 1: p3_item<3, 1>(P, idx, lds); break;
-    case 3 * 4 + 2: p3_item<3, 2>(P, idx, lds); break;
-    case 4 * 4 + 1: p3_item<4, 1>(P, idx, lds); break;
-    default: p3_item<4, 2>(P, idx, lds); break;
+    case 1 * 4 + 1: p3_item<1, 1>(P, idx, lds, tid); break;
+    case 1 * 4 + 2: p3_item<1, 2>(P, idx, lds, tid); break;
+    case 2 * 4 + 1: p3_item<2, 1>(P, idx, lds, tid); break;
+    case 2 * 4 + 2: p3_item<2, 2>(P, idx, lds, tid); break;
+    case 3 * 4 + 1: p3_item<3, 1>(P, idx, lds, tid); break;
+    case 3 * 4 + 2: p3_item<3, 2>(P, idx, lds, tid); break;
+    case 4 * 4 + 1: p3_item<4, 1>(P, idx, lds, tid); break;
+    default: p3_item<4, 2>(P, idx, lds, tid); break;
   }
 }
 
-__device__ __forceinline__ void run_m2(const BProb* probs, int p, int idx) {
-  const BProb P = load_prob(probs, p);
-  m2_item(P, idx);
+__device__ __forceinline__ void run_m2(const BProb* probs, int p, int idx, const int tid) {
+  const ConstProb& P = load_prob(probs, p);
+  m2_item(P, idx, tid);
 }
 
 __device__ __forceinline__ void run_inner(const BProb* probs, int p, const BatchK& a,
-                                                    int m, int idx, unsigned char* lds) {
-  const BProb P = load_prob(probs, p);
+                                                    int m, int idx, unsigned char* lds, const int tid) {
+  const ConstProb& P = load_prob(probs, p);
   switch (P.FL) {
-    case 4: inner_item<4>(P, a, m, idx, lds); break;
-    case 8: inner_item<8>(P, a, m, idx, lds); break;
-    case 16: inner_item<16>(P, a, m, idx, lds); break;
-    case 32: inner_item<32>(P, a, m, idx, lds); break;
-    default: inner_item<64>(P, a, m, idx, lds); break;
+    case 4: inner_item<4>(P, a, m, idx, lds, tid); break;
+    case 8: inner_item<8>(P, a, m, idx, lds, tid); break;
+    case 16: inner_item<16>(P, a, m, idx, lds, tid); break;
+    case 32: inner_item<32>(P, a, m, idx, lds, tid); break;
+    default: inner_item<64>(P, a, m, idx, lds, tid); break;
   }
 }
 
 __device__ __forceinline__ void run_prep(const BProb* probs, int p, const BatchK& a,
-                                                   int m, unsigned char* lds) {
-  const BProb P = load_prob(probs, p);
+                                                   int m, unsigned char* lds, const int tid) {
+  const ConstProb& P = load_prob(probs, p);
   switch (P.NB) {
-    case 1: prep_item<1>(P, a, m, lds); break;
-    case 2: prep_item<2>(P, a, m, lds); break;
-    case 3: prep_item<3>(P, a, m, lds); break;
-    default: prep_item<4>(P, a, m, lds); break;
+    case 1: prep_item<1>(P, a, m, lds, tid); break;
+    case 2: prep_item<2>(P, a, m, lds, tid); break;
+    case 3: prep_item<3>(P, a, m, lds, tid); break;
+    default: prep_item<4>(P, a, m, lds, tid); break;
   }
 }
 
@@ -546,8 +545,13 @@ __global__ __launch_bounds__(256) void k_batch(BatchK a) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ unsigned s_ticket;
   __shared__ int s_last;
-  const int tid = threadIdx.x;
+  const int tid0 = threadIdx.x;
   for (;;) {
+    // The thread index, made opaque to the compiler once per item: it cannot
+    // hoist each item family's thread-index arithmetic out of this loop,
+    // where it would stay live across all the families.
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
     if (tid == 0) s_ticket = atomicAdd(a.head, 1u);
     __syncthreads();
     // (readfirstlane: the ticket is block-uniform, so the item, the problem
@@ -561,37 +565,46 @@ __global__ __launch_bounds__(256) void k_batch(BatchK a) {
     const int idx = __builtin_amdgcn_readfirstlane((int)(it.y & 0xffffffu));
     const ConstProb* P = (const ConstProb*)(a.probs) + p;
     int* ctr = a.ctr + (int64_t)p * kCtrPerProb;
+    const unsigned long long t_take = a.prof ? wall_clock64() : 0ull;
     if (!a.nodeps) {
-      if (tid == 0) {
-        int dk[2], need[2];
-        const int nd = item_deps(kind, P, dk, need);
-        for (int q = 0; q < nd; ++q) wait_count(&ctr[dk[q]], need[q], a);
+      int dk[2], need[2];
+      const int nd = item_deps(kind, P, dk, need);   // block-uniform
+      if (nd > 0) {
+        if (tid == 0) {
+          wait_count(&ctr[dk[0]], need[0], a);
+          if (nd > 1) wait_count(&ctr[dk[1]], need[1], a);
+          // acquire at agent scope, by one wave: invalidates this CU's L1 and
+          // the XCD's L2, so every wave of the block then reads the
+          // producers' data from memory
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      __threadfence();   // acquire: the producers' writes are visible to every wave
     }
+    const unsigned long long t_ready = a.prof ? wall_clock64() : 0ull;
     switch (kind) {
-      case BK_P1: run_p1(a.probs, p, idx, lds); break;
-      case BK_P3: run_p3(a.probs, p, idx, lds); break;
-      case BK_M2: run_m2(a.probs, p, idx); break;
-      case BK_PREP1: run_prep(a.probs, p, a, 0, lds); break;
-      case BK_PREP2: run_prep(a.probs, p, a, 1, lds); break;
-      case BK_PREP3: run_prep(a.probs, p, a, 2, lds); break;
+      case BK_P1: run_p1(a.probs, p, idx, lds, tid); break;
+      case BK_P3: run_p3(a.probs, p, idx, lds, tid); break;
+      case BK_M2: run_m2(a.probs, p, idx, tid); break;
+      case BK_PREP1: run_prep(a.probs, p, a, 0, lds, tid); break;
+      case BK_PREP2: run_prep(a.probs, p, a, 1, lds, tid); break;
+      case BK_PREP3: run_prep(a.probs, p, a, 2, lds, tid); break;
       default: {   // inner sweep of mode m; the last block of the mode forms its Gram
         const int m = (kind == BK_IN1) ? 0 : (kind == BK_IN2) ? 1 : 2;
-        run_inner(a.probs, p, a, m, idx, lds);
-        __threadfence();
+        run_inner(a.probs, p, a, m, idx, lds, tid);
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the L2
         __syncthreads();
         if (tid == 0) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // L2 written back
           const int tk = atomicAdd(&ctr[kArriveIn + m], 1);
-          s_last = (tk == P->n_in[m] - 1) ? 1 : 0;
+          s_last = (tk == ((m == 0) ? P->n_in[0] : (m == 1) ? P->n_in[1] : P->n_in[2]) - 1) ? 1 : 0;
+          if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (s_last) {
-          __threadfence();
-          const int F = P->F, nb = P->n_in[m];
+          const int F = P->F, nb = (m == 0) ? P->n_in[0] : (m == 1) ? P->n_in[1] : P->n_in[2];
           const double* gp = P->gpart;
-          double* gm = P->gram[m];
+          double* gm = (m == 0) ? P->gram[0] : (m == 1) ? P->gram[1] : P->gram[2];
           for (int e = tid; e < F * F; e += 256) {
             double s = 0.0;
             for (int b = 0; b < nb; ++b) s += gp[(int64_t)b * F * F + e];
@@ -601,10 +614,20 @@ __global__ __launch_bounds__(256) void k_batch(BatchK a) {
         break;
       }
     }
-    // release: every wave's writes of this item are visible before the count moves
-    __threadfence();
+    // release: every wave waits for its own stores to reach the L2, then one
+    // wave writes the L2 back (agent scope) before the count moves
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tid == 0) atomicAdd(&ctr[kind], 1);
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      atomicAdd(&ctr[kind], 1);
+      if (a.prof) {
+        const unsigned long long t_done = wall_clock64();
+        atomicAdd(&a.prof[kind * 3 + 0], t_done - t_ready);
+        atomicAdd(&a.prof[kind * 3 + 1], t_ready - t_take);
+        atomicAdd(&a.prof[kind * 3 + 2], 1ull);
+      }
+    }
   }
 }
 

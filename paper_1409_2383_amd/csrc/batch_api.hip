@@ -78,6 +78,7 @@ struct ntf_batch_ctx {
   int* flag = nullptr;
   double* fitpart = nullptr;
   double* fitout = nullptr;     // [n][2]
+  unsigned long long* prof = nullptr;   // [BK_NKINDS][3] profile counters
   int n_items = 0, n_kind[3] = {0, 0, 0};
   int64_t by_kind[BK_NKINDS] = {};
   int grid = 0;
@@ -198,7 +199,7 @@ static ntf_status validate(const ntf_problem* probs, int32_t n, const ntf_opts* 
 struct BatchLayout {
   std::vector<ProbLayout> probs;
   size_t dprobs = 0, items = 0, kind[3] = {0, 0, 0}, ctr = 0, flag = 0, fitpart = 0, fitout = 0,
-         total = 0;
+         prof = 0, total = 0;
   int64_t cap_main = 0, cap_kind[3] = {0, 0, 0};
 };
 
@@ -246,6 +247,7 @@ static BatchLayout make_layout(const ntf_problem* probs, int32_t n) {
   L.flag = take(4);
   L.fitpart = take((size_t)maxfit * 2 * 8);
   L.fitout = take((size_t)n * 2 * 8);
+  L.prof = take((size_t)kProfWords * 8);
   L.total = off;
   return L;
 }
@@ -333,6 +335,7 @@ static BatchK kargs(ntf_batch_ctx* c, const uint2* items, int n_items, int nodep
   k.policy = c->opts.rho_policy;
   k.rho0 = c->opts.rho0;
   k.spin_limit = kSpinLimit;
+  k.prof = nullptr;
   return k;
 }
 
@@ -429,6 +432,7 @@ ntf_status ntf_batch_init(ntf_batch_ctx** out, const ntf_problem* probs, int32_t
   c->flag = reinterpret_cast<int*>(c->ws + L.flag);
   c->fitpart = reinterpret_cast<double*>(c->ws + L.fitpart);
   c->fitout = reinterpret_cast<double*>(c->ws + L.fitout);
+  c->prof = reinterpret_cast<unsigned long long*>(c->ws + L.prof);
   ntf_status st = [&]() -> ntf_status {
     NTFB_HIP(c, hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking));
     c->hp.resize(n);
@@ -658,6 +662,31 @@ ntf_status ntf_batch_autotune(ntf_batch_ctx* c, int32_t reps, ntf_batch_tile* ou
   (void)hipEventDestroy(e1);
   if (result != NTF_OK) return result;
   return ntf_batch_get_tiles(c, out, cap, n_out);
+}
+
+ntf_status ntf_batch_profile(ntf_batch_ctx* c, double* busy_us, double* wait_us, int64_t* items) {
+  if (!c || !busy_us || !wait_us || !items) return NTF_E_INVAL;
+  int dev = 0, khz = 0;
+  NTFB_HIP(c, hipGetDevice(&dev));
+  NTFB_HIP(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) {
+    c->err = "device reports no wall-clock rate";
+    return NTF_E_UNSUPPORTED;
+  }
+  NTFB_HIP(c, launch_zero_ints(reinterpret_cast<int*>(c->prof), 2 * kProfWords, c->s0));
+  NTFB_HIP(c, launch_zero_ints(c->ctr, (int64_t)c->n * kCtrPerProb + 1, c->s0));
+  BatchK k = kargs(c, c->ditems, c->n_items, 0);
+  k.prof = c->prof;
+  NTFB_HIP(c, launch_batch(k, c->grid, c->lds, c->s0));
+  unsigned long long h[kProfWords];
+  NTFB_HIP(c, hipMemcpyAsync(h, c->prof, sizeof(h), hipMemcpyDeviceToHost, c->s0));
+  NTFB_HIP(c, hipStreamSynchronize(c->s0));
+  for (int q = 0; q < BK_NKINDS; ++q) {
+    busy_us[q] = 1e3 * (double)h[3 * q] / khz;
+    wait_us[q] = 1e3 * (double)h[3 * q + 1] / khz;
+    items[q] = (int64_t)h[3 * q + 2];
+  }
+  return NTF_OK;
 }
 
 ntf_status ntf_batch_info_get(ntf_batch_ctx* c, ntf_batch_info* out) {
