@@ -353,10 +353,14 @@ ntf_status ntf_batch_mttkrp(ntf_batch_ctx *ctx, int32_t prob, int32_t mode, doub
  * for mode 3.  Leaves the factors unchanged.  For timing.  Stream-ordered. */
 ntf_status ntf_batch_launch_kind(ntf_batch_ctx *ctx, int32_t kind);
 
-/* Times `candidates` tile choices per bucket present in the batch (pass-only
- * launches, reps each, HIP events), keeps the fastest, rebuilds the work list
- * and re-captures the graph.  Writes the chosen tiles to out (host, up to cap
- * entries; *n_out = entries written).  Factors are unchanged.  Synchronising. */
+/* Autotuner: for each bucket present in the batch, in turn, times six tile
+ * choices (mt 1 or 2 x three item sizes) by launching the whole pass of that
+ * kind (all problems, the other buckets at their current tiles; one untimed
+ * and `reps` timed launches, HIP events), keeps the fastest, then rebuilds
+ * the work list and re-captures the graph.  The `us` of a tile is the whole
+ * pass time it was chosen with.  Writes the chosen tiles to out (host, up to
+ * cap entries; *n_out = entries written).  Factors are unchanged.
+ * Synchronising. */
 ntf_status ntf_batch_autotune(ntf_batch_ctx *ctx, int32_t reps, ntf_batch_tile *out, int32_t cap,
                               int32_t *n_out);
 

@@ -37,9 +37,10 @@ struct BProb {
   int spi1, spi3;        // slabs per pass-1 / pass-3 item
   int mt1, mt3;          // 16-row MFMA tiles per wave step in the two passes
   int n_p1, n_m2, n_p3;  // items per kind
-  int n_in[3];
-  int rpb;               // inner rows per block
-  int pad_;
+  int n_in[3];           // inner row blocks per mode (Gram partials)
+  int ni[3];             // inner items per mode (ipi row blocks each)
+  int rpb;               // inner rows per row block
+  int ipi;               // inner row blocks per item
   const __bf16* Xr;      // [I][J][Kp]  (k fastest, zero padded)
   const __bf16* Xt;      // [I][K][Jp]  (j fastest, zero padded)
   const float* scale;    // [I] power-of-two slab scales

@@ -85,6 +85,51 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
   float* w1p = reinterpret_cast<float*>(lds + (size_t)FP * KCS * 2);   // [4][ns][FP]
   const float* __restrict__ Hb = P.H[1];
   const float* __restrict__ Hc = P.H[2];
+  const int nrg = (J + R - 1) / R;
+  const int ntiles = ns * nrg;
+  const int myt = ntiles > wave ? (ntiles - wave + 3) / 4 : 0;
+  const int nsteps = KC / 64;
+  const int total = myt * nsteps;
+  int l_t = wave, l_kb = 0;
+  const __bf16* l_row[MT];
+  bool l_ok[MT];
+  auto set_rows = [&](int t) {
+    const int sl = t / nrg, rg = t - sl * nrg;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int j = rg * R + mt * 16 + n;
+      l_ok[mt] = j < J;
+      l_row[mt] = P.Xr + ((int64_t)(s0 + sl) * J + (l_ok[mt] ? j : 0)) * Kp + 16 * g;
+    }
+  };
+  bf16x8 xv[U][2][MT];
+  auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (l_ok[mt] && l_kb + 16 * g + 8 * h < Kp) {
+          dst[h][mt] = *reinterpret_cast<const bf16x8*>(l_row[mt] + l_kb + 8 * h);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
+        }
+      }
+    l_kb += 64;
+    if (l_kb >= Kp) {
+      l_kb = 0;
+      l_t += 4;
+      if (l_t < ntiles) set_rows(l_t);
+    }
+  };
+  // the first U steps of tensor loads go out before H3^T is staged, so the
+  // staging overlaps them
+  if (total > 0) {
+    set_rows(l_t);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < total) load_next(xv[u]);
+  }
   for (int e = tid; e < KC * FP; e += 256) {
     const int kk = e / FP, f = e - kk * FP;
     const float v = (kk < K && f < F) ? Hc[(int64_t)kk * F + f] : 0.f;
@@ -93,49 +138,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
   for (int e = tid; e < 4 * ns * FP; e += 256) w1p[e] = 0.f;
   __syncthreads();
 
-  const int nrg = (J + R - 1) / R;
-  const int ntiles = ns * nrg;
-  const int myt = ntiles > wave ? (ntiles - wave + 3) / 4 : 0;
-  const int nsteps = KC / 64;
-  const int total = myt * nsteps;
   if (total > 0) {
-    int l_t = wave, l_kb = 0;
-    const __bf16* l_row[MT];
-    bool l_ok[MT];
-    auto set_rows = [&](int t) {
-      const int sl = t / nrg, rg = t - sl * nrg;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int j = rg * R + mt * 16 + n;
-        l_ok[mt] = j < J;
-        l_row[mt] = P.Xr + ((int64_t)(s0 + sl) * J + (l_ok[mt] ? j : 0)) * Kp + 16 * g;
-      }
-    };
-    set_rows(l_t);
-    bf16x8 xv[U][2][MT];
-    auto load_next = [&](bf16x8 (&dst)[2][MT]) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          if (l_ok[mt] && l_kb + 16 * g + 8 * h < Kp) {
-            dst[h][mt] = *reinterpret_cast<const bf16x8*>(l_row[mt] + l_kb + 8 * h);
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
-          }
-        }
-      l_kb += 64;
-      if (l_kb >= Kp) {
-        l_kb = 0;
-        l_t += 4;
-        if (l_t < ntiles) set_rows(l_t);
-      }
-    };
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (u < total) load_next(xv[u]);
-
     f32x4 acc[MT][FT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -153,11 +156,28 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
     };
     int c_t = wave, c_step = 0;
     const __bf16* cb = Cs + n * KCS + 16 * g;
+    // H2 values of the current tile's epilogue, loaded when the tile starts
+    // so that their latency hides behind the tile's MFMA steps
+    float hbv[MT][FT][4];
+    auto load_hb = [&](int t) {
+      const int rg = t - (t / nrg) * nrg;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            const int j = rg * R + mt * 16 + 4 * g + ii;
+            const int f = ft * 16 + n;
+            hbv[mt][ft][ii] = (j < J && f < F) ? Hb[(int64_t)j * F + f] : 0.f;
+          }
+    };
     for (int s = 0; s < total; s += U) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int sidx = s + u;
         if (sidx < total) {
+          if (c_step == 0) load_hb(c_t);
 #pragma unroll
           for (int ft = 0; ft < FT; ++ft) {
             const __bf16* cp = cb + ft * 16 * KCS + c_step * 64;
@@ -193,7 +213,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
                   if (j < J && f < F) {
                     const float v = sc * acc[mt][ft][ii];
                     P.T[((int64_t)i * J + j) * F + f] = v;
-                    part[ft] += Hb[(int64_t)j * F + f] * v;
+                    part[ft] += hbv[mt][ft][ii] * v;
                   }
                 }
                 acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -241,19 +261,12 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
   __bf16* Bs = reinterpret_cast<__bf16*>(lds);
   const float* __restrict__ Ha = P.H[0];
   const float* __restrict__ Hb = P.H[1];
-  for (int e = tid; e < JC * FP; e += 256) {
-    const int jj = e / FP, f = e - jj * FP;
-    const float v = (jj < J && f < F) ? Hb[(int64_t)jj * F + f] : 0.f;
-    Bs[f * JCS + jj] = (__bf16)v;
-  }
-  __syncthreads();
   const int s0 = idx * P.spi3;
   const int ns = min(P.I, s0 + P.spi3) - s0;
   const int nrg = (K + R - 1) / R;
   const int myrg = nrg > wave ? (nrg - wave + 3) / 4 : 0;
   const int nsteps = JC / 64;
   const int total = myrg * ns * nsteps;
-  if (total == 0) return;   // (wave-uniform; the caller's barrier follows the item)
 
   int l_rgc = 0, l_sl = 0, l_kb = 0;
   const __bf16* l_row[MT];
@@ -267,7 +280,6 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
       l_row[mt] = P.Xt + ((int64_t)(s0 + l_sl) * K + (l_ok[mt] ? k : 0)) * Jp + 16 * g;
     }
   };
-  set_rows();
   bf16x8 xv[U][2][MT];
   auto load_next = [&](bf16x8 (&dst)[2][MT]) {
 #pragma unroll
@@ -291,9 +303,20 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
       if (l_rgc < myrg) set_rows();
     }
   };
+  // the first U steps of tensor loads go out before H2^T is staged
+  if (total > 0) {
+    set_rows();
 #pragma unroll
-  for (int u = 0; u < U; ++u)
-    if (u < total) load_next(xv[u]);
+    for (int u = 0; u < U; ++u)
+      if (u < total) load_next(xv[u]);
+  }
+  for (int e = tid; e < JC * FP; e += 256) {
+    const int jj = e / FP, f = e - jj * FP;
+    const float v = (jj < J && f < F) ? Hb[(int64_t)jj * F + f] : 0.f;
+    Bs[f * JCS + jj] = (__bf16)v;
+  }
+  __syncthreads();
+  if (total == 0) return;   // (wave-uniform; the caller's barrier follows the item)
 
   f32x4 acc[MT][FT], tot[MT][FT];
 #pragma unroll
@@ -428,7 +451,14 @@ __device__ __forceinline__ void inner_item(const ConstProb& P, const BatchK& a, 
   k.gram_part = P.gpart;
   k.resid_part = nullptr;
   k.flag = a.flag;
-  inner_body<float, FL, 1, 4, 1>(k, idx, lds, tid);
+  // ipi row blocks of 256 / FL rows; the barrier keeps one block's last LDS
+  // reads apart from the next block's first writes
+  const int nb = (m == 0) ? P.n_in[0] : (m == 1) ? P.n_in[1] : P.n_in[2];
+  const int b0 = idx * P.ipi, b1 = min(nb, b0 + P.ipi);
+  for (int bid = b0; bid < b1; ++bid) {
+    if (bid > b0) __syncthreads();
+    inner_body<float, FL, 1, 4, 1>(k, bid, lds, tid);
+  }
 }
 
 template <int NB>
@@ -517,11 +547,11 @@ __device__ __forceinline__ void run_prep(const BProb* probs, int p, const BatchK
 __device__ __forceinline__ int item_deps(int kind, const ConstProb* P, int (&dk)[2], int (&need)[2]) {
   switch (kind) {
     case BK_IN1: dk[0] = BK_P1; need[0] = P->n_p1; dk[1] = BK_PREP1; need[1] = 1; return 2;
-    case BK_PREP2: dk[0] = BK_IN1; need[0] = P->n_in[0]; return 1;
-    case BK_M2: dk[0] = BK_P1; need[0] = P->n_p1; dk[1] = BK_IN1; need[1] = P->n_in[0]; return 2;
+    case BK_PREP2: dk[0] = BK_IN1; need[0] = P->ni[0]; return 1;
+    case BK_M2: dk[0] = BK_P1; need[0] = P->n_p1; dk[1] = BK_IN1; need[1] = P->ni[0]; return 2;
     case BK_IN2: dk[0] = BK_M2; need[0] = P->n_m2; dk[1] = BK_PREP2; need[1] = 1; return 2;
-    case BK_PREP3: dk[0] = BK_IN2; need[0] = P->n_in[1]; return 1;
-    case BK_P3: dk[0] = BK_IN2; need[0] = P->n_in[1]; return 1;
+    case BK_PREP3: dk[0] = BK_IN2; need[0] = P->ni[1]; return 1;
+    case BK_P3: dk[0] = BK_IN2; need[0] = P->ni[1]; return 1;
     case BK_IN3: dk[0] = BK_P3; need[0] = P->n_p3; dk[1] = BK_PREP3; need[1] = 1; return 2;
     default: return 0;
   }
@@ -597,7 +627,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchK a) {
         if (tid == 0) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // L2 written back
           const int tk = atomicAdd(&ctr[kArriveIn + m], 1);
-          s_last = (tk == ((m == 0) ? P->n_in[0] : (m == 1) ? P->n_in[1] : P->n_in[2]) - 1) ? 1 : 0;
+          s_last = (tk == ((m == 0) ? P->ni[0] : (m == 1) ? P->ni[1] : P->ni[2]) - 1) ? 1 : 0;
           if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();

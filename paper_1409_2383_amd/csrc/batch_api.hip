@@ -26,6 +26,7 @@ namespace {
 constexpr int kMaxSpi1 = 16;          // pass-1 slabs per item (LDS for the W1 partials)
 constexpr int64_t kDefaultElems1 = 256 * 1024;
 constexpr int64_t kDefaultElems3 = 1024 * 1024;
+constexpr int kInnerRowsPerItem = 32;   // rows of one inner-sweep work item (at least one block)
 constexpr long long kSpinLimit = 1ll << 22;   // polls (>= 50 ns each) before a wait gives up
 constexpr size_t kLdsMax = 156 * 1024;   // dynamic LDS; the kernel also has ~2 KB static
 
@@ -121,7 +122,11 @@ static BProb base_prob(const ntf_problem& pr) {
   b.Jp = rup(b.J, 32);
   b.rpb = batch_inner_rows(b.FL);
   const int d[3] = {b.I, b.J, b.K};
-  for (int m = 0; m < 3; ++m) b.n_in[m] = (d[m] + b.rpb - 1) / b.rpb;
+  b.ipi = std::max(1, kInnerRowsPerItem / b.rpb);
+  for (int m = 0; m < 3; ++m) {
+    b.n_in[m] = (d[m] + b.rpb - 1) / b.rpb;
+    b.ni[m] = (b.n_in[m] + b.ipi - 1) / b.ipi;
+  }
   b.n_m2 = (b.J + 63) / 64;
   return b;
 }
@@ -281,13 +286,13 @@ static ntf_status build_lists(ntf_batch_ctx* c) {
   // every item depends only on kinds of earlier groups
   for (int p : order) add(L, p, BK_PREP1, 1);
   for (int p : order) add(L, p, BK_P1, c->hp[p].n_p1);
-  for (int p : order) add(L, p, BK_IN1, c->hp[p].n_in[0]);
+  for (int p : order) add(L, p, BK_IN1, c->hp[p].ni[0]);
   for (int p : order) add(L, p, BK_PREP2, 1);
   for (int p : order) add(L, p, BK_M2, c->hp[p].n_m2);
-  for (int p : order) add(L, p, BK_IN2, c->hp[p].n_in[1]);
+  for (int p : order) add(L, p, BK_IN2, c->hp[p].ni[1]);
   for (int p : order) add(L, p, BK_PREP3, 1);
   for (int p : order) add(L, p, BK_P3, c->hp[p].n_p3);
-  for (int p : order) add(L, p, BK_IN3, c->hp[p].n_in[2]);
+  for (int p : order) add(L, p, BK_IN3, c->hp[p].ni[2]);
   for (int p : order) add(L1, p, BK_P1, c->hp[p].n_p1);
   for (int p : order) add(L2, p, BK_M2, c->hp[p].n_m2);
   for (int p : order) add(L3, p, BK_P3, c->hp[p].n_p3);
@@ -605,6 +610,12 @@ ntf_status ntf_batch_autotune(ntf_batch_ctx* c, int32_t reps, ntf_batch_tile* ou
       for (const auto& kv : c->tiles) k.push_back(kv.first);
       return k;
     }();
+    std::vector<int> order(c->n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const BProb &x = c->hp[a], &y = c->hp[b];
+      return (int64_t)x.I * x.J * x.K > (int64_t)y.I * y.J * y.K;
+    });
     for (const TileKey& key : keys) {
       const int kind = std::get<0>(key);
       std::vector<int> members;
@@ -617,13 +628,19 @@ ntf_status ntf_batch_autotune(ntf_batch_ctx* c, int32_t reps, ntf_batch_tile* ou
       double best_us = 1e300;
       for (int mt = 1; mt <= 2; ++mt)
         for (int ei = 0; ei < 3; ++ei) {
+          // the candidate for this bucket, every other problem at its current
+          // tiles: the whole pass runs, so the time is the one that matters
+          // (a bucket on its own may not fill the GPU)
           const TileVal cand{mt, elems[ei], 0.0};
-          std::vector<uint2> L;
-          size_t lds = 0;
           for (int p : members) {
             BProb& b = c->hp[p];
             if (kind == 1) apply_tiles(b, cand, c->tiles[key_of(3, b)]);
             else apply_tiles(b, c->tiles[key_of(1, b)], cand);
+          }
+          std::vector<uint2> L;
+          size_t lds = 0;
+          for (int p : order) {
+            const BProb& b = c->hp[p];
             const int cnt = kind == 1 ? b.n_p1 : b.n_p3;
             for (int q = 0; q < cnt; ++q) L.push_back(item(p, kind == 1 ? BK_P1 : BK_P3, q));
             lds = std::max(lds, kind == 1 ? batch_lds_p1(b) : batch_lds_p3(b));
@@ -653,6 +670,10 @@ ntf_status ntf_batch_autotune(ntf_batch_ctx* c, int32_t reps, ntf_batch_tile* ou
           }
         }
       c->tiles[key] = best;
+      for (int p : members) {
+        BProb& b = c->hp[p];
+        apply_tiles(b, c->tiles[key_of(1, b)], c->tiles[key_of(3, b)]);
+      }
     }
     st = build_lists(c);
     if (st != NTF_OK) return st;
