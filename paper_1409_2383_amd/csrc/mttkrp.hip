@@ -23,6 +23,34 @@
 
 namespace ntf {
 
+// zeroed bfloat16 elements after H3^T in the streaming pass-1 LDS (a super
+// step of the last row may read up to 32 past it)
+constexpr int kPass1Tail = 64;
+
+// Raw buffer resources (stride 0, num_records in bytes): the fourth word for
+// gfx9-family parts, and a byte offset past any resource used here (a load
+// past num_records returns zeros).
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kBufferOOB = 0x7ffffff0;
+
+// Waves per SIMD the streaming pass-1 kernel is compiled for: four (two
+// blocks of 512 threads per CU, 128 VGPRs) while F <= 32, two at larger F
+// (its accumulators and prefetched epilogue values need more registers).
+template <int FT>
+static constexpr int kPass1Waves() { return FT <= 2 ? 4 : 2; }
+
+// A raw buffer resource over [p, p + bytes) whose words are read from the
+// first lane: the resource sits in scalar registers even where the compiler
+// cannot prove p wave-uniform (p must be wave-uniform).
+static __device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, int bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void* q = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                           kBufferWord3);
+}
+
 // ---------------------------------------------------------------- set-up
 
 // bfloat16 copies of X with a power-of-two scale per mode-1 slab:
@@ -368,7 +396,7 @@ __global__ __launch_bounds__(512) void k_pass1_bf16(const __bf16* __restrict__ X
 // epilogue of an item (T store and W1 partial) runs between two super steps
 // while the loads of the next item are already in flight.
 template <int FT, int MT>
-__global__ __launch_bounds__(512) void k_pass1_bf16s(const __bf16* __restrict__ Xr,
+__global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __bf16* __restrict__ Xr,
                                                      const float* __restrict__ scale, int I, int J,
                                                      int K, int Kp, int F,
                                                      const float* __restrict__ Hb,
@@ -377,15 +405,27 @@ __global__ __launch_bounds__(512) void k_pass1_bf16s(const __bf16* __restrict__ 
                                                      float* __restrict__ P1, int nch, int KC) {
   constexpr int FP = FT * 16;
   constexpr int R = 16 * MT;
-  constexpr int U = 4;
-  const int KCS = KC + 8;
+  constexpr int U = (FT <= 2) ? 3 : 4;
+  // Rows of H3^T are Kp + 8 long (not KC + 8): two blocks then fit a CU at
+  // F = 64, K = 600.  A super step past Kp reads the start of the next row (or
+  // the zeroed tail after the last row) against tensor operands that are zero
+  // there, so those products vanish.
+  const int KCS = Kp + 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __bf16* Cs = reinterpret_cast<__bf16*>(smem_raw);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
-  for (int idx = threadIdx.x; idx < KC * FP; idx += blockDim.x) {
+  // (wave index made uniform: the items, and the buffer resources derived from
+  // them, then live in scalar registers)
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = lane & 15, g = lane >> 4;
+  for (int idx = threadIdx.x; idx < Kp * FP; idx += blockDim.x) {
     const int kk = idx / FP, f = idx - kk * FP;
     const float v = (kk < K && f < F) ? Hc[(int64_t)kk * F + f] : 0.f;
     Cs[f * KCS + kk] = (__bf16)v;
+  }
+  for (int idx = threadIdx.x; idx < FP * 8 + kPass1Tail; idx += blockDim.x) {
+    // the 8 padding elements of every row, then the tail
+    const int e = (idx < FP * 8) ? (idx >> 3) * KCS + Kp + (idx & 7) : FP * KCS + (idx - FP * 8);
+    Cs[e] = (__bf16)0.f;
   }
   __syncthreads();
   const int64_t nitems = (int64_t)I * nch;
@@ -395,35 +435,36 @@ __global__ __launch_bounds__(512) void k_pass1_bf16s(const __bf16* __restrict__ 
   if (first >= nitems) return;
   const int64_t myitems = (nitems - first + stride - 1) / stride;
   const int nsteps = (Kp + 63) / 64;
-  const int64_t total = myitems * nsteps;
+  // (wave-uniform, and said so: the loop's branches then need no exec masks)
+  const int total = __builtin_amdgcn_readfirstlane((int)(myitems * nsteps));
 
   // load cursor
+  // Loads go through a buffer resource per slab: rows j >= J lie past the
+  // slab's num_records and lanes of a super step past Kp get an offset past
+  // it too, so the hardware returns zeros for both (no per-lane branches, and
+  // 32-bit offsets instead of 64-bit addresses).
   int64_t l_item = first;
   int l_kb = 0;
-  const __bf16* l_row[MT];
-  bool l_ok[MT];
+  const __bf16* l_slab = Xr;
+  int l_off[MT];
   auto set_rows = [&](int64_t item) {
     const int i = (int)(item / nch), ch = (int)(item - (int64_t)i * nch);
+    l_slab = Xr + (int64_t)i * J * Kp;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int j = ch * R + mt * 16 + n;
-      l_ok[mt] = j < J;
-      l_row[mt] = Xr + ((int64_t)i * J + (l_ok[mt] ? j : 0)) * Kp + 16 * g;
-    }
+    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((ch * R + mt * 16 + n) * Kp + 16 * g) * 2;
   };
   set_rows(l_item);
   bf16x8 xv[U][2][MT];
   auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+    const bool tail = l_kb + 64 > Kp;   // wave-uniform
+    const __amdgpu_buffer_rsrc_t l_rs = uniform_rsrc(l_slab, J * Kp * 2);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        if (l_ok[mt] && l_kb + 16 * g + 8 * h < Kp) {
-          dst[h][mt] = *reinterpret_cast<const bf16x8*>(l_row[mt] + l_kb + 8 * h);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
-        }
+        int off = l_off[mt] + (l_kb + 8 * h) * 2;
+        if (tail && l_kb + 16 * g + 8 * h >= Kp) off = kBufferOOB;
+        dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(l_rs, off, 0, 0));
       }
     l_kb += 64;
     if (l_kb >= Kp) {
@@ -444,11 +485,31 @@ __global__ __launch_bounds__(512) void k_pass1_bf16s(const __bf16* __restrict__ 
   int64_t c_item = first;
   int c_step = 0;
   const __bf16* cb = Cs + n * KCS + 16 * g;
+  // H2 values and T offsets of the current item's epilogue, computed when the
+  // item starts so the loads' latency hides behind its MFMA steps
+  const __amdgpu_buffer_rsrc_t hrs = uniform_rsrc(Hb, J * F * 4);
+  float hbv[MT][FT][4];
+  auto eoff = [&](int ch, int mt, int ft, int ii) {   // offset of (row, column) in a [J][F] slab
+    const int j = ch * R + mt * 16 + 4 * g + ii, f = ft * 16 + n;
+    return (f < F) ? (j * F + f) * 4 : kBufferOOB;
+  };
+  auto item_start = [&](int64_t item) {
+    const int ch = (int)(item - (item / nch) * nch);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+          hbv[mt][ft][ii] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(hrs, eoff(ch, mt, ft, ii), 0, 0));
+  };
   for (int64_t s0 = 0; s0 < total; s0 += U) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t sidx = s0 + u;
       if (sidx < total) {
+        if (c_step == 0) item_start(c_item);
 #pragma unroll
         for (int ft = 0; ft < FT; ++ft) {
           const __bf16* cp = cb + ft * 16 * KCS + c_step * 64;
@@ -461,10 +522,14 @@ __global__ __launch_bounds__(512) void k_pass1_bf16s(const __bf16* __restrict__ 
         }
         if (sidx + U < total) load_next(xv[u]);
         if (++c_step == nsteps) {
-          // epilogue of item c_item
-          const int i = (int)(c_item / nch), ch = (int)(c_item - (int64_t)i * nch);
-          const int j0 = ch * R;
+          // epilogue of item c_item: T rows stored through a resource over
+          // slab i of T (rows j >= J and columns f >= F get an offset past it:
+          // the hardware drops those stores); H2 values were loaded at the
+          // item's first step (zeros at the same places)
+          const int i = (int)(c_item / nch);
+          const int ch = (int)(c_item - (int64_t)i * nch);
           const float sc = scale[i];
+          const __amdgpu_buffer_rsrc_t trs = uniform_rsrc(Tout + (int64_t)i * J * F, J * F * 4);
           float part[FT];
 #pragma unroll
           for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
@@ -474,13 +539,10 @@ __global__ __launch_bounds__(512) void k_pass1_bf16s(const __bf16* __restrict__ 
             for (int ft = 0; ft < FT; ++ft) {
 #pragma unroll
               for (int ii = 0; ii < 4; ++ii) {
-                const int j = j0 + mt * 16 + 4 * g + ii;
-                const int f = ft * 16 + n;
-                if (j < J && f < F) {
-                  const float v = sc * acc[mt][ft][ii];
-                  Tout[((int64_t)i * J + j) * F + f] = v;
-                  part[ft] += Hb[(int64_t)j * F + f] * v;
-                }
+                const float v = sc * acc[mt][ft][ii];
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), trs,
+                                                      eoff(ch, mt, ft, ii), 0, 0);
+                part[ft] += hbv[mt][ft][ii] * v;
               }
               acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
@@ -772,10 +834,17 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
     p.Kp = rup(p.K, 32);
     p.JG = cdiv(p.J, 8);
     p.Kp3 = rup(p.K, 16);
-    int64_t kc = rup(p.Kp, 64);
-    while ((size_t)p.FP * (kc + 8) * 2 > kLdsBudget) kc = rup(kc / 2, 64);
-    p.KC1 = (int)kc;
-    p.lds1 = (size_t)p.FP * (kc + 8) * 2;
+    const size_t stream_lds = (size_t)p.FP * (p.Kp + 8) * 2 + kPass1Tail * 2;
+    if (stream_lds <= kLdsBudget) {
+      // streaming form: all of H3^T in LDS, rows Kp + 8 long
+      p.KC1 = (int)rup(p.Kp, 64);
+      p.lds1 = stream_lds;
+    } else {
+      int64_t kc = rup(p.Kp, 64);
+      while ((size_t)p.FP * (kc + 8) * 2 > kLdsBudget) kc = rup(kc / 2, 64);
+      p.KC1 = (int)kc;
+      p.lds1 = (size_t)p.FP * (kc + 8) * 2;
+    }
   } else {
     const size_t es = elem_size(prec);
     int64_t kc = rup(p.K, 32);
@@ -784,6 +853,7 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
     p.lds1 = (size_t)p.FP * kc * es;
   }
   int occ = (int)std::min<size_t>(8, (160 * 1024) / std::max<size_t>(p.lds1 + 512, 1));
+  if (prec == PREC_BF16) occ = std::min(occ, p.FT <= 2 ? 2 : 1);   // register-bound (kPass1Waves)
   if (occ < 1) occ = 1;
   p.grid1 = (int)std::min<int64_t>(cdiv(p.ntiles1, 8), (int64_t)cus * occ);
   // mode 2 from T
@@ -867,7 +937,7 @@ static hipError_t pass1_mt(const Plan& p, const void* X, const void* Hb, const v
 template <int FT>
 static hipError_t pass1_bf16(const Plan& p, const __bf16* Xr, const float* scale, const void* Hb,
                              const void* Hc, void* Tout, void* P1, hipStream_t s) {
-  if (p.KC1 >= p.Kp) {
+  if (p.KC1 >= p.Kp && p.J * p.Kp * 2 < (int64_t)kBufferOOB) {   // slab addressable by one resource
     auto kern = k_pass1_bf16s<FT, 2>;
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds1);
