@@ -4,8 +4,8 @@
 // plus the standalone Gram and direct-fit kernels.
 //
 // One mode update (Section IV, eq. ADMM_NTF_ALS_C with eq. ADMoM_NTF) is
-//   prep:  G = Gram_a (*) Gram_b,  rho,  L = chol(G + rho I),  Linv = L^{-1}
-//   inner: per row, T times:  b = w + rho (h + u);  ht = Linv^T (Linv b);
+//   prep:  G = Gram_a (*) Gram_b,  rho,  L = chol(G + rho I),  Ginv = L^{-T} L^{-1}
+//   inner: per row, T times:  b = w + rho (h + u);  ht = Ginv b;
 //                             v = ht - u;  h = max(0, v);  u = h - v.
 // The system matrix is common to all rows (Appendix B), so it is factored
 // once per mode update; the rows are then independent.
@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_inner(InnerK a) {
 
 template <typename HT, int FL>
 static hipError_t inner_launch(const InnerK& k, int nblk, hipStream_t s) {
-  const size_t lds = (size_t)(2 * FL * FL + 2 * inner_rows_per_block<FL>() * (FL + 1)) * sizeof(double);
+  const size_t lds = (size_t)(FL * FL + 2 * inner_rows_per_block<FL>() * (FL + 1)) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_inner<HT, FL>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -66,7 +66,7 @@ hipError_t launch_inner(const InnerArgs& ia, int nblk, hipStream_t s) {
   k.Pout = ia.Pout;
   k.rows = ia.rows;
   k.F = ia.F;
-  k.Linv = ia.Linv;
+  k.Ginv = ia.Ginv;
   k.rho = ia.rho;
   k.rescale = ia.rescale;
   k.T = ia.T;
@@ -166,7 +166,7 @@ hipError_t launch_prep(const PrepArgs& pa, int nblk, hipStream_t s) {
   k.rho_state = pa.rho_state;
   k.resid_mode = pa.resid_mode;
   k.fresh_mode = pa.fresh_mode;
-  k.Linv = pa.Linv;
+  k.Ginv = pa.Ginv;
   k.G_out = pa.G_out;
   k.taken = pa.taken;
   k.flag = pa.flag;

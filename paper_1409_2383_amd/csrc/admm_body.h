@@ -11,12 +11,12 @@ namespace ntf {
 // Block of 256 threads.  A row of the factor lives on FL consecutive lanes
 // (FL = next power of two >= F, so a row never straddles a wave), and every
 // lane group carries RPL rows at once: lane f holds h_f, u_f, w_f of RPL rows
-// in FP64 registers for the whole sweep.  Both triangular applications are
-// lane-parallel mat-vecs against Linv (zero padded to FL x FL) in LDS, held
-// row-major and transposed so every step reads consecutive banks; each Linv
-// element read from LDS serves the RPL rows of the lane.  The right-hand
-// sides are exchanged through LDS (broadcast reads), two barriers per
-// inner iteration.
+// in FP64 registers for the whole sweep.  The solve with G + rho I is one
+// lane-parallel mat-vec against Ginv = (G + rho I)^{-1} = L^{-T} L^{-1}
+// (formed once per mode update from the Cholesky factor, symmetric, zero
+// padded to FL x FL) in LDS; each Ginv element read serves the RPL rows of
+// the lane.  The right-hand sides are exchanged through two alternating LDS
+// buffers (broadcast reads): one barrier per inner iteration.
 struct InnerK {
   const void* part;
   int part_f64;
@@ -28,7 +28,7 @@ struct InnerK {
   void* Pout;
   int64_t rows;
   int F;
-  const double* Linv;
+  const double* Ginv;          // (G + rho I)^{-1}, [F][F]
   const double* rho;
   int rescale, T;
   double eps_abs, eps_rel;
@@ -97,9 +97,8 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
   constexpr int RPB = NG * RPL;            // rows per block
   constexpr int BS = FL + 1;               // padded row stride of the exchange buffers
   const int F = a.F;
-  double* Ls = reinterpret_cast<double*>(smem_raw);   // Ls[g][f]  = Linv[g][f]
-  double* LTs = Ls + FL * FL;                         // LTs[g][f] = Linv[f][g]
-  double* xb = LTs + FL * FL;                         // [RPB][BS] exchange (b, then y)
+  double* Ms = reinterpret_cast<double*>(smem_raw);   // Ms[g][f] = Ginv[g][f] = Ginv[f][g]
+  double* xb = Ms + FL * FL;                          // [2][RPB][BS] right-hand sides
   __shared__ double red[4][8];
 
   const int grp = tid / FL, f = tid - grp * FL;
@@ -113,16 +112,12 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 256 * q;
       const int r = e / FL, c = e - r * FL;
-      lv[q] = (e < FL * FL && r < F && c < F) ? a.Linv[r * F + c] : 0.0;
+      lv[q] = (e < FL * FL && r < F && c < F) ? a.Ginv[r * F + c] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 256 * q;
-      if (e < FL * FL) {
-        const int r = e / FL, c = e - r * FL;
-        Ls[e] = lv[q];
-        LTs[c * FL + r] = lv[q];
-      }
+      if (e < FL * FL) Ms[e] = lv[q];
     }
   }
   const double rho = a.rho[0];
@@ -161,7 +156,6 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
   const bool early = (a.eps_abs > 0.0) || (a.eps_rel > 0.0);
   const double sqF = sqrt((double)F);
   __shared__ int any_active;
-  double* yb = xb + RPB * BS;   // second exchange buffer: b and y never share one
 
   for (int t = 0; t < a.T; ++t) {
     if (early) {
@@ -174,16 +168,14 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
       __syncthreads();
       if (!any_active) break;
     }
+    // iteration t writes buffer t & 1: a wave still reading the other one
+    // (iteration t - 1) is past the barrier before it is written again
+    double* bb = xb + (t & 1) * RPB * BS;
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) xb[(grp * RPL + q) * BS + f] = act[q] ? w[q] + rho * (h[q] + u[q]) : 0.0;
-    __syncthreads();
-    double y[RPL];
-    lane_matvec<FL, RPL, BS, CH>(LTs, xb + grp * RPL * BS, f, y);  // y = L^{-1} b
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) yb[(grp * RPL + q) * BS + f] = y[q];
+    for (int q = 0; q < RPL; ++q) bb[(grp * RPL + q) * BS + f] = act[q] ? w[q] + rho * (h[q] + u[q]) : 0.0;
     __syncthreads();
     double xn[RPL];
-    lane_matvec<FL, RPL, BS, CH>(Ls, yb + grp * RPL * BS, f, xn);  // x = L^{-T} y
+    lane_matvec<FL, RPL, BS, CH>(Ms, bb + grp * RPL * BS, f, xn);  // x = (G + rho I)^{-1} b
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       if (done[q]) continue;
@@ -247,7 +239,7 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
   }
   // Gram partial of this block's rows (of the stored factor values), rows in order
   {
-    double* hs = xb;  // [RPB][BS]
+    double* hs = xb;  // [RPB][BS]; the barrier after the sweep ends every read of xb
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const double src = a.gram_from_primal ? x[q] : h[q];
@@ -321,7 +313,7 @@ struct PrepK {
   double* rho_state;
   const double* resid_mode;
   int* fresh_mode;
-  double* Linv;
+  double* Ginv;
   double* G_out;
   int* taken;
   int* flag;
@@ -339,7 +331,8 @@ struct PrepK {
 constexpr int kPrepLdsDoubles = 64 * 65 + 256 + 128 + 256 + 2;
 
 // Second half of the prepare step, run by one block of 256 threads: G =
-// gram_a (*) gram_b, the penalty, and L^{-1} by one elimination sweep.  `lds`
+// gram_a (*) gram_b, the penalty, L^{-1} by one elimination sweep, and
+// Ginv = L^{-T} L^{-1} = (G + rho I)^{-1}.  `lds`
 // holds kPrepLdsDoubles doubles.  Also called per work item by the batched
 // persistent kernel.
 template <int NB>
@@ -479,12 +472,27 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
   }
   __syncthreads();
   const bool bad = bad_sh != 0;
+  // Ginv = L^{-T} L^{-1} = (G + rho I)^{-1}: L^{-1} (lower triangular) goes
+  // through LDS, where G is no longer needed, and every thread forms its
+  // elements as sums over k in increasing order
 #pragma unroll
   for (int ia = 0; ia < NB; ++ia)
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
       const int i = ti + 16 * ia, j = tj + 16 * ib;
-      if (i < F && j < F) a.Linv[i * F + j] = bad ? 0.0 : (j <= i ? rr[ia][ib] : 0.0);
+      if (i < F && j < F) Gs[i * 65 + j] = (j <= i) ? rr[ia][ib] : 0.0;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+      const int i = ti + 16 * ia, j = tj + 16 * ib;
+      if (i < F && j < F) {
+        double m = 0.0;
+        for (int k = (i > j ? i : j); k < F; ++k) m += Gs[k * 65 + i] * Gs[k * 65 + j];
+        a.Ginv[i * F + j] = bad ? 0.0 : m;
+      }
     }
   if (bad && tid == 0) atomicOr(a.flag, 2);
 

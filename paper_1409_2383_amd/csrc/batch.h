@@ -51,7 +51,7 @@ struct BProb {
   float* W3p;            // [n_p3][K][F] pass-3 partials
   double* gram[3];       // [F][F] Grams of the current factors
   double* gpart;         // [max n_in][F][F] inner-sweep Gram partials
-  double* Linv;          // [F][F]
+  double* Ginv;          // [F][F]
   double* rho;           // [3][2]: rho of the last update of each mode, and the one before
 };
 

@@ -58,7 +58,7 @@ size_t batch_lds_p3(const BProb& p) {
 // resident blocks per compute unit; latency is hidden by the other items.
 int batch_inner_rows(int FL) { return 256 / FL; }
 size_t batch_lds_inner(int FL) {
-  return (size_t)(2 * FL * FL + 2 * batch_inner_rows(FL) * (FL + 1)) * sizeof(double);
+  return (size_t)(FL * FL + 2 * batch_inner_rows(FL) * (FL + 1)) * sizeof(double);
 }
 size_t batch_lds_prep() { return (size_t)kPrepLdsDoubles * sizeof(double); }
 
@@ -439,7 +439,7 @@ __device__ __forceinline__ void inner_item(const ConstProb& P, const BatchK& a, 
   k.Pout = nullptr;
   k.rows = (m == 0) ? P.I : (m == 1) ? P.J : P.K;
   k.F = P.F;
-  k.Linv = P.Linv;
+  k.Ginv = P.Ginv;
   k.rho = P.rho + 2 * m;
   k.rescale = a.rescale;
   k.T = a.T;
@@ -472,7 +472,7 @@ __device__ __forceinline__ void prep_item(const ConstProb& P, const BatchK& a, i
   k.policy = a.policy;
   k.rho0 = a.rho0;
   k.rho_state = P.rho + 2 * m;
-  k.Linv = P.Linv;
+  k.Ginv = P.Ginv;
   k.flag = a.flag;
   prep_body<NB>(k, reinterpret_cast<double*>(lds), tid);
 }

@@ -56,7 +56,7 @@ int cus() {
 }
 
 struct ProbLayout {
-  size_t xr, xt, scale, T, W[3], W3p, gram[3], gpart, linv, rho, end;
+  size_t xr, xt, scale, T, W[3], W3p, gram[3], gpart, ginv, rho, end;
 };
 
 }  // namespace
@@ -231,7 +231,7 @@ static BatchLayout make_layout(const ntf_problem* probs, int32_t n) {
     for (int m = 0; m < 3; ++m) pl.gram[m] = take((size_t)(F * F) * 8);
     const int maxin = std::max({b.n_in[0], b.n_in[1], b.n_in[2]});
     pl.gpart = take((size_t)maxin * F * F * 8);
-    pl.linv = take((size_t)(F * F) * 8);
+    pl.ginv = take((size_t)(F * F) * 8);
     pl.rho = take(6 * 8);
     pl.end = off;
     L.probs.push_back(pl);
@@ -457,7 +457,7 @@ ntf_status ntf_batch_init(ntf_batch_ctx** out, const ntf_problem* probs, int32_t
       b.T = reinterpret_cast<float*>(c->ws + pl.T);
       b.W3p = reinterpret_cast<float*>(c->ws + pl.W3p);
       b.gpart = reinterpret_cast<double*>(c->ws + pl.gpart);
-      b.Linv = reinterpret_cast<double*>(c->ws + pl.linv);
+      b.Ginv = reinterpret_cast<double*>(c->ws + pl.ginv);
       b.rho = reinterpret_cast<double*>(c->ws + pl.rho);
       c->hp[p] = b;
       NTFB_HIP(c, launch_batch_quantize(reinterpret_cast<const float*>(pr.X), b.I, b.J, b.K, b.Kp,

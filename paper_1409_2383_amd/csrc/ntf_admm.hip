@@ -47,7 +47,7 @@ struct DevState {
 
 struct Layout {
   size_t state = 0, T = 0, P1 = 0, P2 = 0, P3 = 0, W[3] = {0, 0, 0}, prim[3] = {0, 0, 0},
-         gram[3] = {0, 0, 0}, linv[3] = {0, 0, 0}, gpart = 0, rpart = 0, sumsq = 0, fitpart = 0,
+         gram[3] = {0, 0, 0}, ginv[3] = {0, 0, 0}, gpart = 0, rpart = 0, sumsq = 0, fitpart = 0,
          xr = 0, xj8 = 0, scale = 0, wx = 0, wy = 0, wact = 0, wscale = 0, wG[3] = {0, 0, 0},
          total = 0;
 };
@@ -94,7 +94,7 @@ Layout make_layout(const Plan& p, const ntf_opts& o) {
     L.W[m] = c.take((size_t)(d[m] * F) * 8);
     L.prim[m] = (o.factor_source == 1) ? c.take((size_t)(d[m] * F) * es) : 0;
     L.gram[m] = c.take((size_t)(F * F) * 8);
-    L.linv[m] = c.take((size_t)(F * F) * 8);
+    L.ginv[m] = c.take((size_t)(F * F) * 8);
     if (p.nblk_inner[m] > maxblk) maxblk = p.nblk_inner[m];
   }
   L.gpart = c.take((size_t)maxblk * F * F * 8);
@@ -266,7 +266,7 @@ static void prep_args(ntf_admm_ctx* c, int m, PrepArgs& a) {
   a.rho_state = ds->rho[m];
   a.resid_mode = ds->resid[m];
   a.fresh_mode = &ds->fresh[m];
-  a.Linv = c->at<double>(c->lay.linv[m]);
+  a.Ginv = c->at<double>(c->lay.ginv[m]);
   a.G_out = c->warm_on ? c->at<double>(c->lay.wG[m]) : nullptr;
   a.taken = &ds->warm_taken[m];
   a.flag = &ds->flag;
@@ -294,7 +294,7 @@ static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
   a.rows = d[m];
   a.F = p.F;
   a.FL = p.FL;
-  a.Linv = c->at<double>(c->lay.linv[m]);
+  a.Ginv = c->at<double>(c->lay.ginv[m]);
   a.rho = ds->rho[m];
   a.rescale = (c->opts.rescale_dual_on_rho_change || c->opts.rho_policy == NTF_RHO_ADAPTIVE) ? 1 : 0;
   a.T = c->opts.inner_iters;
@@ -830,7 +830,7 @@ ntf_status ntf_gram(const void* H, int64_t rows, int32_t F, int32_t dtype, doubl
 
 namespace {
 struct InnerWs {
-  size_t state, ones, linv, gpart, rpart, total;
+  size_t state, ones, ginv, gpart, rpart, total;
 };
 InnerWs inner_ws(int64_t rows, int F) {
   int FL = 4;
@@ -841,7 +841,7 @@ InnerWs inner_ws(int64_t rows, int F) {
   InnerWs w;
   w.state = c.take(sizeof(DevState));
   w.ones = c.take((size_t)F * F * 8);
-  w.linv = c.take((size_t)F * F * 8);
+  w.ginv = c.take((size_t)F * F * 8);
   w.gpart = c.take((size_t)nblk * F * F * 8);
   w.rpart = c.take((size_t)nblk * 8 * 8);
   w.total = c.off;
@@ -876,7 +876,7 @@ ntf_status ntf_inner_update(const double* W, void* H, void* U, int64_t rows, int
   pa.policy = rho > 0 ? 1 : 0;
   pa.rho0 = rho > 0 ? rho : 1.0;
   pa.rho_state = ds->rho[0];
-  pa.Linv = reinterpret_cast<double*>(base + w.linv);
+  pa.Ginv = reinterpret_cast<double*>(base + w.ginv);
   pa.flag = &ds->flag;
   pa.counter = &ds->counter[0];
   if (launch_prep(pa, 1, s) != hipSuccess) return NTF_E_HIP;
@@ -895,7 +895,7 @@ ntf_status ntf_inner_update(const double* W, void* H, void* U, int64_t rows, int
   ia.rows = rows;
   ia.F = F;
   ia.FL = FL;
-  ia.Linv = pa.Linv;
+  ia.Ginv = pa.Ginv;
   ia.rho = ds->rho[0];
   ia.T = T;
   ia.eps_abs = eps_abs;
