@@ -180,6 +180,32 @@ class Opts:
     # paper): "exact", or bfloat16 operands as in mttkrp_mixed with mode 3 in
     # Khatri-Rao ("bf16_kr") or factored ("bf16_factored") form
     mttkrp_operands: str = "exact"
+    # per-mode set constraints (None: non-negativity on every factor)
+    constraints: Optional[tuple] = None
+
+
+@dataclass(frozen=True)
+class Constraint:
+    """Set constraint of one factor (Section IV-E; Section VI-D for pmf rows).
+
+    kind "nonneg": H >= 0 (eq. g_M_def, the default).
+    kind "box": lo <= H <= hi elementwise; the auxiliary update projects onto
+        the box instead of the non-negative orthant.
+    kind "pmf_rows": every row is a probability mass function: the auxiliary
+        update stays the non-negative projection while the primal update is
+        the least-squares step with the linear constraint that each row sums
+        to one.
+    kind "cardinality": H >= 0 with at most `card` non-zero entries in the
+        whole factor (eq. g_new_def); the auxiliary update keeps the `card`
+        largest positive entries of the matrix (ties by row-major index).
+    """
+    kind: str = "nonneg"
+    lo: float = 0.0
+    hi: float = math.inf
+    card: int = 0
+
+
+NONNEG = Constraint()
 
 
 @dataclass
@@ -228,6 +254,36 @@ def project_nonneg(V: np.ndarray) -> np.ndarray:
     return np.where(V > 0.0, V, 0.0)
 
 
+def project(V: np.ndarray, c: Constraint) -> np.ndarray:
+    """Projection onto the constraint set of the auxiliary variable (Section
+    IV-E: the only change a set constraint makes to the auxiliary update)."""
+    if c.kind in ("nonneg", "pmf_rows"):
+        return project_nonneg(V)
+    if c.kind == "box":
+        return np.minimum(np.maximum(V, c.lo), c.hi)
+    if c.kind == "cardinality":
+        P = project_nonneg(V)
+        flat = P.ravel()
+        order = np.argsort(-flat, kind="stable")          # descending, ties by index
+        keep = np.zeros(flat.size, dtype=bool)
+        keep[order[:c.card]] = True
+        return np.where(keep.reshape(P.shape) & (P > 0.0), P, 0.0)
+    raise ValueError(f"unknown constraint {c.kind!r}")
+
+
+def pmf_rows_ls(G: np.ndarray, rho: float, rhs: np.ndarray) -> np.ndarray:
+    """Least-squares step with each row of the result summing to one (Section
+    VI-D): min_x 1/2 x^T (G + rho I) x - rhs^T x  s.t.  1^T x = 1, row by row,
+    from its KKT system [[G + rho I, 1], [1^T, 0]] [x; lam] = [rhs; 1]."""
+    F = G.shape[0]
+    K = np.zeros((F + 1, F + 1))
+    K[:F, :F] = G + rho * np.eye(F)
+    K[:F, F] = 1.0
+    K[F, :F] = 1.0
+    R = np.concatenate([rhs, np.ones((rhs.shape[0], 1))], axis=1)
+    return np.linalg.solve(K, R.T).T[:, :F]
+
+
 def dual_update(Hn: np.ndarray, V: np.ndarray) -> np.ndarray:
     """U_new = U + H - Ht^T = H - V with V = Ht^T - U (eq. ADMoM_NTF, dual update
     in the scaled form U = -Y/rho)."""
@@ -235,7 +291,8 @@ def dual_update(Hn: np.ndarray, V: np.ndarray) -> np.ndarray:
 
 
 def inner_sweep(W: np.ndarray, H: np.ndarray, U: np.ndarray, G: np.ndarray, rho: float,
-                T: int, eps_abs: float = 0.0, eps_rel: float = 0.0):
+                T: int, eps_abs: float = 0.0, eps_rel: float = 0.0,
+                constraint: Constraint = NONNEG):
     """Run T inner ADMoM iterations on every row (rows are independent).
 
     Returns (H, U, Ht, info).  ``Ht`` is the last regularised-LS solution
@@ -250,6 +307,8 @@ def inner_sweep(W: np.ndarray, H: np.ndarray, U: np.ndarray, G: np.ndarray, rho:
     H = np.asarray(H, dtype=np.float64).copy()
     U = np.asarray(U, dtype=np.float64).copy()
     rows, F = W.shape
+    if constraint.kind == "cardinality" and (eps_abs > 0.0 or eps_rel > 0.0):
+        raise ValueError("the cardinality projection couples all rows: no row-wise early stop")
     M = G + rho * np.eye(F)
     L = np.linalg.cholesky(M)                       # lower, M = L L^T
     Ht = np.zeros_like(W)
@@ -263,9 +322,9 @@ def inner_sweep(W: np.ndarray, H: np.ndarray, U: np.ndarray, G: np.ndarray, rho:
             break
         Wa, Ha, Ua = W[idx], H[idx], U[idx]
         rhs = Wa + rho * (Ha + Ua)
-        Xt = regularised_ls(L, rhs)
+        Xt = pmf_rows_ls(G, rho, rhs) if constraint.kind == "pmf_rows" else regularised_ls(L, rhs)
         V = Xt - Ua
-        Hn = project_nonneg(V)
+        Hn = project(V, constraint)
         Un = dual_update(Hn, V)
         dH = Hn - Ha
         Ht[idx] = Xt
@@ -306,7 +365,9 @@ def mode_update(X: np.ndarray, st: State, n: int, opts: Opts) -> dict:
     if opts.rescale_dual_on_rho_change and rho != st.rho[n]:
         U = U * (st.rho[n] / rho)                   # keep Y = -rho U unchanged
     H_prev = st.H[n].copy()
-    H, U, Ht, info = inner_sweep(W, st.H[n], U, G, rho, opts.inner_iters, opts.eps_abs, opts.eps_rel)
+    cons = opts.constraints[n] if opts.constraints is not None else NONNEG
+    H, U, Ht, info = inner_sweep(W, st.H[n], U, G, rho, opts.inner_iters, opts.eps_abs, opts.eps_rel,
+                                 cons)
     st.H[n], st.U[n], st.P[n] = H, U, Ht
     st.rho[n] = rho
     # Section IV-C residuals of this mode update (matrix form)

@@ -483,17 +483,34 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
       if (i < F && j < F) Gs[i * 65 + j] = (j <= i) ? rr[ia][ib] : 0.0;
     }
   __syncthreads();
+  {
+    // k outermost: the NB x NB sums of a thread advance together (entries of
+    // L^{-1} above the diagonal are zero; rows/columns >= F are not read)
+    double m[NB][NB];
 #pragma unroll
-  for (int ia = 0; ia < NB; ++ia)
+    for (int ia = 0; ia < NB; ++ia)
 #pragma unroll
-    for (int ib = 0; ib < NB; ++ib) {
-      const int i = ti + 16 * ia, j = tj + 16 * ib;
-      if (i < F && j < F) {
-        double m = 0.0;
-        for (int k = (i > j ? i : j); k < F; ++k) m += Gs[k * 65 + i] * Gs[k * 65 + j];
-        a.Ginv[i * F + j] = bad ? 0.0 : m;
+      for (int ib = 0; ib < NB; ++ib) m[ia][ib] = 0.0;
+    for (int k = 0; k < F; ++k) {
+      double li[NB], lj[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        li[q] = (ti + 16 * q <= k) ? Gs[k * 65 + ti + 16 * q] : 0.0;
+        lj[q] = (tj + 16 * q <= k) ? Gs[k * 65 + tj + 16 * q] : 0.0;
       }
+#pragma unroll
+      for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) m[ia][ib] += li[ia] * lj[ib];
     }
+#pragma unroll
+    for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        const int i = ti + 16 * ia, j = tj + 16 * ib;
+        if (i < F && j < F) a.Ginv[i * F + j] = bad ? 0.0 : m[ia][ib];
+      }
+  }
   if (bad && tid == 0) atomicOr(a.flag, 2);
 
   // optional cheap fit terms: <W3, H3> and sum(G1 * G2 * G3)
