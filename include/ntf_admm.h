@@ -273,6 +273,34 @@ size_t ntf_gram_workspace_bytes(int64_t rows, int32_t F);
 ntf_status ntf_gram(const void *H, int64_t rows, int32_t F, int32_t dtype, double *G_out,
                     void *workspace, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------- structural constraints */
+
+/* Set constraint of each factor (Section IV-E: a set constraint changes only
+ * the projection of the auxiliary factor; Section VI-D: rows that are
+ * probability mass functions change the least-squares step instead). */
+typedef enum {
+  NTF_CONS_NONNEG = 0,      /* H >= 0 (the default, eq. g_M_def) */
+  NTF_CONS_BOX = 1,         /* lo <= H <= hi elementwise: the auxiliary update projects onto the box */
+  NTF_CONS_PMF_ROWS = 2,    /* every row non-negative and summing to one: the least-squares step of
+                               each row is solved with the constraint 1^T h = 1 (closed form from
+                               (G + rho I)^{-1}), the auxiliary update stays the non-negative one */
+  NTF_CONS_CARDINALITY = 3  /* H >= 0 with at most card non-zeros in the whole factor (eq.
+                               g_new_def); not implemented: init/set returns NTF_E_UNSUPPORTED */
+} ntf_constraint_kind;
+
+typedef struct {
+  int32_t kind[3];          /* ntf_constraint_kind per mode */
+  int32_t reserved;         /* must be zero */
+  double lo[3], hi[3];      /* NTF_CONS_BOX: finite lo <= hi (hi may be +inf); otherwise ignored */
+  int64_t card[3];          /* NTF_CONS_CARDINALITY: maximum number of non-zeros of the factor */
+} ntf_constraints;
+
+/* Constrain the factors from the next outer iteration on (NULL = all
+ * non-negative).  Not combinable with a learned warm start.  The next step
+ * re-captures the iteration graph (an existing one is dropped after the
+ * stream is synchronised). */
+ntf_status ntf_admm_set_constraints(ntf_admm_ctx *ctx, const ntf_constraints *cons);
+
 /* ------------------------------------------------------------- batched */
 
 /* Many independent problems of uneven shapes factorised together: one

@@ -164,6 +164,26 @@ class NtfAdmm:
         """Algorithmic bytes of each MTTKRP kernel launch."""
         return pass_bytes(tuple(self.X.shape), self.F, self.opts.precision, self.X.element_size())
 
+    def set_constraints(self, constraints=None):
+        """Per-mode set constraints: a sequence of three entries, each None or
+        "nonneg", ("box", lo, hi), or "pmf_rows" (Section IV-E, Section VI-D)."""
+        c = _lib.Constraints()
+        for m, spec in enumerate(constraints or (None, None, None)):
+            if spec is None or spec == "nonneg":
+                c.kind[m] = _lib.CONS_NONNEG
+            elif spec == "pmf_rows":
+                c.kind[m] = _lib.CONS_PMF_ROWS
+            elif isinstance(spec, tuple) and spec[0] == "box":
+                c.kind[m] = _lib.CONS_BOX
+                c.lo[m], c.hi[m] = float(spec[1]), float(spec[2])
+            elif isinstance(spec, tuple) and spec[0] == "cardinality":
+                c.kind[m] = _lib.CONS_CARDINALITY
+                c.card[m] = int(spec[1])
+            else:
+                raise ValueError(f"unknown constraint {spec!r}")
+        _lib.check(_lib.lib().ntf_admm_set_constraints(self._ctx, ctypes.byref(c)),
+                   "ntf_admm_set_constraints", self._ctx)
+
     def get_state(self) -> bytes:
         L = _lib.lib()
         n = L.ntf_admm_state_bytes(self._ctx)

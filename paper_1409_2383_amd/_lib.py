@@ -93,6 +93,19 @@ class Mlp(ctypes.Structure):
     ]
 
 
+class Constraints(ctypes.Structure):
+    _fields_ = [
+        ("kind", c_int32 * 3),
+        ("reserved", c_int32),
+        ("lo", c_double * 3),
+        ("hi", c_double * 3),
+        ("card", c_int64 * 3),
+    ]
+
+
+CONS_NONNEG, CONS_BOX, CONS_PMF_ROWS, CONS_CARDINALITY = 0, 1, 2, 3
+
+
 class BatchTile(ctypes.Structure):
     _fields_ = [
         ("kind", c_int32),
@@ -149,6 +162,7 @@ SIGNATURES = [
     ("ntf_gather_rows", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     ("ntf_mlp_targets", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     ("ntf_admm_mode_problem", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    ("ntf_admm_set_constraints", c_int32, [c_void_p, POINTER(Constraints)]),
     ("ntf_batch_workspace_bytes", c_size_t, [POINTER(Problem), c_int32, POINTER(Opts)]),
     ("ntf_batch_init", c_int32, [POINTER(c_void_p), POINTER(Problem), c_int32, POINTER(Opts), c_void_p,
                                  c_size_t, c_void_p]),

@@ -67,6 +67,9 @@ hipError_t launch_inner(const InnerArgs& ia, int nblk, hipStream_t s) {
   k.rows = ia.rows;
   k.F = ia.F;
   k.Ginv = ia.Ginv;
+  k.proj = ia.proj;
+  k.lo = ia.lo;
+  k.hi = ia.hi;
   k.rho = ia.rho;
   k.rescale = ia.rescale;
   k.T = ia.T;

@@ -28,7 +28,9 @@ struct InnerK {
   void* Pout;
   int64_t rows;
   int F;
-  const double* Ginv;          // (G + rho I)^{-1}, [F][F]
+  const double* Ginv;          // (G + rho I)^{-1}, [F][F], then Ginv 1 [F] and 1^T Ginv 1
+  int proj;                    // 0 non-negative, 1 box [lo, hi], 2 rows summing to one
+  double lo, hi;
   const double* rho;
   int rescale, T;
   double eps_abs, eps_rel;
@@ -122,6 +124,9 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
   }
   const double rho = a.rho[0];
   const double uscale = (a.rescale && a.rho[1] > 0.0) ? a.rho[1] / rho : 1.0;
+  // pmf rows: this lane's entry of Ginv 1 and 1 / (1^T Ginv 1)
+  const double g1f = (a.proj == 2 && f < F) ? a.Ginv[F * F + f] : 0.0;
+  const double inv_1g1 = (a.proj == 2) ? 1.0 / a.Ginv[F * F + F] : 0.0;
 
   // row q of this lane group is block row grp*RPL + q
   double w[RPL], h[RPL], u[RPL], x[RPL], h0[RPL];
@@ -179,8 +184,13 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       if (done[q]) continue;
+      if (a.proj == 2) {
+        // rows summing to one: x -= Ginv 1 (1^T x - 1) / (1^T Ginv 1)
+        const double sx = group_sum(xn[q], FL);
+        xn[q] -= g1f * ((sx - 1.0) * inv_1g1);
+      }
       const double v = xn[q] - u[q];
-      const double hn = (v > 0.0) ? v : 0.0;
+      const double hn = (a.proj == 1) ? fmin(fmax(v, a.lo), a.hi) : ((v > 0.0) ? v : 0.0);
       const double un = hn - v;
       const double dh = hn - h[q];
       h[q] = act[q] ? hn : 0.0;
@@ -510,6 +520,30 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
         const int i = ti + 16 * ia, j = tj + 16 * ib;
         if (i < F && j < F) a.Ginv[i * F + j] = bad ? 0.0 : m[ia][ib];
       }
+    // Ginv 1 and 1^T Ginv 1 (the sum-to-one least-squares step uses them):
+    // Ginv through LDS, row sums in increasing column order
+    __syncthreads();
+#pragma unroll
+    for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        const int i = ti + 16 * ia, j = tj + 16 * ib;
+        if (i < F && j < F) Gs[i * 65 + j] = bad ? 0.0 : m[ia][ib];
+      }
+    __syncthreads();
+    if (tid < F) {
+      double r = 0.0;
+      for (int j = 0; j < F; ++j) r += Gs[tid * 65 + j];
+      a.Ginv[F * F + tid] = r;
+      sred[tid] = r;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int f = 0; f < F; ++f) t += sred[f];
+      a.Ginv[F * F + F] = t;
+    }
+    __syncthreads();   // sred is reused below
   }
   if (bad && tid == 0) atomicOr(a.flag, 2);
 

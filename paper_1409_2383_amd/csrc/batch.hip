@@ -440,6 +440,9 @@ __device__ __forceinline__ void inner_item(const ConstProb& P, const BatchK& a, 
   k.rows = (m == 0) ? P.I : (m == 1) ? P.J : P.K;
   k.F = P.F;
   k.Ginv = P.Ginv;
+  k.proj = 0;
+  k.lo = 0.0;
+  k.hi = 0.0;
   k.rho = P.rho + 2 * m;
   k.rescale = a.rescale;
   k.T = a.T;

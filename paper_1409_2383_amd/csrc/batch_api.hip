@@ -231,7 +231,7 @@ static BatchLayout make_layout(const ntf_problem* probs, int32_t n) {
     for (int m = 0; m < 3; ++m) pl.gram[m] = take((size_t)(F * F) * 8);
     const int maxin = std::max({b.n_in[0], b.n_in[1], b.n_in[2]});
     pl.gpart = take((size_t)maxin * F * F * 8);
-    pl.ginv = take((size_t)(F * F) * 8);
+    pl.ginv = take((size_t)(F * F + F + 1) * 8);   // Ginv, Ginv 1, 1^T Ginv 1
     pl.rho = take(6 * 8);
     pl.end = off;
     L.probs.push_back(pl);

@@ -94,7 +94,7 @@ Layout make_layout(const Plan& p, const ntf_opts& o) {
     L.W[m] = c.take((size_t)(d[m] * F) * 8);
     L.prim[m] = (o.factor_source == 1) ? c.take((size_t)(d[m] * F) * es) : 0;
     L.gram[m] = c.take((size_t)(F * F) * 8);
-    L.ginv[m] = c.take((size_t)(F * F) * 8);
+    L.ginv[m] = c.take((size_t)(F * F + F + 1) * 8);   // Ginv, Ginv 1, 1^T Ginv 1
     if (p.nblk_inner[m] > maxblk) maxblk = p.nblk_inner[m];
   }
   L.gpart = c.take((size_t)maxblk * F * F * 8);
@@ -139,6 +139,7 @@ struct ntf_admm_ctx {
   DevState* host_state = nullptr;  // pinned
   bool warm_on = false;
   ntf_mlp warm{};
+  ntf_constraints cons{};   // all zero: every factor non-negative
   std::string err;
 
   template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -295,6 +296,9 @@ static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
   a.F = p.F;
   a.FL = p.FL;
   a.Ginv = c->at<double>(c->lay.ginv[m]);
+  a.proj = (c->cons.kind[m] == NTF_CONS_BOX) ? 1 : (c->cons.kind[m] == NTF_CONS_PMF_ROWS) ? 2 : 0;
+  a.lo = c->cons.lo[m];
+  a.hi = c->cons.hi[m];
   a.rho = ds->rho[m];
   a.rescale = (c->opts.rescale_dual_on_rho_change || c->opts.rho_policy == NTF_RHO_ADAPTIVE) ? 1 : 0;
   a.T = c->opts.inner_iters;
@@ -727,6 +731,49 @@ ntf_status ntf_mlp_targets(const double* Hstar, const float* scale, int64_t rows
                                                                                        : NTF_E_HIP;
 }
 
+ntf_status ntf_admm_set_constraints(ntf_admm_ctx* c, const ntf_constraints* cons) {
+  if (!c) return NTF_E_INVAL;
+  ntf_constraints z{};
+  const ntf_constraints& k = cons ? *cons : z;
+  if (k.reserved != 0) {
+    c->err = "reserved field must be zero";
+    return NTF_E_INVAL;
+  }
+  bool any = false;
+  for (int m = 0; m < 3; ++m) {
+    switch (k.kind[m]) {
+      case NTF_CONS_NONNEG: break;
+      case NTF_CONS_BOX:
+        if (!std::isfinite(k.lo[m]) || std::isnan(k.hi[m]) || !(k.lo[m] <= k.hi[m])) {
+          c->err = "box constraint needs finite lo <= hi";
+          return NTF_E_INVAL;
+        }
+        any = true;
+        break;
+      case NTF_CONS_PMF_ROWS: any = true; break;
+      case NTF_CONS_CARDINALITY:
+        c->err = "cardinality constraints are not implemented";
+        return NTF_E_UNSUPPORTED;
+      default:
+        c->err = "unknown constraint kind";
+        return NTF_E_INVAL;
+    }
+  }
+  if (any && c->warm_on) {
+    c->err = "constraints and the learned warm start do not combine";
+    return NTF_E_UNSUPPORTED;
+  }
+  if (c->gexec || c->graph) {
+    NTF_HIP(c, hipStreamSynchronize(c->s0));
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+  }
+  c->cons = k;
+  return NTF_OK;
+}
+
 ntf_status ntf_admm_set_warmstart(ntf_admm_ctx* c, const ntf_mlp* net) {
   if (!c) return NTF_E_INVAL;
   if (net) {
@@ -735,6 +782,11 @@ ntf_status ntf_admm_set_warmstart(ntf_admm_ctx* c, const ntf_mlp* net) {
       c->err = "warm start network does not match the context (rank, hidden <= warm_hidden, dtype)";
       return NTF_E_INVAL;
     }
+    for (int m = 0; m < 3; ++m)
+      if (c->cons.kind[m] != NTF_CONS_NONNEG) {
+        c->err = "constraints and the learned warm start do not combine";
+        return NTF_E_UNSUPPORTED;
+      }
     c->warm = *net;
     c->warm_on = true;
   } else {
@@ -841,7 +893,7 @@ InnerWs inner_ws(int64_t rows, int F) {
   InnerWs w;
   w.state = c.take(sizeof(DevState));
   w.ones = c.take((size_t)F * F * 8);
-  w.ginv = c.take((size_t)F * F * 8);
+  w.ginv = c.take((size_t)(F * F + F + 1) * 8);
   w.gpart = c.take((size_t)nblk * F * F * 8);
   w.rpart = c.take((size_t)nblk * 8 * 8);
   w.total = c.off;

@@ -75,7 +75,9 @@ struct InnerArgs {
   int h_f64 = 0;
   int64_t rows = 0;
   int F = 0, FL = 0;
-  const double* Ginv = nullptr;   // [F][F] (G + rho I)^{-1}
+  const double* Ginv = nullptr;   // [F][F] (G + rho I)^{-1}, then Ginv 1 [F], 1^T Ginv 1
+  int proj = 0;                   // constraint of the factor: 0 non-negative, 1 box, 2 pmf rows
+  double lo = 0.0, hi = 0.0;      // box bounds
   const double* rho = nullptr;    // device: [0] rho for this update, [1] rho of the previous update
   int rescale = 0;
   int T = 1;
@@ -105,7 +107,8 @@ struct PrepArgs {
   double* rho_state = nullptr;        // [0] rho (in/out), [1] previous rho (out)
   const double* resid_mode = nullptr; // residual totals of the mode being prepared
   int* fresh_mode = nullptr;
-  double* Ginv = nullptr;             // out [F][F]: (G + rho I)^{-1} = L^{-T} L^{-1}
+  double* Ginv = nullptr;             // out [F][F]: (G + rho I)^{-1} = L^{-T} L^{-1}; then [F]
+                                      // its row sums and [1] their total
   double* G_out = nullptr;            // optional out: G of the mode being prepared [F][F]
   int* taken = nullptr;               // warm-start counter of the mode being prepared (zeroed)
   int* flag = nullptr;

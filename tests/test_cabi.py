@@ -61,7 +61,7 @@ def _c_sizeof(struct_name):
 
 
 @pytest.mark.parametrize("cname,pyname", [("ntf_problem", "Problem"), ("ntf_opts", "Opts"),
-                                          ("ntf_stats", "Stats"), ("ntf_mlp", "Mlp"),
+                                          ("ntf_stats", "Stats"), ("ntf_mlp", "Mlp"), ("ntf_constraints", "Constraints"),
                                           ("ntf_batch_tile", "BatchTile"),
                                           ("ntf_batch_info", "BatchInfo")])
 def test_struct_layouts_match(cname, pyname):
