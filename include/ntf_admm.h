@@ -285,7 +285,12 @@ typedef enum {
                                each row is solved with the constraint 1^T h = 1 (closed form from
                                (G + rho I)^{-1}), the auxiliary update stays the non-negative one */
   NTF_CONS_CARDINALITY = 3  /* H >= 0 with at most card non-zeros in the whole factor (eq.
-                               g_new_def); not implemented: init/set returns NTF_E_UNSUPPORTED */
+                               g_new_def): the auxiliary update keeps the card largest positive
+                               entries of Ht^T - U (ties by row-major index).  The projection
+                               couples every row, so each inner iteration is a row-wise solve
+                               plus one whole-factor select pass; needs inner early stop off
+                               (inner_eps_abs = inner_eps_rel = 0) and rows * F < 2^31, else
+                               NTF_E_UNSUPPORTED; card < 0 is NTF_E_INVAL */
 } ntf_constraint_kind;
 
 typedef struct {

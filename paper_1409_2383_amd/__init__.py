@@ -166,7 +166,8 @@ class NtfAdmm:
 
     def set_constraints(self, constraints=None):
         """Per-mode set constraints: a sequence of three entries, each None or
-        "nonneg", ("box", lo, hi), or "pmf_rows" (Section IV-E, Section VI-D)."""
+        "nonneg", ("box", lo, hi), "pmf_rows" or ("cardinality", c) (Section
+        IV-E, Section VI-D)."""
         c = _lib.Constraints()
         for m, spec in enumerate(constraints or (None, None, None)):
             if spec is None or spec == "nonneg":

@@ -81,6 +81,9 @@ hipError_t launch_inner(const InnerArgs& ia, int nblk, hipStream_t s) {
   k.gram_part = ia.gram_part;
   k.resid_part = ia.resid_part;
   k.flag = ia.flag;
+  k.dv = ia.dv;
+  k.dx = ia.dx;
+  k.dh0 = ia.dh0;
   if (ia.h_f64) return inner_dispatch<double>(k, ia.FL, nblk, s);
   return inner_dispatch<float>(k, ia.FL, nblk, s);
 }

@@ -29,7 +29,8 @@ struct InnerK {
   int64_t rows;
   int F;
   const double* Ginv;          // (G + rho I)^{-1}, [F][F], then Ginv 1 [F] and 1^T Ginv 1
-  int proj;                    // 0 non-negative, 1 box [lo, hi], 2 rows summing to one
+  int proj;                    // 0 non-negative, 1 box [lo, hi], 2 rows summing to one,
+                               // 3 projection deferred to a whole-factor pass (dv, dx, dh0)
   double lo, hi;
   const double* rho;
   int rescale, T;
@@ -39,6 +40,13 @@ struct InnerK {
   double* gram_part;
   double* resid_part;
   int* flag;
+  // proj == 3 (one inner iteration per launch): V = Ht^T - U, Ht^T and, when
+  // dh0 is set, the factor before the update go to these FP64 [rows][F]
+  // buffers; H, U, the partials and the statistics are left to the
+  // whole-factor projection that follows
+  double* dv;
+  double* dx;
+  double* dh0;
 };
 
 template <int FL>
@@ -190,7 +198,8 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
         xn[q] -= g1f * ((sx - 1.0) * inv_1g1);
       }
       const double v = xn[q] - u[q];
-      const double hn = (a.proj == 1) ? fmin(fmax(v, a.lo), a.hi) : ((v > 0.0) ? v : 0.0);
+      const double hn = (a.proj == 1) ? fmin(fmax(v, a.lo), a.hi)
+                        : (a.proj == 3) ? v : ((v > 0.0) ? v : 0.0);
       const double un = hn - v;
       const double dh = hn - h[q];
       h[q] = act[q] ? hn : 0.0;
@@ -210,6 +219,20 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
     }
   }
   __syncthreads();
+
+  if (a.proj == 3) {   // uniform over the block
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t row = row0 + grp * RPL + q;
+      if (act[q]) {
+        if (!isfinite(x[q]) || !isfinite(w[q])) atomicOr(a.flag, 1);
+        a.dv[row * F + f] = h[q];
+        a.dx[row * F + f] = x[q];
+        if (a.dh0) a.dh0[row * F + f] = h0[q];
+      }
+    }
+    return;
+  }
 
   double qs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll

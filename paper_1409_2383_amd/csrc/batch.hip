@@ -454,6 +454,7 @@ __device__ __forceinline__ void inner_item(const ConstProb& P, const BatchK& a, 
   k.gram_part = P.gpart;
   k.resid_part = nullptr;
   k.flag = a.flag;
+  k.dv = k.dx = k.dh0 = nullptr;
   // ipi row blocks of 256 / FL rows; the barrier keeps one block's last LDS
   // reads apart from the next block's first writes
   const int nb = (m == 0) ? P.n_in[0] : (m == 1) ? P.n_in[1] : P.n_in[2];

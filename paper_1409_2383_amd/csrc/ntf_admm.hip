@@ -49,7 +49,7 @@ struct Layout {
   size_t state = 0, T = 0, P1 = 0, P2 = 0, P3 = 0, W[3] = {0, 0, 0}, prim[3] = {0, 0, 0},
          gram[3] = {0, 0, 0}, ginv[3] = {0, 0, 0}, gpart = 0, rpart = 0, sumsq = 0, fitpart = 0,
          xr = 0, xj8 = 0, scale = 0, wx = 0, wy = 0, wact = 0, wscale = 0, wG[3] = {0, 0, 0},
-         total = 0;
+         card = 0, total = 0;
 };
 
 const int kSumsqParts = 1024;
@@ -100,6 +100,9 @@ Layout make_layout(const Plan& p, const ntf_opts& o) {
   L.gpart = c.take((size_t)maxblk * F * F * 8);
   L.rpart = c.take((size_t)maxblk * 8 * 8);
   L.sumsq = c.take((size_t)kSumsqParts * 8);
+  // whole-factor projection (cardinality constraint): V, Ht^T and the factor
+  // before the update, FP64 [rows][F] each, for the largest mode
+  L.card = c.take((size_t)(3 * std::max(p.I, std::max(p.J, p.K)) * F) * 8);
   // fit partials; also scratch for ntf_admm_mode_problem (two Grams + partials)
   L.fitpart = c.take(std::max<size_t>((size_t)fit_parts(p) * 2, (size_t)(2 + maxblk) * F * F) * 8);
   if (p.prec == PREC_BF16) {
@@ -311,6 +314,39 @@ static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
   a.flag = &ds->flag;
 }
 
+// Inner sweep of mode m.  A factor under the cardinality constraint couples
+// every row in its projection: each inner iteration is the row-wise solve
+// (projection deferred) followed by the whole-factor projection, then the
+// Gram partials of the updated factor.
+static ntf_status enqueue_inner(ntf_admm_ctx* c, int m, hipStream_t ms) {
+  const Plan& p = c->plan;
+  InnerArgs ia;
+  inner_args(c, m, ia);
+  if (c->cons.kind[m] != NTF_CONS_CARDINALITY) {
+    NTF_HIP(c, launch_inner(ia, p.nblk_inner[m], ms));
+    return NTF_OK;
+  }
+  const int64_t d[3] = {p.I, p.J, p.K};
+  const int64_t n = d[m] * p.F;
+  double* V = c->at<double>(c->lay.card);
+  double* Xt = V + n;
+  double* H0 = Xt + n;
+  const int T = ia.T;
+  ia.T = 1;
+  ia.proj = 3;
+  ia.dv = V;
+  ia.dx = Xt;
+  for (int t = 0; t < T; ++t) {
+    ia.dh0 = (t == 0) ? H0 : nullptr;
+    if (t > 0) ia.rescale = 0;   // U is already in the scale of this update's rho
+    NTF_HIP(c, launch_inner(ia, p.nblk_inner[m], ms));
+    NTF_HIP(c, launch_card_project(V, Xt, H0, ia.H, ia.U, ia.Pout, ia.h_f64, n, c->cons.card[m],
+                                   (double)T * (double)d[m], ia.resid_part, p.nblk_inner[m], ms));
+  }
+  NTF_HIP(c, launch_gram_part(c->feed(m), c->hf64(), d[m], p.F, p.rpb, ia.gram_f32, ia.gram_part, ms));
+  return NTF_OK;
+}
+
 // Learned warm start of mode m (after its W and its prepare step): row
 // inputs, network forward, and the per-row KKT judge that writes the chosen
 // starting point into H_m, U_m.
@@ -340,7 +376,6 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   const float* scale = p.prec == PREC_BF16 ? c->at<float>(c->lay.scale) : nullptr;
   void* T = c->ws + c->lay.T;
   PrepArgs pa;
-  InnerArgs ia;
   // mode 1 (A): prepare on the side while pass 1 streams X
   NTF_HIP(c, hipEventRecord(c->ev_fork, ms));
   NTF_HIP(c, hipStreamWaitEvent(c->s1, c->ev_fork, 0));
@@ -355,8 +390,10 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
     ntf_status w = enqueue_warm(c, 0, ms);
     if (w != NTF_OK) return w;
   }
-  inner_args(c, 0, ia);
-  NTF_HIP(c, launch_inner(ia, p.nblk_inner[0], ms));
+  {
+    ntf_status st = enqueue_inner(c, 0, ms);
+    if (st != NTF_OK) return st;
+  }
   // mode 2 (B)
   NTF_HIP(c, hipEventRecord(c->ev_inner[0], ms));
   NTF_HIP(c, hipStreamWaitEvent(c->s1, c->ev_inner[0], 0));
@@ -371,8 +408,10 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
     ntf_status w = enqueue_warm(c, 1, ms);
     if (w != NTF_OK) return w;
   }
-  inner_args(c, 1, ia);
-  NTF_HIP(c, launch_inner(ia, p.nblk_inner[1], ms));
+  {
+    ntf_status st = enqueue_inner(c, 1, ms);
+    if (st != NTF_OK) return st;
+  }
   // mode 3 (C)
   NTF_HIP(c, hipEventRecord(c->ev_inner[1], ms));
   NTF_HIP(c, hipStreamWaitEvent(c->s1, c->ev_inner[1], 0));
@@ -387,8 +426,10 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
     ntf_status w = enqueue_warm(c, 2, ms);
     if (w != NTF_OK) return w;
   }
-  inner_args(c, 2, ia);
-  NTF_HIP(c, launch_inner(ia, p.nblk_inner[2], ms));
+  {
+    ntf_status st = enqueue_inner(c, 2, ms);
+    if (st != NTF_OK) return st;
+  }
   return NTF_OK;
 }
 
@@ -751,9 +792,23 @@ ntf_status ntf_admm_set_constraints(ntf_admm_ctx* c, const ntf_constraints* cons
         any = true;
         break;
       case NTF_CONS_PMF_ROWS: any = true; break;
-      case NTF_CONS_CARDINALITY:
-        c->err = "cardinality constraints are not implemented";
-        return NTF_E_UNSUPPORTED;
+      case NTF_CONS_CARDINALITY: {
+        const int64_t d[3] = {c->plan.I, c->plan.J, c->plan.K};
+        if (k.card[m] < 0) {
+          c->err = "cardinality constraint needs card >= 0";
+          return NTF_E_INVAL;
+        }
+        if (d[m] * c->plan.F >= ((int64_t)1 << 31)) {
+          c->err = "cardinality constraint: factor has 2^31 entries or more";
+          return NTF_E_UNSUPPORTED;
+        }
+        if (c->opts.inner_eps_abs > 0.0 || c->opts.inner_eps_rel > 0.0) {
+          c->err = "cardinality constraint couples all rows: inner early stop must be off";
+          return NTF_E_UNSUPPORTED;
+        }
+        any = true;
+        break;
+      }
       default:
         c->err = "unknown constraint kind";
         return NTF_E_INVAL;

@@ -76,7 +76,8 @@ struct InnerArgs {
   int64_t rows = 0;
   int F = 0, FL = 0;
   const double* Ginv = nullptr;   // [F][F] (G + rho I)^{-1}, then Ginv 1 [F], 1^T Ginv 1
-  int proj = 0;                   // constraint of the factor: 0 non-negative, 1 box, 2 pmf rows
+  int proj = 0;                   // constraint of the factor: 0 non-negative, 1 box, 2 pmf rows,
+                                  // 3 deferred to launch_card_project
   double lo = 0.0, hi = 0.0;      // box bounds
   const double* rho = nullptr;    // device: [0] rho for this update, [1] rho of the previous update
   int rescale = 0;
@@ -88,6 +89,9 @@ struct InnerArgs {
   double* gram_part = nullptr;    // [nblk][F][F]
   double* resid_part = nullptr;   // [nblk][8]
   int* flag = nullptr;
+  double* dv = nullptr;           // proj == 3: V, Ht^T and the factor before the update,
+  double* dx = nullptr;           // FP64 [rows][F] (dh0 may be null)
+  double* dh0 = nullptr;
 };
 hipError_t launch_inner(const InnerArgs& a, int nblk, hipStream_t s);
 int inner_rows_per_block(int FL);     // rows one inner-sweep block handles
@@ -134,6 +138,15 @@ hipError_t launch_finish(int F, const double* gram_part, const double* resid_par
                          const double* g0, const double* g1, const double* W3, const void* H3,
                          int h_f64, int64_t K, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+// Cardinality constraint (card.hip): from V, Ht^T and the factor before the
+// update (FP64 [n]), keep the card largest positive entries of V in H (ties
+// by index), U = H - V, Pout = Ht^T (Pout may be null); residual partial 0
+// gets the totals with `iters_total` iterations, partials 1 .. nparts-1 zero.
+// One block; n < 2^31.
+hipError_t launch_card_project(const double* V, const double* X, const double* H0, void* H,
+                               void* U, void* Pout, int h_f64, int64_t n, int64_t card,
+                               double iters_total, double* resid_part, int nparts, hipStream_t s);
 
 // ---- learned warm start (mlp.hip)
 size_t mlp_param_count(int F, int Hd);
