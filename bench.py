@@ -44,10 +44,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def src_hash():
+# The MTTKRP kernels whose HBM traffic the committed counter runs measured
+# live in these sources; a change to them voids the stored traffic figures.
+MTTKRP_SOURCES = ("mttkrp.hip", "ntf_device.h")
+
+
+def src_hash(files=None):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1409_2383_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in sorted(files or os.listdir(csrc)):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -232,7 +237,7 @@ def write_traffic(fetch_csv, write_csv, calib_mib, workload, arm, pass_bytes, cm
     f_cal, _ = find(fetch, "neg_kernel", "FETCH_SIZE")
     w_cal, _ = find(write, "neg_kernel", "WRITE_SIZE")
     f_scale, w_scale = f_cal / kib, w_cal / kib
-    tag = src_hash()
+    tag = src_hash(MTTKRP_SOURCES)
     lines = [f"# HBM traffic per launch, {workload} {arm} arm", "",
              "Commands (run from the repository root, NTF_NO_GRAPH=1):", "",
              "    " + cmd.replace("COUNTER", "FETCH_SIZE").replace("OUT", "pmc_fetch"),
@@ -502,7 +507,7 @@ def main():
     if os.path.exists(tfile):
         with open(tfile) as fh:
             tj = json.load(fh)
-        if tj.get("src_hash") == src_hash():
+        if tj.get("src_hash") == src_hash(MTTKRP_SOURCES):
             traffic = tj.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
