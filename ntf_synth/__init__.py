@@ -25,7 +25,8 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["PlantedTensor", "planted", "init_factors", "config_seed", "batch_shapes"]
+__all__ = ["PlantedTensor", "planted", "init_factors", "config_seed", "batch_shapes",
+           "SparseSample", "sparse_planted"]
 
 
 @dataclass
@@ -119,3 +120,58 @@ def batch_shapes(n: int, seed: int, lo: int, hi: int, ranks: Sequence[int]):
     dims = rng.integers(lo, hi + 1, size=(n, 3))
     Fs = rng.choice(np.asarray(list(ranks)), size=n)
     return [(tuple(int(x) for x in d), int(f)) for d, f in zip(dims, Fs)]
+
+
+@dataclass
+class SparseSample:
+    idx: np.ndarray          # [n][3] int32 coordinates (i, j, k), distinct, in random order
+    val: np.ndarray          # [n] values, dtype as requested
+    dims: tuple
+    A0: np.ndarray           # planted factors, float64
+    B0: np.ndarray
+    C0: np.ndarray
+    sigma: float
+
+
+def sparse_planted(dims: Sequence[int], F: int, nnz: int, seed: int, *, skew: float = 2.0,
+                   noise_rel: float = 0.1, dtype=np.float32, chunk: int = 1 << 22) -> SparseSample:
+    """A sparse tensor observed at about ``nnz`` positions of the planted model.
+
+    Positions: per mode, ``floor(d * u**skew)`` with u ~ Uniform[0,1) (skew > 1
+    gives the few heavy and many light slices that sparse tensors show), the
+    index then relabelled by a random permutation of the mode so that heavy
+    slices are scattered; repeated coordinates are dropped (the first draw is
+    kept), so the result may hold slightly fewer than ``nnz`` entries, in a
+    random order.  Values: the planted rank-F model (U[0,1] factors) at those
+    positions plus Gaussian noise of standard deviation ``noise_rel`` times the
+    RMS of the clean values.
+
+    Draw order from ``default_rng(seed)``: A0, B0, C0 (row-major); the three
+    position streams (i, then j, then k, each ``nnz`` uniforms); the three
+    relabelling permutations; the noise (one normal per kept entry, in kept
+    order); the output permutation.
+    """
+    I, J, K = (int(d) for d in dims)
+    rng = np.random.default_rng(seed)
+    A0 = _draw_factor(rng, I, F, "uniform")
+    B0 = _draw_factor(rng, J, F, "uniform")
+    C0 = _draw_factor(rng, K, F, "uniform")
+    raw = [np.floor(d * rng.random(nnz) ** skew).astype(np.int64) for d in (I, J, K)]
+    perm = [rng.permutation(d) for d in (I, J, K)]
+    coords = [p[r] for p, r in zip(perm, raw)]
+    key = (coords[0] * J + coords[1]) * K + coords[2]
+    _, first = np.unique(key, return_index=True)
+    first.sort()                                       # keep draw order
+    idx = np.stack([c[first] for c in coords], axis=1).astype(np.int32)
+    n = idx.shape[0]
+    clean = np.empty(n, dtype=np.float64)
+    for e0 in range(0, n, chunk):
+        e1 = min(n, e0 + chunk)
+        t = idx[e0:e1]
+        # X0[i, j, k] = sum_f A0[i,f] B0[j,f] C0[k,f]   (the data model of Section II)
+        clean[e0:e1] = np.sum(A0[t[:, 0]] * B0[t[:, 1]] * C0[t[:, 2]], axis=1)
+    sigma = noise_rel * math.sqrt(float(np.mean(clean * clean))) if n else 0.0
+    val = clean + sigma * rng.standard_normal(n)
+    order = rng.permutation(n)
+    return SparseSample(idx=np.ascontiguousarray(idx[order]), val=val[order].astype(dtype),
+                        dims=(I, J, K), A0=A0, B0=B0, C0=C0, sigma=sigma)

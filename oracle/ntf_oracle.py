@@ -16,7 +16,10 @@ tensor factorization via the alternating direction method of multipliers"):
 * the regularised least-squares step uses a Cholesky factorisation
   (LAPACK via numpy/scipy);
 * the projection and dual update follow eq. ADMoM_NTF (Section IV);
-* residuals and stopping follow Section IV-C, penalty adaptation Section IV-D.
+* residuals and stopping follow Section IV-C, penalty adaptation Section IV-D;
+* a sparse tensor (``SparseTensor``: coordinates and values of the non-zeros)
+  takes the MTTKRP from its non-zeros alone (Section IV-A, item 1), by a
+  scatter-add of one product per non-zero; everything else is unchanged.
 
 State convention (the "inner ADMM sweep" form).  For each mode n the state is
 the non-negative auxiliary factor H_n (the paper's A-tilde), the scaled dual
@@ -107,6 +110,58 @@ def kr_for_mode(factors: Sequence[np.ndarray], n: int) -> np.ndarray:
 def mttkrp(X: np.ndarray, factors: Sequence[np.ndarray], n: int) -> np.ndarray:
     """W_n = X^(n) (Khatri-Rao of the other two factors), eq. ADMM_NTF_ALS_C."""
     return unfold(X, n) @ kr_for_mode(factors, n)
+
+
+@dataclass(frozen=True)
+class SparseTensor:
+    """A sparse 3-way tensor by its non-zeros (Section IV-A, item 1: n
+    non-zeros, n << IJK): coordinates ``idx`` [n][3] (distinct) and values
+    ``val`` [n]; every other entry is zero."""
+    idx: np.ndarray
+    val: np.ndarray
+    dims: tuple
+
+    @property
+    def shape(self):
+        return tuple(self.dims)
+
+
+def densify(T: SparseTensor) -> np.ndarray:
+    """The dense tensor the non-zeros describe."""
+    X = np.zeros(tuple(T.dims))
+    for e in range(T.idx.shape[0]):
+        i, j, k = (int(v) for v in T.idx[e])
+        X[i, j, k] += float(T.val[e])
+    return X
+
+
+def mttkrp_sparse(T: SparseTensor, factors: Sequence[np.ndarray], n: int) -> np.ndarray:
+    """W_n from the non-zeros alone (Section IV-A, item 1): each non-zero
+    x_ijk adds x_ijk times the elementwise product of the other two factors'
+    rows to row i (mode 1), j (mode 2) or k (mode 3) of W_n; three flops per
+    non-zero and column, the Khatri-Rao matrix never formed."""
+    others = [m for m in range(3) if m != n]
+    P = np.asarray(factors[others[0]], dtype=np.float64)
+    Q = np.asarray(factors[others[1]], dtype=np.float64)
+    idx = np.asarray(T.idx, dtype=np.int64)
+    contrib = np.asarray(T.val, dtype=np.float64)[:, None] * (P[idx[:, others[0]]] * Q[idx[:, others[1]]])
+    W = np.zeros((int(T.dims[n]), P.shape[1]))
+    np.add.at(W, idx[:, n], contrib)
+    return W
+
+
+def rfe_sparse(T: SparseTensor, factors: Sequence[np.ndarray]) -> float:
+    """RFE (Section VI-A) of a sparse tensor without forming the model:
+    ||X - M||^2 = sum over the non-zeros of (x - m)^2 plus the model's energy
+    off them, ||M||^2 - sum over the non-zeros of m^2, with
+    ||M||^2 = sum(A^T A * B^T B * C^T C) (Hadamard product of the Grams)."""
+    A, B, C = (np.asarray(f, dtype=np.float64) for f in factors)
+    idx = np.asarray(T.idx, dtype=np.int64)
+    x = np.asarray(T.val, dtype=np.float64)
+    m = np.sum(A[idx[:, 0]] * B[idx[:, 1]] * C[idx[:, 2]], axis=1)
+    model2 = float(np.sum((A.T @ A) * (B.T @ B) * (C.T @ C)))
+    err2 = float(np.sum((x - m) ** 2)) + model2 - float(np.sum(m * m))
+    return math.sqrt(max(err2, 0.0)) / math.sqrt(float(np.sum(x * x)))
 
 
 def reconstruct(factors: Sequence[np.ndarray]) -> np.ndarray:
@@ -352,7 +407,9 @@ def mode_update(X: np.ndarray, st: State, n: int, opts: Opts) -> dict:
     projection and dual update of eq. ADMoM_NTF)."""
     feed = st.P if opts.factor_source == 1 else st.H
     factors = [feed[0], feed[1], feed[2]]
-    if opts.mttkrp_operands == "exact":
+    if isinstance(X, SparseTensor):
+        W = mttkrp_sparse(X, factors, n)
+    elif opts.mttkrp_operands == "exact":
         W = mttkrp(X, factors, n)
     else:
         W = mttkrp_mixed(X, factors, n, mode3="factored" if opts.mttkrp_operands == "bf16_factored" else "kr")
@@ -424,7 +481,7 @@ def run(X: np.ndarray, st: State, opts: Opts, outer_iters: int, fit_every: int =
         rec = {"outer": st.outer, "rho": list(st.rho),
                "prim": [i["prim"] for i in infos], "dual": [i["dual"] for i in infos]}
         if fit_every and st.outer % fit_every == 0:
-            rec["rfe"] = rfe(X, st.H)
+            rec["rfe"] = rfe_sparse(X, st.H) if isinstance(X, SparseTensor) else rfe(X, st.H)
         st.stats.append(rec)
         if stop_eps is not None and converged_paper(infos, X.shape, st.H[0].shape[1], *stop_eps):
             break
