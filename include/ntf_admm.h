@@ -133,6 +133,49 @@ size_t ntf_admm_workspace_bytes(const ntf_problem *prob, const ntf_opts *opts);
 ntf_status ntf_admm_init(ntf_admm_ctx **out, const ntf_problem *prob, const ntf_opts *opts,
                          void *workspace, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------- sparse tensors */
+
+/* A sparse 3-way tensor given by its non-zeros (Section IV-A, item 1: n
+ * non-zeros, n << IJK; every other entry is zero). */
+typedef struct {
+  int64_t dims[3];          /* I, J, K >= 1; the packed sort key needs
+                               ceil(log2 I) + ceil(log2 J) + ceil(log2 K) <= 64 */
+  int32_t F;                /* rank, 1..64 */
+  int32_t x_dtype;          /* 0 = float32 values (NTF_PREC_F32), 1 = float64 (NTF_PREC_F64) */
+  int64_t nnz;              /* number of non-zeros, 0 .. 2^31 - 1 */
+  const int32_t *idx;       /* device [nnz][3] coordinates (i, j, k), all distinct, any order;
+                               read during ntf_admm_init_sparse only */
+  const void *val;          /* device [nnz] values; read during ntf_admm_init_sparse only */
+  void *H[3];               /* as in ntf_problem */
+  void *U[3];
+} ntf_sparse_problem;
+
+/* Workspace bytes ntf_admm_init_sparse needs: three sorted copies of the
+ * non-zeros ((12 + value bytes) per non-zero each), the sort scratch of the
+ * set-up (24 bytes per non-zero), the MTTKRP segment carries and the
+ * per-mode buffers of the dense solver; 0 if the arguments are invalid. */
+size_t ntf_admm_sparse_workspace_bytes(const ntf_sparse_problem *prob, const ntf_opts *opts);
+
+/* Create a solver context for a sparse tensor.  Set-up builds, per mode, a
+ * copy of the non-zeros sorted by (that mode's index, then the other two in
+ * mode order) with the library's radix sort; the caller's coordinate and value
+ * arrays are not used afterwards.  Every MTTKRP of the outer iteration then
+ * takes 3 nnz F flops from the sorted copy (one product of the other two
+ * factor rows per non-zero, Section IV-A, item 1); the Gram, penalty,
+ * Cholesky and inner sweep are those of the dense tensor.  All other
+ * ntf_admm_* calls apply unchanged; ntf_admm_fit evaluates
+ * ||X - M||^2 = sum over non-zeros (x - m)^2 + ||M||^2 - sum over non-zeros m^2,
+ * ||M||^2 from the Grams of the factors, in FP64; ntf_admm_launch_pass(p)
+ * runs the MTTKRP of mode p.  Precision NTF_PREC_F32 (FP32 products and
+ * segment sums, FP64 across segments) or NTF_PREC_F64; NTF_PREC_BF16_MIXED
+ * and a learned warm start (warm_hidden > 0) are NTF_E_UNSUPPORTED.  Errors:
+ * a coordinate outside the tensor or repeated is NTF_E_INVAL (found on the
+ * device during set-up; nothing is built from an out-of-range coordinate).
+ * Synchronises the stream. */
+ntf_status ntf_admm_init_sparse(ntf_admm_ctx **out, const ntf_sparse_problem *prob,
+                                const ntf_opts *opts, void *workspace, size_t ws_bytes,
+                                void *stream);
+
 /* One outer iteration (modes 1, 2, 3 in Gauss-Seidel order, eqs. ADMoM_NTF and
  * ADMM_NTF_ALS_C).  The first call captures the iteration into a HIP graph;
  * later calls replay it.  If `stats` is non-NULL the call synchronises and

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import (PREC_BF16_MIXED, PREC_F32, PREC_F64, RHO_ADAPTIVE, RHO_FIXED, RHO_TRACE,
                    NtfError)
 
-__all__ = ["NtfAdmm", "NtfBatch", "AdmmOptions", "inner_update", "gram", "PREC_F32", "PREC_BF16_MIXED",
+__all__ = ["NtfAdmm", "NtfAdmmSparse", "NtfBatch", "AdmmOptions", "inner_update", "gram", "PREC_F32", "PREC_BF16_MIXED",
            "PREC_F64", "RHO_TRACE", "RHO_FIXED", "RHO_ADAPTIVE", "NtfError", "library_path"]
 
 
@@ -98,6 +98,8 @@ class NtfAdmm:
             if self.U[n].shape != self.H[n].shape or self.U[n].dtype != fdt or not self.U[n].is_contiguous():
                 raise ValueError(f"U[{n}] must match H[{n}]")
         self.F = F
+        self.dims = tuple(int(d) for d in X.shape)
+        self.device = X.device
         self.stream = stream
         L = _lib.lib()
         pr = _lib.Problem()
@@ -150,7 +152,7 @@ class NtfAdmm:
 
     def mttkrp(self, mode: int):
         torch = _torch()
-        W = torch.empty((self.X.shape[mode], self.F), dtype=torch.float64, device=self.X.device)
+        W = torch.empty((self.dims[mode], self.F), dtype=torch.float64, device=self.device)
         _lib.check(_lib.lib().ntf_admm_mttkrp(self._ctx, int(mode), ctypes.c_void_p(_ptr(W))),
                    "ntf_admm_mttkrp", self._ctx)
         return W
@@ -207,6 +209,89 @@ class NtfAdmm:
             self.close()
         except Exception:
             pass
+
+
+class NtfAdmmSparse(NtfAdmm):
+    """ADMoM NTF of a sparse tensor given by its non-zeros (Section IV-A,
+    item 1).
+
+    idx: CUDA int32 tensor [nnz, 3] of distinct coordinates (any order);
+    val: CUDA tensor [nnz], float32 (F32) or float64 (F64); dims: (I, J, K).
+    The library sorts three copies of the non-zeros into its workspace at
+    set-up; idx and val are not used afterwards.  Every other method is the
+    dense solver's.
+    """
+
+    def __init__(self, idx, val, dims, H: Sequence, U: Optional[Sequence] = None,
+                 opts: Optional[AdmmOptions] = None, stream=None):
+        torch = _torch()
+        self.opts = opts or AdmmOptions()
+        fdt = torch.float64 if self.opts.precision == PREC_F64 else torch.float32
+        nnz = int(idx.shape[0]) if idx.dim() == 2 else -1
+        if (not idx.is_cuda or idx.dtype != torch.int32 or idx.dim() != 2 or idx.shape[1] != 3
+                or not idx.is_contiguous()):
+            raise ValueError("idx must be a contiguous CUDA int32 tensor of shape (nnz, 3)")
+        if not val.is_cuda or val.dtype != fdt or tuple(val.shape) != (nnz,) or not val.is_contiguous():
+            raise ValueError(f"val must be a contiguous CUDA {fdt} tensor of shape ({nnz},)")
+        self.X = None
+        self.dims = tuple(int(d) for d in dims)
+        self.device = val.device
+        F = H[0].shape[1]
+        self.H = list(H)
+        for n in range(3):
+            h = self.H[n]
+            if (not h.is_cuda or h.dtype != fdt or not h.is_contiguous()
+                    or tuple(h.shape) != (self.dims[n], F)):
+                raise ValueError(f"H[{n}] must be a contiguous CUDA {fdt} tensor of shape "
+                                 f"({self.dims[n]}, {F})")
+        self.U = list(U) if U is not None else [torch.zeros_like(h) for h in self.H]
+        for n in range(3):
+            if self.U[n].shape != self.H[n].shape or self.U[n].dtype != fdt or not self.U[n].is_contiguous():
+                raise ValueError(f"U[{n}] must match H[{n}]")
+        self.F = F
+        self.nnz = nnz
+        self.stream = stream
+        L = _lib.lib()
+        pr = _lib.SparseProblem()
+        for n in range(3):
+            pr.dims[n] = self.dims[n]
+            pr.H[n] = _ptr(self.H[n])
+            pr.U[n] = _ptr(self.U[n])
+        pr.F = F
+        pr.x_dtype = 1 if self.opts.precision == PREC_F64 else 0
+        pr.nnz = nnz
+        pr.idx = _ptr(idx) if nnz > 0 else None
+        pr.val = _ptr(val) if nnz > 0 else None
+        self._prob = pr
+        self._copts = self.opts.to_c()
+        nbytes = L.ntf_admm_sparse_workspace_bytes(ctypes.byref(pr), ctypes.byref(self._copts))
+        if nbytes == 0:
+            ctx = ctypes.c_void_p()
+            st = L.ntf_admm_init_sparse(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
+                                        None, 0, _stream_handle(stream))
+            _lib.check(st, "ntf_admm_init_sparse")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        st = L.ntf_admm_init_sparse(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
+                                    ctypes.c_void_p(_ptr(self.workspace)), nbytes, _stream_handle(stream))
+        _lib.check(st, "ntf_admm_init_sparse", None)
+        self._ctx = ctx
+
+    def plan_info(self) -> dict:
+        """Algorithmic bytes of one sparse MTTKRP launch per mode."""
+        return sparse_pass_bytes(self.dims, self.F, self.nnz, self.opts.precision)
+
+
+def sparse_pass_bytes(dims, F: int, nnz: int, precision: int) -> dict:
+    """Bytes one sparse MTTKRP launch of each mode must move at least: the
+    sorted non-zeros (three int32 indices and the value), the two other
+    factors once, and W (FP64) written once."""
+    es = 8 if precision == PREC_F64 else 4
+    out = {}
+    for m, name in enumerate(("mode1", "mode2", "mode3")):
+        others = [d for q, d in enumerate(dims) if q != m]
+        out[name] = nnz * (12 + es) + (others[0] + others[1]) * F * es + dims[m] * F * 8
+    return out
 
 
 def inner_update(W, H, U, G, rho: float = 0.0, T: int = 1, eps_abs: float = 0.0,

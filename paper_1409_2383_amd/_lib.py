@@ -38,6 +38,19 @@ class Problem(ctypes.Structure):
     ]
 
 
+class SparseProblem(ctypes.Structure):
+    _fields_ = [
+        ("dims", c_int64 * 3),
+        ("F", c_int32),
+        ("x_dtype", c_int32),
+        ("nnz", c_int64),
+        ("idx", c_void_p),
+        ("val", c_void_p),
+        ("H", c_void_p * 3),
+        ("U", c_void_p * 3),
+    ]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [
         ("inner_iters", c_int32),
@@ -135,6 +148,9 @@ SIGNATURES = [
     ("ntf_admm_last_error", c_char_p, [c_void_p]),
     ("ntf_admm_workspace_bytes", c_size_t, [POINTER(Problem), POINTER(Opts)]),
     ("ntf_admm_init", c_int32, [POINTER(c_void_p), POINTER(Problem), POINTER(Opts), c_void_p, c_size_t, c_void_p]),
+    ("ntf_admm_sparse_workspace_bytes", c_size_t, [POINTER(SparseProblem), POINTER(Opts)]),
+    ("ntf_admm_init_sparse", c_int32, [POINTER(c_void_p), POINTER(SparseProblem), POINTER(Opts), c_void_p,
+                                       c_size_t, c_void_p]),
     ("ntf_admm_step", c_int32, [c_void_p, POINTER(Stats)]),
     ("ntf_admm_run", c_int32, [c_void_p, c_int32, c_int32, POINTER(Stats)]),
     ("ntf_admm_fit", c_int32, [c_void_p, POINTER(c_double)]),

@@ -50,6 +50,12 @@ struct Layout {
          gram[3] = {0, 0, 0}, ginv[3] = {0, 0, 0}, gpart = 0, rpart = 0, sumsq = 0, fitpart = 0,
          xr = 0, xj8 = 0, scale = 0, wx = 0, wy = 0, wact = 0, wscale = 0, wG[3] = {0, 0, 0},
          card = 0, total = 0;
+  // sparse tensors: per-mode sorted copies, MTTKRP segment carries, set-up sort scratch
+  size_t sp_row[3] = {0, 0, 0}, sp_ia[3] = {0, 0, 0}, sp_ib[3] = {0, 0, 0}, sp_val[3] = {0, 0, 0},
+         sp_meta = 0, sp_ch = 0, sp_ct = 0, sp_k0 = 0, sp_k1 = 0, sp_p0 = 0, sp_p1 = 0, sp_hist = 0,
+         sp_offs = 0, sp_tot = 0;
+  int64_t sp_nseg = 0;
+  int sp_S = 0;
 };
 
 const int kSumsqParts = 1024;
@@ -78,16 +84,41 @@ int cu_count() {
   return cached;
 }
 
-Layout make_layout(const Plan& p, const ntf_opts& o) {
+// nnz >= 0: a sparse tensor of nnz non-zeros (no dense buffers)
+Layout make_layout(const Plan& p, const ntf_opts& o, int64_t nnz = -1) {
   Layout L;
   Carver c;
   const size_t es = elem_size(p.prec);
   const int64_t F = p.F;
+  const bool sparse = nnz >= 0;
   L.state = c.take(sizeof(DevState));
-  L.T = c.take((size_t)(p.I * p.J * F) * es);
-  L.P1 = c.take((size_t)(p.I * p.nch1 * F) * es);
-  L.P2 = c.take((size_t)((int64_t)p.nich2 * p.J * F) * es);
-  L.P3 = c.take((size_t)((int64_t)p.nrc3 * p.K * F) * es);
+  if (!sparse) {
+    L.T = c.take((size_t)(p.I * p.J * F) * es);
+    L.P1 = c.take((size_t)(p.I * p.nch1 * F) * es);
+    L.P2 = c.take((size_t)((int64_t)p.nich2 * p.J * F) * es);
+    L.P3 = c.take((size_t)((int64_t)p.nrc3 * p.K * F) * es);
+  } else {
+    const size_t n = (size_t)nnz;
+    for (int m = 0; m < 3; ++m) {
+      L.sp_row[m] = c.take(n * 4);
+      L.sp_ia[m] = c.take(n * 4);
+      L.sp_ib[m] = c.take(n * 4);
+      L.sp_val[m] = c.take(n * es);
+    }
+    L.sp_S = sp_segment_len(p.FL);
+    L.sp_nseg = (nnz + L.sp_S - 1) / L.sp_S;
+    const size_t ns = (size_t)L.sp_nseg;
+    L.sp_meta = c.take(ns * 3 * 4);
+    L.sp_ch = c.take(ns * (size_t)F * es);
+    L.sp_ct = c.take(ns * (size_t)F * es);
+    L.sp_k0 = c.take(n * 8);
+    L.sp_k1 = c.take(n * 8);
+    L.sp_p0 = c.take(n * 4);
+    L.sp_p1 = c.take(n * 4);
+    L.sp_hist = c.take(sp_scan_len(nnz) * 4);
+    L.sp_offs = c.take(sp_scan_len(nnz) * 4);
+    L.sp_tot = c.take(sp_scan_chunks(nnz) * 4);
+  }
   const int64_t d[3] = {p.I, p.J, p.K};
   int maxblk = 1;
   for (int m = 0; m < 3; ++m) {
@@ -104,8 +135,12 @@ Layout make_layout(const Plan& p, const ntf_opts& o) {
   // before the update, FP64 [rows][F] each, for the largest mode
   L.card = c.take((size_t)(3 * std::max(p.I, std::max(p.J, p.K)) * F) * 8);
   // fit partials; also scratch for ntf_admm_mode_problem (two Grams + partials)
-  L.fitpart = c.take(std::max<size_t>((size_t)fit_parts(p) * 2, (size_t)(2 + maxblk) * F * F) * 8);
-  if (p.prec == PREC_BF16) {
+  // and for the sparse fit (three Grams + partials, then the non-zero partials)
+  if (!sparse)
+    L.fitpart = c.take(std::max<size_t>((size_t)fit_parts(p) * 2, (size_t)(2 + maxblk) * F * F) * 8);
+  else
+    L.fitpart = c.take(((size_t)(3 + maxblk) * F * F + 2 * (size_t)sp_fit_parts()) * 8);
+  if (p.prec == PREC_BF16 && !sparse) {
     L.xr = c.take((size_t)(p.I * p.J * p.Kp) * 2);
     L.xj8 = c.take((size_t)(p.I * p.JG * p.Kp3 * 8) * 2);
     L.scale = c.take((size_t)p.I * 4);
@@ -143,6 +178,8 @@ struct ntf_admm_ctx {
   bool warm_on = false;
   ntf_mlp warm{};
   ntf_constraints cons{};   // all zero: every factor non-negative
+  bool sparse = false;      // tensor given by its non-zeros (ntf_admm_init_sparse)
+  int64_t nnz = 0;
   std::string err;
 
   template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -161,6 +198,8 @@ struct ntf_admm_ctx {
       return NTF_E_HIP;                                                                \
     }                                                                                  \
   } while (0)
+
+static ntf_status validate_opts(const ntf_opts* o, std::string* why);
 
 static ntf_status validate(const ntf_problem* pr, const ntf_opts* o, std::string* why) {
   auto fail = [&](const char* m) {
@@ -182,6 +221,20 @@ static ntf_status validate(const ntf_problem* pr, const ntf_opts* o, std::string
     if (!pr->H[m] || !pr->U[m]) return fail("null factor or dual");
     if ((((uintptr_t)pr->H[m]) | ((uintptr_t)pr->U[m])) & 15) return fail("factor/dual not 16-byte aligned");
   }
+  {
+    const ntf_status vo = validate_opts(o, why);
+    if (vo != NTF_OK) return vo;
+  }
+  const int64_t I = pr->dims[0], J = pr->dims[1], K = pr->dims[2];
+  if (I * J > ((int64_t)1 << 40) || I * J * K > ((int64_t)1 << 46)) return fail("tensor too large");
+  return NTF_OK;
+}
+
+static ntf_status validate_opts(const ntf_opts* o, std::string* why) {
+  auto fail = [&](const char* m) {
+    if (why) *why = m;
+    return NTF_E_INVAL;
+  };
   if (o->inner_iters < 1) return fail("inner_iters must be >= 1");
   if (o->rho_policy < 0 || o->rho_policy > 2) return fail("unknown rho_policy");
   if (!(o->rho0 > 0.0)) return fail("rho0 must be > 0");
@@ -194,9 +247,50 @@ static ntf_status validate(const ntf_problem* pr, const ntf_opts* o, std::string
   for (int q = 0; q < 3; ++q)
     if (o->reserved[q] != 0) return fail("reserved fields must be zero");
   if (o->warm_hidden < 0 || o->warm_hidden > 1024) return fail("warm_hidden must be in [0, 1024]");
-  const int64_t I = pr->dims[0], J = pr->dims[1], K = pr->dims[2];
-  if (I * J > ((int64_t)1 << 40) || I * J * K > ((int64_t)1 << 46)) return fail("tensor too large");
   return NTF_OK;
+}
+
+static ntf_status validate_sparse(const ntf_sparse_problem* pr, const ntf_opts* o, std::string* why) {
+  auto fail = [&](const char* m, ntf_status st = NTF_E_INVAL) {
+    if (why) *why = m;
+    return st;
+  };
+  if (!pr || !o) return fail("null problem or options");
+  for (int m = 0; m < 3; ++m)
+    if (pr->dims[m] < 1 || pr->dims[m] > (int64_t)1 << 31) return fail("dims must be in [1, 2^31]");
+  if (pr->F < 1 || pr->F > 64) return fail("F must be in [1, 64]");
+  if (o->precision == NTF_PREC_BF16_MIXED)
+    return fail("sparse tensors run in NTF_PREC_F32 or NTF_PREC_F64", NTF_E_UNSUPPORTED);
+  if (o->precision != NTF_PREC_F32 && o->precision != NTF_PREC_F64) return fail("unknown precision");
+  if (pr->x_dtype != 0 && pr->x_dtype != 1) return fail("x_dtype must be 0 or 1");
+  if ((o->precision == NTF_PREC_F64) != (pr->x_dtype == 1)) return fail("x_dtype does not match precision");
+  if (pr->nnz < 0 || pr->nnz >= ((int64_t)1 << 31)) return fail("nnz must be in [0, 2^31)");
+  if (pr->nnz > 0 && (!pr->idx || !pr->val)) return fail("null coordinates or values");
+  if ((((uintptr_t)pr->idx) | ((uintptr_t)pr->val)) & 15) return fail("coordinates/values not 16-byte aligned");
+  if (sp_key_bits(pr->dims) > 64)
+    return fail("dims too large for the 64-bit sort key of the sparse set-up", NTF_E_UNSUPPORTED);
+  for (int m = 0; m < 3; ++m) {
+    if (!pr->H[m] || !pr->U[m]) return fail("null factor or dual");
+    if ((((uintptr_t)pr->H[m]) | ((uintptr_t)pr->U[m])) & 15) return fail("factor/dual not 16-byte aligned");
+  }
+  if (o->warm_hidden != 0) return fail("the learned warm start is not offered for sparse tensors", NTF_E_UNSUPPORTED);
+  return validate_opts(o, why);
+}
+
+// Plan of a sparse problem: only the inner-sweep and prepare geometry.
+static void make_plan_sparse(Plan& p, int prec, const int64_t dims[3], int F) {
+  p = Plan();
+  p.prec = prec;
+  p.I = dims[0];
+  p.J = dims[1];
+  p.K = dims[2];
+  p.F = F;
+  int FL = 4;
+  while (FL < F) FL <<= 1;
+  p.FL = FL;
+  p.rpb = inner_rows_per_block(FL);
+  for (int m = 0; m < 3; ++m) p.nblk_inner[m] = (int)((dims[m] + p.rpb - 1) / p.rpb);
+  p.nprep = (int)std::max<int64_t>(1, ((int64_t)F * F + 63) / 64);
 }
 
 extern "C" {
@@ -225,6 +319,13 @@ size_t ntf_admm_workspace_bytes(const ntf_problem* prob, const ntf_opts* opts) {
   Plan p;
   if (!make_plan(p, opts->precision, prob->dims, prob->F, 256)) return 0;
   return make_layout(p, *opts).total;
+}
+
+size_t ntf_admm_sparse_workspace_bytes(const ntf_sparse_problem* prob, const ntf_opts* opts) {
+  if (validate_sparse(prob, opts, nullptr) != NTF_OK) return 0;
+  Plan p;
+  make_plan_sparse(p, opts->precision, prob->dims, prob->F);
+  return make_layout(p, *opts, prob->nnz).total;
 }
 
 }  // extern "C"
@@ -368,8 +469,54 @@ static ntf_status enqueue_warm(ntf_admm_ctx* c, int m, hipStream_t ms) {
   return NTF_OK;
 }
 
+// Sparse MTTKRP of mode m into W (the other factors as the feed holds them).
+static hipError_t sparse_mttkrp(ntf_admm_ctx* c, int m, double* W, hipStream_t ms) {
+  const Plan& p = c->plan;
+  const int64_t d[3] = {p.I, p.J, p.K};
+  const int ma = (m == 0) ? 1 : 0, mb = (m == 2) ? 1 : 2;
+  SpModeArgs a;
+  a.row = c->at<int32_t>(c->lay.sp_row[m]);
+  a.ia = c->at<int32_t>(c->lay.sp_ia[m]);
+  a.ib = c->at<int32_t>(c->lay.sp_ib[m]);
+  a.val = c->ws + c->lay.sp_val[m];
+  a.Fa = c->feed(ma);
+  a.Fb = c->feed(mb);
+  a.f64 = c->hf64();
+  a.F = p.F;
+  a.FL = p.FL;
+  a.S = c->lay.sp_S;
+  a.n = c->nnz;
+  a.nseg = c->lay.sp_nseg;
+  a.rows = d[m];
+  a.W = W;
+  a.meta = c->at<int32_t>(c->lay.sp_meta);
+  a.carry_h = c->ws + c->lay.sp_ch;
+  a.carry_t = c->ws + c->lay.sp_ct;
+  return sp_mttkrp(a, ms);
+}
+
+// One outer iteration of a sparse tensor: per mode, the prepare step on s1
+// beside the sparse MTTKRP, then the inner sweep.
+static ntf_status enqueue_outer_sparse(ntf_admm_ctx* c, hipStream_t ms) {
+  const Plan& p = c->plan;
+  PrepArgs pa;
+  for (int m = 0; m < 3; ++m) {
+    NTF_HIP(c, hipEventRecord(m == 0 ? c->ev_fork : c->ev_inner[m - 1], ms));
+    NTF_HIP(c, hipStreamWaitEvent(c->s1, m == 0 ? c->ev_fork : c->ev_inner[m - 1], 0));
+    prep_args(c, m, pa);
+    NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
+    NTF_HIP(c, hipEventRecord(c->ev_prep[m], c->s1));
+    NTF_HIP(c, sparse_mttkrp(c, m, c->at<double>(c->lay.W[m]), ms));
+    NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[m], 0));
+    ntf_status st = enqueue_inner(c, m, ms);
+    if (st != NTF_OK) return st;
+  }
+  return NTF_OK;
+}
+
 // Enqueue one outer iteration on `ms` with the prepare kernels on s1.
 static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
+  if (c->sparse) return enqueue_outer_sparse(c, ms);
   const Plan& p = c->plan;
   const __bf16* xr = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xr) : nullptr;
   const __bf16* xj8 = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xj8) : nullptr;
@@ -496,6 +643,53 @@ static ntf_status fill_stats(ntf_admm_ctx* c, ntf_stats* st) {
 
 extern "C" {
 
+// Streams, events, the pinned state mirror and the device state block.
+static ntf_status ctx_setup(ntf_admm_ctx* c) {
+  NTF_HIP(c, hipStreamCreateWithFlags(&c->s1, hipStreamNonBlocking));
+  NTF_HIP(c, hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking));
+  NTF_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  for (int m = 0; m < 3; ++m) {
+    NTF_HIP(c, hipEventCreateWithFlags(&c->ev_inner[m], hipEventDisableTiming));
+    NTF_HIP(c, hipEventCreateWithFlags(&c->ev_prep[m], hipEventDisableTiming));
+  }
+  NTF_HIP(c, hipHostMalloc((void**)&c->host_state, sizeof(DevState), hipHostMallocDefault));
+  DevState init;
+  std::memset(&init, 0, sizeof(init));
+  for (int m = 0; m < 3; ++m) init.rho[m][0] = init.rho[m][1] = c->opts.rho0;
+  *c->host_state = init;
+  NTF_HIP(c, hipMemcpyAsync(c->dstate(), c->host_state, sizeof(DevState), hipMemcpyHostToDevice, c->s0));
+  return NTF_OK;
+}
+
+// Paper initialisation (the given factors seed the primal; auxiliary and
+// duals start at zero) and the Grams of the starting factors.
+static ntf_status ctx_seed(ntf_admm_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t d[3] = {p.I, p.J, p.K};
+  const size_t es = elem_size(p.prec);
+  if (c->opts.factor_source == 1) {
+    for (int m = 0; m < 3; ++m) {
+      NTF_HIP(c, hipMemcpyAsync(c->ws + c->lay.prim[m], c->prob.H[m], (size_t)(d[m] * p.F) * es,
+                                hipMemcpyDeviceToDevice, c->s0));
+      if (c->opts.paper_init) {
+        NTF_HIP(c, hipMemsetAsync(c->prob.H[m], 0, (size_t)(d[m] * p.F) * es, c->s0));
+        NTF_HIP(c, hipMemsetAsync(c->prob.U[m], 0, (size_t)(d[m] * p.F) * es, c->s0));
+      }
+    }
+  }
+  return compute_grams(c);
+}
+
+static ntf_status ctx_attach(ntf_admm_ctx* c, void* workspace, size_t ws_bytes, void* stream) {
+  if (!workspace || ((uintptr_t)workspace & 255)) return NTF_E_INVAL;
+  if (ws_bytes < c->lay.total) return NTF_E_WORKSPACE;
+  c->ws = reinterpret_cast<char*>(workspace);
+  c->s0 = reinterpret_cast<hipStream_t>(stream);
+  const char* ng = std::getenv("NTF_NO_GRAPH");
+  c->use_graph = !(ng && ng[0] == '1');
+  return NTF_OK;
+}
+
 ntf_status ntf_admm_init(ntf_admm_ctx** out, const ntf_problem* prob, const ntf_opts* opts,
                          void* workspace, size_t ws_bytes, void* stream) {
   if (!out) return NTF_E_INVAL;
@@ -513,55 +707,115 @@ ntf_status ntf_admm_init(ntf_admm_ctx** out, const ntf_problem* prob, const ntf_
     return NTF_E_UNSUPPORTED;
   }
   c->lay = make_layout(c->plan, c->opts);
-  if (!workspace || ((uintptr_t)workspace & 255)) {
-    delete c;
-    return NTF_E_INVAL;
-  }
-  if (ws_bytes < c->lay.total) {
-    delete c;
-    return NTF_E_WORKSPACE;
-  }
-  c->ws = reinterpret_cast<char*>(workspace);
-  c->s0 = reinterpret_cast<hipStream_t>(stream);
-  const char* ng = std::getenv("NTF_NO_GRAPH");
-  c->use_graph = !(ng && ng[0] == '1');
-  ntf_status st = [&]() -> ntf_status {
-    NTF_HIP(c, hipStreamCreateWithFlags(&c->s1, hipStreamNonBlocking));
-    NTF_HIP(c, hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking));
-    NTF_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-    for (int m = 0; m < 3; ++m) {
-      NTF_HIP(c, hipEventCreateWithFlags(&c->ev_inner[m], hipEventDisableTiming));
-      NTF_HIP(c, hipEventCreateWithFlags(&c->ev_prep[m], hipEventDisableTiming));
+  {
+    const ntf_status a = ctx_attach(c, workspace, ws_bytes, stream);
+    if (a != NTF_OK) {
+      delete c;
+      return a;
     }
-    NTF_HIP(c, hipHostMalloc((void**)&c->host_state, sizeof(DevState), hipHostMallocDefault));
+  }
+  ntf_status st = [&]() -> ntf_status {
+    ntf_status q = ctx_setup(c);
+    if (q != NTF_OK) return q;
     const Plan& p = c->plan;
-    // state block
-    DevState init;
-    std::memset(&init, 0, sizeof(init));
-    for (int m = 0; m < 3; ++m) init.rho[m][0] = init.rho[m][1] = c->opts.rho0;
-    *c->host_state = init;
-    NTF_HIP(c, hipMemcpyAsync(c->dstate(), c->host_state, sizeof(DevState), hipMemcpyHostToDevice, c->s0));
     // bfloat16 copies
     if (p.prec == PREC_BF16)
       NTF_HIP(c, launch_quantize((const float*)prob->X, p, c->at<__bf16>(c->lay.xr),
                                  c->at<__bf16>(c->lay.xj8), c->at<float>(c->lay.scale), c->s0));
     NTF_HIP(c, launch_sumsq(prob->X, prob->x_dtype, p.I * p.J * p.K, c->at<double>(c->lay.sumsq),
                             kSumsqParts, &c->dstate()->xnorm2, c->s0));
-    // paper initialisation: the given factors seed the primal; auxiliary and duals start at zero
-    const int64_t d[3] = {p.I, p.J, p.K};
-    const size_t es = elem_size(p.prec);
-    if (c->opts.factor_source == 1) {
-      for (int m = 0; m < 3; ++m) {
-        NTF_HIP(c, hipMemcpyAsync(c->ws + c->lay.prim[m], prob->H[m], (size_t)(d[m] * p.F) * es,
-                                  hipMemcpyDeviceToDevice, c->s0));
-        if (c->opts.paper_init) {
-          NTF_HIP(c, hipMemsetAsync(prob->H[m], 0, (size_t)(d[m] * p.F) * es, c->s0));
-          NTF_HIP(c, hipMemsetAsync(prob->U[m], 0, (size_t)(d[m] * p.F) * es, c->s0));
-        }
-      }
+    q = ctx_seed(c);
+    if (q != NTF_OK) return q;
+    NTF_HIP(c, hipStreamSynchronize(c->s0));
+    return NTF_OK;
+  }();
+  if (st != NTF_OK) {
+    g_init_err = c->err;
+    ntf_admm_destroy(c);
+    return st;
+  }
+  *out = c;
+  return NTF_OK;
+}
+
+ntf_status ntf_admm_init_sparse(ntf_admm_ctx** out, const ntf_sparse_problem* prob,
+                                const ntf_opts* opts, void* workspace, size_t ws_bytes,
+                                void* stream) {
+  if (!out) return NTF_E_INVAL;
+  *out = nullptr;
+  std::string why;
+  ntf_status vs = validate_sparse(prob, opts, &why);
+  g_init_err = why;
+  if (vs != NTF_OK) return vs;
+  ntf_admm_ctx* c = new (std::nothrow) ntf_admm_ctx();
+  if (!c) return NTF_E_HIP;
+  c->sparse = true;
+  c->nnz = prob->nnz;
+  std::memset(&c->prob, 0, sizeof(c->prob));
+  for (int m = 0; m < 3; ++m) {
+    c->prob.dims[m] = prob->dims[m];
+    c->prob.H[m] = prob->H[m];
+    c->prob.U[m] = prob->U[m];
+  }
+  c->prob.F = prob->F;
+  c->prob.x_dtype = prob->x_dtype;
+  c->opts = *opts;
+  make_plan_sparse(c->plan, opts->precision, prob->dims, prob->F);
+  c->lay = make_layout(c->plan, c->opts, prob->nnz);
+  {
+    const ntf_status a = ctx_attach(c, workspace, ws_bytes, stream);
+    if (a != NTF_OK) {
+      delete c;
+      return a;
     }
-    ntf_status g = compute_grams(c);
-    if (g != NTF_OK) return g;
+  }
+  ntf_status st = [&]() -> ntf_status {
+    ntf_status q = ctx_setup(c);
+    if (q != NTF_OK) return q;
+    DevState* ds = c->dstate();
+    const int64_t n = prob->nnz;
+    // coordinates in range before anything is built from them
+    NTF_HIP(c, sp_check(prob->idx, n, prob->dims, &ds->flag, c->s0));
+    int flag = 0;
+    NTF_HIP(c, hipMemcpyAsync(&c->host_state->flag, &ds->flag, sizeof(int), hipMemcpyDeviceToHost, c->s0));
+    NTF_HIP(c, hipStreamSynchronize(c->s0));
+    flag = c->host_state->flag;
+    if (flag & kSparseFlagRange) {
+      c->err = "a coordinate lies outside the tensor";
+      return NTF_E_INVAL;
+    }
+    for (int m = 0; m < 3; ++m) {
+      SpBuildArgs b;
+      b.idx = prob->idx;
+      b.val = prob->val;
+      b.val_f64 = prob->x_dtype;
+      b.n = n;
+      for (int q2 = 0; q2 < 3; ++q2) b.dims[q2] = prob->dims[q2];
+      b.mode = m;
+      b.k0 = c->at<uint64_t>(c->lay.sp_k0);
+      b.k1 = c->at<uint64_t>(c->lay.sp_k1);
+      b.p0 = c->at<uint32_t>(c->lay.sp_p0);
+      b.p1 = c->at<uint32_t>(c->lay.sp_p1);
+      b.hist = c->at<uint32_t>(c->lay.sp_hist);
+      b.offs = c->at<uint32_t>(c->lay.sp_offs);
+      b.tot = c->at<uint32_t>(c->lay.sp_tot);
+      b.row = c->at<int32_t>(c->lay.sp_row[m]);
+      b.ia = c->at<int32_t>(c->lay.sp_ia[m]);
+      b.ib = c->at<int32_t>(c->lay.sp_ib[m]);
+      b.val_out = c->ws + c->lay.sp_val[m];
+      b.flag = &ds->flag;
+      NTF_HIP(c, sp_build_mode(b, c->s0));
+    }
+    NTF_HIP(c, hipMemcpyAsync(&c->host_state->flag, &ds->flag, sizeof(int), hipMemcpyDeviceToHost, c->s0));
+    NTF_HIP(c, hipStreamSynchronize(c->s0));
+    if (c->host_state->flag & kSparseFlagDuplicate) {
+      c->err = "a coordinate is given more than once";
+      return NTF_E_INVAL;
+    }
+    NTF_HIP(c, launch_sumsq(c->ws + c->lay.sp_val[0], prob->x_dtype, n, c->at<double>(c->lay.sumsq),
+                            kSumsqParts, &ds->xnorm2, c->s0));
+    q = ctx_seed(c);
+    if (q != NTF_OK) return q;
     NTF_HIP(c, hipStreamSynchronize(c->s0));
     return NTF_OK;
   }();
@@ -607,12 +861,29 @@ ntf_status ntf_admm_fit(ntf_admm_ctx* c, double* rfe) {
   if (!c || !rfe) return NTF_E_INVAL;
   const Plan& p = c->plan;
   DevState* ds = c->dstate();
-  NTF_HIP(c, launch_fit(p, c->prob.X, c->prob.x_dtype, c->prob.H[0], c->prob.H[1], c->prob.H[2],
-                        c->hf64(), c->at<double>(c->lay.fitpart), ds->fit, c->s0, nullptr));
+  if (c->sparse) {
+    // Grams of the factors (FP64), then the non-zero terms
+    const int64_t d[3] = {p.I, p.J, p.K};
+    double* g = c->at<double>(c->lay.fitpart);
+    const int64_t FF = (int64_t)p.F * p.F;
+    double* gp = g + 3 * FF;
+    for (int m = 0; m < 3; ++m) {
+      NTF_HIP(c, launch_gram_part(c->prob.H[m], c->hf64(), d[m], p.F, p.rpb, 0, gp, c->s0));
+      NTF_HIP(c, launch_reduce_partials(gp, 1, FF, p.F, p.nblk_inner[m], p.F, p.F, g + m * FF, c->s0, 4));
+    }
+    double* fp = gp + (int64_t)std::max(p.nblk_inner[0], std::max(p.nblk_inner[1], p.nblk_inner[2])) * FF;
+    NTF_HIP(c, sp_fit(c->at<int32_t>(c->lay.sp_row[0]), c->at<int32_t>(c->lay.sp_ia[0]),
+                      c->at<int32_t>(c->lay.sp_ib[0]), c->ws + c->lay.sp_val[0], c->hf64(), c->prob.H[0],
+                      c->prob.H[1], c->prob.H[2], p.F, c->nnz, g, g + FF, g + 2 * FF, &ds->xnorm2, fp,
+                      ds->fit, c->s0));
+  } else {
+    NTF_HIP(c, launch_fit(p, c->prob.X, c->prob.x_dtype, c->prob.H[0], c->prob.H[1], c->prob.H[2],
+                          c->hf64(), c->at<double>(c->lay.fitpart), ds->fit, c->s0, nullptr));
+  }
   double h[2];
   NTF_HIP(c, hipMemcpyAsync(h, ds->fit, sizeof(h), hipMemcpyDeviceToHost, c->s0));
   NTF_HIP(c, hipStreamSynchronize(c->s0));
-  *rfe = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+  *rfe = h[1] > 0 ? std::sqrt(std::fmax(h[0], 0.0) / h[1]) : 0.0;
   return NTF_OK;
 }
 
@@ -681,6 +952,10 @@ ntf_status ntf_admm_set_state(ntf_admm_ctx* c, const void* buf, size_t bytes) {
 
 ntf_status ntf_admm_mttkrp(ntf_admm_ctx* c, int32_t mode, double* W_out) {
   if (!c || !W_out || mode < 0 || mode > 2) return NTF_E_INVAL;
+  if (c->sparse) {
+    NTF_HIP(c, sparse_mttkrp(c, mode, W_out, c->s0));
+    return NTF_OK;
+  }
   const Plan& p = c->plan;
   const __bf16* xr = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xr) : nullptr;
   const __bf16* xj8 = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xj8) : nullptr;
@@ -707,6 +982,10 @@ ntf_status ntf_admm_mttkrp(ntf_admm_ctx* c, int32_t mode, double* W_out) {
 
 ntf_status ntf_admm_launch_pass(ntf_admm_ctx* c, int32_t pass) {
   if (!c || pass < 0 || pass > 2) return NTF_E_INVAL;
+  if (c->sparse) {
+    NTF_HIP(c, sparse_mttkrp(c, pass, c->at<double>(c->lay.W[pass]), c->s0));
+    return NTF_OK;
+  }
   const Plan& p = c->plan;
   const __bf16* xr = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xr) : nullptr;
   const __bf16* xj8 = p.prec == PREC_BF16 ? c->at<__bf16>(c->lay.xj8) : nullptr;

@@ -148,6 +148,61 @@ hipError_t launch_card_project(const double* V, const double* X, const double* H
                                void* U, void* Pout, int h_f64, int64_t n, int64_t card,
                                double iters_total, double* resid_part, int nparts, hipStream_t s);
 
+// ---- sparse tensors (sparse.hip)
+constexpr int kSparseFlagRange = 16;      // a coordinate outside the tensor
+constexpr int kSparseFlagDuplicate = 32;  // a coordinate given twice
+
+int sp_key_bits(const int64_t dims[3]);   // bits of the packed (i_m, i_a, i_b) sort key
+int64_t sp_tiles(int64_t n);              // radix-sort tiles of n keys
+size_t sp_scan_len(int64_t n);            // digit-count entries per sort pass
+size_t sp_scan_chunks(int64_t n);         // scan chunk totals per sort pass
+int sp_segment_len(int FL);               // non-zeros per MTTKRP segment
+int sp_fit_parts();
+
+struct SpBuildArgs {
+  const int32_t* idx = nullptr;   // [n][3]
+  const void* val = nullptr;      // [n]
+  int val_f64 = 0;
+  int64_t n = 0;
+  int64_t dims[3] = {0, 0, 0};
+  int mode = 0;
+  uint64_t* k0 = nullptr;         // sort scratch: keys x2, permutations x2 [n]
+  uint64_t* k1 = nullptr;
+  uint32_t* p0 = nullptr;
+  uint32_t* p1 = nullptr;
+  uint32_t* hist = nullptr;       // [sp_scan_len]
+  uint32_t* offs = nullptr;       // [sp_scan_len]
+  uint32_t* tot = nullptr;        // [sp_scan_chunks]
+  int32_t* row = nullptr;         // outputs [n]
+  int32_t* ia = nullptr;
+  int32_t* ib = nullptr;
+  void* val_out = nullptr;
+  int* flag = nullptr;
+};
+hipError_t sp_check(const int32_t* idx, int64_t n, const int64_t dims[3], int* flag, hipStream_t s);
+hipError_t sp_build_mode(const SpBuildArgs& a, hipStream_t s);
+
+struct SpModeArgs {
+  const int32_t* row = nullptr;
+  const int32_t* ia = nullptr;
+  const int32_t* ib = nullptr;
+  const void* val = nullptr;
+  const void* Fa = nullptr;       // factor of the slower other mode
+  const void* Fb = nullptr;       // factor of the faster other mode
+  int f64 = 0;
+  int F = 0, FL = 0, S = 0;
+  int64_t n = 0, nseg = 0, rows = 0;
+  double* W = nullptr;            // [rows][F]
+  int32_t* meta = nullptr;        // [nseg][3]
+  void* carry_h = nullptr;        // [nseg][F] float (double for f64)
+  void* carry_t = nullptr;
+};
+hipError_t sp_mttkrp(const SpModeArgs& a, hipStream_t s);
+hipError_t sp_fit(const int32_t* row, const int32_t* ia, const int32_t* ib, const void* val, int f64,
+                  const void* A, const void* B, const void* C, int F, int64_t n, const double* g0,
+                  const double* g1, const double* g2, const double* xnorm2, double* part, double* out,
+                  hipStream_t s);
+
 // ---- learned warm start (mlp.hip)
 size_t mlp_param_count(int F, int Hd);
 hipError_t mlp_forward(const void* params, int f16, int F, int Hd, const float* X, int64_t B,

@@ -63,7 +63,8 @@ def _c_sizeof(struct_name):
 @pytest.mark.parametrize("cname,pyname", [("ntf_problem", "Problem"), ("ntf_opts", "Opts"),
                                           ("ntf_stats", "Stats"), ("ntf_mlp", "Mlp"), ("ntf_constraints", "Constraints"),
                                           ("ntf_batch_tile", "BatchTile"),
-                                          ("ntf_batch_info", "BatchInfo")])
+                                          ("ntf_batch_info", "BatchInfo"),
+                                          ("ntf_sparse_problem", "SparseProblem")])
 def test_struct_layouts_match(cname, pyname):
     from paper_1409_2383_amd import _lib
     assert _c_sizeof(cname) == ctypes.sizeof(getattr(_lib, pyname))
@@ -84,3 +85,30 @@ def test_status_strings_and_host_validation():
     assert L.ntf_admm_workspace_bytes(ctypes.byref(pr), ctypes.byref(op)) == 0
     assert L.ntf_inner_workspace_bytes(10, 0) == 0
     assert L.ntf_gram_workspace_bytes(10, 65) == 0
+
+
+def test_sparse_host_validation():
+    # workspace sizing of a sparse problem is host-only: valid problems get a
+    # size, invalid ones 0 (mixed precision is not offered for sparse tensors)
+    from paper_1409_2383_amd import _lib
+    L = _lib.lib()
+    pr = _lib.SparseProblem()
+    op = _lib.Opts()
+    pr.dims[0], pr.dims[1], pr.dims[2] = 1000, 500, 300
+    pr.F = 16
+    pr.nnz = 100000
+    pr.idx = 4096
+    pr.val = 8192
+    for n in range(3):
+        pr.H[n] = pr.U[n] = 16 * (n + 1)
+    op.inner_iters = 1
+    op.rho0 = 1.0
+    ws = L.ntf_admm_sparse_workspace_bytes(ctypes.byref(pr), ctypes.byref(op))
+    # three sorted copies of 16 bytes per non-zero and 24 bytes of sort scratch
+    assert ws >= 100000 * (3 * 16 + 24)
+    op.precision = 1
+    assert L.ntf_admm_sparse_workspace_bytes(ctypes.byref(pr), ctypes.byref(op)) == 0
+    op.precision = 0
+    pr.dims[0] = 1 << 31
+    pr.dims[1] = pr.dims[2] = 1 << 31
+    assert L.ntf_admm_sparse_workspace_bytes(ctypes.byref(pr), ctypes.byref(op)) == 0   # key > 64 bits

@@ -1,0 +1,159 @@
+"""GPU parity of the sparse-tensor path (Section IV-A, item 1) against the
+oracle, through the C ABI: the sorted set-up, the segmented MTTKRP of every
+mode, whole outer iterations, the fit, and the input checks.  FP64 results
+match to rounding order (1e-12 relative); FP32 products with FP32 segment
+sums to 2e-6."""
+import numpy as np
+import pytest
+
+import ntf_synth
+from oracle import ntf_oracle as orc
+from tests.gpu_helpers import rel, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_2383_amd as ntf
+    ntf.library_path()
+    return torch.device("cuda:0")
+
+
+def _sample(dims, F, nnz, seed, f64, skew=2.0):
+    s = ntf_synth.sparse_planted(dims, F, nnz, seed, skew=skew,
+                                 dtype=np.float64 if f64 else np.float32)
+    T = orc.SparseTensor(idx=s.idx, val=s.val.astype(np.float64), dims=s.dims)
+    H0 = ntf_synth.init_factors(s.dims, F, seed, dtype=np.float64 if f64 else np.float32)
+    return s, T, H0
+
+
+def _solver(ntf, s, H, f64, **kw):
+    idx = torch.from_numpy(s.idx).to("cuda")
+    val = torch.from_numpy(s.val).to("cuda")
+    prec = ntf.PREC_F64 if f64 else ntf.PREC_F32
+    return ntf.NtfAdmmSparse(idx, val, s.dims, H, opts=ntf.AdmmOptions(precision=prec, **kw))
+
+
+CASES = [
+    # dims, F, nnz, skew: several sort tiles and passes, rows cut by many
+    # segments (few heavy rows), empty rows, a ragged last segment
+    ((300, 200, 100), 5, 50000, 2.0),
+    ((3, 60, 70), 20, 8000, 1.0),
+    ((2000, 30, 1500), 33, 20000, 3.0),
+    ((64, 64, 64), 64, 30000, 1.5),
+    ((1, 1, 1), 4, 1, 1.0),
+]
+
+
+@pytest.mark.parametrize("f64", [True, False])
+@pytest.mark.parametrize("dims,F,nnz,skew", CASES)
+def test_sparse_mttkrp_matches_oracle(dev, dims, F, nnz, skew, f64):
+    import paper_1409_2383_amd as ntf
+    s, T, H0 = _sample(dims, F, nnz, 1200 + F, f64, skew)
+    H = to_dev([h.copy() for h in H0], dev)
+    sol = _solver(ntf, s, H, f64)
+    tol = 1e-12 if f64 else 2e-6
+    print(f"[sparse] mttkrp dims={dims} F={F} nnz={s.idx.shape[0]} f64={f64}", flush=True)
+    for m in range(3):
+        W = sol.mttkrp(m).cpu().numpy()
+        ref = orc.mttkrp_sparse(T, [h.astype(np.float64) for h in H0], m)
+        scale = np.maximum(np.abs(ref), np.abs(ref).max() * 1e-3 + 1e-300)
+        err = np.max(np.abs(W - ref) / scale)
+        assert err < tol, (m, err)
+        # rows without non-zeros are exactly zero
+        empty = np.bincount(s.idx[:, m], minlength=dims[m]) == 0
+        assert not np.any(W[empty])
+    sol.close()
+
+
+def test_sparse_mttkrp_is_deterministic(dev):
+    import paper_1409_2383_amd as ntf
+    s, T, H0 = _sample((500, 400, 300), 16, 60000, 1300, False, 2.5)
+    outs = []
+    for _ in range(2):
+        H = to_dev([h.copy() for h in H0], dev)
+        sol = _solver(ntf, s, H, False)
+        outs.append([sol.mttkrp(m).cpu().numpy() for m in range(3)])
+        sol.close()
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("dims,F,nnz,T_in,src", [((60, 50, 40), 6, 9000, 3, 0),
+                                                 ((200, 30, 90), 12, 20000, 1, 1)])
+def test_sparse_outer_steps_match_oracle(dev, dims, F, nnz, T_in, src):
+    import paper_1409_2383_amd as ntf
+    s, T, H0 = _sample(dims, F, nnz, 1400 + F, True)
+    H = to_dev([h.copy() for h in H0], dev)
+    sol = _solver(ntf, s, H, True, inner_iters=T_in, factor_source=src)
+    st = orc.init_state([h.copy() for h in H0])
+    opts = orc.Opts(inner_iters=T_in, factor_source=src)
+    for it in range(4):
+        sol.step()
+        torch.cuda.synchronize()
+        orc.outer_step(T, st, opts)
+        for n in range(3):
+            e = rel(H[n].cpu().numpy(), st.H[n])
+            assert e < 1e-11 * (10 ** it), (it, n, e)
+    r_gpu = sol.fit()
+    r_orc = orc.rfe_sparse(T, st.H)
+    assert r_gpu == pytest.approx(r_orc, rel=1e-9)
+    print(f"[sparse] {dims} F={F}: RFE gpu {r_gpu:.6f} oracle {r_orc:.6f}", flush=True)
+    sol.close()
+
+
+def test_sparse_fp32_run_tracks_the_oracle(dev):
+    import paper_1409_2383_amd as ntf
+    s, T, H0 = _sample((120, 100, 80), 8, 30000, 1500, False)
+    H = to_dev([h.copy() for h in H0], dev)
+    sol = _solver(ntf, s, H, False, inner_iters=5)
+    sol.run(30, stats=False)
+    r_gpu = sol.fit()
+    st = orc.init_state([h.astype(np.float64) for h in H0])
+    orc.run(T, st, orc.Opts(inner_iters=5), 30)
+    r_orc = orc.rfe_sparse(T, st.H)
+    print(f"[sparse] fp32 30 iterations: RFE gpu {r_gpu:.6f} oracle {r_orc:.6f}", flush=True)
+    assert abs(r_gpu - r_orc) < 1e-4 * r_orc
+    sol.close()
+
+
+def test_sparse_fit_equals_dense_definition_on_a_small_tensor(dev):
+    import paper_1409_2383_amd as ntf
+    s, T, H0 = _sample((12, 10, 9), 3, 300, 1600, True)
+    H = to_dev([h.copy() for h in H0], dev)
+    sol = _solver(ntf, s, H, True)
+    assert sol.fit() == pytest.approx(orc.rfe(orc.densify(T), H0), rel=1e-12)
+    sol.close()
+
+
+def test_sparse_empty_tensor_and_input_errors(dev):
+    import paper_1409_2383_amd as ntf
+    dims, F = (10, 11, 12), 3
+    H0 = ntf_synth.init_factors(dims, F, 1700)
+    H = to_dev([h.copy() for h in H0], dev)
+    idx = torch.zeros((0, 3), dtype=torch.int32, device=dev)
+    val = torch.zeros((0,), dtype=torch.float64, device=dev)
+    sol = ntf.NtfAdmmSparse(idx, val, dims, H, opts=ntf.AdmmOptions(precision=ntf.PREC_F64))
+    for m in range(3):
+        assert not torch.any(sol.mttkrp(m))
+    sol.close()
+    good = np.array([[0, 0, 0], [9, 10, 11], [3, 4, 5]], dtype=np.int32)
+    v = torch.ones(3, dtype=torch.float64, device=dev)
+    for bad in (np.array([[0, 0, 0], [9, 10, 12], [3, 4, 5]], dtype=np.int32),    # out of range
+                np.array([[0, 0, 0], [-1, 0, 0], [3, 4, 5]], dtype=np.int32),     # negative
+                np.array([[0, 0, 0], [3, 4, 5], [3, 4, 5]], dtype=np.int32)):     # repeated
+        with pytest.raises(ntf.NtfError):
+            ntf.NtfAdmmSparse(torch.from_numpy(bad).to(dev), v, dims, to_dev([h.copy() for h in H0], dev),
+                              opts=ntf.AdmmOptions(precision=ntf.PREC_F64))
+    sol = ntf.NtfAdmmSparse(torch.from_numpy(good).to(dev), v, dims, to_dev([h.copy() for h in H0], dev),
+                            opts=ntf.AdmmOptions(precision=ntf.PREC_F64))
+    sol.step()
+    sol.close()
+    with pytest.raises(ntf.NtfError):
+        ntf.NtfAdmmSparse(torch.from_numpy(good).to(dev), v.float(), dims,
+                          to_dev([h.astype(np.float32) for h in H0], dev),
+                          opts=ntf.AdmmOptions(precision=ntf.PREC_BF16_MIXED))
