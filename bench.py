@@ -32,6 +32,10 @@ WORKLOADS = {
                arms=("fp32", "mixed")),
     "c3": dict(dims=(1000, 800, 600), F=64, dist="exponential", snr=30.0, clip=False, T=10,
                config=3, arms=("mixed", "fp32")),
+    # sparse: dims, solver rank F, about nnz distinct non-zeros drawn with a skewed
+    # (power-law-like) slice distribution, values from a rank-`planted` model
+    "s1": dict(dims=(12092, 9184, 28818), F=32, nnz=76_000_000, planted=8, skew=2.0, T=10, config=6,
+               arms=("fp32",)),
     # batched: n tensors, every mode uniform on [lo, hi], F uniform on 5..40
     "c5": dict(n=256, lo=50, hi=500, ranks=tuple(range(5, 41)), dist="uniform", snr=20.0,
                clip=False, T=10, config=5, arms=("mixed",)),
@@ -286,9 +290,11 @@ def summarize(args):
     wl = WORKLOADS[args.workload]
     arm = wl["arms"][0]
     if args.write_kernel_stats:
+        # the traced run's own flags: pass the same --steps/--warmup/--pass-reps here
         cmd = (f"rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- python3 "
-               f"<repo>/bench.py --workload {args.workload} --steps 20 --warmup 3 --pass-reps 20 "
-               f"--no-cpu-baseline --single-arm")
+               f"<repo>/bench.py --workload {args.workload} --steps {args.steps} --warmup {args.warmup} "
+               f"--pass-reps {args.pass_reps} --no-cpu-baseline"
+               + ("" if args.workload == "s1" else " --single-arm"))
         write_kernel_stats(args.write_kernel_stats, args.workload, arm, cmd)
     if args.write_traffic:
         import paper_1409_2383_amd as ntf
@@ -432,6 +438,108 @@ def cpu_baseline_batched(jobs, T, shapes, min_seconds=10.0):
             "seconds_measured": dt}
 
 
+def cpu_baseline_sparse(T, H0, Topt, sample_nnz, min_seconds=10.0):
+    """The FP64 oracle on the host: outer iterations on the first
+    `sample_nnz` non-zeros (the order is random), with the MTTKRP share
+    scaled to all non-zeros (its cost is linear in nnz; the rest is not)."""
+    from oracle import ntf_oracle as orc
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        cores = os.cpu_count() or 1
+    n = T.idx.shape[0]
+    S = min(n, sample_nnz)
+    sub = orc.SparseTensor(idx=T.idx[:S], val=T.val[:S], dims=T.dims)
+    st = orc.init_state([h.astype(np.float64) for h in H0])
+    opts = orc.Opts(inner_iters=Topt)
+    t_outer, t_mk, iters = 0.0, 0.0, 0
+    while t_outer < min_seconds and iters < 5:
+        t0 = time.perf_counter()
+        orc.outer_step(sub, st, opts)
+        t_outer += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for m in range(3):
+            orc.mttkrp_sparse(sub, st.H, m)
+        t_mk += time.perf_counter() - t0
+        iters += 1
+    per_iter = (t_outer + t_mk * (n / S - 1.0)) / iters
+    return {"value": 1.0 / per_iter, "unit": "outer_iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{iters} outer iteration(s) (T={Topt}) of the FP64 oracle on the first {S} of "
+                      f"{n} non-zeros ({t_outer:.1f} s), its three MTTKRPs (timed again, "
+                      f"{t_mk / iters:.2f} s per iteration) scaled by {n}/{S}",
+            "seconds_measured": t_outer + t_mk}
+
+
+def bench_sparse(args):
+    """Sparse workload: one outer iteration is three sparse MTTKRPs (one per
+    mode, from the sorted copies) plus the dense per-mode work."""
+    import torch
+    import ntf_synth
+    import paper_1409_2383_amd as ntf
+    from oracle import ntf_oracle as orc
+    ntf.library_path()
+    dev = torch.device("cuda:0")
+    wl = WORKLOADS[args.workload]
+    dims, F, T = wl["dims"], wl["F"], wl["T"]
+    seed = ntf_synth.config_seed(wl["config"])
+    log(f"[bench] generating sparse {dims} nnz~{wl['nnz']} seed {seed}")
+    t0 = time.perf_counter()
+    s = ntf_synth.sparse_planted(dims, wl["planted"], wl["nnz"], seed, skew=wl["skew"], dtype=np.float32)
+    H0 = ntf_synth.init_factors(dims, F, seed, dtype=np.float32)
+    nnz = int(s.idx.shape[0])
+    log(f"[bench] {nnz} non-zeros ready in {time.perf_counter() - t0:.1f} s")
+    idx = torch.from_numpy(s.idx).to(dev)
+    val = torch.from_numpy(s.val).to(dev)
+    H = [torch.from_numpy(h).to(dev) for h in H0]
+    t0 = time.perf_counter()
+    solver = ntf.NtfAdmmSparse(idx, val, dims, H, opts=ntf.AdmmOptions(inner_iters=T, precision=ntf.PREC_F32))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    del idx, val
+    ms, wall = time_steps(torch, solver, args.steps, args.warmup)
+    st = torch.cuda.current_stream()
+    passes = {}
+    for m, name in enumerate(("mode1", "mode2", "mode3")):
+        solver.launch_pass(m)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(args.pass_reps):
+            solver.launch_pass(m)
+        e1.record(st)
+        torch.cuda.synchronize()
+        passes[name] = e0.elapsed_time(e1) / args.pass_reps
+    nbytes = solver.plan_info()
+    rfe = solver.fit()
+    solver.close()
+    log(f"[bench] sparse: {ms:.3f} ms/step, MTTKRP {passes}, set-up {setup_s:.2f} s, RFE {rfe:.4f}")
+    dom = max(passes, key=lambda k: passes[k])
+    achieved = nbytes[dom] / (passes[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"sparse MTTKRP {dom}",
+                "algorithmic_bytes_per_launch": nbytes[dom], "avg_launch_ms": passes[dom]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        Tor = orc.SparseTensor(idx=s.idx, val=s.val.astype(np.float64), dims=tuple(dims))
+        log("[bench] CPU oracle baseline on a sample of the non-zeros")
+        cpu = cpu_baseline_sparse(Tor, H0, T, 3_000_000)
+    line = {
+        "metric": "NTF outer iters/s, sparse tensor",
+        "value": 1e3 / ms, "unit": "outer_iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, dims))} sparse, {nnz} non-zeros (skew {wl['skew']}), "
+                               f"F={F}, T={T} inner iters, fp32",
+                   "dims": list(dims), "nnz": nnz, "F": F, "inner_iters": T},
+        "roofline": roofline, "cpu_baseline": cpu,
+        "mttkrp_ms": passes, "mttkrp_bytes": nbytes,
+        "mttkrp_gbs": {k: nbytes[k] / (passes[k] * 1e-3) / 1e9 for k in passes},
+        "setup_s": setup_s, "rfe": rfe,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,6 +570,9 @@ def main():
 
     if args.workload == "c5":
         bench_batched(args)
+        return
+    if args.workload == "s1":
+        bench_sparse(args)
         return
     import torch
     import ntf_synth

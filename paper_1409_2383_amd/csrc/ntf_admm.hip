@@ -51,9 +51,9 @@ struct Layout {
          xr = 0, xj8 = 0, scale = 0, wx = 0, wy = 0, wact = 0, wscale = 0, wG[3] = {0, 0, 0},
          card = 0, total = 0;
   // sparse tensors: per-mode sorted copies, MTTKRP segment carries, set-up sort scratch
-  size_t sp_row[3] = {0, 0, 0}, sp_ia[3] = {0, 0, 0}, sp_ib[3] = {0, 0, 0}, sp_val[3] = {0, 0, 0},
-         sp_meta = 0, sp_ch = 0, sp_ct = 0, sp_k0 = 0, sp_k1 = 0, sp_p0 = 0, sp_p1 = 0, sp_hist = 0,
-         sp_offs = 0, sp_tot = 0;
+  size_t sp_rec[3] = {0, 0, 0}, sp_val[3] = {0, 0, 0}, sp_tail[3] = {0, 0, 0}, sp_len[3] = {0, 0, 0},
+         sp_heavy[3] = {0, 0, 0}, sp_nheavy = 0, sp_ch = 0, sp_ct = 0, sp_k0 = 0, sp_k1 = 0, sp_p0 = 0,
+         sp_p1 = 0, sp_hist = 0, sp_offs = 0, sp_tot = 0;
   int64_t sp_nseg = 0;
   int sp_S = 0;
 };
@@ -99,16 +99,17 @@ Layout make_layout(const Plan& p, const ntf_opts& o, int64_t nnz = -1) {
     L.P3 = c.take((size_t)((int64_t)p.nrc3 * p.K * F) * es);
   } else {
     const size_t n = (size_t)nnz;
-    for (int m = 0; m < 3; ++m) {
-      L.sp_row[m] = c.take(n * 4);
-      L.sp_ia[m] = c.take(n * 4);
-      L.sp_ib[m] = c.take(n * 4);
-      L.sp_val[m] = c.take(n * es);
-    }
-    L.sp_S = sp_segment_len(p.FL);
+    L.sp_S = sp_segment_len(p.F, p.prec == PREC_F64 ? 1 : 0);
     L.sp_nseg = (nnz + L.sp_S - 1) / L.sp_S;
     const size_t ns = (size_t)L.sp_nseg;
-    L.sp_meta = c.take(ns * 3 * 4);
+    for (int m = 0; m < 3; ++m) {
+      L.sp_rec[m] = c.take(n * 16);
+      if (p.prec == PREC_F64) L.sp_val[m] = c.take(n * 8);
+      L.sp_tail[m] = c.take(ns * 4);
+      L.sp_len[m] = c.take(ns * 4);
+      L.sp_heavy[m] = c.take(ns * 4);
+    }
+    L.sp_nheavy = c.take(3 * 4);
     L.sp_ch = c.take(ns * (size_t)F * es);
     L.sp_ct = c.take(ns * (size_t)F * es);
     L.sp_k0 = c.take(n * 8);
@@ -180,6 +181,7 @@ struct ntf_admm_ctx {
   ntf_constraints cons{};   // all zero: every factor non-negative
   bool sparse = false;      // tensor given by its non-zeros (ntf_admm_init_sparse)
   int64_t nnz = 0;
+  int nheavy[3] = {0, 0, 0};  // rows cut into more than kLightPieces segment pieces, per mode
   std::string err;
 
   template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -475,21 +477,21 @@ static hipError_t sparse_mttkrp(ntf_admm_ctx* c, int m, double* W, hipStream_t m
   const int64_t d[3] = {p.I, p.J, p.K};
   const int ma = (m == 0) ? 1 : 0, mb = (m == 2) ? 1 : 2;
   SpModeArgs a;
-  a.row = c->at<int32_t>(c->lay.sp_row[m]);
-  a.ia = c->at<int32_t>(c->lay.sp_ia[m]);
-  a.ib = c->at<int32_t>(c->lay.sp_ib[m]);
-  a.val = c->ws + c->lay.sp_val[m];
+  a.rec = c->at<int4>(c->lay.sp_rec[m]);
+  a.val = c->hf64() ? (const void*)(c->ws + c->lay.sp_val[m]) : nullptr;
   a.Fa = c->feed(ma);
   a.Fb = c->feed(mb);
   a.f64 = c->hf64();
   a.F = p.F;
-  a.FL = p.FL;
   a.S = c->lay.sp_S;
   a.n = c->nnz;
   a.nseg = c->lay.sp_nseg;
   a.rows = d[m];
   a.W = W;
-  a.meta = c->at<int32_t>(c->lay.sp_meta);
+  a.tail = c->at<int32_t>(c->lay.sp_tail[m]);
+  a.len = c->at<int32_t>(c->lay.sp_len[m]);
+  a.heavy = c->at<int32_t>(c->lay.sp_heavy[m]);
+  a.nheavy = c->nheavy[m];
   a.carry_h = c->ws + c->lay.sp_ch;
   a.carry_t = c->ws + c->lay.sp_ct;
   return sp_mttkrp(a, ms);
@@ -799,21 +801,29 @@ ntf_status ntf_admm_init_sparse(ntf_admm_ctx** out, const ntf_sparse_problem* pr
       b.hist = c->at<uint32_t>(c->lay.sp_hist);
       b.offs = c->at<uint32_t>(c->lay.sp_offs);
       b.tot = c->at<uint32_t>(c->lay.sp_tot);
-      b.row = c->at<int32_t>(c->lay.sp_row[m]);
-      b.ia = c->at<int32_t>(c->lay.sp_ia[m]);
-      b.ib = c->at<int32_t>(c->lay.sp_ib[m]);
-      b.val_out = c->ws + c->lay.sp_val[m];
+      b.rec = c->at<int4>(c->lay.sp_rec[m]);
+      b.val_out = prob->x_dtype ? (void*)(c->ws + c->lay.sp_val[m]) : nullptr;
+      b.S = c->lay.sp_S;
+      b.nseg = c->lay.sp_nseg;
+      b.tail = c->at<int32_t>(c->lay.sp_tail[m]);
+      b.len = c->at<int32_t>(c->lay.sp_len[m]);
+      b.heavy = c->at<int32_t>(c->lay.sp_heavy[m]);
+      b.nheavy = c->at<uint32_t>(c->lay.sp_nheavy) + m;
       b.flag = &ds->flag;
       NTF_HIP(c, sp_build_mode(b, c->s0));
     }
+    uint32_t nh[3] = {0, 0, 0};
+    if (n > 0)
+      NTF_HIP(c, hipMemcpyAsync(nh, c->at<uint32_t>(c->lay.sp_nheavy), sizeof(nh), hipMemcpyDeviceToHost, c->s0));
     NTF_HIP(c, hipMemcpyAsync(&c->host_state->flag, &ds->flag, sizeof(int), hipMemcpyDeviceToHost, c->s0));
     NTF_HIP(c, hipStreamSynchronize(c->s0));
     if (c->host_state->flag & kSparseFlagDuplicate) {
       c->err = "a coordinate is given more than once";
       return NTF_E_INVAL;
     }
-    NTF_HIP(c, launch_sumsq(c->ws + c->lay.sp_val[0], prob->x_dtype, n, c->at<double>(c->lay.sumsq),
-                            kSumsqParts, &ds->xnorm2, c->s0));
+    for (int m = 0; m < 3; ++m) c->nheavy[m] = (int)nh[m];
+    NTF_HIP(c, launch_sumsq(prob->val, prob->x_dtype, n, c->at<double>(c->lay.sumsq), kSumsqParts,
+                            &ds->xnorm2, c->s0));
     q = ctx_seed(c);
     if (q != NTF_OK) return q;
     NTF_HIP(c, hipStreamSynchronize(c->s0));
@@ -872,10 +882,9 @@ ntf_status ntf_admm_fit(ntf_admm_ctx* c, double* rfe) {
       NTF_HIP(c, launch_reduce_partials(gp, 1, FF, p.F, p.nblk_inner[m], p.F, p.F, g + m * FF, c->s0, 4));
     }
     double* fp = gp + (int64_t)std::max(p.nblk_inner[0], std::max(p.nblk_inner[1], p.nblk_inner[2])) * FF;
-    NTF_HIP(c, sp_fit(c->at<int32_t>(c->lay.sp_row[0]), c->at<int32_t>(c->lay.sp_ia[0]),
-                      c->at<int32_t>(c->lay.sp_ib[0]), c->ws + c->lay.sp_val[0], c->hf64(), c->prob.H[0],
-                      c->prob.H[1], c->prob.H[2], p.F, c->nnz, g, g + FF, g + 2 * FF, &ds->xnorm2, fp,
-                      ds->fit, c->s0));
+    NTF_HIP(c, sp_fit(c->at<int4>(c->lay.sp_rec[0]), c->hf64() ? (const void*)(c->ws + c->lay.sp_val[0]) : nullptr,
+                      c->hf64(), c->prob.H[0], c->prob.H[1], c->prob.H[2], p.F, c->nnz, g, g + FF, g + 2 * FF,
+                      &ds->xnorm2, fp, ds->fit, c->s0));
   } else {
     NTF_HIP(c, launch_fit(p, c->prob.X, c->prob.x_dtype, c->prob.H[0], c->prob.H[1], c->prob.H[2],
                           c->hf64(), c->at<double>(c->lay.fitpart), ds->fit, c->s0, nullptr));

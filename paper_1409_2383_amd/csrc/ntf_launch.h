@@ -151,14 +151,19 @@ hipError_t launch_card_project(const double* V, const double* X, const double* H
 // ---- sparse tensors (sparse.hip)
 constexpr int kSparseFlagRange = 16;      // a coordinate outside the tensor
 constexpr int kSparseFlagDuplicate = 32;  // a coordinate given twice
+constexpr int kLightPieces = 16;          // cut rows of more pieces are reduced by a block each
 
 int sp_key_bits(const int64_t dims[3]);   // bits of the packed (i_m, i_a, i_b) sort key
 int64_t sp_tiles(int64_t n);              // radix-sort tiles of n keys
 size_t sp_scan_len(int64_t n);            // digit-count entries per sort pass
 size_t sp_scan_chunks(int64_t n);         // scan chunk totals per sort pass
-int sp_segment_len(int FL);               // non-zeros per MTTKRP segment
+int sp_segment_len(int F, int f64);       // non-zeros per MTTKRP segment
 int sp_fit_parts();
 
+// Set-up of one mode: sort, records, segment structure.  Records are
+// (row, a, b, value bits) with a, b the other two indices in mode order; FP64
+// values go to val_out.  tail/len/heavy describe the rows cut by segment
+// boundaries (see sparse.hip); *nheavy gets the number of heavy cut rows.
 struct SpBuildArgs {
   const int32_t* idx = nullptr;   // [n][3]
   const void* val = nullptr;      // [n]
@@ -173,35 +178,39 @@ struct SpBuildArgs {
   uint32_t* hist = nullptr;       // [sp_scan_len]
   uint32_t* offs = nullptr;       // [sp_scan_len]
   uint32_t* tot = nullptr;        // [sp_scan_chunks]
-  int32_t* row = nullptr;         // outputs [n]
-  int32_t* ia = nullptr;
-  int32_t* ib = nullptr;
-  void* val_out = nullptr;
+  int4* rec = nullptr;            // outputs [n]
+  void* val_out = nullptr;        // FP64 only
+  int S = 0;
+  int64_t nseg = 0;
+  int32_t* tail = nullptr;        // [nseg]
+  int32_t* len = nullptr;         // [nseg]
+  int32_t* heavy = nullptr;       // [nseg]
+  uint32_t* nheavy = nullptr;     // device, one value
   int* flag = nullptr;
 };
 hipError_t sp_check(const int32_t* idx, int64_t n, const int64_t dims[3], int* flag, hipStream_t s);
 hipError_t sp_build_mode(const SpBuildArgs& a, hipStream_t s);
 
 struct SpModeArgs {
-  const int32_t* row = nullptr;
-  const int32_t* ia = nullptr;
-  const int32_t* ib = nullptr;
-  const void* val = nullptr;
+  const int4* rec = nullptr;
+  const void* val = nullptr;      // FP64 values (null for FP32: in the records)
   const void* Fa = nullptr;       // factor of the slower other mode
   const void* Fb = nullptr;       // factor of the faster other mode
   int f64 = 0;
-  int F = 0, FL = 0, S = 0;
+  int F = 0, S = 0;
   int64_t n = 0, nseg = 0, rows = 0;
   double* W = nullptr;            // [rows][F]
-  int32_t* meta = nullptr;        // [nseg][3]
+  const int32_t* tail = nullptr;  // segment structure of this mode
+  const int32_t* len = nullptr;
+  const int32_t* heavy = nullptr;
+  int nheavy = 0;
   void* carry_h = nullptr;        // [nseg][F] float (double for f64)
   void* carry_t = nullptr;
 };
 hipError_t sp_mttkrp(const SpModeArgs& a, hipStream_t s);
-hipError_t sp_fit(const int32_t* row, const int32_t* ia, const int32_t* ib, const void* val, int f64,
-                  const void* A, const void* B, const void* C, int F, int64_t n, const double* g0,
-                  const double* g1, const double* g2, const double* xnorm2, double* part, double* out,
-                  hipStream_t s);
+hipError_t sp_fit(const int4* rec, const void* val, int f64, const void* A, const void* B, const void* C,
+                  int F, int64_t n, const double* g0, const double* g1, const double* g2,
+                  const double* xnorm2, double* part, double* out, hipStream_t s);
 
 // ---- learned warm start (mlp.hip)
 size_t mlp_param_count(int F, int Hd);

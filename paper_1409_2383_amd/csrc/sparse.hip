@@ -193,21 +193,76 @@ __global__ __launch_bounds__(kTileThreads) void k_rs_scatter(const uint64_t* __r
   }
 }
 
+// Sorted keys -> records (row, a, b, value bits) of one mode; FP64 values go
+// to their own array.  A repeated key is a repeated coordinate.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sp_unpack(const uint64_t* __restrict__ key,
                                                    const uint32_t* __restrict__ perm,
                                                    const T* __restrict__ vin, int64_t n, int sa, int sb,
-                                                   int32_t* __restrict__ row, int32_t* __restrict__ ia,
-                                                   int32_t* __restrict__ ib, T* __restrict__ vout,
+                                                   int4* __restrict__ rec, T* __restrict__ vout,
                                                    int* __restrict__ flag) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
   const uint64_t k = key[e];
-  row[e] = (int32_t)(k >> sa);
-  ia[e] = (int32_t)((k >> sb) & ((1ull << (sa - sb)) - 1ull));
-  ib[e] = (int32_t)(k & ((1ull << sb) - 1ull));
-  vout[e] = vin[perm[e]];
+  const T v = vin[perm[e]];
+  int4 r;
+  r.x = (int32_t)(k >> sa);
+  r.y = (int32_t)((k >> sb) & ((1ull << (sa - sb)) - 1ull));
+  r.z = (int32_t)(k & ((1ull << sb) - 1ull));
+  if constexpr (sizeof(T) == 4) {
+    r.w = __float_as_int((float)v);
+  } else {
+    r.w = 0;
+    vout[e] = v;
+  }
+  rec[e] = r;
   if (e > 0 && key[e - 1] == k) atomicOr(flag, kSparseFlagDuplicate);
+}
+
+// Segment structure of one mode (depends on the sparsity pattern only):
+// tail[s] = the row that starts its cut in segment s (its last row goes on
+// into s + 1 and did not come from s - 1 as the whole segment), else -1;
+// whole[s] = 1 if segment s is one row that began earlier and goes on.
+__global__ __launch_bounds__(256) void k_sp_segmeta(const int4* __restrict__ rec, int64_t n, int S,
+                                                    int64_t nseg, int32_t* __restrict__ tail,
+                                                    int32_t* __restrict__ whole) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= nseg) return;
+  const int64_t e0 = s * S, e1 = min(n, e0 + (int64_t)S);
+  const int32_t first = rec[e0].x, last = rec[e1 - 1].x;
+  const bool head = e0 > 0 && rec[e0 - 1].x == first;
+  const bool goes_on = e1 < n && rec[e1].x == last;
+  const bool w = head && goes_on && first == last;
+  whole[s] = w ? 1 : 0;
+  tail[s] = (goes_on && !w) ? last : -1;
+}
+
+// Pieces of each cut row: its tail piece in segment s and the head pieces of
+// s+1 .. t, t the first segment after s that is not whole.  len[s] = t - s + 1
+// (0 where no cut row starts); heavy[s] = 1 if len[s] > kLightPieces.
+__global__ __launch_bounds__(256) void k_sp_chain(const int32_t* __restrict__ tail,
+                                                  const int32_t* __restrict__ whole, int64_t nseg,
+                                                  int32_t* __restrict__ len, uint32_t* __restrict__ heavy) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= nseg) return;
+  int32_t L = 0;
+  if (tail[s] >= 0) {
+    int64_t t = s + 1;
+    while (t < nseg - 1 && whole[t]) ++t;
+    L = (int32_t)(t - s + 1);
+  }
+  len[s] = L;
+  heavy[s] = (L > kLightPieces) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_sp_compact(const uint32_t* __restrict__ flag,
+                                                    const uint32_t* __restrict__ pos, int64_t nseg,
+                                                    int32_t* __restrict__ list,
+                                                    uint32_t* __restrict__ count) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= nseg) return;
+  if (flag[s]) list[pos[s]] = (int32_t)s;
+  if (s == nseg - 1) *count = pos[s] + flag[s];
 }
 
 // ---------------------------------------------------------------- MTTKRP
@@ -217,126 +272,225 @@ struct SpAcc { typedef float type; };
 template <>
 struct SpAcc<double> { typedef double type; };
 
-// Segment seg = blockIdx.x * (256 / FL) + group.  Per segment: head_row (the
-// first row, if it began in an earlier segment, else -1), tail_row (the last
-// row, if it goes on into the next segment and is not the head, else -1) and
-// whole (1 if the segment is one row that began earlier and goes on).
-template <typename T, int FL>
-__global__ __launch_bounds__(256) void k_sp_mttkrp(const int32_t* __restrict__ row,
-                                                   const int32_t* __restrict__ ia,
-                                                   const int32_t* __restrict__ ib,
-                                                   const T* __restrict__ val, const T* __restrict__ Fa,
-                                                   const T* __restrict__ Fb, int F, int64_t n, int S,
-                                                   int64_t nseg, double* __restrict__ W,
-                                                   int32_t* __restrict__ meta,
+// CPL consecutive columns of a row as one 16-byte load (CPL = 1: scalar)
+template <typename T, int CPL>
+__device__ __forceinline__ void load_cols(const T* __restrict__ p, T (&x)[CPL]) {
+  if constexpr (CPL == 1) {
+    x[0] = *p;
+  } else {
+    typedef T V __attribute__((ext_vector_type(CPL)));
+    const V v = *reinterpret_cast<const V*>(p);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) x[c] = v[c];
+  }
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ void store_cols(T* __restrict__ p, const T (&x)[CPL]) {
+  if constexpr (CPL == 1) {
+    *p = x[0];
+  } else {
+    typedef T V __attribute__((ext_vector_type(CPL)));
+    V v;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) v[c] = x[c];
+    *reinterpret_cast<V*>(p) = v;
+  }
+}
+
+template <int CPL>
+__device__ __forceinline__ void store_w(double* __restrict__ p, const float (&x)[CPL]) {
+  double d[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) d[c] = (double)x[c];
+  if constexpr (CPL == 4) {
+    typedef double V2 __attribute__((ext_vector_type(2)));
+    *reinterpret_cast<V2*>(p) = V2{d[0], d[1]};
+    *reinterpret_cast<V2*>(p + 2) = V2{d[2], d[3]};
+  } else {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) p[c] = d[c];
+  }
+}
+template <int CPL>
+__device__ __forceinline__ void store_w(double* __restrict__ p, const double (&x)[CPL]) {
+  store_cols<double, CPL>(p, x);
+}
+
+// Segment seg = blockIdx.x * (256 / VL) + group; a group of VL lanes, lane j
+// owning columns j*CPL .. j*CPL + CPL - 1, walks the segment in batches of VL
+// records (lane j loads record b0 + j, the group reads them back by
+// shuffles).  Rows inside the segment go to W; the first row, when it began
+// in an earlier segment, to carry_h[seg]; the last row, when it goes on into
+// the next segment (and is not that first row), to carry_t[seg].
+template <typename T, int VL, int CPL>
+__global__ __launch_bounds__(256) void k_sp_mttkrp(const int4* __restrict__ rec, const T* __restrict__ val,
+                                                   const T* __restrict__ Fa, const T* __restrict__ Fb, int F,
+                                                   int64_t n, int S, int64_t nseg, double* __restrict__ W,
                                                    typename SpAcc<T>::type* __restrict__ carry_h,
                                                    typename SpAcc<T>::type* __restrict__ carry_t) {
   typedef typename SpAcc<T>::type A;
-  constexpr int NG = 256 / FL;
-  constexpr int U = 8;
-  const int grp = threadIdx.x / FL, f = threadIdx.x - grp * FL;
+  constexpr int NG = 256 / VL;
+  constexpr int U = VL < 8 ? VL : 8;
+  const int grp = threadIdx.x / VL, j = threadIdx.x - grp * VL;
   const int64_t seg = (int64_t)blockIdx.x * NG + grp;
   if (seg >= nseg) return;   // no block barriers below
-  const bool col = f < F;
+  const int c0 = j * CPL;
+  const bool col = c0 < F;
   const int64_t e0 = seg * S, e1 = min(n, e0 + (int64_t)S);
-  const int32_t prev_row = e0 > 0 ? row[e0 - 1] : -1;
-  const int32_t next_row = e1 < n ? row[e1] : -1;
-  int32_t cur = row[e0];
+  const int32_t prev_row = e0 > 0 ? rec[e0 - 1].x : -1;
+  const int32_t next_row = e1 < n ? rec[e1].x : -1;
+  int32_t cur = rec[e0].x;
   const bool head = cur == prev_row;
   bool first = true;
-  A acc = 0;
-  for (int64_t b0 = e0; b0 < e1; b0 += FL) {
-    const int64_t e = b0 + f;
+  A acc[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = 0;
+  for (int64_t b0 = e0; b0 < e1; b0 += VL) {
+    const int64_t e = b0 + j;
     const bool ok = e < e1;
-    const int32_t rl = ok ? row[e] : 0, al = ok ? ia[e] : 0, bl = ok ? ib[e] : 0;
-    const T vl = ok ? val[e] : T(0);
-    const int cnt = (int)min((int64_t)FL, e1 - b0);
+    const int4 r = ok ? rec[e] : int4{0, 0, 0, 0};
+    T vl;
+    if constexpr (sizeof(T) == 4) vl = __int_as_float(r.w);
+    else vl = ok ? val[e] : T(0);
+    const int cnt = (int)min((int64_t)VL, e1 - b0);
     for (int u0 = 0; u0 < cnt; u0 += U) {
       int32_t rr[U];
-      A pv[U];
+      A pv[U][CPL];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         const int u = u0 + q;
-        rr[q] = __shfl(rl, u, FL);
-        const int32_t a = __shfl(al, u, FL), b = __shfl(bl, u, FL);
-        const T v = __shfl(vl, u, FL);
-        const bool live = (u < cnt) && col;
-        const T xa = live ? Fa[(int64_t)a * F + f] : T(0);
-        const T xb = live ? Fb[(int64_t)b * F + f] : T(0);
-        pv[q] = (A)v * (A)xa * (A)xb;
+        rr[q] = __shfl(r.x, u, VL);
+        const int32_t a = __shfl(r.y, u, VL), b = __shfl(r.z, u, VL);
+        const T v = __shfl(vl, u, VL);
+        T xa[CPL], xb[CPL];
+        if ((u < cnt) && col) {
+          load_cols<T, CPL>(Fa + (int64_t)a * F + c0, xa);
+          load_cols<T, CPL>(Fb + (int64_t)b * F + c0, xb);
+        } else {
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) xa[c] = xb[c] = T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) pv[q][c] = (A)v * (A)xa[c] * (A)xb[c];
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         if (u0 + q >= cnt) break;
         if (rr[q] != cur) {
           if (col) {
-            if (first && head) carry_h[seg * F + f] = acc;
-            else W[(int64_t)cur * F + f] = (double)acc;
+            if (first && head) store_cols<A, CPL>(carry_h + seg * F + c0, acc);
+            else store_w<CPL>(W + (int64_t)cur * F + c0, acc);
           }
           first = false;
-          acc = 0;
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) acc[c] = 0;
           cur = rr[q];
         }
-        acc += pv[q];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] += pv[q][c];
       }
     }
   }
-  const bool tail = cur == next_row;
-  const bool whole = first && head && tail;
   if (col) {
-    if (first && head) carry_h[seg * F + f] = acc;
-    else if (tail) carry_t[seg * F + f] = acc;
-    else W[(int64_t)cur * F + f] = (double)acc;
-  }
-  if (f == 0) {
-    meta[3 * seg] = head ? prev_row : -1;
-    meta[3 * seg + 1] = (tail && !(first && head)) ? cur : -1;
-    meta[3 * seg + 2] = whole ? 1 : 0;
+    if (first && head) store_cols<A, CPL>(carry_h + seg * F + c0, acc);
+    else if (cur == next_row) store_cols<A, CPL>(carry_t + seg * F + c0, acc);
+    else store_w<CPL>(W + (int64_t)cur * F + c0, acc);
   }
 }
 
-// Rows cut by segment boundaries: the tail piece of the segment where the row
-// began, then the head pieces of the following segments in order.
-template <typename A, int FL>
-__global__ __launch_bounds__(256) void k_sp_fixup(const int32_t* __restrict__ meta,
+// Cut rows of at most kLightPieces pieces: one group per segment, the pieces
+// summed in segment order.
+template <typename A, int VL, int CPL>
+__global__ __launch_bounds__(256) void k_sp_fixup(const int32_t* __restrict__ tail,
+                                                  const int32_t* __restrict__ len,
                                                   const A* __restrict__ carry_h,
                                                   const A* __restrict__ carry_t, int F, int64_t nseg,
                                                   double* __restrict__ W) {
-  constexpr int NG = 256 / FL;
-  const int grp = threadIdx.x / FL, f = threadIdx.x - grp * FL;
+  constexpr int NG = 256 / VL;
+  const int grp = threadIdx.x / VL, j = threadIdx.x - grp * VL;
   const int64_t seg = (int64_t)blockIdx.x * NG + grp;
-  if (seg >= nseg || f >= F) return;
-  const int32_t R = meta[3 * seg + 1];
-  if (R < 0) return;
-  double acc = (double)carry_t[seg * F + f];
-  for (int64_t t = seg + 1; t < nseg; ++t) {
-    acc += (double)carry_h[t * F + f];
-    if (!meta[3 * t + 2]) break;
+  const int c0 = j * CPL;
+  if (seg >= nseg || c0 >= F) return;
+  const int32_t L = len[seg];
+  if (L == 0 || L > kLightPieces) return;
+  A x[CPL];
+  load_cols<A, CPL>(carry_t + seg * F + c0, x);
+  double acc[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = (double)x[c];
+  for (int p = 1; p < L; ++p) {
+    load_cols<A, CPL>(carry_h + (seg + p) * F + c0, x);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] += (double)x[c];
   }
-  W[(int64_t)R * F + f] = acc;
+  store_w<CPL>(W + (int64_t)tail[seg] * F + c0, acc);
+}
+
+// Cut rows of more pieces: one block per row; group g of VL lanes sums the
+// pieces p = g, g + NG, ... in order, then the group sums are added in group
+// order.
+template <typename A, int VL, int CPL>
+__global__ __launch_bounds__(256) void k_sp_fixup_heavy(const int32_t* __restrict__ list,
+                                                        const int32_t* __restrict__ tail,
+                                                        const int32_t* __restrict__ len,
+                                                        const A* __restrict__ carry_h,
+                                                        const A* __restrict__ carry_t, int F,
+                                                        double* __restrict__ W) {
+  constexpr int NG = 256 / VL;
+  __shared__ double part[NG][VL * CPL];
+  const int grp = threadIdx.x / VL, j = threadIdx.x - grp * VL;
+  const int c0 = j * CPL;
+  const int64_t s = list[blockIdx.x];
+  const int32_t L = len[s];
+  double acc[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
+  if (c0 < F) {
+    for (int p = grp; p < L; p += NG) {
+      A x[CPL];
+      load_cols<A, CPL>((p == 0 ? carry_t + s * F : carry_h + (s + p) * F) + c0, x);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[c] += (double)x[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) part[grp][c0 + c] = acc[c];
+  __syncthreads();
+  if (grp == 0 && c0 < F) {
+    double t[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      t[c] = part[0][c0 + c];
+      for (int g = 1; g < NG; ++g) t[c] += part[g][c0 + c];
+    }
+    store_w<CPL>(W + (int64_t)tail[s] * F + c0, t);
+  }
 }
 
 // ---------------------------------------------------------------- fit
 
 // Per block: sum over its non-zeros of (x - m)^2 and m^2, m the model value
-// sum_f A[i,f] B[j,f] C[k,f]; one thread per non-zero.
+// sum_f A[i,f] B[j,f] C[k,f]; one thread per non-zero (mode-1 records).
 template <typename T>
-__global__ __launch_bounds__(256) void k_sp_fit(const int32_t* __restrict__ row,
-                                                const int32_t* __restrict__ ia,
-                                                const int32_t* __restrict__ ib,
-                                                const T* __restrict__ val, const T* __restrict__ A,
-                                                const T* __restrict__ B, const T* __restrict__ C, int F,
-                                                int64_t n, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_sp_fit(const int4* __restrict__ rec, const T* __restrict__ val,
+                                                const T* __restrict__ A, const T* __restrict__ B,
+                                                const T* __restrict__ C, int F, int64_t n,
+                                                double* __restrict__ part) {
   __shared__ double red[4][2];
   double s0 = 0.0, s1 = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-    const T* a = A + (int64_t)row[e] * F;
-    const T* b = B + (int64_t)ia[e] * F;
-    const T* c = C + (int64_t)ib[e] * F;
+    const int4 r = rec[e];
+    const T* a = A + (int64_t)r.x * F;
+    const T* b = B + (int64_t)r.y * F;
+    const T* c = C + (int64_t)r.z * F;
     double m = 0.0;
     for (int q = 0; q < F; ++q) m += (double)a[q] * (double)b[q] * (double)c[q];
-    const double r = (double)val[e] - m;
-    s0 += r * r;
+    double x;
+    if constexpr (sizeof(T) == 4) x = (double)__int_as_float(r.w);
+    else x = (double)val[e];
+    const double d = x - m;
+    s0 += d * d;
     s1 += m * m;
   }
   s0 = group_sum(s0, 64);
@@ -385,29 +539,40 @@ __global__ __launch_bounds__(256) void k_sp_fit_final(const double* __restrict__
   }
 }
 
-template <typename T, int FL>
-hipError_t sp_mttkrp_fl(const SpModeArgs& a, hipStream_t s) {
+template <typename T, int VL, int CPL>
+hipError_t sp_mttkrp_v(const SpModeArgs& a, hipStream_t s) {
   typedef typename SpAcc<T>::type A;
-  constexpr int NG = 256 / FL;
+  constexpr int NG = 256 / VL;
   const unsigned grid = (unsigned)((a.nseg + NG - 1) / NG);
-  hipLaunchKernelGGL((k_sp_mttkrp<T, FL>), dim3(grid), dim3(256), 0, s, a.row, a.ia, a.ib,
-                     (const T*)a.val, (const T*)a.Fa, (const T*)a.Fb, a.F, a.n, a.S, a.nseg, a.W,
-                     a.meta, (A*)a.carry_h, (A*)a.carry_t);
+  hipLaunchKernelGGL((k_sp_mttkrp<T, VL, CPL>), dim3(grid), dim3(256), 0, s, a.rec, (const T*)a.val,
+                     (const T*)a.Fa, (const T*)a.Fb, a.F, a.n, a.S, a.nseg, a.W, (A*)a.carry_h,
+                     (A*)a.carry_t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sp_fixup<A, FL>), dim3(grid), dim3(256), 0, s, a.meta, (const A*)a.carry_h,
-                     (const A*)a.carry_t, a.F, a.nseg, a.W);
+  hipLaunchKernelGGL((k_sp_fixup<A, VL, CPL>), dim3(grid), dim3(256), 0, s, a.tail, a.len,
+                     (const A*)a.carry_h, (const A*)a.carry_t, a.F, a.nseg, a.W);
+  e = hipGetLastError();
+  if (e != hipSuccess || a.nheavy == 0) return e;
+  hipLaunchKernelGGL((k_sp_fixup_heavy<A, VL, CPL>), dim3((unsigned)a.nheavy), dim3(256), 0, s, a.heavy,
+                     a.tail, a.len, (const A*)a.carry_h, (const A*)a.carry_t, a.F, a.W);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t sp_mttkrp_t(const SpModeArgs& a, int FL, hipStream_t s) {
-  switch (FL) {
-    case 4: return sp_mttkrp_fl<T, 4>(a, s);
-    case 8: return sp_mttkrp_fl<T, 8>(a, s);
-    case 16: return sp_mttkrp_fl<T, 16>(a, s);
-    case 32: return sp_mttkrp_fl<T, 32>(a, s);
-    default: return sp_mttkrp_fl<T, 64>(a, s);
+// lanes per non-zero for a rank and a column width
+int lanes_for(int F, int cpl) {
+  int v = 1;
+  while (v * cpl < F) v <<= 1;
+  return v < 4 ? 4 : v;
+}
+
+template <typename T, int CPL>
+hipError_t sp_mttkrp_c(const SpModeArgs& a, hipStream_t s) {
+  switch (lanes_for(a.F, CPL)) {
+    case 4: return sp_mttkrp_v<T, 4, CPL>(a, s);
+    case 8: return sp_mttkrp_v<T, 8, CPL>(a, s);
+    case 16: return sp_mttkrp_v<T, 16, CPL>(a, s);
+    case 32: return sp_mttkrp_v<T, 32, CPL>(a, s);
+    default: return sp_mttkrp_v<T, 64, CPL>(a, s);
   }
 }
 
@@ -421,7 +586,12 @@ size_t sp_scan_len(int64_t n) { return (size_t)256 * (size_t)sp_tiles(n); }
 
 size_t sp_scan_chunks(int64_t n) { return (sp_scan_len(n) + kTile - 1) / kTile; }
 
-int sp_segment_len(int FL) { return 16 * FL; }
+int sp_cols_per_lane(int F, int f64) {
+  const int v = f64 ? 2 : 4;   // 16-byte loads of a factor row need F * elem % 16 == 0
+  return (F % v == 0) ? v : 1;
+}
+
+int sp_segment_len(int F, int f64) { return 64 * lanes_for(F, sp_cols_per_lane(F, f64)); }
 
 hipError_t sp_check(const int32_t* idx, int64_t n, const int64_t dims[3], int* flag, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -463,31 +633,46 @@ hipError_t sp_build_mode(const SpBuildArgs& a, hipStream_t s) {
   }
   if (a.val_f64)
     hipLaunchKernelGGL(k_sp_unpack<double>, dim3(g256), dim3(256), 0, s, kin, pin, (const double*)a.val, n,
-                       sa, sb, a.row, a.ia, a.ib, (double*)a.val_out, a.flag);
+                       sa, sb, a.rec, (double*)a.val_out, a.flag);
   else
     hipLaunchKernelGGL(k_sp_unpack<float>, dim3(g256), dim3(256), 0, s, kin, pin, (const float*)a.val, n, sa,
-                       sb, a.row, a.ia, a.ib, (float*)a.val_out, a.flag);
+                       sb, a.rec, (float*)nullptr, a.flag);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // segment structure and the list of heavy cut rows
+  const int64_t nseg = a.nseg;
+  const unsigned gs = (unsigned)((nseg + 255) / 256);
+  int32_t* whole = reinterpret_cast<int32_t*>(a.p1 == pin ? a.p0 : a.p1);   // free permutation buffer
+  uint32_t* flags = reinterpret_cast<uint32_t*>(a.k0 == kin ? a.k1 : a.k0);  // free key buffer
+  hipLaunchKernelGGL(k_sp_segmeta, dim3(gs), dim3(256), 0, s, a.rec, n, a.S, nseg, a.tail, whole);
+  hipLaunchKernelGGL(k_sp_chain, dim3(gs), dim3(256), 0, s, a.tail, whole, nseg, a.len, flags);
+  const unsigned nch = (unsigned)((nseg + kTile - 1) / kTile);
+  hipLaunchKernelGGL(k_scan_chunk, dim3(nch), dim3(kTileThreads), 0, s, flags, nseg, a.offs, a.tot);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTileThreads), 0, s, a.tot, (int64_t)nch);
+  hipLaunchKernelGGL(k_scan_add, dim3(gs), dim3(256), 0, s, a.offs, nseg, a.tot);
+  hipLaunchKernelGGL(k_sp_compact, dim3(gs), dim3(256), 0, s, flags, a.offs, nseg, a.heavy, a.nheavy);
   return hipGetLastError();
 }
 
 hipError_t sp_mttkrp(const SpModeArgs& a, hipStream_t s) {
   hipError_t e = launch_fill(a.W, a.rows * a.F, 0.0, s);
   if (e != hipSuccess || a.n <= 0) return e;
-  return a.f64 ? sp_mttkrp_t<double>(a, a.FL, s) : sp_mttkrp_t<float>(a, a.FL, s);
+  const int cpl = sp_cols_per_lane(a.F, a.f64);
+  if (a.f64) return cpl == 2 ? sp_mttkrp_c<double, 2>(a, s) : sp_mttkrp_c<double, 1>(a, s);
+  return cpl == 4 ? sp_mttkrp_c<float, 4>(a, s) : sp_mttkrp_c<float, 1>(a, s);
 }
 
 int sp_fit_parts() { return 1024; }
 
-hipError_t sp_fit(const int32_t* row, const int32_t* ia, const int32_t* ib, const void* val, int f64,
-                  const void* A, const void* B, const void* C, int F, int64_t n, const double* g0,
-                  const double* g1, const double* g2, const double* xnorm2, double* part, double* out,
-                  hipStream_t s) {
+hipError_t sp_fit(const int4* rec, const void* val, int f64, const void* A, const void* B, const void* C,
+                  int F, int64_t n, const double* g0, const double* g1, const double* g2,
+                  const double* xnorm2, double* part, double* out, hipStream_t s) {
   const int nparts = sp_fit_parts();
   if (f64)
-    hipLaunchKernelGGL(k_sp_fit<double>, dim3(nparts), dim3(256), 0, s, row, ia, ib, (const double*)val,
+    hipLaunchKernelGGL(k_sp_fit<double>, dim3(nparts), dim3(256), 0, s, rec, (const double*)val,
                        (const double*)A, (const double*)B, (const double*)C, F, n, part);
   else
-    hipLaunchKernelGGL(k_sp_fit<float>, dim3(nparts), dim3(256), 0, s, row, ia, ib, (const float*)val,
+    hipLaunchKernelGGL(k_sp_fit<float>, dim3(nparts), dim3(256), 0, s, rec, (const float*)nullptr,
                        (const float*)A, (const float*)B, (const float*)C, F, n, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -46,6 +46,9 @@ CASES = [
     ((2000, 30, 1500), 33, 20000, 3.0),
     ((64, 64, 64), 64, 30000, 1.5),
     ((1, 1, 1), 4, 1, 1.0),
+    # two mode-1 rows of ~20000 non-zeros: each cut into far more pieces than
+    # the per-segment fix-up takes (the block-per-row reduction)
+    ((2, 200, 300), 8, 40000, 1.0),
 ]
 
 
