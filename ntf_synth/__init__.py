@@ -26,7 +26,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 __all__ = ["PlantedTensor", "planted", "init_factors", "config_seed", "batch_shapes",
-           "SparseSample", "sparse_planted"]
+           "SparseSample", "sparse_planted", "planted_nway"]
 
 
 @dataclass
@@ -175,3 +175,50 @@ def sparse_planted(dims: Sequence[int], F: int, nnz: int, seed: int, *, skew: fl
     order = rng.permutation(n)
     return SparseSample(idx=np.ascontiguousarray(idx[order]), val=val[order].astype(dtype),
                         dims=(I, J, K), A0=A0, B0=B0, C0=C0, sigma=sigma)
+
+
+def planted_nway(dims: Sequence[int], F: int, seed: int, *, dist: str = "uniform",
+                 snr_db: Optional[float] = None, sigma2: Optional[float] = None,
+                 dtype=np.float32, slab_chunk: int = 8):
+    """Planted non-negative rank-F tensor of any order N >= 3 (the data model
+    of Section II extended as in Appendix A) plus Gaussian noise.
+
+    Draw order from ``default_rng(seed)``: the N factors (row-major, mode
+    order), then the noise in C storage order.  Returns (X, factors, sigma).
+    Noise as in ``planted``."""
+    dims = tuple(int(d) for d in dims)
+    if len(dims) < 3 or min(dims) < 1 or F < 1:
+        raise ValueError("need N >= 3 positive dims and F >= 1")
+    if snr_db is not None and sigma2 is not None:
+        raise ValueError("give snr_db or sigma2, not both")
+    rng = np.random.default_rng(seed)
+    fac = [_draw_factor(rng, d, F, dist) for d in dims]
+    # rows of the trailing modes' outer products, C order (last mode fastest)
+    tail = fac[-1]
+    for g in reversed(fac[1:-1]):
+        tail = (g[:, None, :] * tail[None, :, :]).reshape(-1, F)
+    rest = tail.shape[0]
+
+    def slab(i0, i1):
+        # X0[i, ...] = sum_f A0[i,f] (outer product of the other factors' column f)
+        return fac[0][i0:i1] @ tail.T
+
+    clean_norm2 = 0.0
+    for i0 in range(0, dims[0], slab_chunk):
+        sl = slab(i0, min(dims[0], i0 + slab_chunk))
+        clean_norm2 += float(np.dot(sl.ravel(), sl.ravel()))
+    n = int(np.prod(dims))
+    if snr_db is not None:
+        sigma = math.sqrt(clean_norm2 / (n * 10.0 ** (snr_db / 10.0)))
+    elif sigma2 is not None:
+        sigma = math.sqrt(sigma2)
+    else:
+        sigma = 0.0
+    X = np.empty((dims[0], rest), dtype=dtype)
+    for i0 in range(0, dims[0], slab_chunk):
+        i1 = min(dims[0], i0 + slab_chunk)
+        sl = slab(i0, i1)
+        if sigma > 0.0:
+            sl = sl + sigma * rng.standard_normal(sl.shape)
+        X[i0:i1] = sl.astype(dtype)
+    return X.reshape(dims), fac, sigma

@@ -78,33 +78,32 @@ def khatri_rao(P: np.ndarray, Q: np.ndarray) -> np.ndarray:
 
 
 def unfold(X: np.ndarray, n: int) -> np.ndarray:
-    """Matrix unfolding X^(n), column order matching eq. f_X_matr.
+    """Matrix unfolding X^(n), column order matching eq. f_X_matr for three
+    modes and Appendix A for N modes: the remaining modes index the columns
+    with the first of them fastest and the last slowest.
 
     X^(1) = A (C (.) B)^T : column index k*J + j
     X^(2) = B (C (.) A)^T : column index k*I + i
     X^(3) = C (B (.) A)^T : column index j*I + i
+    (order 4: X^(1) = A (D (.) (C (.) B))^T, and so on)
     """
     X = np.asarray(X, dtype=np.float64)
-    I, J, K = X.shape
-    if n == 0:
-        return X.transpose(0, 2, 1).reshape(I, K * J)
-    if n == 1:
-        return X.transpose(1, 2, 0).reshape(J, K * I)
-    if n == 2:
-        return X.transpose(2, 1, 0).reshape(K, J * I)
-    raise ValueError("mode must be 0, 1 or 2")
+    if not 0 <= n < X.ndim:
+        raise ValueError("mode out of range")
+    others = [m for m in range(X.ndim) if m != n]
+    return X.transpose([n] + others[::-1]).reshape(X.shape[n], -1)
 
 
 def kr_for_mode(factors: Sequence[np.ndarray], n: int) -> np.ndarray:
-    """The Khatri-Rao matrix that multiplies X^(n) in eq. ADMM_NTF_ALS_C."""
-    A, B, C = factors
-    if n == 0:
-        return khatri_rao(C, B)
-    if n == 1:
-        return khatri_rao(C, A)
-    if n == 2:
-        return khatri_rao(B, A)
-    raise ValueError("mode must be 0, 1 or 2")
+    """The Khatri-Rao matrix that multiplies X^(n) in eq. ADMM_NTF_ALS_C
+    (Appendix A for N modes): the other factors, the last one slowest."""
+    if not 0 <= n < len(factors):
+        raise ValueError("mode out of range")
+    others = [m for m in range(len(factors)) if m != n]
+    K = np.asarray(factors[others[-1]], dtype=np.float64)
+    for m in reversed(others[:-1]):
+        K = khatri_rao(K, factors[m])
+    return K
 
 
 def mttkrp(X: np.ndarray, factors: Sequence[np.ndarray], n: int) -> np.ndarray:
@@ -165,11 +164,15 @@ def rfe_sparse(T: SparseTensor, factors: Sequence[np.ndarray]) -> float:
 
 
 def reconstruct(factors: Sequence[np.ndarray]) -> np.ndarray:
-    """[A, B, C] = sum_f a_f o b_f o c_f (Section II), summed term by term."""
-    A, B, C = (np.asarray(f, dtype=np.float64) for f in factors)
-    out = np.zeros((A.shape[0], B.shape[0], C.shape[0]))
-    for f in range(A.shape[1]):
-        out += np.multiply.outer(np.multiply.outer(A[:, f], B[:, f]), C[:, f])
+    """[A, B, C] = sum_f a_f o b_f o c_f (Section II; any number of factors,
+    Appendix A), summed term by term."""
+    fac = [np.asarray(f, dtype=np.float64) for f in factors]
+    out = np.zeros(tuple(f.shape[0] for f in fac))
+    for f in range(fac[0].shape[1]):
+        term = fac[0][:, f]
+        for g in fac[1:]:
+            term = np.multiply.outer(term, g[:, f])
+        out += term
     return out
 
 
@@ -196,9 +199,10 @@ def gram(H: np.ndarray) -> np.ndarray:
 
 
 def gram_hadamard(factors: Sequence[np.ndarray], n: int) -> np.ndarray:
-    """G_n = Hadamard product of H_m^T H_m over m != n (Section IV-A, item 2)."""
+    """G_n = Hadamard product of H_m^T H_m over m != n (Section IV-A, item 2;
+    N - 1 factors for N modes)."""
     G = None
-    for m in range(3):
+    for m in range(len(factors)):
         if m == n:
             continue
         Gm = gram(factors[m])
@@ -291,7 +295,7 @@ def init_state(H0: Sequence[np.ndarray], rho0: float = 1.0, paper: bool = False)
         H = [h.copy() for h in H0]
         P = [h.copy() for h in H0]
     U = [np.zeros_like(h) for h in H0]
-    return State(H=H, U=U, P=P, rho=[float(rho0)] * 3)
+    return State(H=H, U=U, P=P, rho=[float(rho0)] * len(H0))
 
 
 # ---------------------------------------------------------------------------
@@ -406,7 +410,7 @@ def mode_update(X: np.ndarray, st: State, n: int, opts: Opts) -> dict:
     """Update mode n in place (one line of eq. ADMM_NTF_ALS_C plus the
     projection and dual update of eq. ADMoM_NTF)."""
     feed = st.P if opts.factor_source == 1 else st.H
-    factors = [feed[0], feed[1], feed[2]]
+    factors = list(feed)
     if isinstance(X, SparseTensor):
         W = mttkrp_sparse(X, factors, n)
     elif opts.mttkrp_operands == "exact":
@@ -450,9 +454,9 @@ def _adapt_rho(rho: float, prim: float, dual: float, opts: Opts) -> float:
 def outer_step(X: np.ndarray, st: State, opts: Opts) -> List[dict]:
     """One ADMoM iteration: modes 1, 2, 3 in Gauss-Seidel order (eq.
     ADMM_NTF_ALS_C: B uses the new A, C uses the new A and B)."""
-    infos = [mode_update(X, st, n, opts) for n in range(3)]
+    infos = [mode_update(X, st, n, opts) for n in range(len(st.H))]
     if opts.rho_policy == RHO_ADAPTIVE:
-        for n in range(3):
+        for n in range(len(st.H)):
             new = _adapt_rho(st.rho[n], infos[n]["prim"], infos[n]["dual"], opts)
             if new != st.rho[n]:
                 st.U[n] = st.U[n] * (st.rho[n] / new)   # the unscaled dual Y = -rho U is the state
@@ -502,13 +506,13 @@ def paper_admom_iteration(X: np.ndarray, P: List[np.ndarray], Aux: List[np.ndarr
         A-tilde^{k+1} = (A^{k+1} + Y^k / rho)_+,  Y^{k+1} = Y^k + rho (A^{k+1} - A-tilde^{k+1}).
     The Gram is formed as the explicit (KR)^T (KR), not via the Hadamard identity."""
     P = [p.copy() for p in P]
-    for n in range(3):
+    for n in range(len(P)):
         KR = kr_for_mode(P, n)
         lhs = KR.T @ KR + rho[n] * np.eye(KR.shape[1])
         rhs = unfold(X, n) @ KR + rho[n] * Aux[n] - Y[n]
         P[n] = np.linalg.solve(lhs, rhs.T).T       # lhs is symmetric: (rhs) lhs^{-1}
     Aux_new, Y_new = [], []
-    for n in range(3):
+    for n in range(len(P)):
         a = np.maximum(P[n] + Y[n] / rho[n], 0.0)
         Aux_new.append(a)
         Y_new.append(Y[n] + rho[n] * (P[n] - a))
