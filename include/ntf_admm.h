@@ -133,6 +133,68 @@ size_t ntf_admm_workspace_bytes(const ntf_problem *prob, const ntf_opts *opts);
 ntf_status ntf_admm_init(ntf_admm_ctx **out, const ntf_problem *prob, const ntf_opts *opts,
                          void *workspace, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------ order-N tensors */
+
+#define NTF_MAX_ORDER 8
+
+/* A dense tensor of order N = 3 .. NTF_MAX_ORDER (Appendix A: the mode-n
+ * unfolding is A_n times the transposed Khatri-Rao product of the other N - 1
+ * factors, and the method carries over with N - 1 Grams in the Hadamard
+ * product). */
+typedef struct {
+  int32_t order;                   /* N */
+  int32_t F;                       /* rank, 1..64 */
+  int64_t dims[NTF_MAX_ORDER];     /* I_1 .. I_N >= 1 (entries past N ignored); prod <= 2^46 */
+  int32_t x_dtype;                 /* 0 = float32 (NTF_PREC_F32), 1 = float64 (NTF_PREC_F64) */
+  int32_t reserved;                /* must be zero */
+  const void *X;                   /* device, C order [I_1]..[I_N]; BORROWED read-only */
+  void *H[NTF_MAX_ORDER];          /* device in/out [I_n][F] factors, as in ntf_problem */
+  void *U[NTF_MAX_ORDER];          /* device in/out [I_n][F] scaled duals */
+} ntf_nway_problem;
+
+typedef struct {                   /* as ntf_stats, per mode of the N */
+  int64_t outer;
+  double rho[NTF_MAX_ORDER];
+  double prim[NTF_MAX_ORDER];
+  double dual[NTF_MAX_ORDER];
+  double norm_h[NTF_MAX_ORDER];
+  double norm_p[NTF_MAX_ORDER];
+  double norm_y[NTF_MAX_ORDER];
+  double inner_iters_mean[NTF_MAX_ORDER];
+  int32_t numeric_error;
+  int32_t converged;
+} ntf_nway_stats;
+
+typedef struct ntf_nway_ctx ntf_nway_ctx;
+
+/* Workspace bytes for ntf_nway_init; 0 if the arguments are invalid. */
+size_t ntf_nway_workspace_bytes(const ntf_nway_problem *prob, const ntf_opts *opts);
+
+/* Solver context for an order-N tensor.  One outer iteration updates the N
+ * factors in order 1..N (Gauss-Seidel, as eq. ADMM_NTF_ALS_C for three).  The
+ * mode-n MTTKRP runs on a three-way view of X with the modes before n and
+ * after n folded (their factor the Khatri-Rao product of the folded factors,
+ * formed per iteration); the prepare step takes the Hadamard product of the
+ * N - 1 other Grams; the inner sweep is the three-way one.  Options as in
+ * ntf_opts: precision NTF_PREC_F32 or NTF_PREC_F64 (NTF_PREC_BF16_MIXED and
+ * warm_hidden > 0 are NTF_E_UNSUPPORTED); factor_source, paper_init, the
+ * penalty policies, the inner and outer stop tests apply as for three modes.
+ * With N = 3 the iterates are those of ntf_admm_init up to rounding order.
+ * Synchronises the stream. */
+ntf_status ntf_nway_init(ntf_nway_ctx **out, const ntf_nway_problem *prob, const ntf_opts *opts,
+                         void *workspace, size_t ws_bytes, void *stream);
+ntf_status ntf_nway_step(ntf_nway_ctx *ctx, ntf_nway_stats *stats);          /* as ntf_admm_step */
+ntf_status ntf_nway_run(ntf_nway_ctx *ctx, int32_t max_outer, int32_t check_every,
+                        ntf_nway_stats *stats);                              /* as ntf_admm_run */
+/* Direct RFE ||X - [H_1, .., H_N]|| / ||X|| in FP64 over every entry;
+ * synchronises. */
+ntf_status ntf_nway_fit(ntf_nway_ctx *ctx, double *rfe);
+/* W_out (device, FP64 [I_mode][F]) = X^(mode) times the Khatri-Rao product of
+ * the other factors as the next update would see them; enqueued only. */
+ntf_status ntf_nway_mttkrp(ntf_nway_ctx *ctx, int32_t mode, double *W_out);
+const char *ntf_nway_last_error(const ntf_nway_ctx *ctx);   /* NULL ctx: last failed init */
+ntf_status ntf_nway_destroy(ntf_nway_ctx *ctx);
+
 /* ------------------------------------------------------- sparse tensors */
 
 /* A sparse 3-way tensor given by its non-zeros (Section IV-A, item 1: n

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import (PREC_BF16_MIXED, PREC_F32, PREC_F64, RHO_ADAPTIVE, RHO_FIXED, RHO_TRACE,
                    NtfError)
 
-__all__ = ["NtfAdmm", "NtfAdmmSparse", "NtfBatch", "AdmmOptions", "inner_update", "gram", "PREC_F32", "PREC_BF16_MIXED",
+__all__ = ["NtfAdmm", "NtfAdmmSparse", "NtfNway", "NtfBatch", "AdmmOptions", "inner_update", "gram", "PREC_F32", "PREC_BF16_MIXED",
            "PREC_F64", "RHO_TRACE", "RHO_FIXED", "RHO_ADAPTIVE", "NtfError", "library_path"]
 
 
@@ -280,6 +280,111 @@ class NtfAdmmSparse(NtfAdmm):
     def plan_info(self) -> dict:
         """Algorithmic bytes of one sparse MTTKRP launch per mode."""
         return sparse_pass_bytes(self.dims, self.F, self.nnz, self.opts.precision)
+
+
+class NtfNway:
+    """ADMoM NTF of a dense tensor of order N = 3..8 (Appendix A).
+
+    X: contiguous CUDA tensor with N dims, float32 (F32) or float64 (F64);
+    H: N factor tensors [I_n, F], updated in place; U: duals (zeros if
+    omitted).  Same options as NtfAdmm (mixed precision and the learned warm
+    start excepted)."""
+
+    def __init__(self, X, H: Sequence, U: Optional[Sequence] = None,
+                 opts: Optional[AdmmOptions] = None, stream=None):
+        torch = _torch()
+        self.opts = opts or AdmmOptions()
+        fdt = torch.float64 if self.opts.precision == PREC_F64 else torch.float32
+        N = X.dim()
+        if not X.is_cuda or not X.is_contiguous() or not 3 <= N <= _lib.MAX_ORDER:
+            raise ValueError(f"X must be a contiguous CUDA tensor with 3..{_lib.MAX_ORDER} dims")
+        if X.dtype != fdt:
+            raise ValueError(f"X must be {fdt} for this precision")
+        if len(H) != N:
+            raise ValueError("one factor per mode")
+        F = H[0].shape[1]
+        self.X, self.H, self.N, self.F = X, list(H), N, F
+        self.dims = tuple(int(d) for d in X.shape)
+        for n in range(N):
+            h = self.H[n]
+            if not h.is_cuda or h.dtype != fdt or not h.is_contiguous() or tuple(h.shape) != (self.dims[n], F):
+                raise ValueError(f"H[{n}] must be a contiguous CUDA {fdt} tensor of shape ({self.dims[n]}, {F})")
+        self.U = list(U) if U is not None else [torch.zeros_like(h) for h in self.H]
+        for n in range(N):
+            if self.U[n].shape != self.H[n].shape or self.U[n].dtype != fdt or not self.U[n].is_contiguous():
+                raise ValueError(f"U[{n}] must match H[{n}]")
+        L = _lib.lib()
+        pr = _lib.NwayProblem()
+        pr.order = N
+        pr.F = F
+        for n in range(N):
+            pr.dims[n] = self.dims[n]
+            pr.H[n] = _ptr(self.H[n])
+            pr.U[n] = _ptr(self.U[n])
+        pr.x_dtype = 1 if self.opts.precision == PREC_F64 else 0
+        pr.X = _ptr(X)
+        self._prob = pr
+        self._copts = self.opts.to_c()
+        nbytes = L.ntf_nway_workspace_bytes(ctypes.byref(pr), ctypes.byref(self._copts))
+        if nbytes == 0:
+            ctx = ctypes.c_void_p()
+            st = L.ntf_nway_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts), None, 0,
+                                 _stream_handle(stream))
+            _lib.check(st, "ntf_nway_init", None, nway=True)
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
+        ctx = ctypes.c_void_p()
+        st = L.ntf_nway_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
+                             ctypes.c_void_p(_ptr(self.workspace)), nbytes, _stream_handle(stream))
+        _lib.check(st, "ntf_nway_init", None, nway=True)
+        self._ctx = ctx
+
+    def _stats(self, s):
+        d = s.as_dict()
+        for k, v in d.items():
+            if isinstance(v, list):
+                d[k] = v[:self.N]
+        return d
+
+    def step(self, stats: bool = False):
+        L = _lib.lib()
+        if stats:
+            s = _lib.NwayStats()
+            _lib.check(L.ntf_nway_step(self._ctx, ctypes.byref(s)), "ntf_nway_step", self._ctx, nway=True)
+            return self._stats(s)
+        _lib.check(L.ntf_nway_step(self._ctx, None), "ntf_nway_step", self._ctx, nway=True)
+        return None
+
+    def run(self, max_outer: int, check_every: int = 1, stats: bool = True):
+        s = _lib.NwayStats()
+        st = _lib.lib().ntf_nway_run(self._ctx, int(max_outer), int(check_every),
+                                     ctypes.byref(s) if stats else None)
+        _lib.check(st, "ntf_nway_run", self._ctx, ok=(_lib.NTF_OK, _lib.NTF_NOT_CONVERGED), nway=True)
+        out = self._stats(s) if stats else {}
+        out["status"] = st
+        return out
+
+    def fit(self) -> float:
+        r = ctypes.c_double()
+        _lib.check(_lib.lib().ntf_nway_fit(self._ctx, ctypes.byref(r)), "ntf_nway_fit", self._ctx, nway=True)
+        return r.value
+
+    def mttkrp(self, mode: int):
+        torch = _torch()
+        W = torch.empty((self.dims[mode], self.F), dtype=torch.float64, device=self.X.device)
+        _lib.check(_lib.lib().ntf_nway_mttkrp(self._ctx, int(mode), ctypes.c_void_p(_ptr(W))),
+                   "ntf_nway_mttkrp", self._ctx, nway=True)
+        return W
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _lib.lib().ntf_nway_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sparse_pass_bytes(dims, F: int, nnz: int, precision: int) -> dict:

@@ -51,6 +51,44 @@ class SparseProblem(ctypes.Structure):
     ]
 
 
+MAX_ORDER = 8
+
+
+class NwayProblem(ctypes.Structure):
+    _fields_ = [
+        ("order", c_int32),
+        ("F", c_int32),
+        ("dims", c_int64 * MAX_ORDER),
+        ("x_dtype", c_int32),
+        ("reserved", c_int32),
+        ("X", c_void_p),
+        ("H", c_void_p * MAX_ORDER),
+        ("U", c_void_p * MAX_ORDER),
+    ]
+
+
+class NwayStats(ctypes.Structure):
+    _fields_ = [
+        ("outer", c_int64),
+        ("rho", c_double * MAX_ORDER),
+        ("prim", c_double * MAX_ORDER),
+        ("dual", c_double * MAX_ORDER),
+        ("norm_h", c_double * MAX_ORDER),
+        ("norm_p", c_double * MAX_ORDER),
+        ("norm_y", c_double * MAX_ORDER),
+        ("inner_iters_mean", c_double * MAX_ORDER),
+        ("numeric_error", c_int32),
+        ("converged", c_int32),
+    ]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
 class Opts(ctypes.Structure):
     _fields_ = [
         ("inner_iters", c_int32),
@@ -151,6 +189,15 @@ SIGNATURES = [
     ("ntf_admm_sparse_workspace_bytes", c_size_t, [POINTER(SparseProblem), POINTER(Opts)]),
     ("ntf_admm_init_sparse", c_int32, [POINTER(c_void_p), POINTER(SparseProblem), POINTER(Opts), c_void_p,
                                        c_size_t, c_void_p]),
+    ("ntf_nway_workspace_bytes", c_size_t, [POINTER(NwayProblem), POINTER(Opts)]),
+    ("ntf_nway_init", c_int32, [POINTER(c_void_p), POINTER(NwayProblem), POINTER(Opts), c_void_p, c_size_t,
+                                c_void_p]),
+    ("ntf_nway_step", c_int32, [c_void_p, POINTER(NwayStats)]),
+    ("ntf_nway_run", c_int32, [c_void_p, c_int32, c_int32, POINTER(NwayStats)]),
+    ("ntf_nway_fit", c_int32, [c_void_p, POINTER(c_double)]),
+    ("ntf_nway_mttkrp", c_int32, [c_void_p, c_int32, c_void_p]),
+    ("ntf_nway_last_error", c_char_p, [c_void_p]),
+    ("ntf_nway_destroy", c_int32, [c_void_p]),
     ("ntf_admm_step", c_int32, [c_void_p, POINTER(Stats)]),
     ("ntf_admm_run", c_int32, [c_void_p, c_int32, c_int32, POINTER(Stats)]),
     ("ntf_admm_fit", c_int32, [c_void_p, POINTER(c_double)]),
@@ -225,9 +272,10 @@ class NtfError(RuntimeError):
         super().__init__(f"{where}: {msg} ({status})" + (f": {detail}" if detail else ""))
 
 
-def check(status: int, where: str, ctx=None, ok=(NTF_OK,), batch=False):
+def check(status: int, where: str, ctx=None, ok=(NTF_OK,), batch=False, nway=False):
     if status not in ok:
-        err = lib().ntf_batch_last_error if batch else lib().ntf_admm_last_error
+        err = (lib().ntf_batch_last_error if batch else
+               lib().ntf_nway_last_error if nway else lib().ntf_admm_last_error)
         detail = err(ctx).decode(errors="replace")
         raise NtfError(status, where, detail)
     return status

@@ -30,6 +30,11 @@
 
 using namespace ntf;
 
+namespace ntf {
+ntf_status validate_opts(const ntf_opts* o, std::string* why);
+int cu_count();
+}
+
 namespace {
 
 struct DevState {
@@ -71,7 +76,11 @@ struct Carver {
   }
 };
 
-int cu_count() {
+}  // namespace
+
+// Compute units of the current device (256 if the query fails); shared with
+// the order-N host layer.
+int ntf::cu_count() {
   static int cached = 0;
   if (cached == 0) {
     int dev = 0, n = 0;
@@ -83,6 +92,8 @@ int cu_count() {
   }
   return cached;
 }
+
+namespace {
 
 // nnz >= 0: a sparse tensor of nnz non-zeros (no dense buffers)
 Layout make_layout(const Plan& p, const ntf_opts& o, int64_t nnz = -1) {
@@ -201,8 +212,6 @@ struct ntf_admm_ctx {
     }                                                                                  \
   } while (0)
 
-static ntf_status validate_opts(const ntf_opts* o, std::string* why);
-
 static ntf_status validate(const ntf_problem* pr, const ntf_opts* o, std::string* why) {
   auto fail = [&](const char* m) {
     if (why) *why = m;
@@ -232,7 +241,8 @@ static ntf_status validate(const ntf_problem* pr, const ntf_opts* o, std::string
   return NTF_OK;
 }
 
-static ntf_status validate_opts(const ntf_opts* o, std::string* why) {
+// Option checks shared by every entry point that takes ntf_opts.
+ntf_status ntf::validate_opts(const ntf_opts* o, std::string* why) {
   auto fail = [&](const char* m) {
     if (why) *why = m;
     return NTF_E_INVAL;

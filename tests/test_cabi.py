@@ -64,7 +64,8 @@ def _c_sizeof(struct_name):
                                           ("ntf_stats", "Stats"), ("ntf_mlp", "Mlp"), ("ntf_constraints", "Constraints"),
                                           ("ntf_batch_tile", "BatchTile"),
                                           ("ntf_batch_info", "BatchInfo"),
-                                          ("ntf_sparse_problem", "SparseProblem")])
+                                          ("ntf_sparse_problem", "SparseProblem"),
+                                          ("ntf_nway_problem", "NwayProblem"), ("ntf_nway_stats", "NwayStats")])
 def test_struct_layouts_match(cname, pyname):
     from paper_1409_2383_amd import _lib
     assert _c_sizeof(cname) == ctypes.sizeof(getattr(_lib, pyname))

@@ -1,0 +1,138 @@
+"""GPU parity of order-N tensors (Appendix A) against the oracle, through
+the C ABI: the MTTKRP of every mode on the three-way views, whole outer
+iterations in FP64 (1e-11 after one iteration, rounding order only), FP32,
+the paper's variant, the direct fit, and order 3 against the three-way
+solver."""
+import numpy as np
+import pytest
+
+import ntf_synth
+from oracle import ntf_oracle as orc
+from tests.gpu_helpers import rel, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_2383_amd as ntf
+    ntf.library_path()
+    return torch.device("cuda:0")
+
+
+def _problem(dims, F, seed, f64):
+    dt = np.float64 if f64 else np.float32
+    X, fac, _ = ntf_synth.planted_nway(dims, F, seed, snr_db=20.0, dtype=dt)
+    H0 = ntf_synth.init_factors(dims, F, seed, dtype=dt)
+    return X, H0
+
+
+SHAPES = [((9, 8, 7, 6), 5), ((5, 4, 6, 3, 7), 3), ((20, 3, 17, 5), 33), ((4, 5, 3, 2, 3, 4), 4)]
+
+
+@pytest.mark.parametrize("f64", [True, False])
+@pytest.mark.parametrize("dims,F", SHAPES)
+def test_nway_mttkrp_matches_oracle(dev, dims, F, f64):
+    import paper_1409_2383_amd as ntf
+    X, H0 = _problem(dims, F, 1800 + F, f64)
+    H = to_dev([h.copy() for h in H0], dev)
+    s = ntf.NtfNway(torch.from_numpy(X).to(dev), H,
+                    opts=ntf.AdmmOptions(precision=ntf.PREC_F64 if f64 else ntf.PREC_F32))
+    print(f"[nway] mttkrp dims={dims} F={F} f64={f64}", flush=True)
+    for n in range(len(dims)):
+        W = s.mttkrp(n).cpu().numpy()
+        ref = orc.mttkrp(X.astype(np.float64), [h.astype(np.float64) for h in H0], n)
+        e = rel(W, ref)
+        assert e < (1e-13 if f64 else 2e-6), (n, e)
+    s.close()
+
+
+@pytest.mark.parametrize("dims,F,T,src", [((9, 8, 7, 6), 5, 3, 0), ((5, 4, 6, 3, 7), 3, 2, 1),
+                                          ((20, 3, 17, 5), 33, 1, 0)])
+def test_nway_outer_steps_match_oracle(dev, dims, F, T, src):
+    import paper_1409_2383_amd as ntf
+    X, H0 = _problem(dims, F, 1900 + F, True)
+    H = to_dev([h.copy() for h in H0], dev)
+    s = ntf.NtfNway(torch.from_numpy(X).to(dev), H,
+                    opts=ntf.AdmmOptions(inner_iters=T, precision=ntf.PREC_F64, factor_source=src))
+    st = orc.init_state(H0)
+    opts = orc.Opts(inner_iters=T, factor_source=src)
+    for it in range(3):
+        stats = s.step(stats=True)
+        torch.cuda.synchronize()
+        infos = orc.outer_step(X, st, opts)
+        for n in range(len(dims)):
+            e = rel(H[n].cpu().numpy(), st.H[n])
+            assert e < 1e-11 * (10 ** it), (it, n, e)
+            assert stats["prim"][n] == pytest.approx(infos[n]["prim"], rel=1e-8 * 10 ** it, abs=1e-12)
+    assert s.fit() == pytest.approx(orc.rfe(X, st.H), rel=1e-10)
+    s.close()
+
+
+def test_nway_paper_variant_matches_oracle(dev):
+    import paper_1409_2383_amd as ntf
+    dims, F = (8, 7, 6, 5), 3
+    X, H0 = _problem(dims, F, 2000, True)
+    H = to_dev([h.copy() for h in H0], dev)
+    s = ntf.NtfNway(torch.from_numpy(X).to(dev), H,
+                    opts=ntf.AdmmOptions(inner_iters=1, precision=ntf.PREC_F64, factor_source=1,
+                                         rho_policy=ntf.RHO_ADAPTIVE, rho0=1.0, paper_init=1,
+                                         rescale_dual_on_rho_change=1))
+    st = orc.init_state(H0, paper=True)
+    opts = orc.Opts(inner_iters=1, factor_source=1, rho_policy=orc.RHO_ADAPTIVE,
+                    rescale_dual_on_rho_change=True)
+    for it in range(6):
+        s.step()
+        torch.cuda.synchronize()
+        orc.outer_step(X, st, opts)
+    for n in range(4):
+        assert rel(H[n].cpu().numpy(), st.H[n]) < 1e-8
+    s.close()
+
+
+def test_nway_fp32_run_tracks_the_oracle(dev):
+    import paper_1409_2383_amd as ntf
+    dims, F = (24, 20, 16, 12), 6
+    X, H0 = _problem(dims, F, 2100, False)
+    H = to_dev([h.copy() for h in H0], dev)
+    s = ntf.NtfNway(torch.from_numpy(X).to(dev), H, opts=ntf.AdmmOptions(inner_iters=5))
+    s.run(40, stats=False)
+    r_gpu = s.fit()
+    st = orc.init_state([h.astype(np.float64) for h in H0])
+    orc.run(X.astype(np.float64), st, orc.Opts(inner_iters=5), 40)
+    r_orc = orc.rfe(X.astype(np.float64), st.H)
+    print(f"[nway] fp32 4-way 40 iterations: RFE gpu {r_gpu:.6f} oracle {r_orc:.6f}", flush=True)
+    assert abs(r_gpu - r_orc) < 1e-4 * r_orc
+    s.close()
+
+
+def test_order_three_matches_the_three_way_solver(dev):
+    import paper_1409_2383_amd as ntf
+    dims, F = (30, 25, 20), 6
+    X, H0 = _problem(dims, F, 2200, True)
+    Xd = torch.from_numpy(X).to(dev)
+    Ha = to_dev([h.copy() for h in H0], dev)
+    Hb = to_dev([h.copy() for h in H0], dev)
+    a = ntf.NtfAdmm(Xd, Ha, opts=ntf.AdmmOptions(inner_iters=4, precision=ntf.PREC_F64))
+    b = ntf.NtfNway(Xd, Hb, opts=ntf.AdmmOptions(inner_iters=4, precision=ntf.PREC_F64))
+    for _ in range(5):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    for n in range(3):
+        assert rel(Hb[n].cpu().numpy(), Ha[n].cpu().numpy()) < 1e-11
+    assert b.fit() == pytest.approx(a.fit(), rel=1e-12)
+    a.close()
+    b.close()
+
+
+def test_nway_rejects_unsupported_options(dev):
+    import paper_1409_2383_amd as ntf
+    dims, F = (4, 5, 6, 3), 2
+    X, H0 = _problem(dims, F, 2300, False)
+    with pytest.raises(ntf.NtfError):
+        ntf.NtfNway(torch.from_numpy(X).to(dev), to_dev(H0, dev),
+                    opts=ntf.AdmmOptions(precision=ntf.PREC_BF16_MIXED))
