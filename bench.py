@@ -36,6 +36,8 @@ WORKLOADS = {
     # (power-law-like) slice distribution, values from a rank-`planted` model
     "s1": dict(dims=(12092, 9184, 28818), F=32, nnz=76_000_000, planted=8, skew=2.0, T=10, config=6,
                arms=("fp32",)),
+    # order N: a dense four-way tensor (Appendix A)
+    "n4": dict(dims=(120, 110, 100, 90), F=32, dist="uniform", snr=20.0, T=10, config=7, arms=("fp32",)),
     # batched: n tensors, every mode uniform on [lo, hi], F uniform on 5..40
     "c5": dict(n=256, lo=50, hi=500, ranks=tuple(range(5, 41)), dist="uniform", snr=20.0,
                clip=False, T=10, config=5, arms=("mixed",)),
@@ -294,7 +296,7 @@ def summarize(args):
         cmd = (f"rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- python3 "
                f"<repo>/bench.py --workload {args.workload} --steps {args.steps} --warmup {args.warmup} "
                f"--pass-reps {args.pass_reps} --no-cpu-baseline"
-               + ("" if args.workload == "s1" else " --single-arm"))
+               + ("" if args.workload in ("s1", "n4") else " --single-arm"))
         write_kernel_stats(args.write_kernel_stats, args.workload, arm, cmd)
     if args.write_traffic:
         import paper_1409_2383_amd as ntf
@@ -540,6 +542,90 @@ def bench_sparse(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_nway(args):
+    """Order-N workload: one outer iteration updates the N factors, each
+    MTTKRP a pass over X on a three-way view of it."""
+    import torch
+    import ntf_synth
+    import paper_1409_2383_amd as ntf
+    from oracle import ntf_oracle as orc
+    ntf.library_path()
+    dev = torch.device("cuda:0")
+    wl = WORKLOADS[args.workload]
+    dims, F, T = wl["dims"], wl["F"], wl["T"]
+    N = len(dims)
+    seed = ntf_synth.config_seed(wl["config"])
+    log(f"[bench] generating {dims} F={F} ({wl['snr']} dB) seed {seed}")
+    t0 = time.perf_counter()
+    X, _, _ = ntf_synth.planted_nway(dims, F, seed, dist=wl["dist"], snr_db=wl["snr"], dtype=np.float32)
+    H0 = ntf_synth.init_factors(dims, F, seed, dtype=np.float32)
+    log(f"[bench] data ready in {time.perf_counter() - t0:.1f} s")
+    Xd = torch.from_numpy(X).to(dev)
+    H = [torch.from_numpy(h).to(dev) for h in H0]
+    solver = ntf.NtfNway(Xd, H, opts=ntf.AdmmOptions(inner_iters=T, precision=ntf.PREC_F32))
+    ms, wall = time_steps(torch, solver, args.steps, args.warmup)
+    st = torch.cuda.current_stream()
+    passes = {}
+    Ws = [torch.empty((d, F), dtype=torch.float64, device=dev) for d in dims]
+    import ctypes
+    from paper_1409_2383_amd import _lib
+    L = _lib.lib()
+    for m in range(N):
+        L.ntf_nway_mttkrp(solver._ctx, m, ctypes.c_void_p(Ws[m].data_ptr()))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(args.pass_reps):
+            L.ntf_nway_mttkrp(solver._ctx, m, ctypes.c_void_p(Ws[m].data_ptr()))
+        e1.record(st)
+        torch.cuda.synchronize()
+        passes[f"mode{m + 1}"] = e0.elapsed_time(e1) / args.pass_reps
+    rfe = solver.fit()
+    solver.close()
+    log(f"[bench] {N}-way: {ms:.3f} ms/step, MTTKRP {passes}, RFE {rfe:.4f}")
+    # one pass over X per mode (the folded factors and W are small beside it)
+    xbytes = int(np.prod(dims)) * 4
+    dom = max(passes, key=lambda k: passes[k])
+    achieved = xbytes / (passes[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"MTTKRP {dom}",
+                "algorithmic_bytes_per_launch": xbytes, "avg_launch_ms": passes[dom]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        S = max(1, dims[0] // 8)
+        log(f"[bench] CPU oracle baseline on {S} of {dims[0]} mode-1 slabs")
+        Xs = np.ascontiguousarray(X[:S], dtype=np.float64)
+        sto = orc.init_state([H0[0][:S].astype(np.float64)] + [h.astype(np.float64) for h in H0[1:]])
+        n_it, t_cpu = 0, 0.0
+        while t_cpu < 10.0 and n_it < 5:
+            t0 = time.perf_counter()
+            orc.outer_step(Xs, sto, orc.Opts(inner_iters=T))
+            t_cpu += time.perf_counter() - t0
+            n_it += 1
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
+        except Exception:
+            cores = os.cpu_count() or 1
+        per_iter = t_cpu / n_it * dims[0] / S
+        cpu = {"value": 1.0 / per_iter, "unit": "outer_iters/s", "cores": cores, "kind": "oracle",
+               "sample": f"{n_it} outer iteration(s) (T={T}) of the FP64 oracle on the first {S} of "
+                         f"{dims[0]} mode-1 slabs ({t_cpu:.1f} s), scaled by {dims[0]}/{S}",
+               "seconds_measured": t_cpu}
+    line = {
+        "metric": "NTF outer iters/s, order-N dense tensor",
+        "value": 1e3 / ms, "unit": "outer_iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, dims))} dense {N}-way, F={F} planted U[0,1] factors, "
+                               f"{wl['snr']:.0f} dB, T={T} inner iters, fp32",
+                   "dims": list(dims), "F": F, "inner_iters": T},
+        "roofline": roofline, "cpu_baseline": cpu, "mttkrp_ms": passes,
+        "mttkrp_gbs": {k: xbytes / (v * 1e-3) / 1e9 for k, v in passes.items()}, "rfe": rfe,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -573,6 +659,9 @@ def main():
         return
     if args.workload == "s1":
         bench_sparse(args)
+        return
+    if args.workload == "n4":
+        bench_nway(args)
         return
     import torch
     import ntf_synth

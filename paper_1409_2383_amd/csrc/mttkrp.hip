@@ -200,7 +200,7 @@ __global__ __launch_bounds__(512) void k_pass1(const T* __restrict__ X, int I, i
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
             if (rowok[mt] && valid > 0) {
-              load4<T>(xrow[mt] + kb + 4 * h, valid, vec != 0, dst[h][mt]);
+              load4<T>(xrow[mt] + kb + 4 * h, valid, vec, dst[h][mt]);
             } else {
 #pragma unroll
               for (int c = 0; c < 4; ++c) dst[h][mt][c] = T(0);
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(512) void k_pass3(const T* __restrict__ X, int64_t 
   };
   auto load = [&](int64_t r, T (&dst)[4]) {
     if (kact && r < rend && valid > 0) {
-      load4<T>(X + r * K + kl, valid, vec != 0, dst);
+      load4<T>(X + r * K + kl, valid, vec, dst);
     } else {
 #pragma unroll
       for (int c = 0; c < 4; ++c) dst[c] = T(0);
@@ -817,7 +817,7 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   p.F = F;
   p.FT = (F + 15) / 16;
   p.FP = p.FT * 16;
-  p.vec = (p.K % 4) == 0;
+  p.vec = (p.K % 4) == 0 ? 4 : (p.K % 2) == 0 ? 2 : 1;
   const int cus = cu_count > 0 ? cu_count : 256;
   // pass 1: one wave per (slab, 16*MT rows) item, four waves per block
   if (prec == PREC_BF16) {
@@ -923,7 +923,7 @@ static hipError_t pass1_t(const Plan& p, const void* X, const void* Hb, const vo
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(512), p.lds1, s, (const T*)X, (int)p.I, (int)p.J,
                      (int)p.K, p.F, (const T*)Hb, (const T*)Hc, (T*)Tout, (T*)P1, p.nch1, p.KC1,
-                     p.vec ? 1 : 0);
+                     p.vec);
   return hipGetLastError();
 }
 
@@ -1000,7 +1000,7 @@ static void pass3_t(const Plan& p, const void* X, const void* Ha, const void* Hb
                     hipStream_t s) {
   hipLaunchKernelGGL((k_pass3<T, FT>), dim3(p.nrc3, p.nkg3), dim3(64 * p.nw3), 0, s, (const T*)X,
                      p.I * p.J, (int)p.J, (int)p.K, p.F, (const T*)Ha, (const T*)Hb, (T*)P3,
-                     p.rpc3, p.vec ? 1 : 0);
+                     p.rpc3, p.vec);
 }
 
 template <int FT>

@@ -64,10 +64,29 @@ template <> struct Vec4Load<double> {
   }
 };
 
+template <typename T> struct Vec2Load;
+template <> struct Vec2Load<float> {
+  static __device__ __forceinline__ void load(const float* p, float (&v)[4]) {
+    const float2 a = reinterpret_cast<const float2*>(p)[0];
+    const float2 b = reinterpret_cast<const float2*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+};
+template <> struct Vec2Load<double> {
+  static __device__ __forceinline__ void load(const double* p, double (&v)[4]) {
+    Vec4Load<double>::load(p, v);
+  }
+};
+
+// Four consecutive row elements.  vec = 4: p is 16-byte aligned (row length
+// a multiple of 4); vec = 2: p is aligned to two elements (even row length);
+// otherwise element loads.  `valid` < 4 at a row's end: the rest read as 0.
 template <typename T>
-static __device__ __forceinline__ void load4(const T* p, int valid, bool vec, T (&v)[4]) {
-  if (vec && valid >= 4) {
+static __device__ __forceinline__ void load4(const T* p, int valid, int vec, T (&v)[4]) {
+  if (vec == 4 && valid >= 4) {
     Vec4Load<T>::load(p, v);
+  } else if (vec == 2 && valid >= 4) {
+    Vec2Load<T>::load(p, v);
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = (c < valid) ? p[c] : T(0);

@@ -16,7 +16,7 @@ struct Plan {
   int prec = 0;
   int64_t I = 0, J = 0, K = 0;
   int F = 0, FT = 0, FP = 0;      // rank, 16-column MFMA tiles, padded rank
-  bool vec = true;                // K % 4 == 0: 16-byte row loads of the FP32/FP64 tensor
+  int vec = 4;                    // row loads of the FP32/FP64 tensor: 4 (K % 4 == 0), 2 (K even), 1
   // bfloat16 copies: row-major [I][J][Kp] and j-interleaved [I][JG][Kp3][8]
   int64_t Kp = 0, JG = 0, Kp3 = 0;
   // pass 1 (mode-1 MTTKRP plus the k-contracted intermediate T = X x_3 C)
