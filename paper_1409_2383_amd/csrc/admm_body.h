@@ -49,8 +49,11 @@ struct InnerK {
   double* dh0;
 };
 
+// Rows per lane group: two at FL = 32 (each LDS read of Ginv serves both);
+// one at FL = 64, where twice the blocks fill more of the chip (measured
+// faster at F = 64, 1000 rows)
 template <int FL>
-static constexpr int inner_rpl() { return FL >= 32 ? 2 : 1; }
+static constexpr int inner_rpl() { return FL == 32 ? 2 : 1; }
 
 // out[q] = sum_g M[g*FL + f] * V[q*BS + g] for the RPL rows of a lane, with
 // the LDS reads of chunk c+1 issued before the FMAs of chunk c (register
