@@ -613,19 +613,28 @@ def _round_bf16(x: np.ndarray) -> np.ndarray:
     return r.astype(np.uint32).view(np.float32)
 
 
-def quantize_slabs_bf16(X: np.ndarray):
-    """Per-slab scale s_i = 2^e_i with max|X[i]| / s_i in [1, 2) (s_i = 1 for an
-    all-zero slab), and the bfloat16 values of X[i] / s_i.  Returns
-    (Xq as float64 holding the bfloat16 values, s as float64)."""
+def slab_scales(X: np.ndarray) -> np.ndarray:
+    """Per-slab scale s_i = 2^e_i with max|X[i]| / s_i in [1, 2) (s_i = 1 for
+    an all-zero slab)."""
     X = np.asarray(X, dtype=np.float32)
-    I = X.shape[0]
-    s = np.ones(I)
-    Xq = np.empty(X.shape, dtype=np.float64)
-    for i in range(I):
+    s = np.ones(X.shape[0])
+    for i in range(X.shape[0]):
         m = float(np.max(np.abs(X[i])))
         if m > 0.0 and math.isfinite(m):
             _, e = math.frexp(m)                    # m = mant * 2^e, mant in [0.5, 1)
             s[i] = math.ldexp(1.0, e - 1)
+    return s
+
+
+def quantize_slabs_bf16(X: np.ndarray, s: Optional[np.ndarray] = None):
+    """The bfloat16 values of X[i] / s_i (scales from ``slab_scales`` unless
+    given).  Returns (Xq as float64 holding the bfloat16 values, s as
+    float64)."""
+    X = np.asarray(X, dtype=np.float32)
+    if s is None:
+        s = slab_scales(X)
+    Xq = np.empty(X.shape, dtype=np.float64)
+    for i in range(X.shape[0]):
         Xq[i] = _round_bf16((X[i].astype(np.float64) / s[i]).astype(np.float32)).astype(np.float64)
     return Xq, s
 
@@ -660,3 +669,66 @@ def mttkrp_mixed(X: np.ndarray, factors: Sequence[np.ndarray], n: int, mode3: st
     KRb = _round_bf16(KR).astype(np.float64).reshape(I * J, -1)
     Xflat = Xq.reshape(I * J, -1)                                      # rows (i, j), columns k
     return Xflat.T @ KRb
+
+
+# ---------------------------------------------------------------------------
+# Selected output rows (for checks of full-size runs, one row at a time)
+# ---------------------------------------------------------------------------
+
+def mttkrp_rows(X: np.ndarray, factors: Sequence[np.ndarray], n: int, rows) -> np.ndarray:
+    """Rows ``rows`` of W_n = X^(n) (Khatri-Rao of the other factors): the
+    MTTKRP of the sub-tensor holding only those indices of mode n (any order
+    N; each output row depends on its own slice of X only)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    Xs = np.take(np.asarray(X), rows, axis=n).astype(np.float64)
+    fac = [np.asarray(f, dtype=np.float64) for f in factors]
+    fac[n] = fac[n][rows]
+    return mttkrp(Xs, fac, n)
+
+
+def mttkrp_mixed_rows(X: np.ndarray, factors: Sequence[np.ndarray], n: int, rows,
+                      mode3: str = "kr") -> np.ndarray:
+    """Rows ``rows`` of ``mttkrp_mixed`` (three modes): the per-slab scales
+    come from the whole tensor, the rounding and contraction from the slice
+    of X that the rows read."""
+    rows = np.asarray(rows, dtype=np.int64)
+    X = np.asarray(X, dtype=np.float32)
+    s = slab_scales(X)
+    fac = [np.asarray(f, dtype=np.float32) for f in factors]
+    if n == 0:
+        Xq, _ = quantize_slabs_bf16(X[rows], s[rows])
+        A = fac[0][rows]
+        return mttkrp_mixed_from(Xq, s[rows], [A, fac[1], fac[2]], 0, mode3)
+    Xsub = np.ascontiguousarray(X[:, rows, :] if n == 1 else X[:, :, rows])
+    Xq, _ = quantize_slabs_bf16(Xsub, s)
+    sub = list(fac)
+    sub[n] = fac[n][rows]
+    return mttkrp_mixed_from(Xq, s, sub, n, mode3)
+
+
+def mttkrp_mixed_from(Xq: np.ndarray, s: np.ndarray, factors: Sequence[np.ndarray], n: int,
+                      mode3: str = "kr") -> np.ndarray:
+    """The contraction step of ``mttkrp_mixed`` for given bfloat16 values Xq
+    and slab scales s."""
+    A, B, C = (np.asarray(f, dtype=np.float32) for f in factors)
+    Xs = Xq * s[:, None, None]
+    if n in (0, 1):
+        Cb = _round_bf16(C).astype(np.float64)
+        return mttkrp(Xs, [A.astype(np.float64), B.astype(np.float64), Cb], n)
+    if mode3 == "factored":
+        Bb = _round_bf16(B).astype(np.float64)
+        return mttkrp(Xs, [A.astype(np.float64), Bb, C.astype(np.float64)], 2)
+    I, J = A.shape[0], B.shape[0]
+    sA = (s.astype(np.float32)[:, None] * A).astype(np.float32)
+    KR = (sA[:, None, :] * B[None, :, :]).astype(np.float32)
+    KRb = _round_bf16(KR).astype(np.float64).reshape(I * J, -1)
+    return Xq.reshape(I * J, -1).T @ KRb
+
+
+def mttkrp_sparse_rows(T: SparseTensor, factors: Sequence[np.ndarray], n: int, rows) -> np.ndarray:
+    """Rows ``rows`` of ``mttkrp_sparse``: the non-zeros of those rows only."""
+    rows = np.asarray(rows, dtype=np.int64)
+    idx = np.asarray(T.idx, dtype=np.int64)
+    keep = np.isin(idx[:, n], rows)
+    sub = SparseTensor(idx=idx[keep], val=np.asarray(T.val)[keep], dims=T.dims)
+    return mttkrp_sparse(sub, factors, n)[rows]

@@ -378,3 +378,29 @@ def test_mixed_mttkrp_factored_brute_force():
                 tot += s[i] * A32[i, f] * inner
             W[k, f] = tot
     np.testing.assert_allclose(orc.mttkrp_mixed(X, [A, B, C], 2, mode3="factored"), W, rtol=1e-12)
+
+
+def test_row_restricted_mttkrps_equal_the_full_ones():
+    # the selected-row forms used by the full-size checks return exactly the
+    # rows of the whole-tensor functions
+    rng = np.random.default_rng(300)
+    dims, F = (7, 9, 8), 4
+    X = rng.standard_normal(dims).astype(np.float32)
+    fac = [rng.random((d, F)).astype(np.float32) for d in dims]
+    for n in range(3):
+        rows = np.array(sorted(rng.choice(dims[n], 3, replace=False)))
+        np.testing.assert_allclose(orc.mttkrp_rows(X, fac, n, rows), orc.mttkrp(X, fac, n)[rows],
+                                   rtol=1e-12)
+        for m3 in ("kr", "factored"):
+            np.testing.assert_allclose(orc.mttkrp_mixed_rows(X, fac, n, rows, m3),
+                                       orc.mttkrp_mixed(X, fac, n, m3)[rows], rtol=1e-12, atol=1e-12)
+    X4 = rng.standard_normal((4, 5, 3, 6))
+    fac4 = [rng.random((d, 2)) for d in X4.shape]
+    for n in range(4):
+        np.testing.assert_allclose(orc.mttkrp_rows(X4, fac4, n, [0, 2]), orc.mttkrp(X4, fac4, n)[[0, 2]],
+                                   rtol=1e-12)
+    idx = np.stack(np.unravel_index(rng.choice(7 * 9 * 8, 120, replace=False), dims), 1).astype(np.int32)
+    T = orc.SparseTensor(idx=idx, val=rng.standard_normal(120), dims=dims)
+    for n in range(3):
+        np.testing.assert_allclose(orc.mttkrp_sparse_rows(T, fac, n, [1, 3]),
+                                   orc.mttkrp_sparse(T, fac, n)[[1, 3]], rtol=1e-12, atol=1e-14)
