@@ -670,6 +670,136 @@ __global__ __launch_bounds__(512) void k_pass3(const T* __restrict__ X, int64_t 
       }
 }
 
+// Streaming form of pass 3 (FP32, rows of a length divisible by V = 4 or 2;
+// eight waves per block): each wave's load cursor runs U steps ahead over
+// the block's rows, across the 64-row epochs, through a buffer resource over
+// those rows, and rows past the block's end or columns past K read as zeros,
+// so every path issues the same loads (the compiler's wait before a step
+// then covers that step only).  The Khatri-Rao values of epoch e + 2 are
+// loaded during epoch e + 1's predecessor and stored to the free LDS buffer
+// after the epoch's MFMAs; each step's B operands are read one step ahead.
+template <typename T, int FT, int V>
+__global__ __launch_bounds__(512, 2) void k_pass3s(const T* __restrict__ X, int64_t IJ, int J, int K,
+                                                int F, const T* __restrict__ Ha,
+                                                const T* __restrict__ Hb, T* __restrict__ P3,
+                                                int64_t rpc, int I) {
+  static_assert(sizeof(T) == 4, "FP32 only");
+  typedef Mfma<T> M;
+  typedef typename M::acc_t acc_t;
+  constexpr int FP = FT * 16;
+  constexpr int KRS = FP + ((FT % 2 == 0) ? 16 : 0);
+  constexpr int U = 4;
+  constexpr int PER = 64 * FP / 512;     // Khatri-Rao entries per thread and epoch (512 threads)
+  __shared__ __align__(16) T KRs[2][64 * KRS];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int kw0 = (blockIdx.y * nw + wave) * 64;
+  const bool kact = kw0 < K;
+  const int64_t rbeg = (int64_t)blockIdx.x * rpc;
+  const int nrows = (int)(min(IJ, rbeg + rpc) - rbeg);
+  const int nep = (nrows + 63) >> 6;
+  const int kl = kw0 + 4 * n;
+  const __amdgpu_buffer_rsrc_t xrs = uniform_rsrc(X + rbeg * K, nrows * K * (int)sizeof(T));
+  const __amdgpu_buffer_rsrc_t ars = uniform_rsrc(Ha, I * F * (int)sizeof(T));
+  const __amdgpu_buffer_rsrc_t brs = uniform_rsrc(Hb, J * F * (int)sizeof(T));
+  acc_t acc[4][FT];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) acc[c][ft] = M::zero();
+
+  T xv[U][4];
+  auto xload = [&](int st, T (&dst)[4]) {
+    const int row = 4 * st + g;
+    const bool rok = row < nrows;
+    if constexpr (sizeof(T) == 4 && V == 4) {
+      const int off = (rok && kl < K) ? (row * K + kl) * 4 : kBufferOOB;
+      const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(xrs, off, 0, 0));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dst[c] = v[c];
+    } else {
+      typedef float f2 __attribute__((ext_vector_type(2)));
+      const int o0 = (rok && kl < K) ? (row * K + kl) * 4 : kBufferOOB;
+      const int o1 = (rok && kl + 2 < K) ? (row * K + kl + 2) * 4 : kBufferOOB;
+      const f2 a = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(xrs, o0, 0, 0));
+      const f2 b = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(xrs, o1, 0, 0));
+      dst[0] = a[0];
+      dst[1] = a[1];
+      dst[2] = b[0];
+      dst[3] = b[1];
+    }
+  };
+  T ha[PER], hb[PER];
+  auto hload = [&](int e) {   // factor values of epoch e (zeros past the block's rows)
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + nthr * q;
+      const int rr = idx / FP, f = idx - rr * FP;
+      const int64_t r = rbeg + 64LL * e + rr;
+      const bool ok = idx < 64 * FP && (64 * e + rr < nrows) && f < F;
+      const int64_t i = r / J, j = r - i * J;
+      const int oa = ok ? (int)(i * F + f) * (int)sizeof(T) : kBufferOOB;
+      const int ob = ok ? (int)(j * F + f) * (int)sizeof(T) : kBufferOOB;
+      ha[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ars, oa, 0, 0));
+      hb[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(brs, ob, 0, 0));
+    }
+  };
+  auto hstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + nthr * q;
+      const int rr = idx / FP, f = idx - rr * FP;
+      if (idx < 64 * FP) KRs[buf][rr * KRS + f] = ha[q] * hb[q];
+    }
+  };
+  hload(0);
+  hstore(0);
+  hload(1);
+#pragma unroll
+  for (int u = 0; u < U; ++u) xload(u, xv[u]);
+  __syncthreads();
+  for (int e = 0; e < nep; ++e) {
+    const T* kb0 = KRs[e & 1] + g * KRS + n;
+    T bc[FT], bn[FT];
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) bc[ft] = kb0[ft * 16];
+#pragma unroll 1
+    for (int st0 = 0; st0 < 16; st0 += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int st = st0 + u;
+        const int sn = min(st + 1, 15);   // the last step re-reads its own operands
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) bn[ft] = kb0[(4 * sn) * KRS + ft * 16];
+        if (kact) {
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c][ft] = M::mma(xv[u][c], bc[ft], acc[c][ft]);
+        }
+        xload(16 * e + st + U, xv[u]);
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) bc[ft] = bn[ft];
+      }
+    }
+    if (e + 1 < nep) hstore((e + 1) & 1);
+    hload(e + 2);
+    __syncthreads();
+  }
+  if (!kact) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int k = kw0 + 4 * M::row(g, ii) + c;
+        const int f = ft * 16 + n;
+        if (k < K && f < F) P3[((int64_t)blockIdx.x * K + k) * F + f] = acc[c][ft][ii];
+      }
+}
+
 // ---------------------------------------------------------------- pass 3, BF16
 
 // X from the j-interleaved copy Xj8[q][k][e] (q = i*JG + jg, row j = 8jg + e):
@@ -998,6 +1128,24 @@ hipError_t launch_mode2(const Plan& p, const void* Tin, const void* Ha, void* P2
 template <typename T, int FT>
 static void pass3_t(const Plan& p, const void* X, const void* Ha, const void* Hb, void* P3,
                     hipStream_t s) {
+  // FP32 rows of even length whose block range fits 32-bit buffer offsets:
+  // the streaming form (eight waves per block; waves past K only share the
+  // loads of the Khatri-Rao values)
+  if constexpr (sizeof(T) == 4) {
+    if (p.vec >= 2 && p.rpc3 * p.K * 4 < kBufferOOB && p.I * p.F * 4 < kBufferOOB &&
+        p.J * p.F * 4 < kBufferOOB) {
+      const int nw = 8;
+      if (p.vec == 4)
+        hipLaunchKernelGGL((k_pass3s<float, FT, 4>), dim3(p.nrc3, p.nkg3), dim3(64 * nw), 0, s,
+                           (const float*)X, p.I * p.J, (int)p.J, (int)p.K, p.F, (const float*)Ha,
+                           (const float*)Hb, (float*)P3, p.rpc3, (int)p.I);
+      else
+        hipLaunchKernelGGL((k_pass3s<float, FT, 2>), dim3(p.nrc3, p.nkg3), dim3(64 * nw), 0, s,
+                           (const float*)X, p.I * p.J, (int)p.J, (int)p.K, p.F, (const float*)Ha,
+                           (const float*)Hb, (float*)P3, p.rpc3, (int)p.I);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_pass3<T, FT>), dim3(p.nrc3, p.nkg3), dim3(64 * p.nw3), 0, s, (const T*)X,
                      p.I * p.J, (int)p.J, (int)p.K, p.F, (const T*)Ha, (const T*)Hb, (T*)P3,
                      p.rpc3, p.vec);
