@@ -561,6 +561,174 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
   }
 }
 
+// Streaming form of the FP32 pass 1 (all of H3 in LDS, rows of a length
+// divisible by V = 4 or 2): items as in k_pass1, one load cursor per wave
+// running U super steps (32 k) ahead across its items through a buffer
+// resource per slab; rows j >= J and k >= K read as zeros, so every path
+// issues the same loads and the wait before a step covers that step only.
+template <int FT, int MT, int V>
+__global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, int I, int J, int K,
+                                                   int F, const float* __restrict__ Hb,
+                                                   const float* __restrict__ Hc,
+                                                   float* __restrict__ Tout, float* __restrict__ P1,
+                                                   int nch, int KC) {
+  typedef Mfma<float> M;
+  typedef typename M::acc_t acc_t;
+  constexpr int FP = FT * 16;
+  constexpr int R = 16 * MT;
+  constexpr int U = 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* Cs = reinterpret_cast<float*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = lane & 15, g = lane >> 4;
+  for (int idx = threadIdx.x; idx < KC * FP; idx += blockDim.x) {
+    const int kk = idx / FP, f = idx - kk * FP;
+    const float v = (kk < K && f < F) ? Hc[(int64_t)kk * F + f] : 0.f;
+    Cs[((kk >> 2) * FP + f) * 4 + (kk & 3)] = v;
+  }
+  __syncthreads();
+  const int64_t nitems = (int64_t)I * nch;
+  const int nwb = blockDim.x >> 6;
+  const int64_t stride = (int64_t)gridDim.x * nwb;
+  const int64_t first = (int64_t)blockIdx.x * nwb + wave;
+  if (first >= nitems) return;
+  const int64_t myitems = (nitems - first + stride - 1) / stride;
+  const int nsteps = (K + 31) / 32;
+  const int total = __builtin_amdgcn_readfirstlane((int)(myitems * nsteps));
+
+  // load cursor (the cursor stays on the last item past the wave's end and
+  // re-reads in-bounds data that nothing consumes)
+  int64_t l_item = first;
+  int l_kb = 0;
+  const float* l_slab = X;
+  int l_row[MT];
+  auto set_rows = [&](int64_t item) {
+    const int i = (int)(item / nch), ch = (int)(item - (int64_t)i * nch);
+    l_slab = X + (int64_t)i * J * K;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) l_row[mt] = ch * R + mt * 16 + n;
+  };
+  set_rows(l_item);
+  float xv[U][2][MT][4];
+  auto load_next = [&](float (&dst)[2][MT][4]) {
+    const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(l_slab, J * K * 4);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int k = l_kb + 8 * g + 4 * h;
+        const bool rok = l_row[mt] < J;
+        if constexpr (V == 4) {
+          const int off = (rok && k < K) ? (l_row[mt] * K + k) * 4 : kBufferOOB;
+          const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+#pragma unroll
+          for (int c = 0; c < 4; ++c) dst[h][mt][c] = v[c];
+        } else {
+          typedef float f2 __attribute__((ext_vector_type(2)));
+          const int o0 = (rok && k < K) ? (l_row[mt] * K + k) * 4 : kBufferOOB;
+          const int o1 = (rok && k + 2 < K) ? (l_row[mt] * K + k + 2) * 4 : kBufferOOB;
+          const f2 a = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, o0, 0, 0));
+          const f2 b = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, o1, 0, 0));
+          dst[h][mt][0] = a[0];
+          dst[h][mt][1] = a[1];
+          dst[h][mt][2] = b[0];
+          dst[h][mt][3] = b[1];
+        }
+      }
+    l_kb += 32;
+    if (l_kb >= K) {
+      l_kb = 0;
+      l_item += stride;
+      if (l_item < nitems) set_rows(l_item);
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < U; ++u) load_next(xv[u]);
+
+  acc_t acc[MT][FT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = M::zero();
+  int64_t c_item = first;
+  int c_step = 0;
+  const __amdgpu_buffer_rsrc_t hrs = uniform_rsrc(Hb, J * F * 4);
+  float hbv[MT][FT][4];
+  auto eoff = [&](int ch, int mt, int ft, int ii) {   // offset of (row, column) in a [J][F] slab
+    const int j = ch * R + mt * 16 + M::row(g, ii), f = ft * 16 + n;
+    return (f < F && j < J) ? (j * F + f) * 4 : kBufferOOB;
+  };
+  auto item_start = [&](int64_t item) {
+    const int ch = (int)(item - (item / nch) * nch);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+          hbv[mt][ft][ii] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(hrs, eoff(ch, mt, ft, ii), 0, 0));
+  };
+  auto step = [&](int u, bool reload) {
+    if (c_step == 0) item_start(c_item);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float* cbase = Cs + (((c_step * 32) >> 2) + 2 * g + h) * FP * 4 + n * 4;
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) {
+        float cv[4];
+        Vec4Load<float>::load(cbase + ft * 64, cv);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = M::mma(xv[u][h][mt][c], cv[c], acc[mt][ft]);
+      }
+    }
+    if (reload) load_next(xv[u]);
+    if (++c_step == nsteps) {
+      // epilogue of item c_item: T rows (rows past J and columns past F get
+      // an offset past the slab: the hardware drops those stores) and this
+      // item's share of W1 against H2
+      const int i = (int)(c_item / nch);
+      const int ch = (int)(c_item - (int64_t)i * nch);
+      const __amdgpu_buffer_rsrc_t trs = uniform_rsrc(Tout + (int64_t)i * J * F, J * F * 4);
+      float part[FT];
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            const float v = acc[mt][ft][ii];
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), trs,
+                                                  eoff(ch, mt, ft, ii), 0, 0);
+            part[ft] += hbv[mt][ft][ii] * v;
+          }
+          acc[mt][ft] = M::zero();
+        }
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) {
+        part[ft] += __shfl_xor(part[ft], 16);
+        part[ft] += __shfl_xor(part[ft], 32);
+        const int f = ft * 16 + n;
+        if (g == 0 && f < F) P1[((int64_t)i * nch + ch) * F + f] = part[ft];
+      }
+      c_step = 0;
+      c_item += stride;
+    }
+  };
+  const int full = total - total % U;
+  for (int s0 = 0; s0 < full; s0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) step(u, true);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (full + u < total) step(u, false);
+}
+
 // ---------------------------------------------------------------- mode 2 from T
 
 // P2[ic][j][f] = sum_{i in chunk ic} A[i][f] * T[i][j][f]; one thread per (j,f),
@@ -1047,6 +1215,20 @@ hipError_t launch_sumsq(const void* X, int x_is_f64, int64_t n, double* partial,
 template <typename T, int FT, int MT>
 static hipError_t pass1_t(const Plan& p, const void* X, const void* Hb, const void* Hc, void* Tout,
                           void* P1, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    // all of H3 in LDS, even rows, slab addressable by one resource: the streaming form
+    if (p.KC1 >= p.K && p.vec >= 2 && p.J * p.K * 4 < (int64_t)kBufferOOB &&
+        p.J * p.F * 4 < (int64_t)kBufferOOB) {
+      auto kern = (p.vec == 4) ? k_pass1s<FT, MT, 4> : k_pass1s<FT, MT, 2>;
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)p.lds1);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(512), p.lds1, s, (const float*)X, (int)p.I,
+                         (int)p.J, (int)p.K, p.F, (const float*)Hb, (const float*)Hc, (float*)Tout,
+                         (float*)P1, p.nch1, p.KC1);
+      return hipGetLastError();
+    }
+  }
   auto kern = k_pass1<T, FT, MT>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)p.lds1);
