@@ -90,30 +90,29 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
   const int myt = ntiles > wave ? (ntiles - wave + 3) / 4 : 0;
   const int nsteps = KC / 64;
   const int total = myt * nsteps;
+  // Loads go through a buffer resource per slab: rows j >= J lie past its
+  // num_records and k >= Kp gets an offset past it, so both read as zeros,
+  // and every path issues the same loads (the cursor stays on its last tile
+  // past the wave's end and re-reads in-bounds data nothing consumes): the
+  // wait before a step then covers that step's loads only.
   int l_t = wave, l_kb = 0;
-  const __bf16* l_row[MT];
-  bool l_ok[MT];
+  const __bf16* l_slab = P.Xr;
+  int l_off[MT];
   auto set_rows = [&](int t) {
     const int sl = t / nrg, rg = t - sl * nrg;
+    l_slab = P.Xr + (int64_t)(s0 + sl) * J * Kp;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int j = rg * R + mt * 16 + n;
-      l_ok[mt] = j < J;
-      l_row[mt] = P.Xr + ((int64_t)(s0 + sl) * J + (l_ok[mt] ? j : 0)) * Kp + 16 * g;
-    }
+    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Kp + 16 * g) * 2;
   };
   bf16x8 xv[U][2][MT];
   auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+    const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(l_slab, J * Kp * 2);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        if (l_ok[mt] && l_kb + 16 * g + 8 * h < Kp) {
-          dst[h][mt] = *reinterpret_cast<const bf16x8*>(l_row[mt] + l_kb + 8 * h);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
-        }
+        const int off = (l_kb + 16 * g + 8 * h < Kp) ? l_off[mt] + (l_kb + 8 * h) * 2 : kBufferOOB;
+        dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
       }
     l_kb += 64;
     if (l_kb >= Kp) {
@@ -127,8 +126,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
   if (total > 0) {
     set_rows(l_t);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (u < total) load_next(xv[u]);
+    for (int u = 0; u < U; ++u) load_next(xv[u]);
   }
   for (int e = tid; e < KC * FP; e += 256) {
     const int kk = e / FP, f = e - kk * FP;
@@ -158,7 +156,14 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
     const __bf16* cb = Cs + n * KCS + 16 * g;
     // H2 values of the current tile's epilogue, loaded when the tile starts
     // so that their latency hides behind the tile's MFMA steps
+    // H2 values and T stores through resources too (rows past J, columns
+    // past F: offsets past them, zeros in, stores dropped)
     float hbv[MT][FT][4];
+    const __amdgpu_buffer_rsrc_t hrs = uniform_rsrc(Hb, J * F * 4);
+    auto eoff = [&](int rg, int mt, int ft, int ii) {
+      const int j = rg * R + mt * 16 + 4 * g + ii, f = ft * 16 + n;
+      return (j < J && f < F) ? (j * F + f) * 4 : kBufferOOB;
+    };
     auto load_hb = [&](int t) {
       const int rg = t - (t / nrg) * nrg;
 #pragma unroll
@@ -166,17 +171,11 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
 #pragma unroll
         for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
-          for (int ii = 0; ii < 4; ++ii) {
-            const int j = rg * R + mt * 16 + 4 * g + ii;
-            const int f = ft * 16 + n;
-            hbv[mt][ft][ii] = (j < J && f < F) ? Hb[(int64_t)j * F + f] : 0.f;
-          }
+          for (int ii = 0; ii < 4; ++ii)
+            hbv[mt][ft][ii] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(hrs, eoff(rg, mt, ft, ii), 0, 0));
     };
-    for (int s = 0; s < total; s += U) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int sidx = s + u;
-        if (sidx < total) {
+    auto step = [&](int u, bool reload) {
           if (c_step == 0) load_hb(c_t);
 #pragma unroll
           for (int ft = 0; ft < FT; ++ft) {
@@ -188,7 +187,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], c1, acc[mt][ft]);
           }
-          if (sidx + U < total) load_next(xv[u]);
+          if (reload) load_next(xv[u]);
           if (++c_step == nsteps) {
             const int sl = c_t / nrg, rg = c_t - sl * nrg;
             const int i = s0 + sl;
@@ -199,6 +198,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
 #pragma unroll
               for (int ft = 0; ft < FT; ++ft) wrun[ft] = 0.f;
             }
+            const __amdgpu_buffer_rsrc_t trs = uniform_rsrc(P.T + (int64_t)i * J * F, J * F * 4);
             float part[FT];
 #pragma unroll
             for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
@@ -208,13 +208,10 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
               for (int ft = 0; ft < FT; ++ft) {
 #pragma unroll
                 for (int ii = 0; ii < 4; ++ii) {
-                  const int j = rg * R + mt * 16 + 4 * g + ii;
-                  const int f = ft * 16 + n;
-                  if (j < J && f < F) {
-                    const float v = sc * acc[mt][ft][ii];
-                    P.T[((int64_t)i * J + j) * F + f] = v;
-                    part[ft] += hbv[mt][ft][ii] * v;
-                  }
+                  const float v = sc * acc[mt][ft][ii];
+                  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), trs,
+                                                        eoff(rg, mt, ft, ii), 0, 0);
+                  part[ft] += hbv[mt][ft][ii] * v;
                 }
                 acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
               }
@@ -227,9 +224,15 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
             c_step = 0;
             c_t += 4;
           }
-        }
-      }
+    };
+    const int full = total - total % U;
+    for (int s = 0; s < full; s += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(u, true);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (full + u < total) step(u, false);
     flush();
   }
   __syncthreads();
@@ -268,47 +271,43 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
   const int nsteps = JC / 64;
   const int total = myrg * ns * nsteps;
 
+  // Loads through a buffer resource per slab, as in pass 1: rows k >= K and
+  // columns j >= Jp read as zeros, and past the wave's last step the cursor
+  // keeps re-reading its last (in-bounds) row group.
   int l_rgc = 0, l_sl = 0, l_kb = 0;
-  const __bf16* l_row[MT];
-  bool l_ok[MT];
+  int l_off[MT];
   auto set_rows = [&]() {
     const int rg = wave + 4 * l_rgc;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int k = rg * R + mt * 16 + n;
-      l_ok[mt] = k < K;
-      l_row[mt] = P.Xt + ((int64_t)(s0 + l_sl) * K + (l_ok[mt] ? k : 0)) * Jp + 16 * g;
-    }
+    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Jp + 16 * g) * 2;
   };
   bf16x8 xv[U][2][MT];
   auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+    const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(P.Xt + (int64_t)(s0 + l_sl) * K * Jp, K * Jp * 2);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        if (l_ok[mt] && l_kb + 16 * g + 8 * h < Jp) {
-          dst[h][mt] = *reinterpret_cast<const bf16x8*>(l_row[mt] + l_kb + 8 * h);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
-        }
+        const int off = (l_kb + 16 * g + 8 * h < Jp) ? l_off[mt] + (l_kb + 8 * h) * 2 : kBufferOOB;
+        dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
       }
     l_kb += 64;
     if (l_kb >= Jp) {
       l_kb = 0;
       if (++l_sl == ns) {
         l_sl = 0;
-        ++l_rgc;
+        if (l_rgc + 1 < myrg) {
+          ++l_rgc;
+          set_rows();
+        }
       }
-      if (l_rgc < myrg) set_rows();
     }
   };
   // the first U steps of tensor loads go out before H2^T is staged
   if (total > 0) {
     set_rows();
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (u < total) load_next(xv[u]);
+    for (int u = 0; u < U; ++u) load_next(xv[u]);
   }
   for (int e = tid; e < JC * FP; e += 256) {
     const int jj = e / FP, f = e - jj * FP;
@@ -328,11 +327,9 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
     }
   int c_step = 0, c_sl = 0, c_rgc = 0;
   const __bf16* bb = Bs + n * JCS + 16 * g;
-  for (int s = 0; s < total; s += U) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int sidx = s + u;
-      if (sidx < total) {
+  const __amdgpu_buffer_rsrc_t ars = uniform_rsrc(Ha, P.I * F * 4);
+  const __amdgpu_buffer_rsrc_t wrs = uniform_rsrc(P.W3p + (int64_t)idx * K * F, K * F * 4);
+  auto step = [&](int u, bool reload) {
 #pragma unroll
         for (int ft = 0; ft < FT; ++ft) {
           const __bf16* bp = bb + ft * 16 * JCS + c_step * 64;
@@ -343,7 +340,7 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], b1, acc[mt][ft]);
         }
-        if (sidx + U < total) load_next(xv[u]);
+        if (reload) load_next(xv[u]);
         if (++c_step == nsteps) {
           // end of a slab: scale by s_i * H1[i, f] and accumulate
           const int i = s0 + c_sl;
@@ -351,7 +348,9 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
 #pragma unroll
           for (int ft = 0; ft < FT; ++ft) {
             const int f = ft * 16 + n;
-            const float coef = (f < F) ? sc * Ha[(int64_t)i * F + f] : 0.f;
+            const float h = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(ars, f < F ? (i * F + f) * 4 : kBufferOOB, 0, 0));
+            const float coef = sc * h;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
@@ -361,7 +360,8 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
           }
           c_step = 0;
           if (++c_sl == ns) {
-            // end of a row group: write this item's partial rows
+            // end of a row group: write this item's partial rows (rows past
+            // K and columns past F get offsets past the resource: dropped)
             const int rg = wave + 4 * c_rgc;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -371,7 +371,11 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
                 for (int ii = 0; ii < 4; ++ii) {
                   const int k = rg * R + mt * 16 + 4 * g + ii;
                   const int f = ft * 16 + n;
-                  if (k < K && f < F) P.W3p[((int64_t)idx * K + k) * F + f] = tot[mt][ft][ii];
+                  // (the element is copied out first: a bit cast of a vector
+                  // element lvalue reads element 0 with this compiler)
+                  const float t = tot[mt][ft][ii];
+                  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, t), wrs,
+                                                        (k < K && f < F) ? (k * F + f) * 4 : kBufferOOB, 0, 0);
                 }
                 tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
               }
@@ -379,9 +383,15 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
             ++c_rgc;
           }
         }
-      }
-    }
+  };
+  const int full = total - total % U;
+  for (int s = 0; s < full; s += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) step(u, true);
   }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (full + u < total) step(u, false);
 }
 
 // ---------------------------------------------------------------- mode-2 item

@@ -194,6 +194,11 @@ static ntf_status validate(const ntf_problem* probs, int32_t n, const ntf_opts* 
         return fail("factor/dual null or not 16-byte aligned" + at);
     if (pr.dims[0] * pr.dims[1] * pr.dims[2] > ((int64_t)1 << 40)) return fail("tensor too large" + at);
     const BProb b = base_prob(pr);
+    // the work items address one slab, a factor or a partial of W3 through
+    // 32-bit byte offsets (plus a tile of rows past the end)
+    if ((int64_t)(b.J + 64) * b.Kp * 2 >= kBufferOOB || (int64_t)(b.K + 64) * b.Jp * 2 >= kBufferOOB ||
+        (int64_t)(std::max({b.I, b.J, b.K}) + 64) * b.F * 4 >= kBufferOOB)
+      return fail("the batched solver takes slabs J x K and factors under 1 GiB" + at, NTF_E_UNSUPPORTED);
     if (max_lds(b) > kLdsMax)
       return fail("work items of this shape exceed the LDS" + at, NTF_E_UNSUPPORTED);
   }

@@ -27,29 +27,11 @@ namespace ntf {
 // step of the last row may read up to 32 past it)
 constexpr int kPass1Tail = 64;
 
-// Raw buffer resources (stride 0, num_records in bytes): the fourth word for
-// gfx9-family parts, and a byte offset past any resource used here (a load
-// past num_records returns zeros).
-constexpr int kBufferWord3 = 0x00020000;
-constexpr int kBufferOOB = 0x7ffffff0;
-
 // Waves per SIMD the streaming pass-1 kernel is compiled for: four (two
 // blocks of 512 threads per CU, 128 VGPRs) while F <= 32, two at larger F
 // (its accumulators and prefetched epilogue values need more registers).
 template <int FT>
 static constexpr int kPass1Waves() { return FT <= 2 ? 4 : 2; }
-
-// A raw buffer resource over [p, p + bytes) whose words are read from the
-// first lane: the resource sits in scalar registers even where the compiler
-// cannot prove p wave-uniform (p must be wave-uniform).
-static __device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, int bytes) {
-  const uint64_t a = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-  void* q = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
-  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, __builtin_amdgcn_readfirstlane(bytes),
-                                           kBufferWord3);
-}
 
 // ---------------------------------------------------------------- set-up
 

@@ -93,6 +93,24 @@ static __device__ __forceinline__ void load4(const T* p, int valid, int vec, T (
   }
 }
 
+// Raw buffer resources (stride 0, num_records in bytes): the fourth word for
+// gfx9-family parts.  kBufferOOB (the launch header) is a byte offset past
+// any resource used here: a load past num_records returns zeros, a store
+// there is dropped.
+constexpr int kBufferWord3 = 0x00020000;
+
+// A raw buffer resource over [p, p + bytes) whose words are read from the
+// first lane: the resource sits in scalar registers even where the compiler
+// cannot prove p wave-uniform (p must be wave-uniform).
+static __device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, int bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void* q = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                           kBufferWord3);
+}
+
 // Reduce across the `width` lanes of an aligned lane group (width a power of 2, <= 64).
 template <typename T>
 static __device__ __forceinline__ T group_sum(T v, int width) {

@@ -8,6 +8,10 @@
 
 namespace ntf {
 
+// A byte offset past every buffer resource the kernels build (their sizes
+// stay below it; the host checks that before choosing such a kernel).
+constexpr int kBufferOOB = 0x7ffffff0;
+
 enum Prec { PREC_F32 = 0, PREC_BF16 = 1, PREC_F64 = 3 };
 
 // Launch geometry of the three MTTKRP kernels and the inner sweep for one
