@@ -7,12 +7,16 @@
 //   mode 2:  W2[j,:]  = sum_i A_new[i,:] * T[i,j,:]   (T re-read; X is not)
 //   pass 3:  W3[k,:]  = sum_{i,j} X[i,j,k] A_new[i,:] * B_new[j,:]
 //                                                    (MFMA, contraction over (i,j);
-//                                                     Khatri-Rao rows built per tile in LDS)
+//                                                     FP32/FP64: Khatri-Rao rows built
+//                                                     per tile in LDS; BF16: B_new in
+//                                                     LDS, A_new applied per slab)
 //
 // Modes 1 and 2 both contract C^k over k (the update of B uses A^{k+1} and C^k),
 // so the k-contraction T is shared by them: two passes over X per outer
 // iteration instead of three.  The Khatri-Rao matrix is never materialised:
-// pass 1 keeps C in LDS, pass 3 builds 64 Khatri-Rao rows at a time in LDS.
+// pass 1 keeps C in LDS; pass 3 builds 64 Khatri-Rao rows at a time in LDS
+// (FP32/FP64) or contracts each slab against B and scales the result by the
+// slab's row of A (BF16).
 //
 // All partial sums are written to fixed slots and reduced later in a fixed
 // order, so results are bitwise reproducible.
@@ -952,101 +956,164 @@ __global__ __launch_bounds__(512, 2) void k_pass3s(const T* __restrict__ X, int6
 
 // ---------------------------------------------------------------- pass 3, BF16
 
-// X from the j-interleaved copy Xj8[q][k][e] (q = i*JG + jg, row j = 8jg + e):
-// lane (n,g) loads the 8 rows of group jg0 + 4s + g at k = kt + n with one
-// 16-byte read, which is exactly the A operand of v_mfma_f32_16x16x32_bf16
-// (contraction over 32 rows, result rows = 16 consecutive k).  A block owns a
-// range of slabs; per slab (or chunk of JCG groups of a slab, when a whole slab
-// does not fit) it builds the Khatri-Rao rows s_i * A[i][f] * B[j][f] of the
-// slab in LDS as bf16, transposed [FP][8*JCG+8], with coalesced loads of B,
-// so the B operand is again one 16-byte read; X loads of the slab are issued
-// before the build and run U steps ahead.
+// Mode-3 MTTKRP in factored form: W3[k,:] = sum_i s_i A[i,:] *
+// (sum_j Xq[i,j,k] bf16(B[j,:])).  The inner sum is an MFMA contraction over
+// j whose B operand does not depend on the slab, so a block stages
+// bf16(H2)^T for one chunk of 8-row groups of j in LDS once ([FP][JCS], zero
+// past J and past the chunk).  X comes from the j-interleaved copy
+// Xj8[q][k][e] (q = i*JG + jg, row j = 8jg + e): lane (n,g) of a 32-row step
+// loads the 8 rows of group 4*step + g at row k with one 16-byte read, which
+// is exactly the A operand of v_mfma_f32_16x16x32_bf16.  Each wave owns 64
+// rows of k (four 16-row tiles) and a run of slabs, walked as one continuous
+// sequence of (slab, step) with U steps of loads in flight through a buffer
+// resource per (slab, chunk): groups past the chunk and rows past Kp3 read
+// as zeros, so every path issues the same loads.  At the end of a slab the
+// FP32 products are scaled by s_i A[i,f] (loaded when the slab starts) and
+// added to the wave's running sums, which go to the partial of its (chunk,
+// slab group): P3[chunk * ngroups + group][K][F].
 template <int FT>
-__global__ __launch_bounds__(768) void k_pass3_bf16(const __bf16* __restrict__ Xj8,
-                                                    const float* __restrict__ scale, int I,
-                                                    int J, int JG, int K, int Kp3, int F,
-                                                    const float* __restrict__ Ha,
-                                                    const float* __restrict__ Hb,
-                                                    float* __restrict__ P3, int spb, int JCG) {
+__global__ __launch_bounds__(512) void k_pass3_bf16s(const __bf16* __restrict__ Xj8,
+                                                     const float* __restrict__ scale, int I, int J,
+                                                     int JG, int K, int Kp3, int F,
+                                                     const float* __restrict__ Ha,
+                                                     const float* __restrict__ Hb,
+                                                     float* __restrict__ P3, int nkt, int spg,
+                                                     int ngroups, int jcg, int bpc) {
   constexpr int FP = FT * 16;
-  constexpr int U = 2;
+  constexpr int MT = 4;
+  constexpr int U = 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __bf16* KRt = reinterpret_cast<__bf16*>(smem_raw);
-  const int KRL = 32 * ((JCG + 3) / 4);  // rows per chunk rounded up to whole MFMA steps
-  const int KRP = KRL + 8;               // LDS row stride (elements), 16-byte multiple
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int kw0 = (blockIdx.y * nw + wave) * 64;
-  const bool kact = kw0 < Kp3;
-  const int ibeg = blockIdx.x * spb, iend = min(I, ibeg + spb);
-  const int nchunk = (JG + JCG - 1) / JCG;
-  f32x4 acc[4][FT];
+  __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = lane & 15, g = lane >> 4;
+  const int c = blockIdx.x / bpc, lb = blockIdx.x - c * bpc;
+  const int jg0 = c * jcg, ng = min(jcg, JG - jg0);
+  const int nsteps = (ng + 3) >> 2;
+  const int JL = 32 * nsteps;                  // staged rows of this chunk (whole steps)
+  const int JCS = 32 * ((jcg + 3) >> 2) + 8;   // LDS row stride, a 16-byte multiple
+  const int gw = lb * (int)(blockDim.x >> 6) + wave;
+  const int grp = gw / nkt, kt = gw - grp * nkt;
+  const int i0 = grp * spg;
+  const int ns = grp < ngroups ? min(I, i0 + spg) - i0 : 0;
+  const int total = __builtin_amdgcn_readfirstlane(ns * nsteps);
+
+  // load cursor: (slab l_sl of the run, step l_st of the chunk); past the
+  // end it stays on the run's last slab (in-bounds reads nothing consumes).
+  // Rows k >= Kp3 get a byte offset of at least kBufferOOB, groups past the
+  // chunk an offset past the (slab, chunk) resource: both read as zeros, and
+  // every step issues the same loads, so the wait before a step covers that
+  // step's loads only.  Each step also loads the A row of its slab (lane l:
+  // A[i, l]); the slab's last step takes its coefficients from it.
+  int kof[MT];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int i = ibeg; i < iend; ++i) {
-    for (int cj = 0; cj < nchunk; ++cj) {
-      const int jg0 = cj * JCG, ng = min(JCG, JG - jg0);
-      const int nsteps = (ng + 3) >> 2;
-      const __bf16* xq = Xj8 + ((int64_t)i * JG + jg0) * Kp3 * 8;
-      bf16x8 xv[U][4];
-      auto load = [&](int st, bf16x8 (&dst)[4]) {
-        const int gq = 4 * st + g;
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-          const int kt = kw0 + mt * 16;
-          if (kact && gq < ng && kt < Kp3) {
-            dst[mt] = *reinterpret_cast<const bf16x8*>(xq + ((int64_t)gq * Kp3 + kt + n) * 8);
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) dst[mt][e] = (__bf16)0.f;
-          }
-        }
-      };
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (u < nsteps) load(u, xv[u]);
-      __syncthreads();  // previous chunk's MFMAs are done with KRt
-      const float si = scale[i];
-      for (int idx = threadIdx.x; idx < KRL * FP; idx += blockDim.x) {
-        const int rr = idx / FP, f = idx - rr * FP;
-        const int j = jg0 * 8 + rr;
-        float v = 0.f;
-        if (rr < 8 * ng && j < J && f < F) v = si * Ha[(int64_t)i * F + f] * Hb[(int64_t)j * F + f];
-        KRt[f * KRP + rr] = (__bf16)v;
-      }
-      __syncthreads();
-      if (kact) {
-        const __bf16* kr = KRt + n * KRP + 8 * g;
-        for (int st0 = 0; st0 < nsteps; st0 += U) {
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int st = st0 + u;
-            if (st < nsteps) {
-#pragma unroll
-              for (int ft = 0; ft < FT; ++ft) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(kr + ft * 16 * KRP + st * 32);
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt) acc[mt][ft] = mma_bf16(xv[u][mt], bv, acc[mt][ft]);
-              }
-              if (st + U < nsteps) load(st + U, xv[u]);
-            }
-          }
-        }
-      }
-    }
+  for (int mt = 0; mt < MT; ++mt) {
+    const int k = kt * 64 + mt * 16 + n;
+    kof[mt] = k < Kp3 ? k * 16 : kBufferOOB;
   }
-  if (!kact) return;
+  const int aof = lane < F ? lane * 4 : kBufferOOB;
+  const int chunk_bytes = ng * Kp3 * 16, gstride = Kp3 * 16;
+  int l_sl = 0, l_st = 0;
+  bf16x8 xv[U][MT];
+  float ar[U];
+  auto load_next = [&](bf16x8 (&dst)[MT], float& adst) {
+    const int i = i0 + l_sl;
+    const __amdgpu_buffer_rsrc_t ars = uniform_rsrc(Ha + (int64_t)i * F, F * 4);
+    adst = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ars, aof, 0, 0));
+    const __amdgpu_buffer_rsrc_t rs =
+        uniform_rsrc(Xj8 + ((int64_t)i * JG + jg0) * Kp3 * 8, chunk_bytes);
+    const int qoff = (4 * l_st + g) * gstride;
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
+      dst[mt] = __builtin_bit_cast(
+          bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((unsigned)qoff + (unsigned)kof[mt]), 0, 0));
+    if (++l_st == nsteps) {
+      l_st = 0;
+      if (l_sl + 1 < ns) ++l_sl;
+    }
+  };
+  // the first U steps go out before the chunk of H2^T is staged
+  if (total > 0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) load_next(xv[u], ar[u]);
+  }
+  for (int idx = threadIdx.x; idx < JL * FP; idx += blockDim.x) {
+    const int jj = idx / FP, f = idx - jj * FP;
+    const int j = jg0 * 8 + jj;
+    const float v = (jj < 8 * ng && j < J && f < F) ? Hb[(int64_t)j * F + f] : 0.f;
+    Bs[f * JCS + jj] = (__bf16)v;
+  }
+  __syncthreads();
+  if (total == 0) return;
+
+  f32x4 acc[MT][FT], tot[MT][FT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+      acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+      tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  int c_sl = 0, c_st = 0;
+  const __bf16* bb = Bs + n * JCS + 8 * g;
+  auto step = [&](int u, bool reload) {
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(bb + ft * 16 * JCS + c_st * 32);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][mt], bv, acc[mt][ft]);
+    }
+    // (the coefficients are read out of ar[u] before its reload, so the
+    // reload can write the same registers: no copy, no wait, at the loop end)
+    const bool last = c_st + 1 == nsteps;
+    float coef[FT];
+    if (last) {
+      const float sc = scale[i0 + c_sl];
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) coef[ft] = sc * __shfl(ar[u], ft * 16 + n);
+    }
+    if (reload) load_next(xv[u], ar[u]);
+    if (last) {
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) tot[mt][ft][ii] += coef[ft] * acc[mt][ft][ii];
+          acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    // (both counters assigned on every path: an increment of one or the
+    // other in two branches becomes a store through a pointer select, and
+    // the counters then live in scratch memory)
+    c_sl += last ? 1 : 0;
+    c_st = last ? 0 : c_st + 1;
+  };
+  const int full = total - total % U;
+  for (int s0 = 0; s0 < full; s0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) step(u, true);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (full + u < total) step(u, false);
+
+  // the wave's 64 rows of the partial (rows past K, columns past F: dropped)
+  const int krows = min(64, K - kt * 64);
+  const __amdgpu_buffer_rsrc_t wrs =
+      uniform_rsrc(P3 + ((int64_t)(c * ngroups + grp) * K + kt * 64) * F, krows * F * 4);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
-        const int k = kw0 + mt * 16 + 4 * g + ii;
+        const int r = mt * 16 + 4 * g + ii;
         const int f = ft * 16 + n;
-        if (k < K && f < F) P3[((int64_t)blockIdx.x * K + k) * F + f] = acc[mt][ft][ii];
+        // (the element is copied to a scalar first: a bit cast of a vector
+        // element lvalue reads element 0 with this compiler)
+        const float t = tot[mt][ft][ii];
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, t), wrs,
+                                              (r < krows && f < F) ? (r * F + f) * 4 : kBufferOOB, 0, 0);
       }
 }
 
@@ -1141,21 +1208,31 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   p.nich2 = (int)cdiv(p.I, p.ich2);
   // pass 3: k split into 64-column wave tiles.  FP32/FP64: at most 8 waves per
   // block, balanced over ceil(tiles/8) k-groups, row chunks for about two
-  // blocks per CU.  BF16: up to 12 waves per block, blocks own whole slabs
-  // (or slab chunks of JCG 8-row groups whose Khatri-Rao rows fit in LDS).
+  // blocks per CU.  BF16: see below.
   const int64_t kspan = (prec == PREC_BF16) ? p.Kp3 : p.K;
   const int ktiles = (int)cdiv(kspan, 64);
   if (prec == PREC_BF16) {
-    p.nkg3 = (int)cdiv(ktiles, 12);
-    p.nw3 = (int)cdiv(ktiles, p.nkg3);
-    int64_t jcg = p.JG;
+    // one block of 8 waves per CU; a wave owns 64 rows of k and a run of
+    // slabs of one chunk of j, the chunk's bf16(H2)^T staged in LDS
+    p.nkt3 = ktiles;
     auto lds_of = [&](int64_t q) { return (size_t)p.FP * (32 * cdiv(q, 4) + 8) * 2; };
-    while (lds_of(jcg) > kLdsBudget) jcg = cdiv(jcg, 2);
+    int64_t jcg = p.JG;
+    // (a chunk's byte offsets, three groups past its end included, stay
+    // below 2^31, so an offset plus kBufferOOB does not wrap)
+    auto fits = [&](int64_t q) {
+      return lds_of(q) <= kLdsBudget && (q + 4) * p.Kp3 * 16 < (int64_t)kBufferOOB;
+    };
+    while (jcg > 4 && !fits(jcg)) jcg = rup(cdiv(jcg, 2), 4);
+    if (!fits(jcg)) return false;
     p.jcg3 = (int)jcg;
     p.lds3 = lds_of(jcg);
-    const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(p.I, (int64_t)cus / p.nkg3));
-    p.rpc3 = cdiv(p.I, nblk);          // slabs per block
-    p.nrc3 = (int)cdiv(p.I, p.rpc3);
+    p.nch3 = (int)cdiv(p.JG, jcg);
+    const int64_t waves = (int64_t)cus * 8;
+    const int64_t ng = std::max<int64_t>(1, std::min<int64_t>(p.I, waves / ((int64_t)ktiles * p.nch3)));
+    p.rpc3 = cdiv(p.I, ng);                 // slabs per group
+    p.ngr3 = (int)cdiv(p.I, p.rpc3);
+    p.bpc3 = (int)cdiv((int64_t)p.ngr3 * ktiles, 8);
+    p.nrc3 = p.nch3 * p.ngr3;               // partials: one per (chunk, group)
   } else {
     p.nkg3 = (int)cdiv(ktiles, 8);
     p.nw3 = (int)cdiv(ktiles, p.nkg3);
@@ -1318,13 +1395,13 @@ static void pass3_t(const Plan& p, const void* X, const void* Ha, const void* Hb
 template <int FT>
 static hipError_t pass3_bf16(const Plan& p, const __bf16* Xj8, const float* scale, const void* Ha,
                              const void* Hb, void* P3, hipStream_t s) {
-  auto kern = k_pass3_bf16<FT>;
+  auto kern = k_pass3_bf16s<FT>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)p.lds3);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(p.nrc3, p.nkg3), dim3(64 * p.nw3), p.lds3, s, Xj8, scale,
+  hipLaunchKernelGGL(kern, dim3((unsigned)(p.nch3 * p.bpc3)), dim3(512), p.lds3, s, Xj8, scale,
                      (int)p.I, (int)p.J, (int)p.JG, (int)p.K, (int)p.Kp3, p.F, (const float*)Ha,
-                     (const float*)Hb, (float*)P3, (int)p.rpc3, p.jcg3);
+                     (const float*)Hb, (float*)P3, p.nkt3, (int)p.rpc3, p.ngr3, p.jcg3, p.bpc3);
   return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@ struct Plan {
   // pass 3 (mode-3 MTTKRP): waves per block, k-groups, row chunks
   int nw3 = 0, nkg3 = 0, nrc3 = 0;
   int64_t rpc3 = 0;               // rows (FP32/FP64) or slabs (BF16) per block
-  int jcg3 = 0;                   // BF16: 8-row groups per Khatri-Rao chunk in LDS
+  int jcg3 = 0;                   // BF16: 8-row groups of j per chunk staged in LDS
+  int nkt3 = 0, nch3 = 0, ngr3 = 0, bpc3 = 0;   // BF16: k tiles, j chunks, slab groups, blocks per chunk
   size_t lds3 = 0;
   // inner sweep: lanes per row, rows per block, blocks per mode
   int FL = 0, rpb = 0;
