@@ -67,10 +67,10 @@ size_t batch_lds_prep() { return (size_t)kPrepLdsDoubles * sizeof(double); }
 // Slabs s0 .. s0+ns-1 of one problem.  H3^T (BF16) sits in LDS; each wave
 // walks its 16*MT-row tiles (slab-major, tiles wave, wave+4, ...) as one
 // continuous sequence of 64-element super steps with U steps of loads in
-// flight, so its pipeline does not drain between tiles.  A lane's 32-byte
-// load covers contraction elements 16g .. 16g+15 of a super step; the two
-// MFMAs of the step take the first and second 8 (the contraction order
-// inside an instruction is free as long as both operands agree).
+// flight, so its pipeline does not drain between tiles.  The two MFMAs of a
+// super step contract its elements 0-31 and 32-63 (lane group g: 8g .. 8g+7
+// of each half), so each 16-byte load instruction reads 64 contiguous bytes
+// of 16 rows.
 template <int FT, int MT>
 __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned char* lds, const int tid) {
   constexpr int FP = FT * 16;
@@ -102,7 +102,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
     const int sl = t / nrg, rg = t - sl * nrg;
     l_slab = P.Xr + (int64_t)(s0 + sl) * J * Kp;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Kp + 16 * g) * 2;
+    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Kp + 8 * g) * 2;
   };
   bf16x8 xv[U][2][MT];
   auto load_next = [&](bf16x8 (&dst)[2][MT]) {
@@ -111,7 +111,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        const int off = (l_kb + 16 * g + 8 * h < Kp) ? l_off[mt] + (l_kb + 8 * h) * 2 : kBufferOOB;
+        const int off = (l_kb + 8 * g + 32 * h < Kp) ? l_off[mt] + (l_kb + 32 * h) * 2 : kBufferOOB;
         dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
       }
     l_kb += 64;
@@ -153,7 +153,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
       }
     };
     int c_t = wave, c_step = 0;
-    const __bf16* cb = Cs + n * KCS + 16 * g;
+    const __bf16* cb = Cs + n * KCS + 8 * g;
     // H2 values of the current tile's epilogue, loaded when the tile starts
     // so that their latency hides behind the tile's MFMA steps
     // H2 values and T stores through resources too (rows past J, columns
@@ -181,7 +181,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
           for (int ft = 0; ft < FT; ++ft) {
             const __bf16* cp = cb + ft * 16 * KCS + c_step * 64;
             const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(cp);
-            const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(cp + 8);
+            const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(cp + 32);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], c0, acc[mt][ft]);
 #pragma unroll
@@ -279,7 +279,7 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
   auto set_rows = [&]() {
     const int rg = wave + 4 * l_rgc;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Jp + 16 * g) * 2;
+    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Jp + 8 * g) * 2;
   };
   bf16x8 xv[U][2][MT];
   auto load_next = [&](bf16x8 (&dst)[2][MT]) {
@@ -288,7 +288,7 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        const int off = (l_kb + 16 * g + 8 * h < Jp) ? l_off[mt] + (l_kb + 8 * h) * 2 : kBufferOOB;
+        const int off = (l_kb + 8 * g + 32 * h < Jp) ? l_off[mt] + (l_kb + 32 * h) * 2 : kBufferOOB;
         dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
       }
     l_kb += 64;
@@ -326,7 +326,7 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
       tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
   int c_step = 0, c_sl = 0, c_rgc = 0;
-  const __bf16* bb = Bs + n * JCS + 16 * g;
+  const __bf16* bb = Bs + n * JCS + 8 * g;
   const __amdgpu_buffer_rsrc_t ars = uniform_rsrc(Ha, P.I * F * 4);
   const __amdgpu_buffer_rsrc_t wrs = uniform_rsrc(P.W3p + (int64_t)idx * K * F, K * F * 4);
   auto step = [&](int u, bool reload) {
@@ -334,7 +334,7 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
         for (int ft = 0; ft < FT; ++ft) {
           const __bf16* bp = bb + ft * 16 * JCS + c_step * 64;
           const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(bp);
-          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(bp + 8);
+          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(bp + 32);
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], b0, acc[mt][ft]);
 #pragma unroll

@@ -376,11 +376,19 @@ __global__ __launch_bounds__(512) void k_pass1_bf16(const __bf16* __restrict__ X
   }
 }
 
-// BF16 pass 1, streaming form (C fits in LDS, loaded once per block): each
-// wave walks its items (i, chunk) as one continuous sequence of 64-k super
-// steps, so its U-deep load pipeline never drains at item boundaries; the
-// epilogue of an item (T store and W1 partial) runs between two super steps
-// while the loads of the next item are already in flight.
+// BF16 pass 1, streaming form (C fits in LDS, loaded once per block).  Work
+// is split into (row tile ch of j, run of consecutive slabs) pairs, tiles
+// fastest, so a wave keeps one tile for a long run: its H2 values (the
+// epilogue's W1 weights, 32 per lane) load once per run, and the X loads of
+// the run go through a per-slab buffer resource at lane offsets fixed for the
+// run.  The wave walks (slab, 64-k super step) as one continuous sequence with
+// U steps of loads in flight; every step issues the same loads (rows j >= J
+// lie past the slab, columns past Kp in the last super step get kBufferOOB),
+// so the wait before a step covers that step only.  The two MFMAs of a super
+// step contract its columns 0-31 and 32-63, so each load instruction reads 64
+// contiguous bytes of 16 rows (lane group g: columns 8g .. 8g+7 of a half).  The epilogue of a slab
+// (T rows and the W1 partial of (i, ch)) stores through resources at offsets
+// that drop rows past J, columns past F and the lanes that hold no partial.
 template <int FT, int MT>
 __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __bf16* __restrict__ Xr,
                                                      const float* __restrict__ scale, int I, int J,
@@ -391,7 +399,9 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
                                                      float* __restrict__ P1, int nch, int KC) {
   constexpr int FP = FT * 16;
   constexpr int R = 16 * MT;
-  constexpr int U = (FT <= 2) ? 3 : 4;
+  // (four waves per SIMD at FT <= 2, two at FT > 2: the same 128 KB of
+  // tensor loads in flight per CU either way)
+  constexpr int U = (FT <= 2) ? 2 : 4;
   // Rows of H3^T are Kp + 8 long (not KC + 8): two blocks then fit a CU at
   // F = 64, K = 600.  A super step past Kp reads the start of the next row (or
   // the zeroed tail after the last row) against tensor operands that are zero
@@ -399,8 +409,6 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
   const int KCS = Kp + 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __bf16* Cs = reinterpret_cast<__bf16*>(smem_raw);
-  // (wave index made uniform: the items, and the buffer resources derived from
-  // them, then live in scalar registers)
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n = lane & 15, g = lane >> 4;
   for (int idx = threadIdx.x; idx < Kp * FP; idx += blockDim.x) {
@@ -414,136 +422,135 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
     Cs[e] = (__bf16)0.f;
   }
   __syncthreads();
-  const int64_t nitems = (int64_t)I * nch;
   const int nwb = blockDim.x >> 6;
-  const int64_t stride = (int64_t)gridDim.x * nwb;
-  const int64_t first = (int64_t)blockIdx.x * nwb + wave;
-  if (first >= nitems) return;
-  const int64_t myitems = (nitems - first + stride - 1) / stride;
+  const int W = gridDim.x * nwb;
+  const int gw = blockIdx.x * nwb + wave;
+  // G slab groups per tile (at least one), spg slabs per group
+  const int G0 = max(1, W / nch);
+  const int spg = (I + G0 - 1) / G0;
+  const int G = (I + spg - 1) / spg;
+  const int64_t npairs = (int64_t)nch * G;
   const int nsteps = (Kp + 63) / 64;
-  // (wave-uniform, and said so: the loop's branches then need no exec masks)
-  const int total = __builtin_amdgcn_readfirstlane((int)(myitems * nsteps));
-
-  // load cursor
-  // Loads go through a buffer resource per slab: rows j >= J lie past the
-  // slab's num_records and lanes of a super step past Kp get an offset past
-  // it too, so the hardware returns zeros for both (no per-lane branches, and
-  // 32-bit offsets instead of 64-bit addresses).
-  int64_t l_item = first;
-  int l_kb = 0;
-  const __bf16* l_slab = Xr;
-  int l_off[MT];
-  auto set_rows = [&](int64_t item) {
-    const int i = (int)(item / nch), ch = (int)(item - (int64_t)i * nch);
-    l_slab = Xr + (int64_t)i * J * Kp;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((ch * R + mt * 16 + n) * Kp + 16 * g) * 2;
-  };
-  set_rows(l_item);
-  bf16x8 xv[U][2][MT];
-  auto load_next = [&](bf16x8 (&dst)[2][MT]) {
-    const bool tail = l_kb + 64 > Kp;   // wave-uniform
-    const __amdgpu_buffer_rsrc_t l_rs = uniform_rsrc(l_slab, J * Kp * 2);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        int off = l_off[mt] + (l_kb + 8 * h) * 2;
-        if (tail && l_kb + 16 * g + 8 * h >= Kp) off = kBufferOOB;
-        dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(l_rs, off, 0, 0));
-      }
-    l_kb += 64;
-    if (l_kb >= Kp) {
-      l_kb = 0;
-      l_item += stride;
-      if (l_item < nitems) set_rows(l_item);
-    }
-  };
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-    if (u < total) load_next(xv[u]);
-
-  f32x4 acc[MT][FT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int64_t c_item = first;
-  int c_step = 0;
-  const __bf16* cb = Cs + n * KCS + 16 * g;
-  // H2 values and T offsets of the current item's epilogue, computed when the
-  // item starts so the loads' latency hides behind its MFMA steps
+  const __bf16* cb = Cs + n * KCS + 8 * g;
   const __amdgpu_buffer_rsrc_t hrs = uniform_rsrc(Hb, J * F * 4);
-  float hbv[MT][FT][4];
-  auto eoff = [&](int ch, int mt, int ft, int ii) {   // offset of (row, column) in a [J][F] slab
-    const int j = ch * R + mt * 16 + 4 * g + ii, f = ft * 16 + n;
-    return (f < F) ? (j * F + f) * 4 : kBufferOOB;
-  };
-  auto item_start = [&](int64_t item) {
-    const int ch = (int)(item - (item / nch) * nch);
+  // byte offset of column f = 16 ft + n in a row of T (past F: kBufferOOB);
+  // OR-ed with gmask it is the offset in the W1 partial, which lane group 0
+  // stores (for the others it is at least kBufferOOB)
+  int fo[FT];
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) fo[ft] = ft * 16 + n < F ? (ft * 16 + n) * 4 : kBufferOOB;
+  const int gmask = g == 0 ? 0 : kBufferOOB;
+
+  for (int64_t pr = gw; pr < npairs; pr += W) {
+    // (said to be wave-uniform: slab indices then live in scalar registers
+    // and the slab scale is a scalar load, outside the vector-load count)
+    const int ch = __builtin_amdgcn_readfirstlane((int)(pr % nch));
+    const int i0 = __builtin_amdgcn_readfirstlane((int)(pr / nch) * spg);
+    const int ns = min(I, i0 + spg) - i0;
+    const int total = ns * nsteps;   // >= 1
+
+    // H2 values of the tile (zeros past J and F), loaded before the run's
+    // first tensor loads: the wait before the first step covers them
+    float hbv[MT][FT][4];
+    // byte offset of the tile row (mt, ii) of this lane in a [J][F] slab
+    const int tb = (ch * R + 4 * g) * F * 4;
+    auto trow = [&](int mt, int ii) { return tb + (mt * 16 + ii) * F * 4; };
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int ft = 0; ft < FT; ++ft)
+      for (int ii = 0; ii < 4; ++ii)
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii)
+        for (int ft = 0; ft < FT; ++ft)
           hbv[mt][ft][ii] = __builtin_bit_cast(
-              float, __builtin_amdgcn_raw_buffer_load_b32(hrs, eoff(ch, mt, ft, ii), 0, 0));
-  };
-  for (int64_t s0 = 0; s0 < total; s0 += U) {
+              float, __builtin_amdgcn_raw_buffer_load_b32(
+                         hrs, (int)((unsigned)trow(mt, ii) + (unsigned)fo[ft]), 0, 0));
+
+    // load cursor: (slab l_sl of the run, super step at column l_kb)
+    int l_off[MT];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t sidx = s0 + u;
-      if (sidx < total) {
-        if (c_step == 0) item_start(c_item);
+    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((ch * R + mt * 16 + n) * Kp + 8 * g) * 2;
+    int l_sl = 0, l_kb = 0;
+    bf16x8 xv[U][2][MT];
+    auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+      const bool tail = l_kb + 64 > Kp;   // wave-uniform
+      const __amdgpu_buffer_rsrc_t l_rs = uniform_rsrc(Xr + (int64_t)(i0 + l_sl) * J * Kp, J * Kp * 2);
 #pragma unroll
-        for (int ft = 0; ft < FT; ++ft) {
-          const __bf16* cp = cb + ft * 16 * KCS + c_step * 64;
-          const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(cp);
-          const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(cp + 8);
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], c0, acc[mt][ft]);
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], c1, acc[mt][ft]);
+        for (int mt = 0; mt < MT; ++mt) {
+          int off = l_off[mt] + (l_kb + 32 * h) * 2;
+          if (tail && l_kb + 8 * g + 32 * h >= Kp) off = kBufferOOB;
+          dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(l_rs, off, 0, 0));
         }
-        if (sidx + U < total) load_next(xv[u]);
-        if (++c_step == nsteps) {
-          // epilogue of item c_item: T rows stored through a resource over
-          // slab i of T (rows j >= J and columns f >= F get an offset past it:
-          // the hardware drops those stores); H2 values were loaded at the
-          // item's first step (zeros at the same places)
-          const int i = (int)(c_item / nch);
-          const int ch = (int)(c_item - (int64_t)i * nch);
-          const float sc = scale[i];
-          const __amdgpu_buffer_rsrc_t trs = uniform_rsrc(Tout + (int64_t)i * J * F, J * F * 4);
-          float part[FT];
+      l_kb += 64;
+      const bool wrap = l_kb >= Kp;
+      l_kb = wrap ? 0 : l_kb;
+      l_sl += (wrap && l_sl + 1 < ns) ? 1 : 0;   // past the run's end: stay on its last slab
+    };
 #pragma unroll
-          for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
+    for (int u = 0; u < U; ++u) load_next(xv[u]);
+
+    f32x4 acc[MT][FT];
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int ft = 0; ft < FT; ++ft) {
+      for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int c_sl = 0, c_step = 0;
+    auto step = [&](int u, bool reload) {
 #pragma unroll
-              for (int ii = 0; ii < 4; ++ii) {
-                const float v = sc * acc[mt][ft][ii];
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), trs,
-                                                      eoff(ch, mt, ft, ii), 0, 0);
-                part[ft] += hbv[mt][ft][ii] * v;
-              }
-              acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
+      for (int ft = 0; ft < FT; ++ft) {
+        const __bf16* cp = cb + ft * 16 * KCS + c_step * 64;
+        const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(cp);
+        const bf16x8 c1 = *reinterpret_cast<const bf16x8*>(cp + 32);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], c0, acc[mt][ft]);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], c1, acc[mt][ft]);
+      }
+      if (reload) load_next(xv[u]);
+      const bool last = c_step + 1 == nsteps;
+      if (last) {
+        // epilogue of slab i: T rows (scale folded in) and the W1 partial of
+        // (i, ch), reduced over the 4 lane groups and stored by group 0
+        const int i = __builtin_amdgcn_readfirstlane(i0 + c_sl);
+        const float sc = scale[i];
+        const __amdgpu_buffer_rsrc_t trs = uniform_rsrc(Tout + (int64_t)i * J * F, J * F * 4);
+        float part[FT];
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int ft = 0; ft < FT; ++ft) {
-            part[ft] += __shfl_xor(part[ft], 16);
-            part[ft] += __shfl_xor(part[ft], 32);
-            const int f = ft * 16 + n;
-            if (g == 0 && f < F) P1[((int64_t)i * nch + ch) * F + f] = part[ft];
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+              const float v = sc * acc[mt][ft][ii];
+              __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), trs,
+                                                    (int)((unsigned)trow(mt, ii) + (unsigned)fo[ft]), 0, 0);
+              part[ft] += hbv[mt][ft][ii] * v;
+            }
+            acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
           }
-          c_step = 0;
-          c_item += stride;
+        const __amdgpu_buffer_rsrc_t prs = uniform_rsrc(P1 + ((int64_t)i * nch + ch) * F, F * 4);
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) {
+          part[ft] += __shfl_xor(part[ft], 16);
+          part[ft] += __shfl_xor(part[ft], 32);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, part[ft]), prs, fo[ft] | gmask, 0, 0);
         }
       }
+      // (both counters assigned on every path, so they stay in registers)
+      c_sl += last ? 1 : 0;
+      c_step = last ? 0 : c_step + 1;
+    };
+    const int full = total - total % U;
+    for (int s0 = 0; s0 < full; s0 += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(u, true);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (full + u < total) step(u, false);
   }
 }
 
