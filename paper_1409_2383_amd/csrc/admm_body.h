@@ -478,14 +478,18 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
         if (tid == 0) bad_sh = 1;
         akk = 1.0;
       }
-      const double inv = 1.0 / akk;
-      const double sc = 1.0 / sqrt(akk);
-      double rkl[NB], rkr[NB];
+      // (every LDS read of the step is issued here, before any branch, so
+      // the step waits for one LDS round trip)
+      double rkl[NB], rkr[NB], cm[NB];
 #pragma unroll
       for (int ib = 0; ib < NB; ++ib) {
         rkl[ib] = rowbuf[buf][tj + 16 * ib];
         rkr[ib] = rowbuf[buf][64 + tj + 16 * ib];
       }
+#pragma unroll
+      for (int ia = 0; ia < NB; ++ia) cm[ia] = colbuf[buf][ti + 16 * ia];
+      const double inv = 1.0 / akk;
+      const double sc = 1.0 / sqrt(akk);
 #pragma unroll
       for (int ia = 0; ia < NB; ++ia) {
         const int i = ti + 16 * ia;
@@ -496,7 +500,7 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
             rr[ia][ib] = rkr[ib] * sc;
           }
         } else if (i > k && i < F) {
-          const double m = colbuf[buf][i] * inv;
+          const double m = cm[ia] * inv;
 #pragma unroll
           for (int ib = 0; ib < NB; ++ib) {
             rl[ia][ib] -= m * rkl[ib];

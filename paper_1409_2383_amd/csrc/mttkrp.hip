@@ -389,7 +389,11 @@ __global__ __launch_bounds__(512) void k_pass1_bf16(const __bf16* __restrict__ X
 // contiguous bytes of 16 rows (lane group g: columns 8g .. 8g+7 of a half).  The epilogue of a slab
 // (T rows and the W1 partial of (i, ch)) stores through resources at offsets
 // that drop rows past J, columns past F and the lanes that hold no partial.
-template <int FT, int MT>
+// TS (F a multiple of 4, LDS to spare): the T rows of a slab go through a
+// per-wave LDS area (row stride FP + 4 floats: the column writes of the lane
+// groups then fall in distinct banks) and leave as 16-byte stores, four
+// whole 64-column rows per instruction, instead of 64-byte pieces.
+template <int FT, int MT, bool TS>
 __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __bf16* __restrict__ Xr,
                                                      const float* __restrict__ scale, int I, int J,
                                                      int K, int Kp, int F,
@@ -432,6 +436,9 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
   const int64_t npairs = (int64_t)nch * G;
   const int nsteps = (Kp + 63) / 64;
   const __bf16* cb = Cs + n * KCS + 8 * g;
+  // per-wave T staging area (TS), after H3^T and its tail
+  constexpr int TSS = FP + 4;
+  float* Ts = reinterpret_cast<float*>(smem_raw + ((size_t)FP * KCS + kPass1Tail) * 2) + wave * R * TSS;
   const __amdgpu_buffer_rsrc_t hrs = uniform_rsrc(Hb, J * F * 4);
   // byte offset of column f = 16 ft + n in a row of T (past F: kBufferOOB);
   // OR-ed with gmask it is the offset in the W1 partial, which lane group 0
@@ -525,12 +532,29 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
 #pragma unroll
             for (int ii = 0; ii < 4; ++ii) {
               const float v = sc * acc[mt][ft][ii];
-              __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), trs,
-                                                    (int)((unsigned)trow(mt, ii) + (unsigned)fo[ft]), 0, 0);
+              if constexpr (TS) {
+                Ts[(mt * 16 + 4 * g + ii) * TSS + ft * 16 + n] = v;
+              } else {
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), trs,
+                                                      (int)((unsigned)trow(mt, ii) + (unsigned)fo[ft]), 0, 0);
+              }
               part[ft] += hbv[mt][ft][ii] * v;
             }
             acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
           }
+        if constexpr (TS) {
+          // lane l stores columns 4(l % 16) .. +3 of row 4q + l / 16 of the
+          // tile (rows of one wave's LDS area: its own writes, in order)
+          const int cq = 4 * (lane & 15), rq = lane >> 4;
+          const int co = cq < F ? cq * 4 : kBufferOOB;
+#pragma unroll
+          for (int q = 0; q < R / 4; ++q) {
+            const int r = 4 * q + rq;
+            const f32x4 v = *reinterpret_cast<const f32x4*>(Ts + r * TSS + cq);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), trs,
+                                                   (int)((unsigned)((ch * R + r) * F * 4) + (unsigned)co), 0, 0);
+          }
+        }
         const __amdgpu_buffer_rsrc_t prs = uniform_rsrc(P1 + ((int64_t)i * nch + ch) * F, F * 4);
 #pragma unroll
         for (int ft = 0; ft < FT; ++ft) {
@@ -1189,10 +1213,16 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
     p.JG = cdiv(p.J, 8);
     p.Kp3 = rup(p.K, 16);
     const size_t stream_lds = (size_t)p.FP * (p.Kp + 8) * 2 + kPass1Tail * 2;
+    // T staging of the streaming form: 8 waves x 32 rows x (FP + 4) floats
+    const size_t ts_lds = (size_t)8 * 32 * (p.FP + 4) * 4;
+    const int blocks = p.FT <= 2 ? 2 : 1;   // per CU (kPass1Waves)
     if (stream_lds <= kLdsBudget) {
       // streaming form: all of H3^T in LDS, rows Kp + 8 long
       p.KC1 = (int)rup(p.Kp, 64);
-      p.lds1 = stream_lds;
+      // (not at FT = 2: four waves per SIMD leave no registers for it)
+      p.ts1 = (p.F % 4 == 0) && p.FT != 2 && stream_lds + ts_lds <= kLdsBudget &&
+              blocks * (stream_lds + ts_lds) <= 160 * 1024;
+      p.lds1 = stream_lds + (p.ts1 ? ts_lds : 0);
     } else {
       int64_t kc = rup(p.Kp, 64);
       while ((size_t)p.FP * (kc + 8) * 2 > kLdsBudget) kc = rup(kc / 2, 64);
@@ -1315,8 +1345,12 @@ static hipError_t pass1_mt(const Plan& p, const void* X, const void* Hb, const v
 template <int FT>
 static hipError_t pass1_bf16(const Plan& p, const __bf16* Xr, const float* scale, const void* Hb,
                              const void* Hc, void* Tout, void* P1, hipStream_t s) {
-  if (p.KC1 >= p.Kp && p.J * p.Kp * 2 < (int64_t)kBufferOOB) {   // slab addressable by one resource
-    auto kern = k_pass1_bf16s<FT, 2>;
+  // (slabs of the copy and of T addressable by one resource each)
+  if (p.KC1 >= p.Kp && p.J * p.Kp * 2 < (int64_t)kBufferOOB && (p.J + 32) * p.F * 4 < (int64_t)kBufferOOB) {
+    auto kern = k_pass1_bf16s<FT, 2, false>;
+    if constexpr (FT != 2) {
+      if (p.ts1) kern = k_pass1_bf16s<FT, 2, true>;
+    }
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds1);
     if (e != hipSuccess) return e;

@@ -27,6 +27,7 @@ struct Plan {
   int MT1 = 1, R1 = 16, nch1 = 0, KC1 = 0, grid1 = 0;  // 16*MT1 rows per wave item
   int64_t ntiles1 = 0;
   size_t lds1 = 0;
+  bool ts1 = false;               // BF16 streaming pass 1: T rows staged in LDS, 16-byte stores
   // mode 2 from T
   int ich2 = 16, nich2 = 0;
   // pass 3 (mode-3 MTTKRP): waves per block, k-groups, row chunks
