@@ -114,12 +114,74 @@ static __device__ void resid_totals(const double* __restrict__ part, int nparts,
   __syncthreads();
 }
 
+template <typename HT>
+__device__ void gram_rows(const HT* __restrict__ H, int64_t r0, int64_t r1, int F, int gram_f32,
+                          double* __restrict__ part, double* hs);
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   const int F = a.F;
   const int tid = threadIdx.x;
   __shared__ int is_last;
-  if (a.gram_part) {
+  __shared__ double prep_lds[kPrepLdsDoubles];
+  static_assert(kPrepLdsDoubles >= 64 * 64, "the Gram stage borrows the prepare LDS");
+  if (a.gram_h) {
+    // direct Gram: block b sums rows [b rpp, (b+1) rpp) of the updated factor
+    // in FP64; the last block to finish reduces the partials (4 fixed groups)
+    const int64_t r0 = (int64_t)blockIdx.x * a.gram_rpp;
+    const int64_t r1 = min(a.gram_rows, r0 + a.gram_rpp);
+    double* part = a.gram_scratch + (int64_t)blockIdx.x * F * F;
+    if (a.h_f64)
+      gram_rows<double>(reinterpret_cast<const double*>(a.gram_h), r0, r1, F, 0, part, prep_lds);
+    else
+      gram_rows<float>(reinterpret_cast<const float*>(a.gram_h), r0, r1, F, 0, part, prep_lds);
+    if (blockIdx.x == 0) resid_totals(a.resid_part, a.nparts, a.resid_dst);
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned ticket = atomicAdd(a.counter, 1u);
+      is_last = (ticket == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    if (tid == 0) {
+      *a.counter = 0u;
+      if (a.fresh_dst) *a.fresh_dst = 1;
+    }
+    // group g sums partials g, g+4, ... in order, the four group sums are
+    // added in order (the order of the 4-group reduction kernel); the loads
+    // of four partials for all sixteen entries of a thread go out together
+    const int nent = F * F;
+    double gs[4][16];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) gs[g][k] = 0.0;
+    for (int p0 = 0; p0 < a.gram_nb; p0 += 4) {
+      double v[4][16];
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int e = tid + 256 * k;
+          v[g][k] = (p0 + g < a.gram_nb && e < nent) ? a.gram_scratch[(int64_t)(p0 + g) * nent + e] : 0.0;
+        }
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        if (p0 + g < a.gram_nb) {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) gs[g][k] += v[g][k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + 256 * k;
+      if (e < nent) a.gram_dst[e] = ((gs[0][k] + gs[1][k]) + gs[2][k]) + gs[3][k];
+    }
+    __threadfence_block();
+    __syncthreads();
+  } else if (a.gram_part) {
     // grouped fixed-order reduction (the same order as launch_reduce_partials
     // with 4 groups): block b reduces entries b*64 .. b*64+63
     __shared__ double gred[4][64];
@@ -149,7 +211,6 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   } else if (blockIdx.x != 0) {
     return;
   }
-  __shared__ double prep_lds[kPrepLdsDoubles];
   prep_body<NB>(a, prep_lds, tid);
 }
 
@@ -183,7 +244,12 @@ hipError_t launch_prep(const PrepArgs& pa, int nblk, hipStream_t s) {
   k.K = pa.K;
   k.gram_c = pa.gram_c;
   k.fit_out = pa.fit_out;
-  const int grid = pa.gram_part ? nblk : 1;
+  k.gram_h = pa.gram_h;
+  k.gram_rows = pa.gram_rows;
+  k.gram_rpp = pa.gram_rpp;
+  k.gram_nb = pa.gram_nb;
+  k.gram_scratch = pa.gram_scratch;
+  const int grid = pa.gram_h ? pa.gram_nb : pa.gram_part ? nblk : 1;
   switch ((pa.F + 15) / 16) {
     case 1: hipLaunchKernelGGL(k_prep<1>, dim3(grid), dim3(256), 0, s, k); break;
     case 2: hipLaunchKernelGGL(k_prep<2>, dim3(grid), dim3(256), 0, s, k); break;
@@ -199,6 +265,7 @@ hipError_t launch_prep(const PrepArgs& pa, int nblk, hipStream_t s) {
 // touching the solver state) and the cheap fit terms <W3,H3> and
 // sum(G1 * G2 * G3): out[0..7] residual totals, out[8], out[9] fit terms.
 __global__ __launch_bounds__(256) void k_finish(int F, const double* __restrict__ gram_part,
+                                                int gram_nparts,
                                                 const double* __restrict__ resid_part, int nparts,
                                                 const double* __restrict__ g0,
                                                 const double* __restrict__ g1,
@@ -218,7 +285,7 @@ __global__ __launch_bounds__(256) void k_finish(int F, const double* __restrict_
     const int el = tid & 63, pg = tid >> 6;
     for (int e0 = 0; e0 < F * F; e0 += 64) {
       const int e = e0 + el;
-      gred[pg][el] = (e < F * F) ? group_partial(gram_part + e, (int64_t)F * F, nparts, pg, 4) : 0.0;
+      gred[pg][el] = (e < F * F) ? group_partial(gram_part + e, (int64_t)F * F, gram_nparts, pg, 4) : 0.0;
       __syncthreads();
       if (pg == 0 && e < F * F) {
         const double g2 = ((gred[0][el] + gred[1][el]) + gred[2][el]) + gred[3][el];
@@ -244,11 +311,11 @@ __global__ __launch_bounds__(256) void k_finish(int F, const double* __restrict_
   if (tid == 0) out[9] = sred[0];
 }
 
-hipError_t launch_finish(int F, const double* gram_part, const double* resid_part, int nparts,
-                         const double* g0, const double* g1, const double* W3, const void* H3,
-                         int h_f64, int64_t K, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, F, gram_part, resid_part, nparts, g0, g1,
-                     W3, H3, h_f64, K, out);
+hipError_t launch_finish(int F, const double* gram_part, int gram_nparts, const double* resid_part,
+                         int nparts, const double* g0, const double* g1, const double* W3,
+                         const void* H3, int h_f64, int64_t K, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, F, gram_part, gram_nparts, resid_part, nparts,
+                     g0, g1, W3, H3, h_f64, K, out);
   return hipGetLastError();
 }
 
@@ -269,47 +336,82 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
 // Partial p covers rows [p*rpp, (p+1)*rpp) and sums them in row order, the
 // same partition and order the inner sweep uses for its fused Gram partials
 // when rpp equals its rows per block, so both give bitwise identical Grams.
+// One partial: rows [r0, r1) of H into part[0 .. F*F), each entry summed in
+// row order (256 threads; hs holds 64*64 doubles of LDS).  Thread (ti,tj)
+// owns entries (ti+16a, tj+16b): per row eight LDS reads feed sixteen
+// independent products.
 template <typename HT>
-__global__ __launch_bounds__(256) void k_gram_part(const HT* __restrict__ H, int64_t rows, int F,
-                                                   int64_t rpp, int gram_f32,
-                                                   double* __restrict__ part) {
-  __shared__ double hs[64 * 64];
-  const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * rpp, r1 = min(rows, r0 + rpp);
-  double acc[16];
-  float accf[16];
+__device__ void gram_rows(const HT* __restrict__ H, int64_t r0, int64_t r1, int F, int gram_f32,
+                          double* __restrict__ part, double* hs) {
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  double acc[4][4];
+  float accf[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    acc[q] = 0.0;
-    accf[q] = 0.f;
-  }
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc[p][q] = 0.0;
+      accf[p][q] = 0.f;
+    }
   for (int64_t rb = r0; rb < r1; rb += 64) {
     const int nr = (int)min((int64_t)64, r1 - rb);
     __syncthreads();
     for (int e = tid; e < nr * F; e += 256) hs[e] = (double)H[rb * F + e];
     __syncthreads();
+    // (columns past F read other rows' values into entries that are never
+    // stored; every index stays inside the 64 x 64 buffer)
+    if (gram_f32) {
+      for (int t = 0; t < nr; ++t) {
+        float vi[4], vj[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + 256 * q;
-      if (e < F * F) {
-        const int r = e / F, c = e - r * F;
-        if (gram_f32) {
-          float sf = accf[q];
-          for (int t = 0; t < nr; ++t) sf += (float)hs[t * F + r] * (float)hs[t * F + c];
-          accf[q] = sf;
-        } else {
-          double sd = acc[q];
-          for (int t = 0; t < nr; ++t) sd += hs[t * F + r] * hs[t * F + c];
-          acc[q] = sd;
+        for (int p = 0; p < 4; ++p) {
+          vi[p] = (float)hs[t * F + ti + 16 * p];
+          vj[p] = (float)hs[t * F + tj + 16 * p];
         }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) accf[p][q] += vi[p] * vj[q];
+      }
+    } else {
+      for (int t = 0; t < nr; ++t) {
+        double vi[4], vj[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          vi[p] = hs[t * F + ti + 16 * p];
+          vj[p] = hs[t * F + tj + 16 * p];
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[p][q] += vi[p] * vj[q];
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = tid + 256 * q;
-    if (e < F * F) part[(int64_t)blockIdx.x * F * F + e] = gram_f32 ? (double)accf[q] : acc[q];
-  }
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = ti + 16 * p, c = tj + 16 * q;
+      if (r < F && c < F) part[r * F + c] = gram_f32 ? (double)accf[p][q] : acc[p][q];
+    }
+}
+
+template <typename HT>
+__global__ __launch_bounds__(256) void k_gram_part(const HT* __restrict__ H, int64_t rows, int F,
+                                                   int64_t rpp, int gram_f32,
+                                                   double* __restrict__ part) {
+  __shared__ double hs[64 * 64];
+  const int64_t r0 = (int64_t)blockIdx.x * rpp, r1 = min(rows, r0 + rpp);
+  gram_rows<HT>(H, r0, r1, F, gram_f32, part + (int64_t)blockIdx.x * F * F, hs);
+}
+
+void gram_split(int64_t rows, int64_t* rpp, int* nb) {
+  // at most 16 partials of whole 64-row chunks
+  const int64_t chunks = (rows + 63) / 64;
+  const int64_t per = (chunks + 15) / 16;
+  *rpp = per * 64;
+  *nb = (int)((rows + *rpp - 1) / *rpp);
 }
 
 hipError_t launch_gram_part(const void* H, int h_f64, int64_t rows, int F, int64_t rpp,

@@ -273,8 +273,9 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
       if (tid == 6 || tid == 7) a.resid_part[bid * 8 + tid] = 0.0;
     }
   }
-  // Gram partial of this block's rows (of the stored factor values), rows in order
-  {
+  // Gram partial of this block's rows (of the stored factor values), rows in
+  // order (skipped when the caller forms the Gram from the factor itself)
+  if (a.gram_part) {
     double* hs = xb;  // [RPB][BS]; the barrier after the sweep ends every read of xb
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
@@ -360,6 +361,12 @@ struct PrepK {
   int64_t K;
   const double* gram_c;
   double* fit_out;
+  // direct Gram of the mode just updated (instead of gram_part): blocks
+  // 0 .. gram_nb-1 each sum gram_rpp rows of gram_h into gram_scratch[b]
+  const void* gram_h;
+  int64_t gram_rows, gram_rpp;
+  int gram_nb;
+  double* gram_scratch;
 };
 
 // LDS of prep_body: G [64][65], row/column broadcast buffers, a reduction

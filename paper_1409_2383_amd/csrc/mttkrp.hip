@@ -400,7 +400,8 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
                                                      const float* __restrict__ Hb,
                                                      const float* __restrict__ Hc,
                                                      float* __restrict__ Tout,
-                                                     float* __restrict__ P1, int nch, int KC) {
+                                                     float* __restrict__ P1, int nch, int spg,
+                                                     int G) {
   constexpr int FP = FT * 16;
   constexpr int R = 16 * MT;
   // (four waves per SIMD at FT <= 2, two at FT > 2: the same 128 KB of
@@ -429,10 +430,7 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
   const int nwb = blockDim.x >> 6;
   const int W = gridDim.x * nwb;
   const int gw = blockIdx.x * nwb + wave;
-  // G slab groups per tile (at least one), spg slabs per group
-  const int G0 = max(1, W / nch);
-  const int spg = (I + G0 - 1) / G0;
-  const int G = (I + spg - 1) / spg;
+  // G slab groups of spg slabs per tile (the host's split)
   const int64_t npairs = (int64_t)nch * G;
   const int nsteps = (Kp + 63) / 64;
   const __bf16* cb = Cs + n * KCS + 8 * g;
@@ -1185,6 +1183,13 @@ static int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
 static const size_t kLdsBudget = 158 * 1024;
 
+// The BF16 streaming pass 1 applies: H3^T fits LDS whole, and slabs of the
+// copy and of T are addressable by one buffer resource each.
+static bool stream1_ok(const Plan& p) {
+  return p.KC1 >= p.Kp && p.J * p.Kp * 2 < (int64_t)kBufferOOB &&
+         (p.J + 32) * p.F * 4 < (int64_t)kBufferOOB;
+}
+
 bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   if (F < 1 || F > 64) return false;
   p = Plan();
@@ -1240,6 +1245,18 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   if (prec == PREC_BF16) occ = std::min(occ, p.FT <= 2 ? 2 : 1);   // register-bound (kPass1Waves)
   if (occ < 1) occ = 1;
   p.grid1 = (int)std::min<int64_t>(cdiv(p.ntiles1, 8), (int64_t)cus * occ);
+  if (prec == PREC_BF16 && stream1_ok(p)) {
+    // streaming form: (row tile, run of spg1 slabs) pairs, G1 runs per tile,
+    // about one pair per wave of a full grid; the grid is just large enough
+    // for the pairs, so the CUs left over take the prepare step that runs
+    // beside the pass instead of delaying one of its blocks
+    const int64_t W0 = (int64_t)p.grid1 * 8;
+    const int64_t g0 = std::max<int64_t>(1, W0 / p.nch1);
+    p.spg1 = (int)cdiv(p.I, g0);
+    p.G1 = (int)cdiv(p.I, p.spg1);
+    const int64_t pairs = (int64_t)p.nch1 * p.G1;
+    p.grid1 = (int)std::max<int64_t>(1, std::min<int64_t>(p.grid1, cdiv(pairs, 8)));
+  }
   // mode 2 from T
   p.ich2 = 16;
   p.nich2 = (int)cdiv(p.I, p.ich2);
@@ -1345,8 +1362,7 @@ static hipError_t pass1_mt(const Plan& p, const void* X, const void* Hb, const v
 template <int FT>
 static hipError_t pass1_bf16(const Plan& p, const __bf16* Xr, const float* scale, const void* Hb,
                              const void* Hc, void* Tout, void* P1, hipStream_t s) {
-  // (slabs of the copy and of T addressable by one resource each)
-  if (p.KC1 >= p.Kp && p.J * p.Kp * 2 < (int64_t)kBufferOOB && (p.J + 32) * p.F * 4 < (int64_t)kBufferOOB) {
+  if (stream1_ok(p)) {
     auto kern = k_pass1_bf16s<FT, 2, false>;
     if constexpr (FT != 2) {
       if (p.ts1) kern = k_pass1_bf16s<FT, 2, true>;
@@ -1356,7 +1372,7 @@ static hipError_t pass1_bf16(const Plan& p, const __bf16* Xr, const float* scale
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(p.grid1), dim3(512), p.lds1, s, Xr, scale, (int)p.I, (int)p.J,
                        (int)p.K, (int)p.Kp, p.F, (const float*)Hb, (const float*)Hc, (float*)Tout,
-                       (float*)P1, p.nch1, p.KC1);
+                       (float*)P1, p.nch1, p.spg1, p.G1);
     return hipGetLastError();
   }
   auto kern = k_pass1_bf16<FT, 2>;

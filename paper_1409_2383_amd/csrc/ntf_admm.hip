@@ -140,7 +140,9 @@ Layout make_layout(const Plan& p, const ntf_opts& o, int64_t nnz = -1) {
     L.ginv[m] = c.take((size_t)(F * F + F + 1) * 8);   // Ginv, Ginv 1, 1^T Ginv 1
     if (p.nblk_inner[m] > maxblk) maxblk = p.nblk_inner[m];
   }
-  L.gpart = c.take((size_t)maxblk * F * F * 8);
+  // Gram partials: the direct Gram of the prepare step (at most 16), the
+  // standalone Gram partials of the statistics, and the inner sweep's own
+  L.gpart = c.take((size_t)std::max<int64_t>(maxblk, 16) * F * F * 8);
   L.rpart = c.take((size_t)maxblk * 8 * 8);
   L.sumsq = c.take((size_t)kSumsqParts * 8);
   // whole-factor projection (cardinality constraint): V, Ht^T and the factor
@@ -342,19 +344,26 @@ size_t ntf_admm_sparse_workspace_bytes(const ntf_sparse_problem* prob, const ntf
 
 }  // extern "C"
 
-// Grams of the three current factors, with mode 3's partials left in place for
-// the first prepare step, exactly as the inner kernel would have left them.
-static ntf_status compute_grams(ntf_admm_ctx* c) {
+// Gram of one factor (as fed to the updates) by the partition and order of
+// the prepare step's direct Gram: FP64 partials of whole 64-row chunks,
+// reduced in 4 fixed groups, so both give bitwise identical Grams.
+static hipError_t direct_gram(ntf_admm_ctx* c, int m, double* out, hipStream_t s) {
   const Plan& p = c->plan;
   const int64_t d[3] = {p.I, p.J, p.K};
-  const int gf32 = (p.prec == PREC_BF16) ? 1 : 0;
+  int64_t rpp;
+  int nb;
+  gram_split(d[m], &rpp, &nb);
   double* gpart = c->at<double>(c->lay.gpart);
-  for (int m = 0; m < 3; ++m) {
-    NTF_HIP(c, launch_gram_part(c->feed(m), c->hf64(), d[m], p.F, p.rpb, gf32, gpart, c->s0));
-    NTF_HIP(c, launch_reduce_partials(gpart, 1, (int64_t)p.F * p.F, p.F, p.nblk_inner[m], p.F, p.F,
-                                      c->at<double>(c->lay.gram[m]), c->s0, 4));
-  }
-  // leave mode 3's partials (the buffer already holds them) and zero residual partials
+  hipError_t e = launch_gram_part(c->feed(m), c->hf64(), d[m], p.F, rpp, 0, gpart, s);
+  if (e != hipSuccess) return e;
+  return launch_reduce_partials(gpart, 1, (int64_t)p.F * p.F, p.F, nb, p.F, p.F, out, s, 4);
+}
+
+// Grams of the three current factors, and zero residual partials for the
+// first prepare step.
+static ntf_status compute_grams(ntf_admm_ctx* c) {
+  const Plan& p = c->plan;
+  for (int m = 0; m < 3; ++m) NTF_HIP(c, direct_gram(c, m, c->at<double>(c->lay.gram[m]), c->s0));
   NTF_HIP(c, launch_fill(c->at<double>(c->lay.rpart), (int64_t)p.nblk_inner[2] * 8, 0.0, c->s0));
   return NTF_OK;
 }
@@ -367,8 +376,14 @@ static void prep_args(ntf_admm_ctx* c, int m, PrepArgs& a) {
   DevState* ds = c->dstate();
   a = PrepArgs();
   a.F = p.F;
-  a.gram_part = c->at<double>(c->lay.gpart);
-  a.nparts = p.nblk_inner[src];
+  // the Gram of the mode updated last, directly from that factor
+  const int64_t d[3] = {p.I, p.J, p.K};
+  a.gram_h = c->feed(src);
+  a.h_f64 = c->hf64();
+  a.gram_rows = d[src];
+  gram_split(d[src], &a.gram_rpp, &a.gram_nb);
+  a.gram_scratch = c->at<double>(c->lay.gpart);
+  a.nparts = p.nblk_inner[src];   // its residual partials
   a.gram_dst = c->at<double>(c->lay.gram[src]);
   a.resid_part = c->at<double>(c->lay.rpart);
   a.resid_dst = ds->resid[src];
@@ -422,7 +437,7 @@ static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
   a.eps_rel = c->opts.inner_eps_rel;
   a.gram_from_primal = (c->opts.factor_source == 1) ? 1 : 0;
   a.gram_f32 = (p.prec == PREC_BF16) ? 1 : 0;
-  a.gram_part = c->at<double>(c->lay.gpart);
+  a.gram_part = nullptr;   // the prepare step forms the Gram from the factor itself
   a.resid_part = c->at<double>(c->lay.rpart);
   a.flag = &ds->flag;
 }
@@ -456,7 +471,6 @@ static ntf_status enqueue_inner(ntf_admm_ctx* c, int m, hipStream_t ms) {
     NTF_HIP(c, launch_card_project(V, Xt, H0, ia.H, ia.U, ia.Pout, ia.h_f64, n, c->cons.card[m],
                                    (double)T * (double)d[m], ia.resid_part, p.nblk_inner[m], ms));
   }
-  NTF_HIP(c, launch_gram_part(c->feed(m), c->hf64(), d[m], p.F, p.rpb, ia.gram_f32, ia.gram_part, ms));
   return NTF_OK;
 }
 
@@ -616,13 +630,25 @@ static ntf_status launch_outer(ntf_admm_ctx* c) {
   return NTF_OK;
 }
 
+// Residual totals of the last mode and the fit terms, into out[0..9]: the
+// Gram of mode 3 is formed from the factor (partials in the Gram scratch).
+static hipError_t finish_stats(ntf_admm_ctx* c, double* out) {
+  const Plan& p = c->plan;
+  int64_t rpp;
+  int nb;
+  gram_split(p.K, &rpp, &nb);
+  double* gpart = c->at<double>(c->lay.gpart);
+  hipError_t e = launch_gram_part(c->feed(2), c->hf64(), p.K, p.F, rpp, 0, gpart, c->s0);
+  if (e != hipSuccess) return e;
+  return launch_finish(p.F, gpart, nb, c->at<double>(c->lay.rpart), p.nblk_inner[2],
+                       c->at<double>(c->lay.gram[0]), c->at<double>(c->lay.gram[1]),
+                       c->at<double>(c->lay.W[2]), c->prob.H[2], c->hf64(), p.K, out, c->s0);
+}
+
 static ntf_status fill_stats(ntf_admm_ctx* c, ntf_stats* st) {
   const Plan& p = c->plan;
   DevState* ds = c->dstate();
-  NTF_HIP(c, launch_finish(p.F, c->at<double>(c->lay.gpart), c->at<double>(c->lay.rpart),
-                           p.nblk_inner[2], c->at<double>(c->lay.gram[0]),
-                           c->at<double>(c->lay.gram[1]), c->at<double>(c->lay.W[2]),
-                           c->prob.H[2], c->hf64(), p.K, ds->fin, c->s0));
+  NTF_HIP(c, finish_stats(c, ds->fin));
   NTF_HIP(c, hipMemcpyAsync(c->host_state, ds, sizeof(DevState), hipMemcpyDeviceToHost, c->s0));
   NTF_HIP(c, hipStreamSynchronize(c->s0));
   const DevState& h = *c->host_state;
@@ -922,10 +948,7 @@ ntf_status ntf_admm_get_state(ntf_admm_ctx* c, void* buf, size_t bytes) {
   // The last mode's residuals are still partials; fold their totals into the
   // snapshot (fin[0..7]) so it is self-contained (the penalty rule reads them).
   const Plan& p = c->plan;
-  NTF_HIP(c, launch_finish(p.F, c->at<double>(c->lay.gpart), c->at<double>(c->lay.rpart),
-                           p.nblk_inner[2], c->at<double>(c->lay.gram[0]),
-                           c->at<double>(c->lay.gram[1]), c->at<double>(c->lay.W[2]),
-                           c->prob.H[2], c->hf64(), p.K, c->dstate()->fin, c->s0));
+  NTF_HIP(c, finish_stats(c, c->dstate()->fin));
   NTF_HIP(c, hipStreamSynchronize(c->s0));
   NTF_HIP(c, hipMemcpy(o, c->dstate(), sizeof(DevState), hipMemcpyDeviceToHost));
   std::memcpy(o + sizeof(DevState), &c->outer, sizeof(int64_t));

@@ -27,7 +27,8 @@ struct Plan {
   int MT1 = 1, R1 = 16, nch1 = 0, KC1 = 0, grid1 = 0;  // 16*MT1 rows per wave item
   int64_t ntiles1 = 0;
   size_t lds1 = 0;
-  bool ts1 = false;               // BF16 streaming pass 1: T rows staged in LDS, 16-byte stores
+  bool ts1 = false;
+  int spg1 = 0, G1 = 0;           // BF16 streaming pass 1: slabs per run, runs per row tile               // BF16 streaming pass 1: T rows staged in LDS, 16-byte stores
   // mode 2 from T
   int ich2 = 16, nich2 = 0;
   // pass 3 (mode-3 MTTKRP): waves per block, k-groups, row chunks
@@ -130,6 +131,13 @@ struct PrepArgs {
   int64_t K = 0;
   const double* gram_c = nullptr;     // third Gram for sum(G1*G2*G3)
   double* fit_out = nullptr;          // [2]
+  // direct Gram of the mode just updated (used instead of gram_part when set):
+  // gram_nb blocks each sum gram_rpp rows of gram_h (h_f64 dtype) in FP64
+  // into gram_scratch[b], and the last block reduces them (4 fixed groups)
+  const void* gram_h = nullptr;
+  int64_t gram_rows = 0, gram_rpp = 0;
+  int gram_nb = 0;
+  double* gram_scratch = nullptr;
 };
 hipError_t launch_prep(const PrepArgs& a, int nblk, hipStream_t s);
 
@@ -140,9 +148,12 @@ hipError_t launch_fit(const Plan& p, const void* X, int x_f64, const void* H1, c
                       const void* H3, int h_f64, double* part, double* out, hipStream_t s,
                       int* nparts_out);
 int fit_parts(const Plan& p);
-hipError_t launch_finish(int F, const double* gram_part, const double* resid_part, int nparts,
-                         const double* g0, const double* g1, const double* W3, const void* H3,
-                         int h_f64, int64_t K, double* out, hipStream_t s);
+hipError_t launch_finish(int F, const double* gram_part, int gram_nparts, const double* resid_part,
+                         int nparts, const double* g0, const double* g1, const double* W3,
+                         const void* H3, int h_f64, int64_t K, double* out, hipStream_t s);
+// Gram of a factor by rows: the partition (rows per partial, partials) the
+// prepare step's direct Gram uses for `rows` rows
+void gram_split(int64_t rows, int64_t* rpp, int* nb);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 
 // Cardinality constraint (card.hip): from V, Ht^T and the factor before the

@@ -467,7 +467,7 @@ ntf_status fill_stats(ntf_nway_ctx* c, ntf_nway_stats* st) {
   const int N = su.N;
   NwState* ds = c->dstate();
   // the last mode's residual partials are still unreduced: total them apart
-  NW_HIP(c, launch_finish(su.F, c->at<double>(c->lay.gpart), c->at<double>(c->lay.rpart), su.nblk[N - 1],
+  NW_HIP(c, launch_finish(su.F, c->at<double>(c->lay.gpart), su.nblk[N - 1], c->at<double>(c->lay.rpart), su.nblk[N - 1],
                           c->at<double>(c->lay.gram[0]), c->at<double>(c->lay.gram[1]), c->at<double>(c->lay.W),
                           c->prob.H[N - 1], c->hf64(), su.d[N - 1], ds->fin, c->s0));
   NW_HIP(c, hipMemcpyAsync(c->host_state, ds, sizeof(NwState), hipMemcpyDeviceToHost, c->s0));
