@@ -59,7 +59,7 @@ typedef enum {
                                MTTKRP on BF16 MFMA with FP32 accumulation against
                                bfloat16(H_3) (modes 1, 2) or bfloat16(H_2) (mode 3, each
                                slab's result scaled by the slab's row of H_1 in FP32);
-                               Gram FP32; Cholesky and solves FP64; H,U float32 */
+                               Gram, Cholesky and solves FP64; H,U float32 */
   NTF_PREC_F64 = 3          /* X float64; everything FP64 (MFMA f64); H,U float64 */
 } ntf_precision;
 
