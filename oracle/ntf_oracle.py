@@ -237,7 +237,8 @@ class Opts:
     rescale_dual_on_rho_change: bool = False   # keep Y = -rho U fixed when rho changes
     # operand rounding of the MTTKRP (the mixed-precision recipe; not in the
     # paper): "exact", or bfloat16 operands as in mttkrp_mixed with mode 3 in
-    # Khatri-Rao ("bf16_kr") or factored ("bf16_factored") form
+    # Khatri-Rao ("bf16_kr"), factored ("bf16_factored") or split factored
+    # ("bf16_split") form
     mttkrp_operands: str = "exact"
     # per-mode set constraints (None: non-negativity on every factor)
     constraints: Optional[tuple] = None
@@ -416,7 +417,8 @@ def mode_update(X: np.ndarray, st: State, n: int, opts: Opts) -> dict:
     elif opts.mttkrp_operands == "exact":
         W = mttkrp(X, factors, n)
     else:
-        W = mttkrp_mixed(X, factors, n, mode3="factored" if opts.mttkrp_operands == "bf16_factored" else "kr")
+        m3 = {"bf16_factored": "factored", "bf16_split": "split"}.get(opts.mttkrp_operands, "kr")
+        W = mttkrp_mixed(X, factors, n, mode3=m3)
     G = gram_hadamard(factors, n)
     if opts.rho_policy == RHO_TRACE:
         rho = rho_trace(G, opts.rho0)
@@ -639,6 +641,16 @@ def quantize_slabs_bf16(X: np.ndarray, s: Optional[np.ndarray] = None):
     return Xq, s
 
 
+def _mode3_b(B: np.ndarray, mode3: str) -> np.ndarray:
+    """The B operand of the factored mode-3 forms (float32 B in): bf16(B),
+    or bf16(B) + bf16(fl32(B - bf16(B))) for the split form."""
+    hi = _round_bf16(B)
+    if mode3 == "factored":
+        return hi.astype(np.float64)
+    lo = _round_bf16((B - hi.astype(np.float32)).astype(np.float32))
+    return hi.astype(np.float64) + lo.astype(np.float64)
+
+
 def mttkrp_mixed(X: np.ndarray, factors: Sequence[np.ndarray], n: int, mode3: str = "kr") -> np.ndarray:
     """MTTKRP with the operand rounding of the mixed-precision recipe (the
     method itself is unchanged): X is replaced by its per-slab bfloat16 copy
@@ -646,10 +658,13 @@ def mttkrp_mixed(X: np.ndarray, factors: Sequence[np.ndarray], n: int, mode3: st
     factor in float32.  Mode 3, mode3="kr": against Khatri-Rao rows formed in
     float32 as (s_i * A[i,:]) * B[j,:] and rounded to bfloat16; mode3=
     "factored": against bfloat16(B) with A in float32 applied per slab
-    (W3[k,:] = sum_i s_i A[i,:] * sum_j Xq[i,j,k] bf16(B[j,:])).  Accumulation
-    is exact up to float64 rounding."""
-    if mode3 not in ("kr", "factored"):
-        raise ValueError("mode3 must be 'kr' or 'factored'")
+    (W3[k,:] = sum_i s_i A[i,:] * sum_j Xq[i,j,k] bf16(B[j,:])); mode3=
+    "split": as "factored" with B carried as two bfloat16 terms, hi =
+    bf16(B) and lo = bf16(fl32(B - hi)) (then a rounding of B shared by all
+    slabs no longer biases every slab the same way).  Accumulation is exact
+    up to float64 rounding."""
+    if mode3 not in ("kr", "factored", "split"):
+        raise ValueError("mode3 must be 'kr', 'factored' or 'split'")
     Xq, s = quantize_slabs_bf16(X)
     A, B, C = (np.asarray(f, dtype=np.float32) for f in factors)
     Xs = Xq * s[:, None, None]
@@ -659,9 +674,8 @@ def mttkrp_mixed(X: np.ndarray, factors: Sequence[np.ndarray], n: int, mode3: st
     if n == 1:
         Cb = _round_bf16(C).astype(np.float64)
         return mttkrp(Xs, [A.astype(np.float64), B.astype(np.float64), Cb], 1)
-    if mode3 == "factored":
-        Bb = _round_bf16(B).astype(np.float64)
-        return mttkrp(Xs, [A.astype(np.float64), Bb, C.astype(np.float64)], 2)
+    if mode3 in ("factored", "split"):
+        return mttkrp(Xs, [A.astype(np.float64), _mode3_b(B, mode3), C.astype(np.float64)], 2)
     # mode 3: KR[(i,j), f] = bf16(fl32(fl32(s_i A[i,f]) B[j,f]))
     I, J = A.shape[0], B.shape[0]
     sA = (s.astype(np.float32)[:, None] * A).astype(np.float32)
@@ -715,9 +729,8 @@ def mttkrp_mixed_from(Xq: np.ndarray, s: np.ndarray, factors: Sequence[np.ndarra
     if n in (0, 1):
         Cb = _round_bf16(C).astype(np.float64)
         return mttkrp(Xs, [A.astype(np.float64), B.astype(np.float64), Cb], n)
-    if mode3 == "factored":
-        Bb = _round_bf16(B).astype(np.float64)
-        return mttkrp(Xs, [A.astype(np.float64), Bb, C.astype(np.float64)], 2)
+    if mode3 in ("factored", "split"):
+        return mttkrp(Xs, [A.astype(np.float64), _mode3_b(B, mode3), C.astype(np.float64)], 2)
     I, J = A.shape[0], B.shape[0]
     sA = (s.astype(np.float32)[:, None] * A).astype(np.float32)
     KR = (sA[:, None, :] * B[None, :, :]).astype(np.float32)

@@ -350,11 +350,12 @@ def test_mixed_mttkrp_reduces_to_exact_on_bfloat16_values():
     fac = [A, B, C]
     X64 = X.astype(np.float64)
     for n in (0, 1):
-        for m3 in ("kr", "factored"):
+        for m3 in ("kr", "factored", "split"):
             np.testing.assert_allclose(orc.mttkrp_mixed(X, fac, n, mode3=m3), orc.mttkrp(X64, fac, n),
                                        rtol=1e-14, atol=0)
-    np.testing.assert_allclose(orc.mttkrp_mixed(X, fac, 2, mode3="factored"), orc.mttkrp(X64, fac, 2),
-                               rtol=1e-14, atol=0)
+    for m3 in ("factored", "split"):   # (lo is zero when B is a bfloat16 value)
+        np.testing.assert_allclose(orc.mttkrp_mixed(X, fac, 2, mode3=m3), orc.mttkrp(X64, fac, 2),
+                                   rtol=1e-14, atol=0)
     # the Khatri-Rao form rounds the products A[i,f] B[j,f]: not exact here
     kr = orc.mttkrp_mixed(X, fac, 2, mode3="kr")
     assert np.max(np.abs(kr - orc.mttkrp(X64, fac, 2))) > 1e-6 * np.max(np.abs(kr))
@@ -380,6 +381,47 @@ def test_mixed_mttkrp_factored_brute_force():
     np.testing.assert_allclose(orc.mttkrp_mixed(X, [A, B, C], 2, mode3="factored"), W, rtol=1e-12)
 
 
+def test_mixed_mttkrp_split_brute_force():
+    # the split factored mode-3 rounding written out element by element: B as
+    # a bfloat16 pair (hi, lo) whose sum differs from B by at most 2^-16 |B|
+    rng = np.random.default_rng(123)
+    I, J, K, F = 3, 4, 5, 2
+    X = (rng.random((I, J, K)) * 3.0).astype(np.float32)
+    A, B, C = (rng.random((d, F)) for d in (I, J, K))
+    Xq, s = orc.quantize_slabs_bf16(X)
+    B32 = B.astype(np.float32)
+    W = np.zeros((K, F))
+    for k in range(K):
+        for f in range(F):
+            tot = 0.0
+            for i in range(I):
+                inner = 0.0
+                for j in range(J):
+                    b = float(B32[j, f])
+                    hi = float(orc._round_bf16(np.float32(b)))
+                    lo = float(orc._round_bf16(np.float32(b - hi)))
+                    assert abs((hi + lo) - b) <= 2.0 ** -16 * abs(b)
+                    inner += float(Xq[i, j, k]) * (hi + lo)
+                tot += float(s[i]) * float(np.float32(A[i, f])) * inner
+            W[k, f] = tot
+    np.testing.assert_allclose(orc.mttkrp_mixed(X, [A, B, C], 2, mode3="split"), W, rtol=1e-12)
+
+
+def test_mixed_mttkrp_split_is_closer_to_exact_than_factored():
+    # the same quantised X: only the rounding of B differs, and the split form
+    # carries B to ~2^-16, so its error against the MTTKRP of the quantised
+    # tensor with float32 factors is far below the factored form's
+    rng = np.random.default_rng(124)
+    I, J, K, F = 20, 30, 25, 4
+    X = (rng.random((I, J, K)) * 2.0).astype(np.float32)
+    fac = [rng.random((d, F)).astype(np.float32) for d in (I, J, K)]
+    Xq, s = orc.quantize_slabs_bf16(X)
+    ref = orc.mttkrp(Xq * s[:, None, None], [f.astype(np.float64) for f in fac], 2)
+    e_f = np.abs(orc.mttkrp_mixed(X, fac, 2, mode3="factored") - ref).max()
+    e_s = np.abs(orc.mttkrp_mixed(X, fac, 2, mode3="split") - ref).max()
+    assert e_s < e_f / 64, (e_s, e_f)
+
+
 def test_row_restricted_mttkrps_equal_the_full_ones():
     # the selected-row forms used by the full-size checks return exactly the
     # rows of the whole-tensor functions
@@ -391,7 +433,7 @@ def test_row_restricted_mttkrps_equal_the_full_ones():
         rows = np.array(sorted(rng.choice(dims[n], 3, replace=False)))
         np.testing.assert_allclose(orc.mttkrp_rows(X, fac, n, rows), orc.mttkrp(X, fac, n)[rows],
                                    rtol=1e-12)
-        for m3 in ("kr", "factored"):
+        for m3 in ("kr", "factored", "split"):
             np.testing.assert_allclose(orc.mttkrp_mixed_rows(X, fac, n, rows, m3),
                                        orc.mttkrp_mixed(X, fac, n, m3)[rows], rtol=1e-12, atol=1e-12)
     X4 = rng.standard_normal((4, 5, 3, 6))
