@@ -985,11 +985,14 @@ __global__ __launch_bounds__(512, 2) void k_pass3s(const T* __restrict__ X, int6
 
 // ---------------------------------------------------------------- pass 3, BF16
 
-// Mode-3 MTTKRP in factored form: W3[k,:] = sum_i s_i A[i,:] *
-// (sum_j Xq[i,j,k] bf16(B[j,:])).  The inner sum is an MFMA contraction over
-// j whose B operand does not depend on the slab, so a block stages
-// bf16(H2)^T for one chunk of 8-row groups of j in LDS once ([FP][JCS], zero
-// past J and past the chunk).  X comes from the j-interleaved copy
+// Mode-3 MTTKRP in split factored form: W3[k,:] = sum_i s_i A[i,:] *
+// (sum_j Xq[i,j,k] (hi[j,:] + lo[j,:])), with H2 carried as two bfloat16
+// terms hi = bf16(B), lo = bf16(B - hi) (one rounding of B shared by every
+// slab would bias all slabs alike).  The inner sum is an MFMA contraction
+// over j whose B operands do not depend on the slab, so a block stages hi^T
+// and lo^T for one chunk of 8-row groups of j in LDS once ([FP][JCS] each,
+// zero past J and past the chunk), and every step issues two MFMAs per
+// operand pair.  X comes from the j-interleaved copy
 // Xj8[q][k][e] (q = i*JG + jg, row j = 8jg + e): lane (n,g) of a 32-row step
 // loads the 8 rows of group 4*step + g at row k with one 16-byte read, which
 // is exactly the A operand of v_mfma_f32_16x16x32_bf16.  Each wave owns 64
@@ -1065,11 +1068,14 @@ __global__ __launch_bounds__(512) void k_pass3_bf16s(const __bf16* __restrict__ 
 #pragma unroll
     for (int u = 0; u < U; ++u) load_next(xv[u], ar[u]);
   }
+  __bf16* Bl = Bs + FP * JCS;   // the lo tile after the hi tile
   for (int idx = threadIdx.x; idx < JL * FP; idx += blockDim.x) {
     const int jj = idx / FP, f = idx - jj * FP;
     const int j = jg0 * 8 + jj;
     const float v = (jj < 8 * ng && j < J && f < F) ? Hb[(int64_t)j * F + f] : 0.f;
-    Bs[f * JCS + jj] = (__bf16)v;
+    const __bf16 hi = (__bf16)v;
+    Bs[f * JCS + jj] = hi;
+    Bl[f * JCS + jj] = (__bf16)(v - (float)hi);   // (the difference is exact in FP32)
   }
   __syncthreads();
   if (total == 0) return;
@@ -1087,9 +1093,12 @@ __global__ __launch_bounds__(512) void k_pass3_bf16s(const __bf16* __restrict__ 
   auto step = [&](int u, bool reload) {
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) {
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(bb + ft * 16 * JCS + c_st * 32);
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(bb + ft * 16 * JCS + c_st * 32);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(bb + FP * JCS + ft * 16 * JCS + c_st * 32);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][mt], bv, acc[mt][ft]);
+      for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][mt], bh, acc[mt][ft]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][mt], bl, acc[mt][ft]);
     }
     // (the coefficients are read out of ar[u] before its reload, so the
     // reload can write the same registers: no copy, no wait, at the loop end)
@@ -1267,9 +1276,10 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   const int ktiles = (int)cdiv(kspan, 64);
   if (prec == PREC_BF16) {
     // one block of 8 waves per CU; a wave owns 64 rows of k and a run of
-    // slabs of one chunk of j, the chunk's bf16(H2)^T staged in LDS
+    // slabs of one chunk of j, the chunk's bf16 hi and lo tiles of H2^T in LDS
     p.nkt3 = ktiles;
-    auto lds_of = [&](int64_t q) { return (size_t)p.FP * (32 * cdiv(q, 4) + 8) * 2; };
+    // (two bfloat16 tiles, hi and lo of H2^T)
+    auto lds_of = [&](int64_t q) { return (size_t)2 * p.FP * (32 * cdiv(q, 4) + 8) * 2; };
     int64_t jcg = p.JG;
     // (a chunk's byte offsets, three groups past its end included, stay
     // below 2^31, so an offset plus kBufferOOB does not wrap)

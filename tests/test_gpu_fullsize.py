@@ -53,7 +53,7 @@ def test_c3_mttkrp_sampled_rows(dev, c3, arm):
         rows = _rows(X.shape[n], rng)
         W = s.mttkrp(n).cpu().numpy()[rows]
         if arm == "mixed":
-            ref = orc.mttkrp_mixed_rows(X, fac, n, rows, mode3="factored")
+            ref = orc.mttkrp_mixed_rows(X, fac, n, rows, mode3="split")
         else:
             ref = orc.mttkrp_rows(X, fac, n, rows)
         tol = 1e-6

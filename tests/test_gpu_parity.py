@@ -7,7 +7,7 @@ Tolerances (relative Frobenius norm unless stated):
     accumulation (chains of at most a few hundred terms before an FP64
     reduction) and the final float32 rounding of H and U.
   BF16 mixed mode: MTTKRP against the oracle's mixed-operand MTTKRP (same
-    bfloat16 operands, mode 3 in factored form, exact accumulation) at 1e-5;
+    bfloat16 operands, mode 3 in split factored form, exact accumulation) at 1e-5;
     against the exact MTTKRP at 2e-2.
 """
 import numpy as np
@@ -77,7 +77,7 @@ def test_mttkrp_bf16(dev, dims, F):
     s, X, H = _solver(pt, H0, dev, ntf.AdmmOptions(precision=ntf.PREC_BF16_MIXED))
     for n in range(3):
         W = s.mttkrp(n).cpu().numpy()
-        assert rel(W, orc.mttkrp_mixed(pt.X, H0, n, mode3="factored")) < 1e-5, n
+        assert rel(W, orc.mttkrp_mixed(pt.X, H0, n, mode3="split")) < 1e-5, n
         assert rel(W, orc.mttkrp(pt.X, H0, n)) < 2e-2, n
     s.close()
 
