@@ -39,6 +39,9 @@ namespace ntf {
 
 static __host__ __device__ __forceinline__ int rup_i(int x, int a) { return (x + a - 1) / a * a; }
 
+// Columns of j per chunk of the pass-3 item's H2 tiles (a multiple of 64).
+constexpr int kP3ChunkCols = 256;
+
 // Problem descriptors are read-only for a whole launch: the kernel reads them
 // through the constant address space (scalar loads into scalar registers),
 // by reference, never as a local copy (a copy indexed at run time would live
@@ -50,8 +53,9 @@ size_t batch_lds_p1(const BProb& p) {
   return (size_t)FP * KCS * 2 + (size_t)4 * p.spi1 * FP * 4;
 }
 size_t batch_lds_p3(const BProb& p) {
-  const int FP = p.FT * 16, JCS = rup_i(p.Jp, 64) + 8;
-  return (size_t)FP * JCS * 2;
+  // hi and lo tiles of a chunk of at most kP3Chunk columns of j
+  const int FP = p.FT * 16, JCS = std::min(rup_i(p.Jp, 64), kP3ChunkCols) + 8;
+  return (size_t)2 * FP * JCS * 2;
 }
 // The batched kernel runs the inner sweep with one row per lane group
 // (256 / FL rows per block), which keeps its register budget within two
@@ -248,11 +252,16 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
 
 // ---------------------------------------------------------------- pass 3 item
 
-// Slabs s0 .. s0+ns-1 of one problem, from the j-fastest copy.  H2^T (BF16)
-// sits in LDS.  Each wave owns 16*MT-row groups of k (rg = wave, wave+4, ..)
-// and, for each, streams the slabs of the item: the FP32 result of a slab is
-// scaled by s_i * H1[i,:] and added to the group's total, which is written
-// to this item's partial of W3 at the end.
+// Slabs s0 .. s0+ns-1 of one problem, from the j-fastest copy.  H2^T sits in
+// LDS as two bfloat16 tiles, hi = bf16(B) and lo = bf16(B - hi) (one rounding
+// of B shared by every slab would bias all slabs alike), for a chunk of
+// kP3Chunk columns of j at a time.  Per chunk, each wave owns 16*MT-row groups
+// of k (rg = wave, wave+4, ..) and, for each, streams the slabs of the item:
+// the FP32 result of a slab is scaled by s_i * H1[i,:] and added to the
+// group's total, which the first chunk stores into this item's partial of W3
+// and every later chunk adds to it (same block, in chunk order).
+constexpr int kP3Chunk = kP3ChunkCols;
+
 template <int FT, int MT>
 __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned char* lds, const int tid) {
   constexpr int FP = FT * 16;
@@ -260,85 +269,100 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
   constexpr int U = 4;
   const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
   const int J = P.J, K = P.K, F = P.F, Jp = P.Jp;
-  const int JC = rup_i(Jp, 64), JCS = JC + 8;
-  __bf16* Bs = reinterpret_cast<__bf16*>(lds);
+  const int JC = rup_i(Jp, 64);
+  const int JCH = min(JC, kP3Chunk), JCS = JCH + 8;
+  __bf16* Bs = reinterpret_cast<__bf16*>(lds);   // hi tile [FP][JCS], then the lo tile
+  __bf16* Bl = Bs + FP * JCS;
   const float* __restrict__ Ha = P.H[0];
   const float* __restrict__ Hb = P.H[1];
   const int s0 = idx * P.spi3;
   const int ns = min(P.I, s0 + P.spi3) - s0;
   const int nrg = (K + R - 1) / R;
   const int myrg = nrg > wave ? (nrg - wave + 3) / 4 : 0;
-  const int nsteps = JC / 64;
-  const int total = myrg * ns * nsteps;
-
-  // Loads through a buffer resource per slab, as in pass 1: rows k >= K and
-  // columns j >= Jp read as zeros, and past the wave's last step the cursor
-  // keeps re-reading its last (in-bounds) row group.
-  int l_rgc = 0, l_sl = 0, l_kb = 0;
-  int l_off[MT];
-  auto set_rows = [&]() {
-    const int rg = wave + 4 * l_rgc;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Jp + 8 * g) * 2;
-  };
-  bf16x8 xv[U][2][MT];
-  auto load_next = [&](bf16x8 (&dst)[2][MT]) {
-    const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(P.Xt + (int64_t)(s0 + l_sl) * K * Jp, K * Jp * 2);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int off = (l_kb + 8 * g + 32 * h < Jp) ? l_off[mt] + (l_kb + 32 * h) * 2 : kBufferOOB;
-        dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-      }
-    l_kb += 64;
-    if (l_kb >= Jp) {
-      l_kb = 0;
-      if (++l_sl == ns) {
-        l_sl = 0;
-        if (l_rgc + 1 < myrg) {
-          ++l_rgc;
-          set_rows();
-        }
-      }
-    }
-  };
-  // the first U steps of tensor loads go out before H2^T is staged
-  if (total > 0) {
-    set_rows();
-#pragma unroll
-    for (int u = 0; u < U; ++u) load_next(xv[u]);
-  }
-  for (int e = tid; e < JC * FP; e += 256) {
-    const int jj = e / FP, f = e - jj * FP;
-    const float v = (jj < J && f < F) ? Hb[(int64_t)jj * F + f] : 0.f;
-    Bs[f * JCS + jj] = (__bf16)v;
-  }
-  __syncthreads();
-  if (total == 0) return;   // (wave-uniform; the caller's barrier follows the item)
-
-  f32x4 acc[MT][FT], tot[MT][FT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int ft = 0; ft < FT; ++ft) {
-      acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
-      tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-  int c_step = 0, c_sl = 0, c_rgc = 0;
-  const __bf16* bb = Bs + n * JCS + 8 * g;
+  const int nchunk = (JC + JCH - 1) / JCH;
   const __amdgpu_buffer_rsrc_t ars = uniform_rsrc(Ha, P.I * F * 4);
   const __amdgpu_buffer_rsrc_t wrs = uniform_rsrc(P.W3p + (int64_t)idx * K * F, K * F * 4);
-  auto step = [&](int u, bool reload) {
+
+  for (int chk = 0; chk < nchunk; ++chk) {
+    const int j0 = chk * JCH, jw = min(JCH, JC - j0);
+    const int nsteps = jw / 64;
+    const int total = myrg * ns * nsteps;
+
+    // Loads through a buffer resource per slab, as in pass 1: rows k >= K and
+    // columns j >= Jp read as zeros, and past the wave's last step the cursor
+    // keeps re-reading its last (in-bounds) row group.
+    int l_rgc = 0, l_sl = 0, l_kb = j0;
+    int l_off[MT];
+    auto set_rows = [&]() {
+      const int rg = wave + 4 * l_rgc;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Jp + 8 * g) * 2;
+    };
+    bf16x8 xv[U][2][MT];
+    auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+      const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(P.Xt + (int64_t)(s0 + l_sl) * K * Jp, K * Jp * 2);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int off = (l_kb + 8 * g + 32 * h < Jp) ? l_off[mt] + (l_kb + 32 * h) * 2 : kBufferOOB;
+          dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        }
+      l_kb += 64;
+      if (l_kb >= j0 + jw) {
+        l_kb = j0;
+        if (++l_sl == ns) {
+          l_sl = 0;
+          if (l_rgc + 1 < myrg) {
+            ++l_rgc;
+            set_rows();
+          }
+        }
+      }
+    };
+    // the first U steps of tensor loads go out before the chunk is staged
+    if (total > 0) {
+      set_rows();
+#pragma unroll
+      for (int u = 0; u < U; ++u) load_next(xv[u]);
+    }
+    __syncthreads();   // the previous chunk's MFMAs are done with the tiles
+    for (int e = tid; e < jw * FP; e += 256) {
+      const int jj = e / FP, f = e - jj * FP;
+      const int j = j0 + jj;
+      const float v = (j < J && f < F) ? Hb[(int64_t)j * F + f] : 0.f;
+      const __bf16 hi = (__bf16)v;
+      Bs[f * JCS + jj] = hi;
+      Bl[f * JCS + jj] = (__bf16)(v - (float)hi);   // (the difference is exact in FP32)
+    }
+    __syncthreads();
+    if (total > 0) {   // (wave-uniform; waves without rows still take every barrier)
+      f32x4 acc[MT][FT], tot[MT][FT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) {
+          acc[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+          tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      int c_step = 0, c_sl = 0, c_rgc = 0;
+      const __bf16* bb = Bs + n * JCS + 8 * g;
+      auto step = [&](int u, bool reload) {
 #pragma unroll
         for (int ft = 0; ft < FT; ++ft) {
           const __bf16* bp = bb + ft * 16 * JCS + c_step * 64;
           const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(bp);
           const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(bp + 32);
+          const bf16x8 l0 = *reinterpret_cast<const bf16x8*>(bp + FP * JCS);
+          const bf16x8 l1 = *reinterpret_cast<const bf16x8*>(bp + FP * JCS + 32);
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], b0, acc[mt][ft]);
 #pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][0][mt], l0, acc[mt][ft]);
+#pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], b1, acc[mt][ft]);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], l1, acc[mt][ft]);
         }
         if (reload) load_next(xv[u]);
         if (++c_step == nsteps) {
@@ -360,8 +384,9 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
           }
           c_step = 0;
           if (++c_sl == ns) {
-            // end of a row group: write this item's partial rows (rows past
-            // K and columns past F get offsets past the resource: dropped)
+            // end of a row group: its rows of this item's partial (rows past
+            // K and columns past F get offsets past the resource: dropped);
+            // a later chunk adds to what the earlier ones stored
             const int rg = wave + 4 * c_rgc;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -371,11 +396,13 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
                 for (int ii = 0; ii < 4; ++ii) {
                   const int k = rg * R + mt * 16 + 4 * g + ii;
                   const int f = ft * 16 + n;
+                  const int off = (k < K && f < F) ? (k * F + f) * 4 : kBufferOOB;
                   // (the element is copied out first: a bit cast of a vector
                   // element lvalue reads element 0 with this compiler)
-                  const float t = tot[mt][ft][ii];
-                  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, t), wrs,
-                                                        (k < K && f < F) ? (k * F + f) * 4 : kBufferOOB, 0, 0);
+                  float t = tot[mt][ft][ii];
+                  if (chk > 0)
+                    t = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wrs, off, 0, 0)) + t;
+                  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, t), wrs, off, 0, 0);
                 }
                 tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
               }
@@ -383,15 +410,17 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
             ++c_rgc;
           }
         }
-  };
-  const int full = total - total % U;
-  for (int s = 0; s < full; s += U) {
+      };
+      const int full = total - total % U;
+      for (int s = 0; s < full; s += U) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) step(u, true);
+        for (int u = 0; u < U; ++u) step(u, true);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (full + u < total) step(u, false);
+    }
   }
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-    if (full + u < total) step(u, false);
 }
 
 // ---------------------------------------------------------------- mode-2 item

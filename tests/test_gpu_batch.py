@@ -2,7 +2,7 @@
 persistent kernel per outer iteration) against the oracle, through the C ABI.
 
 Expected values come from the oracle with the batched path's operand rounding
-(mttkrp_mixed, mode 3 in factored form): the same bfloat16 operands, exact
+(mttkrp_mixed, mode 3 in split factored form): the same bfloat16 operands, exact
 accumulation.  Tolerances (relative Frobenius norm):
   MTTKRP, every mode of every problem: 1e-5 (FP32 MFMA accumulation of at
     most a few thousand terms per slab, FP64 across slabs); against the exact
@@ -13,8 +13,13 @@ accumulation.  Tolerances (relative Frobenius norm):
     accumulation pass through T regularised least-squares solves and three
     Gauss-Seidel mode updates, which amplify them by 1e2 - 1e3 on ill-posed
     shapes (e.g. I = 3 < F); the gate scales with that sensitivity.
-  Fit after 15 outer iterations: at most 3x the drift of the float32 recipe
-    reference from the oracle over the same iterations.
+  Fit after 15 outer iterations: at most 3x the larger of the drift of the
+    float32 recipe reference from the oracle over the same iterations and the
+    oracle's own spread when its initial factors are perturbed by one float32
+    rounding (+-2^-24 relative): these short runs on small, unconverged
+    problems amplify such a perturbation to 1e-4 in the fit, so a single
+    float32 replay can land closer to the oracle than another float32
+    summation order does.
 """
 import numpy as np
 import pytest
@@ -62,7 +67,7 @@ def _check_mttkrp(b, pts, H0s, tag):
     for p, (pt, H0) in enumerate(zip(pts, H0s)):
         for n in range(3):
             W = b.mttkrp(p, n).cpu().numpy()
-            ref = orc.mttkrp_mixed(pt.X, H0, n, mode3="factored")
+            ref = orc.mttkrp_mixed(pt.X, H0, n, mode3="split")
             e = rel(W, ref)
             worst = max(worst, e)
             assert e < 1e-5, (tag, p, n, e)
@@ -88,7 +93,7 @@ def _oracle_after(pts, H0s, steps, T):
     out = []
     for pt, H0 in zip(pts, H0s):
         st = orc.init_state([h.astype(np.float64) for h in H0])
-        opts = orc.Opts(inner_iters=T, mttkrp_operands="bf16_factored")
+        opts = orc.Opts(inner_iters=T, mttkrp_operands="bf16_split")
         for _ in range(steps):
             orc.outer_step(pt.X, st, opts)
         out.append(st)
@@ -117,10 +122,11 @@ def _f32_recipe_reference(X, H0, T, steps=1):
         elif n == 1:
             W = np.einsum("ijf,if->jf", Tm.astype(np.float64), A.astype(np.float64))
         else:
-            Bb = orc._round_bf16(B)
+            Bh = orc._round_bf16(B)
+            Bl = orc._round_bf16((B - Bh).astype(np.float32))
             W = np.zeros((K, F))
             for i in range(I):
-                W += (s32[i] * A[i][None, :] * (Xq32[i].T @ Bb)).astype(np.float64)
+                W += (s32[i] * A[i][None, :] * (Xq32[i].T @ Bh + Xq32[i].T @ Bl)).astype(np.float64)
         grams = [(h.astype(np.float32).T @ h.astype(np.float32)).astype(np.float64) for h in st.H]
         G = np.ones((F, F))
         for m in range(3):
@@ -153,10 +159,26 @@ def test_batch_one_step_matches_oracle(dev):
     b.close()
 
 
+def _oracle_fit_spread(X, H0, steps, T):
+    """Fits of the oracle after `steps` outer iterations from the initial
+    factors perturbed by +-2^-24 relative (one float32 rounding)."""
+    out = []
+    for sgn in (1.0, -1.0):
+        rng = np.random.default_rng(0)
+        H = [h.astype(np.float64) * (1.0 + sgn * 2.0 ** -24 * rng.standard_normal(h.shape)) for h in H0]
+        st = orc.init_state(H)
+        opts = orc.Opts(inner_iters=T, mttkrp_operands="bf16_split")
+        for _ in range(steps):
+            orc.outer_step(X, st, opts)
+        out.append(orc.rfe(X, st.H))
+    return out
+
+
 def test_batch_fit_and_invariants_after_run(dev):
-    # Fit after 15 outer iterations: within 3x the distance the float32
-    # recipe reference drifts from the oracle over the same iterations (floor
-    # 1e-6 relative), and complementarity of H and U exact.
+    # Fit after 15 outer iterations: within 3x the larger of the float32
+    # recipe reference's drift and the oracle's spread under a one-rounding
+    # perturbation of the start (floor 1e-6 relative), and complementarity of
+    # H and U exact.
     T, steps = 5, 15
     spec = BATCH[:1] + BATCH[2:6]
     b, pts, H0s, Hs = _batch(dev, spec, T=T, seed0=760)
@@ -167,8 +189,10 @@ def test_batch_fit_and_invariants_after_run(dev):
     for p, st in enumerate(ref):
         r = orc.rfe(pts[p].X, st.H)
         r32 = orc.rfe(pts[p].X, _f32_recipe_reference(pts[p].X, H0s[p], T, steps).H)
-        bound = max(1e-6 * r, 3.0 * abs(r32 - r))
-        print(f"[batch] fit p={p} gpu {fits[p]:.8f} oracle {r:.8f} f32 recipe {r32:.8f}", flush=True)
+        spread = max(abs(x - r) for x in _oracle_fit_spread(pts[p].X, H0s[p], steps, T))
+        bound = max(1e-6 * r, 3.0 * abs(r32 - r), 3.0 * spread)
+        print(f"[batch] fit p={p} gpu {fits[p]:.8f} oracle {r:.8f} f32 recipe {r32:.8f} "
+              f"spread {spread:.2e}", flush=True)
         assert abs(fits[p] - r) < bound, (p, fits[p], r, bound)
         for n in range(3):
             h = Hs[p][n].cpu().numpy()
