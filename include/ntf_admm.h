@@ -57,8 +57,9 @@ typedef enum {
   NTF_PREC_F32 = 0,         /* X float32; MTTKRP on FP32 MFMA; Gram, Cholesky, solves FP64; H,U float32 */
   NTF_PREC_BF16_MIXED = 1,  /* X float32 + bfloat16 copy with a power-of-two scale per mode-1 slab;
                                MTTKRP on BF16 MFMA with FP32 accumulation against
-                               bfloat16(H_3) (modes 1, 2) or bfloat16(H_2) (mode 3, each
-                               slab's result scaled by the slab's row of H_1 in FP32);
+                               bfloat16(H_3) (modes 1, 2) or H_2 as two bfloat16 terms
+                               hi + lo (mode 3, each slab's result scaled by the slab's
+                               row of H_1 in FP32);
                                Gram, Cholesky and solves FP64; H,U float32 */
   NTF_PREC_F64 = 3          /* X float64; everything FP64 (MFMA f64); H,U float64 */
 } ntf_precision;
@@ -426,8 +427,9 @@ ntf_status ntf_admm_set_constraints(ntf_admm_ctx *ctx, const ntf_constraints *co
  * bfloat16 copies of each X with a power-of-two scale per mode-1 slab
  * ([I][J][Kp], k fastest, and [I][K][Jp], j fastest; Kp, Jp = K, J rounded
  * up to 32), then the MTTKRPs run on BF16 MFMA with FP32 accumulation (as
- * in the single-problem solver, the mode-3 product scales each slab's result
- * by the row of H_1), Grams in FP32 per row block summed in FP64, and
+ * in the single-problem solver, the mode-3 product takes H_2 as two bfloat16
+ * terms and scales each slab's result by the row of H_1), Grams in FP32 per
+ * row block summed in FP64, and
  * Cholesky and solves in FP64.  Options used: inner_iters, rho_policy
  * (TRACE or FIXED), rho0, inner_eps_abs/rel, rescale_dual_on_rho_change;
  * factor_source, paper_init, warm_hidden and the outer stop test must be 0.
