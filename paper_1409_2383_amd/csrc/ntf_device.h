@@ -99,6 +99,9 @@ static __device__ __forceinline__ void load4(const T* p, int valid, int vec, T (
 // any resource used here: a load past num_records returns zeros, a store
 // there is dropped.
 constexpr int kBufferWord3 = 0x00020000;
+// Cache-policy bits of a buffer access (gfx9-family encoding of the aux
+// operand): non-temporal.
+constexpr int kAuxNonTemporal = 2;
 
 // A raw buffer resource over [p, p + bytes) whose words are read from the
 // first lane: the resource sits in scalar registers even where the compiler
