@@ -356,11 +356,13 @@ __device__ void gram_rows(const HT* __restrict__ H, int64_t r0, int64_t r1, int 
   for (int64_t rb = r0; rb < r1; rb += 64) {
     const int nr = (int)min((int64_t)64, r1 - rb);
     __syncthreads();
+#pragma unroll 4
     for (int e = tid; e < nr * F; e += 256) hs[e] = (double)H[rb * F + e];
     __syncthreads();
     // (columns past F read other rows' values into entries that are never
     // stored; every index stays inside the 64 x 64 buffer)
     if (gram_f32) {
+#pragma unroll 4
       for (int t = 0; t < nr; ++t) {
         float vi[4], vj[4];
 #pragma unroll
@@ -374,6 +376,7 @@ __device__ void gram_rows(const HT* __restrict__ H, int64_t r0, int64_t r1, int 
           for (int q = 0; q < 4; ++q) accf[p][q] += vi[p] * vj[q];
       }
     } else {
+#pragma unroll 4
       for (int t = 0; t < nr; ++t) {
         double vi[4], vj[4];
 #pragma unroll
@@ -407,9 +410,11 @@ __global__ __launch_bounds__(256) void k_gram_part(const HT* __restrict__ H, int
 }
 
 void gram_split(int64_t rows, int64_t* rpp, int* nb) {
-  // at most 16 partials of whole 64-row chunks
+  // at most 8 partials of whole 64-row chunks: the last block of the
+  // prepare step reads every partial from the L2 of the XCD that wrote it,
+  // and fewer, longer partials cost less there than they add to the row loop
   const int64_t chunks = (rows + 63) / 64;
-  const int64_t per = (chunks + 15) / 16;
+  const int64_t per = (chunks + 7) / 8;
   *rpp = per * 64;
   *nb = (int)((rows + *rpp - 1) / *rpp);
 }

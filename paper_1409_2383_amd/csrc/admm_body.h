@@ -369,9 +369,9 @@ struct PrepK {
   double* gram_scratch;
 };
 
-// LDS of prep_body: G [64][65], row/column broadcast buffers, a reduction
-// buffer, rho and the failure flag.
-constexpr int kPrepLdsDoubles = 64 * 65 + 256 + 128 + 256 + 2;
+// LDS of prep_body: G [64][65], row/column broadcast buffers (two rows and
+// two columns, double buffered), a reduction buffer, rho and the failure flag.
+constexpr int kPrepLdsDoubles = 64 * 65 + 512 + 256 + 256 + 2;
 
 // Second half of the prepare step, run by one block of 256 threads: G =
 // gram_a (*) gram_b, the penalty, L^{-1} by one elimination sweep, and
@@ -382,9 +382,9 @@ template <int NB>
 __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int tid) {
   const int F = a.F;
   double* Gs = lds;                                   // [64][65]
-  double (*rowbuf)[128] = reinterpret_cast<double (*)[128]>(lds + 64 * 65);
-  double (*colbuf)[64] = reinterpret_cast<double (*)[64]>(lds + 64 * 65 + 256);
-  double* sred = lds + 64 * 65 + 256 + 128;           // [256]
+  double (*rowbuf)[2][128] = reinterpret_cast<double (*)[2][128]>(lds + 64 * 65);       // [2][2][128]
+  double (*colbuf)[2][64] = reinterpret_cast<double (*)[2][64]>(lds + 64 * 65 + 512);   // [2][2][64]
+  double* sred = lds + 64 * 65 + 512 + 256;           // [256]
   double& rho_sh = sred[256];
   int& bad_sh = *reinterpret_cast<int*>(&sred[257]);
 
@@ -447,8 +447,13 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
   // subtracted from every row i > k.  The left block becomes L^T and the
   // right block L^{-1} (L the Cholesky factor), i.e. the factorisation and
   // the triangular inverse in F steps.  Thread (ti,tj) owns rows ti+16a and
-  // columns tj+16b of both blocks; row k and column k are broadcast through
-  // LDS (double buffered, one barrier per step).
+  // columns tj+16b of both blocks.  Steps k and k+1 share one barrier: rows
+  // k, k+1 and columns k, k+1 as they stand before step k are broadcast
+  // through LDS (double buffered), and every thread forms from them the
+  // values step k leaves in row k+1 and column k+1 (c = a_{k+1,k} / a_kk,
+  // row k+1 - c row k, a_{i,k+1} - (a_ik / a_kk) a_{k,k+1}) with the same
+  // products and fused multiply-adds as the owners would, so the result is
+  // that of the step-by-step sweep, bit for bit.
   const int ti = tid >> 4, tj = tid & 15;
   double rl[NB][NB], rr[NB][NB];
 #pragma unroll
@@ -464,39 +469,64 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
     }
 #pragma unroll
   for (int kb = 0; kb < NB; ++kb) {
-    for (int kk = 0; kk < 16; ++kk) {
+    for (int kk = 0; kk < 16; kk += 2) {
       const int k = 16 * kb + kk;
       if (k >= F) break;
-      const int buf = k & 1;
-      if (ti == kk) {
+      const bool two = k + 1 < F;
+      const int buf = (kk >> 1) & 1;
+      if (ti == kk || ti == kk + 1) {
+        const int w = ti - kk;
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
-          rowbuf[buf][tj + 16 * ib] = rl[kb][ib];
-          rowbuf[buf][64 + tj + 16 * ib] = rr[kb][ib];
+          rowbuf[buf][w][tj + 16 * ib] = rl[kb][ib];
+          rowbuf[buf][w][64 + tj + 16 * ib] = rr[kb][ib];
         }
       }
-      if (tj == kk) {
+      if (tj == kk || tj == kk + 1) {
+        const int w = tj - kk;
 #pragma unroll
-        for (int ia = 0; ia < NB; ++ia) colbuf[buf][ti + 16 * ia] = rl[ia][kb];
+        for (int ia = 0; ia < NB; ++ia) colbuf[buf][w][ti + 16 * ia] = rl[ia][kb];
       }
       __syncthreads();
-      double akk = rowbuf[buf][k];
+      // (every LDS read of the pair is issued here, before any branch)
+      double akk = rowbuf[buf][0][k];
+      const double ak_k1 = rowbuf[buf][0][k + 1];   // a_{k,k+1}
+      const double ak1_k1 = rowbuf[buf][1][k + 1];  // a_{k+1,k+1}
+      const double ak1_k = colbuf[buf][0][k + 1];   // a_{k+1,k}
+      double rkl[NB], rkr[NB], r1l[NB], r1r[NB], cm[NB], cm1[NB];
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        rkl[ib] = rowbuf[buf][0][tj + 16 * ib];
+        rkr[ib] = rowbuf[buf][0][64 + tj + 16 * ib];
+        r1l[ib] = rowbuf[buf][1][tj + 16 * ib];
+        r1r[ib] = rowbuf[buf][1][64 + tj + 16 * ib];
+      }
+#pragma unroll
+      for (int ia = 0; ia < NB; ++ia) {
+        cm[ia] = colbuf[buf][0][ti + 16 * ia];
+        cm1[ia] = colbuf[buf][1][ti + 16 * ia];
+      }
       if (!(akk > 0.0) || !isfinite(akk)) {
         if (tid == 0) bad_sh = 1;
         akk = 1.0;
       }
-      // (every LDS read of the step is issued here, before any branch, so
-      // the step waits for one LDS round trip)
-      double rkl[NB], rkr[NB], cm[NB];
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        rkl[ib] = rowbuf[buf][tj + 16 * ib];
-        rkr[ib] = rowbuf[buf][64 + tj + 16 * ib];
-      }
-#pragma unroll
-      for (int ia = 0; ia < NB; ++ia) cm[ia] = colbuf[buf][ti + 16 * ia];
       const double inv = 1.0 / akk;
       const double sc = 1.0 / sqrt(akk);
+      // step k applied to row k+1: its pivot and its values at my columns
+      const double c = ak1_k * inv;
+      double d2 = ak1_k1 - c * ak_k1;
+      if (two && (!(d2 > 0.0) || !isfinite(d2))) {
+        if (tid == 0) bad_sh = 1;
+        d2 = 1.0;
+      }
+      const double inv2 = 1.0 / d2;
+      const double sc2 = 1.0 / sqrt(d2);
+      double ul[NB], ur[NB];
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        ul[ib] = r1l[ib] - c * rkl[ib];
+        ur[ib] = r1r[ib] - c * rkr[ib];
+      }
 #pragma unroll
       for (int ia = 0; ia < NB; ++ia) {
         const int i = ti + 16 * ia;
@@ -506,12 +536,26 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
             rl[ia][ib] = rkl[ib] * sc;
             rr[ia][ib] = rkr[ib] * sc;
           }
+        } else if (two && i == k + 1) {
+#pragma unroll
+          for (int ib = 0; ib < NB; ++ib) {
+            rl[ia][ib] = ul[ib] * sc2;
+            rr[ia][ib] = ur[ib] * sc2;
+          }
         } else if (i > k && i < F) {
           const double m = cm[ia] * inv;
 #pragma unroll
           for (int ib = 0; ib < NB; ++ib) {
             rl[ia][ib] -= m * rkl[ib];
             rr[ia][ib] -= m * rkr[ib];
+          }
+          if (two) {
+            const double m2 = (cm1[ia] - m * ak_k1) * inv2;
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib) {
+              rl[ia][ib] -= m2 * ul[ib];
+              rr[ia][ib] -= m2 * ur[ib];
+            }
           }
         }
       }
