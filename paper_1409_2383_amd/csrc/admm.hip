@@ -410,11 +410,13 @@ __global__ __launch_bounds__(256) void k_gram_part(const HT* __restrict__ H, int
 }
 
 void gram_split(int64_t rows, int64_t* rpp, int* nb) {
-  // at most 8 partials of whole 64-row chunks: the last block of the
-  // prepare step reads every partial from the L2 of the XCD that wrote it,
-  // and fewer, longer partials cost less there than they add to the row loop
+  // partials of whole 64-row chunks: one chunk each up to 8 chunks, then at
+  // least two each and at most 16 partials.  The last block of the prepare
+  // step reads every partial back from the L2 of the XCD that wrote it, so
+  // fewer, longer partials pay while the factor is short; for long factors
+  // the row loop dominates and 16 blocks share it
   const int64_t chunks = (rows + 63) / 64;
-  const int64_t per = (chunks + 7) / 8;
+  const int64_t per = chunks <= 8 ? 1 : std::max<int64_t>(2, (chunks + 15) / 16);
   *rpp = per * 64;
   *nb = (int)((rows + *rpp - 1) / *rpp);
 }

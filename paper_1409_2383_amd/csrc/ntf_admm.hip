@@ -140,7 +140,7 @@ Layout make_layout(const Plan& p, const ntf_opts& o, int64_t nnz = -1) {
     L.ginv[m] = c.take((size_t)(F * F + F + 1) * 8);   // Ginv, Ginv 1, 1^T Ginv 1
     if (p.nblk_inner[m] > maxblk) maxblk = p.nblk_inner[m];
   }
-  // Gram partials: the direct Gram of the prepare step (at most 8), the
+  // Gram partials: the direct Gram of the prepare step (at most 16), the
   // standalone Gram partials of the statistics, and the inner sweep's own
   L.gpart = c.take((size_t)std::max<int64_t>(maxblk, 16) * F * F * 8);
   L.rpart = c.take((size_t)maxblk * 8 * 8);
