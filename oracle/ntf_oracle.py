@@ -344,6 +344,13 @@ def pmf_rows_ls(G: np.ndarray, rho: float, rhs: np.ndarray) -> np.ndarray:
     return np.linalg.solve(K, R.T).T[:, :F]
 
 
+def rescale_dual(U: np.ndarray, rho_old: float, rho_new: float) -> np.ndarray:
+    """Scaled dual after a penalty change: the unscaled multiplier Y = -rho U
+    is the ADMoM state (Section IV-D changes rho only), so U_new = -Y/rho_new
+    = U rho_old / rho_new."""
+    return U * (rho_old / rho_new)
+
+
 def dual_update(Hn: np.ndarray, V: np.ndarray) -> np.ndarray:
     """U_new = U + H - Ht^T = H - V with V = Ht^T - U (eq. ADMoM_NTF, dual update
     in the scaled form U = -Y/rho)."""
@@ -426,7 +433,7 @@ def mode_update(X: np.ndarray, st: State, n: int, opts: Opts) -> dict:
         rho = st.rho[n]
     U = st.U[n]
     if opts.rescale_dual_on_rho_change and rho != st.rho[n]:
-        U = U * (st.rho[n] / rho)                   # keep Y = -rho U unchanged
+        U = rescale_dual(U, st.rho[n], rho)         # keep Y = -rho U unchanged
     H_prev = st.H[n].copy()
     cons = opts.constraints[n] if opts.constraints is not None else NONNEG
     H, U, Ht, info = inner_sweep(W, st.H[n], U, G, rho, opts.inner_iters, opts.eps_abs, opts.eps_rel,
@@ -461,7 +468,7 @@ def outer_step(X: np.ndarray, st: State, opts: Opts) -> List[dict]:
         for n in range(len(st.H)):
             new = _adapt_rho(st.rho[n], infos[n]["prim"], infos[n]["dual"], opts)
             if new != st.rho[n]:
-                st.U[n] = st.U[n] * (st.rho[n] / new)   # the unscaled dual Y = -rho U is the state
+                st.U[n] = rescale_dual(st.U[n], st.rho[n], new)   # Y = -rho U is the state
             st.rho[n] = new
     st.outer += 1
     return infos

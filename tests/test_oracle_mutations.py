@@ -66,3 +66,38 @@ def test_transposed_unfolding_caught(monkeypatch):
         return good(X, n)
     monkeypatch.setattr(orc, "unfold", bad)
     assert _fails(pins.test_unfoldings_match_cp_model_bruteforce)
+
+
+def test_dual_rescale_in_wrong_direction_caught(monkeypatch):
+    monkeypatch.setattr(orc, "rescale_dual", lambda U, rho_old, rho_new: U * (rho_new / rho_old))
+    assert _fails(pins.test_paper_form_equals_sweep_form_under_adaptive_rho)
+    assert _fails(pins.test_paper_form_equals_sweep_form_with_trace_rho_rescaled)
+
+
+def test_missing_dual_rescale_caught(monkeypatch):
+    monkeypatch.setattr(orc, "rescale_dual", lambda U, rho_old, rho_new: U)
+    assert _fails(pins.test_paper_form_equals_sweep_form_under_adaptive_rho)
+    assert _fails(pins.test_paper_form_equals_sweep_form_with_trace_rho_rescaled)
+
+
+def _bad_stop(variant):
+    import math
+
+    def conv(infos, dims, F, eps_abs, eps_rel):
+        for n, inf in enumerate(infos):
+            s = {"sqrt_d_times_F": math.sqrt(dims[n]) * F * eps_abs,
+                 "sqrt_F": math.sqrt(F) * eps_abs}.get(variant, math.sqrt(dims[n] * F) * eps_abs)
+            big = min(inf["norm_p"], inf["norm_h"]) if variant == "min" else max(inf["norm_p"], inf["norm_h"])
+            ny = inf["norm_y"] / 2.0 if variant == "y_over_rho" else inf["norm_y"]
+            if inf["prim"] > s + eps_rel * big:
+                return False
+            if inf["dual"] > s + eps_rel * ny:
+                return False
+        return True
+    return conv
+
+
+@pytest.mark.parametrize("variant", ["sqrt_d_times_F", "sqrt_F", "min", "y_over_rho"])
+def test_wrong_stop_test_caught(monkeypatch, variant):
+    monkeypatch.setattr(orc, "converged_paper", _bad_stop(variant))
+    assert _fails(pins.test_stop_test_hand_computed_thresholds)

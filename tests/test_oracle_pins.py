@@ -255,6 +255,134 @@ def test_paper_form_equals_inner_sweep_form():
             np.testing.assert_allclose(-rho[n] * st.U[n], Y[n], rtol=1e-9, atol=1e-11)
 
 
+def _paper_form_along(X, H0, rho_seq):
+    """Eq. ADMoM_NTF / ADMM_NTF_ALS_C as printed, explicit unscaled Y, with
+    the penalty of every mode taken from rho_seq[k] at iteration k (Y is the
+    state and is never rescaled: Section IV-D changes rho only)."""
+    P = [h.copy() for h in H0]
+    Aux = [np.zeros_like(h) for h in H0]
+    Y = [np.zeros_like(h) for h in H0]
+    out = []
+    for rho in rho_seq:
+        P, Aux, Y = orc.paper_admom_iteration(X, P, Aux, Y, rho)
+        out.append(([p.copy() for p in P], [a.copy() for a in Aux], [y.copy() for y in Y]))
+    return out
+
+
+def test_paper_form_equals_sweep_form_under_adaptive_rho():
+    # Residual balancing (eq. varying_penalty_rule) changes each mode's rho
+    # between iterations; the sweep form carries U = -Y/rho and must rescale
+    # it on every change.  The paper form keeps Y itself, so both must give
+    # the same A, A-tilde and Y along the whole run.  A rescale in the wrong
+    # direction (rho_new/rho_old) or a missing one diverges at the first change.
+    dims, F = (7, 8, 9), 3
+    pt = ntf_synth.planted(dims, F, seed=101, sigma2=1e-2, dtype=np.float64)
+    H0 = ntf_synth.init_factors(dims, F, 101)
+    st = orc.init_state(H0, rho0=1.0, paper=True)
+    opts = orc.Opts(inner_iters=1, rho_policy=orc.RHO_ADAPTIVE, rho0=1.0, mu=8.0, tau_incr=4.0,
+                    tau_decr=2.0, factor_source=1)
+    rho_used, snaps = [], []
+    for _ in range(25):
+        rho_used.append(list(st.rho))                 # the penalties this iteration runs with
+        orc.outer_step(pt.X, st, opts)
+        assert any(np.any(u != 0) for u in st.U)       # the rescale has something to act on
+        snaps.append(([p.copy() for p in st.P], [h.copy() for h in st.H],
+                      [-st.rho[n] * st.U[n] for n in range(3)]))     # U already on the new rho
+    seq = np.array(rho_used)
+    assert np.any(seq[1:] > seq[:-1]) and np.any(seq[1:] < seq[:-1]), seq   # both directions taken
+    ref = _paper_form_along(pt.X, H0, rho_used)
+    for k, ((P, Aux, Y), (Ps, Hs, Ys)) in enumerate(zip(ref, snaps)):
+        for n in range(3):
+            np.testing.assert_allclose(Ps[n], P[n], rtol=1e-8, atol=1e-10, err_msg=f"A, iter {k}")
+            np.testing.assert_allclose(Hs[n], Aux[n], rtol=1e-8, atol=1e-10, err_msg=f"A~, iter {k}")
+            np.testing.assert_allclose(Ys[n], Y[n], rtol=1e-8, atol=1e-10, err_msg=f"Y, iter {k}")
+
+
+def test_paper_form_equals_sweep_form_with_trace_rho_rescaled():
+    # rho = tr(G)/F changes at every mode update; with the dual rescale on,
+    # the sweep form is the paper's form run with that penalty sequence.
+    # (noise at sigma2 = 0.5 puts negative entries in the LS solutions, so U
+    # is non-zero and the rescale matters; with little noise U stays zero)
+    dims, F = (6, 9, 8), 3
+    pt = ntf_synth.planted(dims, F, seed=102, sigma2=0.5, dtype=np.float64)
+    H0 = ntf_synth.init_factors(dims, F, 102)
+    st = orc.init_state(H0, rho0=1.0, paper=True)
+    opts = orc.Opts(inner_iters=1, rho_policy=orc.RHO_TRACE, factor_source=1,
+                    rescale_dual_on_rho_change=True)
+    rho_used, snaps = [], []
+    for _ in range(12):
+        orc.outer_step(pt.X, st, opts)
+        assert any(np.any(u != 0) for u in st.U)       # the rescale has something to act on
+        rho_used.append(list(st.rho))
+        snaps.append(([p.copy() for p in st.P], [h.copy() for h in st.H],
+                      [-st.rho[n] * st.U[n] for n in range(3)]))
+    seq = np.array(rho_used)
+    assert np.all(np.abs(seq[1:] / seq[:-1] - 1.0) > 1e-6)        # every update changes rho
+    ref = _paper_form_along(pt.X, H0, rho_used)
+    for k, ((P, Aux, Y), (Ps, Hs, Ys)) in enumerate(zip(ref, snaps)):
+        for n in range(3):
+            np.testing.assert_allclose(Ps[n], P[n], rtol=1e-8, atol=1e-10, err_msg=f"A, iter {k}")
+            np.testing.assert_allclose(Hs[n], Aux[n], rtol=1e-8, atol=1e-10, err_msg=f"A~, iter {k}")
+            np.testing.assert_allclose(Ys[n], Y[n], rtol=1e-8, atol=1e-10, err_msg=f"Y, iter {k}")
+
+
+def _stop_infos():
+    # Hand-set residuals for dims (4, 9, 16), F = 4: sqrt(d F) = 4, 6, 8.
+    # With eps_abs = 0.01, eps_rel = 0.1 the Section IV-C thresholds are
+    #   mode 1: primal 0.04 + 0.1 max(3, 5) = 0.54,  dual 0.04 + 0.1 * 2 = 0.24
+    #   mode 2: primal 0.06 + 0.1 max(7, 1) = 0.76,  dual 0.06 + 0.1 * 4 = 0.46
+    #   mode 3: primal 0.08 + 0.1 max(2, 2) = 0.28,  dual 0.08 + 0.1 * 1 = 0.18
+    return [
+        {"prim": 0.535, "dual": 0.235, "norm_p": 3.0, "norm_h": 5.0, "norm_y": 2.0},
+        {"prim": 0.755, "dual": 0.455, "norm_p": 7.0, "norm_h": 1.0, "norm_y": 4.0},
+        {"prim": 0.275, "dual": 0.175, "norm_p": 2.0, "norm_h": 2.0, "norm_y": 1.0},
+    ]
+
+
+def test_stop_test_hand_computed_thresholds():
+    dims, F, ea, er = (4, 9, 16), 4, 0.01, 0.1
+    assert orc.converged_paper(_stop_infos(), dims, F, ea, er)
+    # each of the six conditions pushed just past its threshold alone stops nothing
+    for n, key, val in [(0, "prim", 0.545), (0, "dual", 0.245), (1, "prim", 0.765),
+                        (1, "dual", 0.465), (2, "prim", 0.285), (2, "dual", 0.185)]:
+        infos = _stop_infos()
+        infos[n][key] = val
+        assert not orc.converged_paper(infos, dims, F, ea, er), (n, key)
+    # the relative part uses the larger of ||A|| and ||A-tilde||, whichever it is
+    infos = _stop_infos()
+    infos[0]["norm_p"], infos[0]["norm_h"] = 5.0, 3.0
+    assert orc.converged_paper(infos, dims, F, ea, er)
+    # the absolute part alone: with eps_rel = 0 the thresholds are sqrt(d F) eps_abs
+    infos = [{"prim": 0.039, "dual": 0.039, "norm_p": 1e9, "norm_h": 1e9, "norm_y": 1e9},
+             {"prim": 0.059, "dual": 0.059, "norm_p": 1e9, "norm_h": 1e9, "norm_y": 1e9},
+             {"prim": 0.079, "dual": 0.079, "norm_p": 1e9, "norm_h": 1e9, "norm_y": 1e9}]
+    assert orc.converged_paper(infos, dims, F, 0.01, 0.0)
+    infos[2]["dual"] = 0.081
+    assert not orc.converged_paper(infos, dims, F, 0.01, 0.0)
+
+
+def test_run_stops_at_the_first_iteration_meeting_the_test():
+    # run(..., stop_eps) ends after the first outer iteration whose residuals
+    # pass the Section IV-C test and not before: replaying the same iterations
+    # one at a time finds that iteration by the test on each iteration's infos.
+    dims, F = (12, 10, 9), 3
+    pt = ntf_synth.planted(dims, F, seed=103, sigma2=1e-2, dtype=np.float64)
+    H0 = ntf_synth.init_factors(dims, F, 103)
+    opts = orc.Opts(inner_iters=1, rho_policy=orc.RHO_ADAPTIVE, factor_source=1)
+    eps = (1e-3, 1e-3)
+    st = orc.run(pt.X, orc.init_state(H0, paper=True), opts, 2000, stop_eps=eps)
+    assert st.outer < 2000
+    st2 = orc.init_state(H0, paper=True)
+    first = None
+    for k in range(st.outer):
+        infos = orc.outer_step(pt.X, st2, opts)
+        if first is None and orc.converged_paper(infos, dims, F, *eps):
+            first = k + 1
+    assert first == st.outer
+    for n in range(3):
+        np.testing.assert_array_equal(st.H[n], st2.H[n])
+
+
 @pytest.mark.parametrize("blocks", [2, 3])
 def test_partitioned_update_equals_centralized(blocks):
     # Appendix B: the block-partitioned update evolves exactly like the centralized one.
