@@ -7,7 +7,7 @@ Exponential(1) planted factors at 30 dB SNR, 10 inner iterations, in the
 mixed-precision arm (BF16 MTTKRP with FP32 accumulation, FP32 Gram, FP64
 Cholesky/solves); the FP32 arm is timed beside it.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--ttt]
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c5|s1|n4] [--no-ttt]
 """
 from __future__ import annotations
 
@@ -64,12 +64,13 @@ def src_hash(files=None):
     return h.hexdigest()[:16]
 
 
-def make_solver(ntf, torch, Xd, H0, arm, T, dev):
+def make_solver(ntf, torch, Xd, H0, arm, T, dev, warm_hidden=0):
     prec = {"fp32": ntf.PREC_F32, "mixed": ntf.PREC_BF16_MIXED, "fp64": ntf.PREC_F64}[arm]
     fdt = torch.float64 if arm == "fp64" else torch.float32
     H = [torch.from_numpy(h).to(dev, dtype=fdt) for h in H0]
     X = Xd.to(fdt) if Xd.dtype != fdt else Xd
-    return ntf.NtfAdmm(X, H, opts=ntf.AdmmOptions(inner_iters=T, precision=prec)), H
+    return ntf.NtfAdmm(X, H, opts=ntf.AdmmOptions(inner_iters=T, precision=prec,
+                                                  warm_hidden=warm_hidden)), H
 
 
 def time_steps(torch, solver, steps, warmup):
@@ -106,17 +107,29 @@ def time_passes(torch, solver, reps):
     return out
 
 
+def blas_info():
+    """BLAS library numpy uses and its thread count, and the host cores this
+    process may run on."""
+    info = {"affinity_cores": len(os.sched_getaffinity(0)), "blas": None, "blas_threads": None}
+    try:
+        from threadpoolctl import threadpool_info
+        for lib in threadpool_info():
+            if lib.get("user_api") == "blas":
+                info["blas"] = f"{lib.get('internal_api')} {lib.get('version')}"
+                info["blas_threads"] = int(lib.get("num_threads", 1))
+                break
+    except Exception:
+        pass
+    return info
+
+
 def cpu_baseline(X, H0, T, sample_slabs, min_seconds=10.0, max_iters=5):
     """The FP64 oracle (as it stands) on the host: outer iterations over the
     first `sample_slabs` mode-1 slabs of the same tensor (all of them by
     default), repeated until `min_seconds` have passed, scaled to the full
     tensor by the slab ratio (MTTKRP work is linear in I)."""
     from oracle import ntf_oracle as orc
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
-    except Exception:
-        cores = os.cpu_count() or 1
+    bi = blas_info()
     I = X.shape[0]
     S = min(I, sample_slabs) if sample_slabs > 0 else I
     Xs = np.ascontiguousarray(X[:S], dtype=np.float64)
@@ -133,10 +146,11 @@ def cpu_baseline(X, H0, T, sample_slabs, min_seconds=10.0, max_iters=5):
             break
     per_iter = dt / n * I / S
     where = f"all {I}" if S == I else f"the first {S} of {I}"
-    return {"value": 1.0 / per_iter, "unit": "outer_iters/s", "cores": cores, "kind": "oracle",
+    return {"value": 1.0 / per_iter, "unit": "outer_iters/s",
+            "cores": bi["blas_threads"] or bi["affinity_cores"], "kind": "oracle",
             "sample": f"{n} outer iteration(s) (T={T}) of the FP64 oracle on {where} mode-1 slabs "
                       f"of the same tensor ({dt:.1f} s)" + ("" if S == I else f", scaled by {I}/{S}"),
-            "seconds_measured": dt}
+            "seconds_measured": dt, "blas": bi["blas"], "affinity_cores": bi["affinity_cores"]}
 
 
 def copy_calibration(torch, dev, mib, reps=3):
@@ -154,60 +168,70 @@ def copy_calibration(torch, dev, mib, reps=3):
     del src, dst
 
 
-def time_to_target(torch, ntf, Xd, H0, T, arms, dev, ref_arm="fp64", max_outer=3000, every=10,
-                   tol=1e-4):
-    """Time for each arm to reach (RFE - RFE*)/RFE* <= tol.  RFE* is the RFE
-    the reference arm converges to (|dRFE|/RFE < 1e-9 over `every` steps, or
-    the cap).  Step time is measured with HIP events; fits are untimed."""
-    res = {}
-    ref, H = make_solver(ntf, torch, Xd, H0, ref_arm, T, dev)
-    prev = None
-    it = 0
-    while it < max_outer:
-        ref.run(every, stats=False)
-        it += every
-        r = ref.fit()
-        if prev is not None and abs(prev - r) < 1e-9 * r:
-            break
-        prev = r
-    rfe_star = ref.fit()
-    ref.close()
-    del ref, H
-    torch.cuda.empty_cache()
-    res["rfe_star"] = rfe_star
-    res["rfe_star_source"] = f"{ref_arm} GPU run to |dRFE|/RFE < 1e-9 ({it} outer iterations)"
+def load_rfe_star(workload):
+    """RFE* of the workload from the FP64 oracle's converged run, stored by
+    tests/golden/make_golden.py (None if that file is absent)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_rfe_star.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        g = json.load(fh)
+    return {"rfe_star": g["rfe_star"],
+            "source": f"FP64 oracle run to {g['stop']} ({g['outer_iters']} outer iterations; "
+                      f"tests/golden/{os.path.basename(path)})",
+            "exact_iters": g.get("exact_iters_to_rel_1e-4")}
+
+
+def time_to_target(torch, ntf, Xd, H0, T, arms, dev, star, max_outer=400, tol=1e-4, warm=None):
+    """Time for each arm to reach (RFE - RFE*)/RFE* <= tol.  The clock
+    (HIP events on the stream the library launches on) covers the arm's
+    set-up on the device (BF16 copies of X, graph capture, which happen in
+    the first step) and every outer iteration up to the first whose RFE meets
+    the target; the RFE is evaluated after every iteration, outside the
+    clock.  `warm` maps an arm name to a warm-start network (an ntf.Mlp-like
+    argument for set_warmstart) and its one-off cost in ms."""
+    rfe_star = star["rfe_star"]
+    res = {"rfe_star": rfe_star, "rfe_star_source": star["source"], "target_rel": tol,
+           "check_every": 1}
     s = torch.cuda.current_stream()
     for arm in arms:
+        base = "mixed" if arm.startswith("mixed") else arm
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
-        solver, H = make_solver(ntf, torch, Xd, H0, arm, T, dev)   # includes BF16 quantization
-        solver.step()                                               # and the graph capture
+        solver, H = make_solver(ntf, torch, Xd, H0, base, T, dev,
+                                warm_hidden=(warm[arm]["hidden"] if warm and arm in warm else 0))
+        extra_ms = 0.0
+        if warm and arm in warm:
+            warm[arm]["attach"](solver)
+            extra_ms = warm[arm].get("setup_ms", 0.0)
+        solver.step()
         e1.record(s)
         torch.cuda.synchronize()
-        init_ms = e0.elapsed_time(e1)
+        init_ms = e0.elapsed_time(e1) + extra_ms
         total_ms, it = init_ms, 1
-        hit = None
         r = solver.fit()
+        hit = (it, total_ms, r) if (r - rfe_star) / rfe_star <= tol else None
         trace = [(it, total_ms, r)]
-        while it < max_outer:
+        while hit is None and it < max_outer:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
-            for _ in range(every):
-                solver.step()
+            solver.step()
             e1.record(s)
             torch.cuda.synchronize()
             total_ms += e0.elapsed_time(e1)
-            it += every
+            it += 1
             r = solver.fit()
             trace.append((it, total_ms, r))
             if (r - rfe_star) / rfe_star <= tol:
                 hit = (it, total_ms, r)
-                break
         res[arm] = {"reached": hit is not None, "outer_iters": hit[0] if hit else None,
-                    "init_and_first_step_ms": init_ms,
-                    "seconds": hit[1] / 1e3 if hit else None, "rfe": r,
-                    "rel_to_star": (r - rfe_star) / rfe_star, "trace_tail": trace[-3:]}
+                    "ms": hit[1] if hit else None, "init_and_first_step_ms": init_ms,
+                    "rfe": r, "rel_to_star": (r - rfe_star) / rfe_star,
+                    "rel_before": ((trace[-2][2] - rfe_star) / rfe_star) if len(trace) > 1 else None,
+                    "trace_every_10": [t for t in trace if t[0] % 10 == 0 or t[0] == 1]}
+        log(f"[bench] ttt {arm}: " + (f"{hit[0]} outer iterations, {hit[1]:.1f} ms" if hit else
+                                       f"not reached in {max_outer} (rel {(r - rfe_star) / rfe_star:.2e})"))
         solver.close()
         del solver, H
         torch.cuda.empty_cache()
@@ -323,7 +347,7 @@ def bench_batched(args):
     """Batched workload: many planted tensors of uneven shapes factorised
     together (one persistent kernel per outer iteration).  value = problem
     outer iterations per second over the whole batch."""
-    import multiprocessing as mp
+    import concurrent.futures as cf
     import torch
     import ntf_synth
     import paper_1409_2383_amd as ntf
@@ -337,9 +361,11 @@ def bench_batched(args):
     log(f"[bench] generating {n} tensors (modes {wl['lo']}..{wl['hi']}, F 5..40)")
     t0 = time.perf_counter()
     Xs, Hs = [], []
-    workers = max(1, min(16, os.cpu_count() or 1))
-    with mp.get_context("spawn").Pool(workers) as pool:
-        for t, (X, H0) in enumerate(pool.imap(_gen_tensor, jobs, chunksize=1)):
+    # threads of this process (numpy releases the GIL in its matrix products
+    # and bulk random draws): a profiled run then holds one process only
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(workers) as pool:
+        for t, (X, H0) in enumerate(pool.map(_gen_tensor, jobs)):
             Xs.append(torch.from_numpy(X).to(dev))
             Hs.append([torch.from_numpy(h).to(dev) for h in H0])
             if (t + 1) % 64 == 0:
@@ -383,9 +409,12 @@ def bench_batched(args):
     prof = b.profile()          # one more outer iteration, instrumented per item kind
     fits = b.fit()
     dom = max(("pass1", "pass3"), key=lambda k: pass_ms[k])
-    roofline = {"bound": "hbm", "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs[dom] / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_batch ({dom} items only)",
-                "algorithmic_bytes_per_launch": nbytes[dom], "avg_launch_ms": pass_ms[dom]}
+    # algorithmic bytes of one MTTKRP of every problem: one read of each BF16 tensor copy
+    ach = info["x_bytes"] / (pass_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_batch ({dom} items only)",
+                "algorithmic_bytes_per_launch": info["x_bytes"],
+                "kernel_bytes_per_launch": nbytes[dom], "avg_launch_ms": pass_ms[dom]}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_batched(jobs, T, shapes)
@@ -414,11 +443,8 @@ def cpu_baseline_batched(jobs, T, shapes, min_seconds=10.0):
     min_seconds of oracle time have passed, scaled to the whole batch by
     MTTKRP work (sum of I J K F)."""
     from oracle import ntf_oracle as orc
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
-    except Exception:
-        cores = os.cpu_count() or 1
+    bi = blas_info()
+    cores = bi['blas_threads'] or bi['affinity_cores']
     work = [d[0] * d[1] * d[2] * F for d, F in shapes]
     done, used, dt = 0.0, 0, 0.0
     for job in jobs:
@@ -434,7 +460,7 @@ def cpu_baseline_batched(jobs, T, shapes, min_seconds=10.0):
             break
     per_batch_iter = dt * sum(work) / done
     return {"value": len(shapes) / per_batch_iter, "unit": "problem_outer_iters/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "blas": bi["blas"], "affinity_cores": bi["affinity_cores"],
             "sample": f"1 outer iteration (T={T}) of the FP64 oracle on each of the first {used} tensors "
                       f"({dt:.1f} s), scaled to all {len(shapes)} by sum(I J K F)",
             "seconds_measured": dt}
@@ -445,11 +471,8 @@ def cpu_baseline_sparse(T, H0, Topt, sample_nnz, min_seconds=10.0):
     `sample_nnz` non-zeros (the order is random), with the MTTKRP share
     scaled to all non-zeros (its cost is linear in nnz; the rest is not)."""
     from oracle import ntf_oracle as orc
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
-    except Exception:
-        cores = os.cpu_count() or 1
+    bi = blas_info()
+    cores = bi['blas_threads'] or bi['affinity_cores']
     n = T.idx.shape[0]
     S = min(n, sample_nnz)
     sub = orc.SparseTensor(idx=T.idx[:S], val=T.val[:S], dims=T.dims)
@@ -466,7 +489,8 @@ def cpu_baseline_sparse(T, H0, Topt, sample_nnz, min_seconds=10.0):
         t_mk += time.perf_counter() - t0
         iters += 1
     per_iter = (t_outer + t_mk * (n / S - 1.0)) / iters
-    return {"value": 1.0 / per_iter, "unit": "outer_iters/s", "cores": cores, "kind": "oracle",
+    return {"value": 1.0 / per_iter, "unit": "outer_iters/s", "cores": cores, "kind": "oracle", "blas": bi["blas"],
+            "affinity_cores": bi["affinity_cores"],
             "sample": f"{iters} outer iteration(s) (T={Topt}) of the FP64 oracle on the first {S} of "
                       f"{n} non-zeros ({t_outer:.1f} s), its three MTTKRPs (timed again, "
                       f"{t_mk / iters:.2f} s per iteration) scaled by {n}/{S}",
@@ -602,13 +626,11 @@ def bench_nway(args):
             orc.outer_step(Xs, sto, orc.Opts(inner_iters=T))
             t_cpu += time.perf_counter() - t0
             n_it += 1
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
-        except Exception:
-            cores = os.cpu_count() or 1
+        bi = blas_info()
+        cores = bi['blas_threads'] or bi['affinity_cores']
         per_iter = t_cpu / n_it * dims[0] / S
-        cpu = {"value": 1.0 / per_iter, "unit": "outer_iters/s", "cores": cores, "kind": "oracle",
+        cpu = {"value": 1.0 / per_iter, "unit": "outer_iters/s", "cores": cores, "kind": "oracle", "blas": bi["blas"],
+            "affinity_cores": bi["affinity_cores"],
                "sample": f"{n_it} outer iteration(s) (T={T}) of the FP64 oracle on the first {S} of "
                          f"{dims[0]} mode-1 slabs ({t_cpu:.1f} s), scaled by {dims[0]}/{S}",
                "seconds_measured": t_cpu}
@@ -637,7 +659,7 @@ def main():
     ap.add_argument("--cpu-sample-slabs", type=int, default=0, help="0 = all slabs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also launch a known-size copy kernel (for byte-counter scaling)")
-    ap.add_argument("--ttt", action="store_true", help="also measure time to rel fit 1e-4")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time to rel fit 1e-4")
     ap.add_argument("--single-arm", action="store_true")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into profiles/ and exit")
@@ -701,7 +723,13 @@ def main():
     head = arms[0]
     r = results[head]
     dom = max(("pass1", "pass3"), key=lambda k: r["pass_ms"][k])
-    achieved = r["pass_gbs"][dom]
+    # Algorithmic bytes of one MTTKRP of the method: one read of the tensor in
+    # the arm's storage type, IJK s (the Khatri-Rao factors are L2-resident).
+    # Pass 1 is the mode-1 MTTKRP; it also writes the I x J x F intermediate
+    # that the mode-2 MTTKRP reads instead of X (counted in kernel_bytes only).
+    x_es = 8 if head == "fp64" else (2 if head == "mixed" else 4)
+    method_bytes = int(np.prod(dims)) * x_es
+    achieved = method_bytes / (r["pass_ms"][dom] * 1e-3) / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{head}_{dom}.json")
     if os.path.exists(tfile):
@@ -709,10 +737,17 @@ def main():
             tj = json.load(fh)
         if tj.get("src_hash") == src_hash(MTTKRP_SOURCES):
             traffic = tj.get("bytes_per_launch")
+    per_step = 3 * method_bytes / (r["ms_per_step"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                "algorithmic_bytes_per_launch": r["pass_bytes"][dom],
-                "avg_launch_ms": r["pass_ms"][dom]}
+                "algorithmic_bytes_per_launch": method_bytes,
+                "algorithmic_bytes": "IJK s: one read of the tensor copy the arm streams",
+                "kernel_bytes_per_launch": r["pass_bytes"][dom],
+                "avg_launch_ms": r["pass_ms"][dom],
+                "per_step": {"bytes": 3 * method_bytes, "ms": r["ms_per_step"], "GB/s": per_step,
+                             "frac": per_step / HBM_PEAK_GBS,
+                             "note": "three MTTKRPs of IJK s each per outer iteration over the "
+                                     "whole step time"}}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -721,9 +756,13 @@ def main():
         cpu = cpu_baseline(pt.X, H0, T, slabs)
 
     ttt = None
-    if args.ttt and args.workload == "c3":
-        log("[bench] time to rel fit 1e-4")
-        ttt = time_to_target(torch, ntf, Xd, H0, T, ("mixed", "fp32"), dev)
+    if not args.no_ttt and args.workload == "c3" and not args.single_arm:
+        star = load_rfe_star(args.workload)
+        if star is None:
+            log("[bench] no stored oracle RFE*: time to target skipped")
+        else:
+            log("[bench] time to rel fit 1e-4")
+            ttt = time_to_target(torch, ntf, Xd, H0, T, ("mixed", "fp32"), dev, star)
 
     dtype = {"mixed": "bf16", "fp32": "f32", "fp64": "f64"}[head]
     line = {

@@ -1,0 +1,94 @@
+"""Parity at the benchmark workloads' own sizes, against values the FP64 oracle
+wrote (tests/golden/, by tests/golden/make_golden.py, which calls only the
+oracle and the input generator).
+
+* 400 x 400 x 400 FP32 tensor, F = 20 U[0,1] planted factors, 20 dB, T = 10:
+  factors after one outer iteration (the oracle's step computed here) within
+  2x the error float32 library arithmetic gives, and the RFE after 200 outer
+  iterations within 1e-6 relative of the oracle's stored RFE.
+* 16 tensors of the 256-tensor batch (modes uniform on 50..500, F on 5..40,
+  U[0,1] factors, 20 dB, the batch's mixed precision): after the stored
+  number of outer iterations, every tensor's RFE within 1e-4 relative of the
+  exact FP64 oracle's (the headline's relative-fit target: the mixed path
+  reaches the exact method's fit within it).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ntf_oracle as orc
+from tests.gpu_helpers import rel, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_2383_amd as ntf
+    ntf.library_path()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def c2(dev):
+    import ntf_synth
+    with open(os.path.join(GOLDEN, "c2_fp32_400cubed.json")) as fh:
+        g = json.load(fh)
+    dims, F = (400, 400, 400), 20
+    pt = ntf_synth.planted(dims, F, g["seed"], snr_db=20.0, dtype=np.float32)
+    H0 = ntf_synth.init_factors(dims, F, g["seed"], dtype=np.float32)
+    return g, pt, H0
+
+
+def _fp32_library_step(X32, H0, T):
+    """One outer iteration of the oracle's sweep fed with MTTKRPs that a
+    float32 library matmul computes (float32 accumulation)."""
+    st = orc.init_state([h.astype(np.float64) for h in H0])
+    for n in range(3):
+        fs = [h.astype(np.float32) for h in st.H]
+        W = orc.unfold(X32, n).astype(np.float32) @ orc.kr_for_mode(fs, n).astype(np.float32)
+        G = orc.gram_hadamard(st.H, n)
+        st.H[n], st.U[n], _, _ = orc.inner_sweep(W.astype(np.float64), st.H[n], st.U[n], G,
+                                                 orc.rho_trace(G), T)
+    return st
+
+
+def test_config2_one_step_factors(dev, c2):
+    import paper_1409_2383_amd as ntf
+    g, pt, H0 = c2
+    print("[c2] 400^3 F=20 FP32: one outer iteration", flush=True)
+    s = ntf.NtfAdmm(torch.from_numpy(pt.X).to(dev), to_dev(H0, dev),
+                    opts=ntf.AdmmOptions(inner_iters=10, precision=ntf.PREC_F32))
+    s.step()
+    torch.cuda.synchronize()
+    ref = orc.init_state([h.astype(np.float64) for h in H0])
+    orc.outer_step(pt.X.astype(np.float64), ref, orc.Opts(inner_iters=10))
+    lib = _fp32_library_step(pt.X, H0, 10)
+    for n in range(3):
+        got = rel(s.H[n].cpu().numpy(), ref.H[n])
+        bound = max(1e-6, 2.0 * rel(lib.H[n], ref.H[n]))
+        print(f"[c2] mode {n}: factor error {got:.3e}, bound {bound:.3e}", flush=True)
+        assert got < bound, n
+    s.close()
+
+
+def test_config2_fit_after_200_iterations(dev, c2):
+    import paper_1409_2383_amd as ntf
+    g, pt, H0 = c2
+    print("[c2] 400^3 F=20 FP32: 200 outer iterations", flush=True)
+    s = ntf.NtfAdmm(torch.from_numpy(pt.X).to(dev), to_dev(H0, dev),
+                    opts=ntf.AdmmOptions(inner_iters=10, precision=ntf.PREC_F32))
+    s.run(g["outer_iters"], stats=False)
+    r = s.fit()
+    err = abs(r - g["rfe_final"]) / g["rfe_final"]
+    print(f"[c2] RFE after {g['outer_iters']}: GPU {r:.12f}, oracle {g['rfe_final']:.12f}, "
+          f"relative {err:.2e}", flush=True)
+    assert err <= 1e-6
+    s.close()

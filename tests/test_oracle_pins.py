@@ -85,6 +85,23 @@ def test_mttkrp_planted_closed_form():
         np.testing.assert_allclose(orc.mttkrp(pt.X, Hs, n), closed, rtol=1e-12)
 
 
+def test_rfe_expanded_equals_the_definition():
+    # The expansion ||X||^2 - 2<X,M> + ||M||^2 against the residual formed
+    # entry by entry from the reconstructed model, on a noisy planted tensor
+    # and on factors far from it.
+    dims, F = (9, 7, 11), 4
+    pt = ntf_synth.planted(dims, F, seed=31, snr_db=20.0, dtype=np.float64)
+    for fac in ([pt.A0, pt.B0, pt.C0], _rand_factors(dims, F, 32)):
+        M = np.zeros(dims)
+        for i in range(dims[0]):
+            for j in range(dims[1]):
+                for k in range(dims[2]):
+                    M[i, j, k] = sum(fac[0][i, f] * fac[1][j, f] * fac[2][k, f] for f in range(F))
+        direct = math.sqrt(np.sum((pt.X - M) ** 2) / np.sum(pt.X ** 2))
+        assert abs(orc.rfe_expanded(pt.X, fac) - direct) < 1e-12 * max(direct, 1e-3)
+        assert abs(orc.rfe(pt.X, fac) - direct) < 1e-13 * direct
+
+
 def test_gram_hadamard_identity():
     Hs = _rand_factors((6, 7, 8), 5, 5)
     for n in range(3):
