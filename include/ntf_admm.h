@@ -375,6 +375,25 @@ ntf_status ntf_inner_update(const double *W, void *H, void *U, int64_t rows, int
                             int32_t *iters_out, void *Ht_out, void *workspace, size_t ws_bytes,
                             void *stream);
 
+/* ntf_inner_update for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments and results (H, U, iters_out, Ht_out bitwise those of
+ * ntf_inner_update) but no workspace.  Its scratch (device state, the system
+ * G + rho I in factored form) lives in a fixed 128 KiB array in the library's
+ * device memory, one copy per GPU, held until the process ends; a call needs
+ * ntf_inner_static_scratch_bytes(F) of it (at most ~67 KB, for F = 64) and
+ * returns NTF_E_WORKSPACE if that exceeded the array.  The call allocates
+ * nothing and issues no memset (fill kernels only).  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (different streams, or
+ * host threads without ordering) race and give undefined results; calls
+ * ordered on one stream are safe.  Errors: NTF_E_INVAL as ntf_inner_update,
+ * NTF_E_HIP if the array's address cannot be obtained or a launch fails. */
+size_t ntf_inner_static_scratch_bytes(int32_t F);
+ntf_status ntf_inner_update_noalloc(const double *W, void *H, void *U, int64_t rows, int32_t F,
+                                    int32_t dtype, const double *G, double rho, int32_t T,
+                                    double eps_abs, double eps_rel, int32_t *iters_out,
+                                    void *Ht_out, void *stream);
+
 /* Gram matrix H^T H of a [rows][F] factor (dtype 0 = float32, 1 = float64),
  * accumulated in FP64, into G_out (device float64 [F][F]).  Stream-ordered. */
 size_t ntf_gram_workspace_bytes(int64_t rows, int32_t F);

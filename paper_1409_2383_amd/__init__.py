@@ -423,6 +423,22 @@ def inner_update(W, H, U, G, rho: float = 0.0, T: int = 1, eps_abs: float = 0.0,
     return iters, ht
 
 
+def inner_update_noalloc(W, H, U, G, rho: float = 0.0, T: int = 1, eps_abs: float = 0.0,
+                         eps_rel: float = 0.0, iters=None, ht=None, stream=None):
+    """inner_update without a workspace: the library keeps its scratch in a
+    fixed device array per GPU (calls overlapping on one GPU race).  `iters`
+    (int32 [rows]) and `ht` (like H) are optional caller-owned outputs; this
+    call allocates nothing and does not synchronise."""
+    torch = _torch()
+    rows, F = H.shape
+    dtype = 1 if H.dtype == torch.float64 else 0
+    st = _lib.lib().ntf_inner_update_noalloc(
+        _ptr(W), _ptr(H), _ptr(U), rows, F, dtype, _ptr(G), float(rho), int(T), float(eps_abs),
+        float(eps_rel), ctypes.c_void_p(_ptr(iters)) if iters is not None else None,
+        ctypes.c_void_p(_ptr(ht)) if ht is not None else None, _stream_handle(stream))
+    _lib.check(st, "ntf_inner_update_noalloc")
+
+
 def gram(H, stream=None):
     """H^T H accumulated in FP64 on the device."""
     torch = _torch()

@@ -211,6 +211,10 @@ SIGNATURES = [
     ("ntf_inner_update", c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,
                                    c_double, c_int32, c_double, c_double, c_void_p, c_void_p, c_void_p,
                                    c_size_t, c_void_p]),
+    ("ntf_inner_static_scratch_bytes", c_size_t, [c_int32]),
+    ("ntf_inner_update_noalloc", c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_int32,
+                                           c_void_p, c_double, c_int32, c_double, c_double, c_void_p,
+                                           c_void_p, c_void_p]),
     ("ntf_gram_workspace_bytes", c_size_t, [c_int64, c_int32]),
     ("ntf_gram", c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("ntf_admm_set_warmstart", c_int32, [c_void_p, POINTER(Mlp)]),

@@ -25,6 +25,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -1331,6 +1332,126 @@ ntf_status ntf_inner_update(const double* W, void* H, void* U, int64_t rows, int
   ia.iters_out = iters_out;
   ia.gram_part = reinterpret_cast<double*>(base + w.gpart);
   ia.resid_part = reinterpret_cast<double*>(base + w.rpart);
+  ia.flag = &ds->flag;
+  const int rpb = inner_rows_per_block(FL);
+  if (launch_inner(ia, (int)((rows + rpb - 1) / rpb), s) != hipSuccess) return NTF_E_HIP;
+  return NTF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- mode update without allocation
+//
+// ntf_inner_update_noalloc runs the kernels of ntf_inner_update with their
+// scratch (device state, the all-ones Hadamard partner, the factored system)
+// in the file-scope array below instead of a caller workspace.  The Gram and
+// residual partials that ntf_inner_update also leaves in its workspace are
+// outputs nobody reads there, so this variant skips them; H, U, the
+// iteration counts and Ht are bitwise the same.  Host code never passes
+// `scratch` itself to a kernel: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+
+namespace {
+constexpr size_t kStaticScratchBytes = 128 * 1024;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+struct StaticInnerLayout {
+  size_t state, ones, ginv, total;
+};
+StaticInnerLayout static_inner_layout(int F) {
+  Carver c;
+  StaticInnerLayout l;
+  l.state = c.take(sizeof(DevState));
+  l.ones = c.take((size_t)F * F * 8);
+  l.ginv = c.take((size_t)(F * F + F + 1) * 8);
+  l.total = c.off;
+  return l;
+}
+
+// Device address of this device's copy of `scratch` (looked up once per device).
+hipError_t static_scratch(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = reinterpret_cast<char*>(g_scratch_ptr[dev]);
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+size_t ntf_inner_static_scratch_bytes(int32_t F) {
+  if (F < 1 || F > 64) return 0;
+  return static_inner_layout(F).total;
+}
+
+ntf_status ntf_inner_update_noalloc(const double* W, void* H, void* U, int64_t rows, int32_t F,
+                                    int32_t dtype, const double* G, double rho, int32_t T,
+                                    double eps_abs, double eps_rel, int32_t* iters_out,
+                                    void* Ht_out, void* stream) {
+  if (!W || !H || !U || !G || rows < 1 || F < 1 || F > 64 || (dtype != 0 && dtype != 1) || T < 1 ||
+      eps_abs < 0 || eps_rel < 0)
+    return NTF_E_INVAL;
+  const StaticInnerLayout l = static_inner_layout(F);
+  if (l.total > kStaticScratchBytes) return NTF_E_WORKSPACE;
+  char* base = nullptr;
+  if (static_scratch(&base) != hipSuccess) return NTF_E_HIP;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  DevState* ds = reinterpret_cast<DevState*>(base + l.state);
+  // the array keeps the previous call's contents: state restarts at zero
+  if (launch_fill(reinterpret_cast<double*>(ds), sizeof(DevState) / 8, 0.0, s) != hipSuccess) return NTF_E_HIP;
+  if (launch_fill(reinterpret_cast<double*>(base + l.ones), (int64_t)F * F, 1.0, s) != hipSuccess)
+    return NTF_E_HIP;
+  PrepArgs pa;
+  pa.F = F;
+  pa.gram_a = G;
+  pa.gram_b = reinterpret_cast<double*>(base + l.ones);
+  pa.policy = rho > 0 ? 1 : 0;
+  pa.rho0 = rho > 0 ? rho : 1.0;
+  pa.rho_state = ds->rho[0];
+  pa.Ginv = reinterpret_cast<double*>(base + l.ginv);
+  pa.flag = &ds->flag;
+  pa.counter = &ds->counter[0];
+  if (launch_prep(pa, 1, s) != hipSuccess) return NTF_E_HIP;
+  int FL = 4;
+  while (FL < F) FL <<= 1;
+  InnerArgs ia;
+  ia.part = W;
+  ia.part_f64 = 1;
+  ia.pstride = 0;
+  ia.rowstride = F;
+  ia.nparts = 1;
+  ia.H = H;
+  ia.U = U;
+  ia.Pout = Ht_out;
+  ia.h_f64 = dtype;
+  ia.rows = rows;
+  ia.F = F;
+  ia.FL = FL;
+  ia.Ginv = pa.Ginv;
+  ia.rho = ds->rho[0];
+  ia.T = T;
+  ia.eps_abs = eps_abs;
+  ia.eps_rel = eps_rel;
+  ia.iters_out = iters_out;
+  ia.gram_part = nullptr;
+  ia.resid_part = nullptr;
   ia.flag = &ds->flag;
   const int rpb = inner_rows_per_block(FL);
   if (launch_inner(ia, (int)((rows + rpb - 1) / rpb), s) != hipSuccess) return NTF_E_HIP;
