@@ -92,6 +92,9 @@ def table(realizations: int = 10, scenarios=None, n_max: int = 400, precision: i
             pt = ntf_synth.planted(dims, F, seed, sigma2=sigma2, dtype=dt)
             X = torch.from_numpy(pt.X).to(dev)
             res.append(solve_with_restarts(X, F, seed, n_max=n_max, eps=eps, precision=precision))
+            r = res[-1]
+            log(f"# {dims} F={F} sigma2={sigma2:g} realisation {t}: rfe {r['rfe']:.6f}, "
+                f"iters {r['iters']}, restarts {r['restarts']}, {r['seconds']:.2f} s")
             del X
         ok = [r for r in res if r["converged"]]
         row = {"dims": list(dims), "F": F, "sigma2": sigma2, "eps": eps, "realizations": realizations,
@@ -114,7 +117,8 @@ def main():
     ap.add_argument("--out", default="")
     args = ap.parse_args()
     scen = list(SCENARIOS) + ([TABLE2] if args.with_table2 else [])
-    rows = table(args.realizations, scen, args.n_max, PREC_F32 if args.fp32 else PREC_F64)
+    rows = table(args.realizations, scen, args.n_max, PREC_F32 if args.fp32 else PREC_F64,
+                 log=lambda *a: print(*a, flush=True))
     if args.out:
         with open(args.out, "w") as fh:
             json.dump(rows, fh, indent=1)
