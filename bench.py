@@ -225,17 +225,41 @@ def time_to_target(torch, ntf, Xd, H0, T, arms, dev, star, max_outer=400, tol=1e
             trace.append((it, total_ms, r))
             if (r - rfe_star) / rfe_star <= tol:
                 hit = (it, total_ms, r)
+        taken = None
+        if warm and arm in warm:
+            # (untimed, after the run) rows the judge started from the network in one more step
+            taken = [int(v) for v in solver.step(stats=True)["warm_taken"]]
         res[arm] = {"reached": hit is not None, "outer_iters": hit[0] if hit else None,
                     "ms": hit[1] if hit else None, "init_and_first_step_ms": init_ms,
                     "rfe": r, "rel_to_star": (r - rfe_star) / rfe_star,
                     "rel_before": ((trace[-2][2] - rfe_star) / rfe_star) if len(trace) > 1 else None,
                     "trace_every_10": [t for t in trace if t[0] % 10 == 0 or t[0] == 1]}
+        if taken is not None:
+            res[arm]["warm_rows_taken_next_step"] = taken
         log(f"[bench] ttt {arm}: " + (f"{hit[0]} outer iterations, {hit[1]:.1f} ms" if hit else
                                        f"not reached in {max_outer} (rel {(r - rfe_star) / rfe_star:.2e})"))
         solver.close()
         del solver, H
         torch.cuda.empty_cache()
     return res
+
+
+def warm_arm(torch, ntf, log):
+    """The F = 64 warm-start network for the mixed arm, trained by the
+    library's kernels on pairs from small planted tensors of the same kind."""
+    import ctypes
+    from paper_1409_2383_amd import _lib, warmstart as ws
+    t0 = time.perf_counter()
+    net = ws.train_rank64(log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    st = net.struct(True)
+
+    def attach(solver):
+        _lib.check(_lib.lib().ntf_admm_set_warmstart(solver._ctx, ctypes.byref(st)),
+                   "set_warmstart", solver._ctx)
+    return {"mixed+mlp": {"hidden": net.hidden, "attach": attach, "setup_ms": 0.0,
+                          "net": net}}, train_s
 
 
 PASS_KERNELS = {"pass1": "k_pass1", "mode2": "k_mode2", "pass3": "k_pass3"}
@@ -314,13 +338,14 @@ def write_kernel_stats(stats_csv, workload, arm, cmd):
 
 def summarize(args):
     wl = WORKLOADS[args.workload]
-    arm = wl["arms"][0]
+    arm = args.arm or wl["arms"][0]
     if args.write_kernel_stats:
         # the traced run's own flags: pass the same --steps/--warmup/--pass-reps here
         cmd = (f"rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- python3 "
                f"<repo>/bench.py --workload {args.workload} --steps {args.steps} --warmup {args.warmup} "
                f"--pass-reps {args.pass_reps} --no-cpu-baseline"
-               + ("" if args.workload in ("s1", "n4") else " --single-arm"))
+               + ("" if args.workload in ("s1", "n4") else
+                  (f" --arm {args.arm}" if args.arm else " --single-arm")))
         write_kernel_stats(args.write_kernel_stats, args.workload, arm, cmd)
     if args.write_traffic:
         import paper_1409_2383_amd as ntf
@@ -660,7 +685,11 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also launch a known-size copy kernel (for byte-counter scaling)")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time to rel fit 1e-4")
+    ap.add_argument("--ttt-warm", action="store_true",
+                    help="also time the mixed arm with the learned warm start (trains the F = 64 "
+                         "network first; its training time is reported, not counted)")
     ap.add_argument("--single-arm", action="store_true")
+    ap.add_argument("--arm", default="", help="run this arm only (e.g. fp32, mixed)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into profiles/ and exit")
     ap.add_argument("--write-kernel-stats", metavar="STATS_CSV",
@@ -703,6 +732,10 @@ def main():
     log(f"[bench] data ready in {time.perf_counter() - t0:.1f} s")
 
     arms = wl["arms"][:1] if args.single_arm else wl["arms"]
+    if args.arm:
+        if args.arm not in wl["arms"]:
+            raise SystemExit(f"arm {args.arm} not in {wl['arms']}")
+        arms = (args.arm,)
     results = {}
     for arm in arms:
         solver, H = make_solver(ntf, torch, Xd, H0, arm, T, dev)
@@ -756,13 +789,21 @@ def main():
         cpu = cpu_baseline(pt.X, H0, T, slabs)
 
     ttt = None
-    if not args.no_ttt and args.workload == "c3" and not args.single_arm:
+    if not args.no_ttt and args.workload == "c3" and not args.single_arm and not args.arm:
         star = load_rfe_star(args.workload)
         if star is None:
             log("[bench] no stored oracle RFE*: time to target skipped")
         else:
+            arms_t, warm = ("mixed", "fp32"), None
+            if args.ttt_warm:
+                warm, train_s = warm_arm(torch, ntf, log)
+                arms_t = ("mixed", "mixed+mlp", "fp32")
             log("[bench] time to rel fit 1e-4")
-            ttt = time_to_target(torch, ntf, Xd, H0, T, ("mixed", "fp32"), dev, star)
+            ttt = time_to_target(torch, ntf, Xd, H0, T, arms_t, dev, star, warm=warm)
+            if warm:
+                ttt["mixed+mlp"]["network"] = {"F": 64, "hidden": 256, "train_s": train_s,
+                                               "note": "trained once on 64 small planted tensors "
+                                                       "(not counted in the time)"}
 
     dtype = {"mixed": "bf16", "fp32": "f32", "fp64": "f64"}[head]
     line = {

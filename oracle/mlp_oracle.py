@@ -134,15 +134,24 @@ def kkt_violation(G, W, Hr):
     return np.linalg.norm(np.minimum(Hr, Hr @ G - W), axis=1)
 
 
+def natural_residual(G, W, Hr, rho):
+    """||min(h, (h G - w) / rho)|| per row: the KKT violation of one row's
+    NNLS (eq. KKT_NTF with Y = -rho U, so rho u = h G - w) in the units of h.
+    It is h - max(0, h - (h G - w)/rho), the change one projected-gradient
+    step of length 1/rho would make, zero exactly at the row's solution."""
+    return np.linalg.norm(np.minimum(Hr, (Hr @ G - W) / rho), axis=1)
+
+
 def warm_start(p, G, W, rho, H_prev, U_prev, Hid: int = 256):
     """Per row: the MLP candidate (h, u with u = max(0, (hG - w)/rho) on the
     zero set of h) or the previous iterate, whichever has the smaller KKT
-    violation (ties keep the previous iterate)."""
+    violation in the units of h (natural_residual; ties keep the previous
+    iterate)."""
     h = predict_rows(p, G, W, rho, Hid)
     g = h @ G - W
     u = np.where(h > 0, 0.0, np.maximum(g / rho, 0.0))
-    k_new = kkt_violation(G, W, h)
-    k_old = kkt_violation(G, W, H_prev)
+    k_new = natural_residual(G, W, h, rho)
+    k_old = natural_residual(G, W, H_prev, rho)
     take = k_new < k_old
     Hs = np.where(take[:, None], h, H_prev)
     Us = np.where(take[:, None], u, U_prev)

@@ -22,8 +22,125 @@ __global__ __launch_bounds__(256) void k_inner(InnerK a) {
   inner_body<HT, FL>(a, (int64_t)blockIdx.x, smem_raw, (int)threadIdx.x);
 }
 
+// Value of lane l's v (wave-uniform l) in every lane.
+static __device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Register form of the inner sweep for 33 <= F <= 64 (FL = 64), used when
+// no Gram partial is fused and the projection is row-wise: one row per wave
+// (the same rows per block, 4, as k_inner at FL = 64), lane f holding column f
+// of Ginv (= row f, Ginv is symmetric) in 64 FP64 registers.  The right-hand
+// side of the row is read from its lanes with lane reads, so an inner
+// iteration touches neither LDS nor a barrier; the mat-vec keeps four
+// interleaved partial sums (g = 0 mod 4, 1 mod 4, ...) to shorten the
+// dependent FMA chain.  Loads, projections, stop test, stores and residual
+// partials are those of inner_body.
+template <typename HT>
+__global__ __launch_bounds__(256) void k_inner_reg64(InnerK a) {
+  const int tid = threadIdx.x, f = tid & 63, wave = tid >> 6;
+  const int F = a.F;
+  const int64_t bid = blockIdx.x;
+  const int64_t row = bid * 4 + wave;
+  const bool act = (row < a.rows) && (f < F);
+  __shared__ double red[4][8];
+  double gc[64];
+#pragma unroll
+  for (int r = 0; r < 64; ++r) gc[r] = (r < F && f < F) ? a.Ginv[r * F + f] : 0.0;
+  const double rho = a.rho[0];
+  const double uscale = (a.rescale && a.rho[1] > 0.0) ? a.rho[1] / rho : 1.0;
+  const double g1f = (a.proj == 2 && f < F) ? a.Ginv[F * F + f] : 0.0;
+  const double inv_1g1 = (a.proj == 2) ? 1.0 / a.Ginv[F * F + F] : 0.0;
+  double w = 0.0, h = 0.0, u = 0.0, x = 0.0;
+  if (act) {
+    const int64_t off = row * a.rowstride + f;
+    double sw = 0.0;
+    if (a.part_f64) {
+      const double* p = reinterpret_cast<const double*>(a.part) + off;
+#pragma unroll 8
+      for (int t = 0; t < a.nparts; ++t) sw += p[t * a.pstride];
+    } else {
+      const float* p = reinterpret_cast<const float*>(a.part) + off;
+#pragma unroll 8
+      for (int t = 0; t < a.nparts; ++t) sw += (double)p[t * a.pstride];
+    }
+    w = sw;
+    if (a.Wout) a.Wout[row * F + f] = sw;
+    h = (double)reinterpret_cast<const HT*>(a.H)[row * F + f];
+    u = (double)reinterpret_cast<const HT*>(a.U)[row * F + f] * uscale;
+  }
+  const double h0 = h;
+  bool done = row >= a.rows;
+  int iters = 0;
+  const bool early = (a.eps_abs > 0.0) || (a.eps_rel > 0.0);
+  const double sqF = sqrt((double)F);
+  for (int t = 0; t < a.T && !done; ++t) {   // (done is uniform over the wave)
+    const double b = act ? w + rho * (h + u) : 0.0;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 64; ++r) s4[r & 3] += gc[r] * lane_value(b, r);
+    double xn = (s4[0] + s4[1]) + (s4[2] + s4[3]);   // x = (G + rho I)^{-1} b
+    if (a.proj == 2) {
+      const double sx = group_sum(xn, 64);
+      xn -= g1f * ((sx - 1.0) * inv_1g1);
+    }
+    const double v = xn - u;
+    const double hn = (a.proj == 1) ? fmin(fmax(v, a.lo), a.hi) : ((v > 0.0) ? v : 0.0);
+    const double un = hn - v;
+    const double dh = hn - h;
+    h = act ? hn : 0.0;
+    u = act ? un : 0.0;
+    x = act ? xn : 0.0;
+    ++iters;
+    if (early) {
+      const double sp = group_sum((h - x) * (h - x), 64);
+      const double sx = group_sum(x * x, 64);
+      const double sh = group_sum(h * h, 64);
+      const double sd = group_sum(act ? dh * dh : 0.0, 64);
+      const double su = group_sum(u * u, 64);
+      const double tol_p = sqF * a.eps_abs + a.eps_rel * fmax(sqrt(sx), sqrt(sh));
+      const double tol_d = sqF * a.eps_abs + a.eps_rel * rho * sqrt(su);
+      if (sqrt(sp) <= tol_p && rho * sqrt(sd) <= tol_d) done = true;
+    }
+  }
+  double qs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (act) {
+    if (!isfinite(x) || !isfinite(w)) atomicOr(a.flag, 1);
+    reinterpret_cast<HT*>(a.H)[row * F + f] = (HT)h;
+    reinterpret_cast<HT*>(a.U)[row * F + f] = (HT)u;
+    if (a.Pout) reinterpret_cast<HT*>(a.Pout)[row * F + f] = (HT)x;
+    if (a.iters_out && f == 0) a.iters_out[row] = iters;
+    const double hv = (double)(HT)h, xv = (double)(HT)x, uv = (double)(HT)u;
+    qs[0] = (hv - xv) * (hv - xv);
+    qs[1] = (hv - h0) * (hv - h0);
+    qs[2] = hv * hv;
+    qs[3] = xv * xv;
+    qs[4] = uv * uv;
+    if (f == 0) qs[5] = (double)iters;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double sum = group_sum(qs[k], 64);
+    if (f == 0) red[wave][k] = sum;
+  }
+  __syncthreads();
+  if (a.resid_part) {
+    if (tid < 6) a.resid_part[bid * 8 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    if (tid == 6 || tid == 7) a.resid_part[bid * 8 + tid] = 0.0;
+  }
+}
+
 template <typename HT, int FL>
 static hipError_t inner_launch(const InnerK& k, int nblk, hipStream_t s) {
+  if constexpr (FL == 64) {
+    if (!k.gram_part && (k.proj == 0 || k.proj == 1 || k.proj == 2)) {
+      hipLaunchKernelGGL((k_inner_reg64<HT>), dim3(nblk), dim3(256), 0, s, k);
+      return hipGetLastError();
+    }
+  }
   const size_t lds = (size_t)(FL * FL + 2 * inner_rows_per_block<FL>() * (FL + 1)) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_inner<HT, FL>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

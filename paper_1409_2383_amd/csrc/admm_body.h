@@ -369,24 +369,37 @@ struct PrepK {
   double* gram_scratch;
 };
 
-// LDS of prep_body: G [64][65], row/column broadcast buffers (two rows and
-// two columns, double buffered), a reduction buffer, rho and the failure flag.
-constexpr int kPrepLdsDoubles = 64 * 65 + 512 + 256 + 256 + 2;
+// LDS of prep_body: S [64][65] (G + rho I, inverted in place), the blocks
+// D_J = P S_KJ of one block step [3][16][17], a reduction buffer, rho and the
+// failure flag.
+constexpr int kPrepLdsDoubles = 64 * 65 + 3 * 16 * 17 + 256 + 2;
 
 // Second half of the prepare step, run by one block of 256 threads: G =
-// gram_a (*) gram_b, the penalty, L^{-1} by one elimination sweep, and
-// Ginv = L^{-T} L^{-1} = (G + rho I)^{-1}.  `lds`
-// holds kPrepLdsDoubles doubles.  Also called per work item by the batched
-// persistent kernel.
+// gram_a (*) gram_b, the penalty, and Ginv = (G + rho I)^{-1} by in-place
+// Gauss-Jordan inversion in 16 x 16 blocks.  `lds` holds kPrepLdsDoubles
+// doubles.  Also called per work item by the batched persistent kernel.
+//
+// Block step K (S padded with the identity to 16 NB x 16 NB):
+//   P = S_KK^{-1}                 (one wave: 16 scalar pivots in registers)
+//   D_J = P S_KJ                  (J != K)
+//   S_IJ -= S_IK D_J,  S_IK <- -S_IK P   (I, J != K)
+//   S_KJ <- D_J,  S_KK <- P
+// which leaves S^{-1} after the last step.  No pivoting: the pivots are the
+// diagonal entries of successive Schur complements of the symmetric positive
+// definite S, so a pivot that is not positive and finite means S is not
+// (numerically) positive definite: the failure flag is set and Ginv is zero.
+// The serial part is 16 NB scalar pivots inside one wave (lane shuffles, no
+// barriers); everything else is four barriers per block step.
 template <int NB>
 __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int tid) {
+  constexpr int LD = 65;
   const int F = a.F;
-  double* Gs = lds;                                   // [64][65]
-  double (*rowbuf)[2][128] = reinterpret_cast<double (*)[2][128]>(lds + 64 * 65);       // [2][2][128]
-  double (*colbuf)[2][64] = reinterpret_cast<double (*)[2][64]>(lds + 64 * 65 + 512);   // [2][2][64]
-  double* sred = lds + 64 * 65 + 512 + 256;           // [256]
+  double* S = lds;                                    // [64][65]
+  double* Dt = lds + 64 * LD;                         // [3][16][17]
+  double* sred = Dt + 3 * 16 * 17;                    // [256]
   double& rho_sh = sred[256];
   int& bad_sh = *reinterpret_cast<int*>(&sred[257]);
+  constexpr int N = 16 * NB;
 
   {
     double ga[NB * NB], gb[NB * NB];
@@ -402,9 +415,14 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
       if (e < F * F) {
         const int r = e / F, c = e - r * F;
         const double gv = ga[q] * gb[q];
-        Gs[r * 65 + c] = gv;
+        S[r * LD + c] = gv;
         if (a.G_out) a.G_out[e] = gv;
       }
+    }
+    // identity padding of the rows and columns past F (up to 16 NB)
+    for (int e = tid; e < N * N; e += 256) {
+      const int r = e / N, c = e - r * N;
+      if (r >= F || c >= F) S[r * LD + c] = (r == c) ? 1.0 : 0.0;
     }
   }
   if (tid == 0) {
@@ -413,216 +431,141 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
   }
   __syncthreads();
 
-  // penalty
-  if (tid == 0) {
-    const double rho_prev = a.rho_state[0];
-    double rho;
-    if (a.policy == 0) {
-      double tr = 0.0;
-#pragma unroll 8
-      for (int f = 0; f < F; ++f) tr += Gs[f * 65 + f];
-      rho = tr / F;
-      if (!(rho > 0.0) || !isfinite(rho)) rho = a.rho0;
-    } else if (a.policy == 1) {
-      rho = a.rho0;
-    } else {
-      rho = rho_prev > 0.0 ? rho_prev : a.rho0;
-      if (a.fresh_mode && *a.fresh_mode) {
-        const double prim = sqrt(a.resid_mode[0]);
-        const double dual = rho * sqrt(a.resid_mode[1]);
-        if (prim > a.mu * dual) rho = rho * a.tau_incr;
-        else if (dual > a.mu * prim) rho = rho / a.tau_decr;
-        *a.fresh_mode = 0;
-      }
-    }
-    a.rho_state[1] = (rho_prev > 0.0) ? rho_prev : rho;
-    a.rho_state[0] = rho;
-    rho_sh = rho;
-  }
-  __syncthreads();
-  const double rho = rho_sh;
-
-  // One elimination sweep over the augmented matrix [G + rho I | I]: row k is
-  // divided by sqrt(a_kk) and a_ik / a_kk times the unscaled row k is
-  // subtracted from every row i > k.  The left block becomes L^T and the
-  // right block L^{-1} (L the Cholesky factor), i.e. the factorisation and
-  // the triangular inverse in F steps.  Thread (ti,tj) owns rows ti+16a and
-  // columns tj+16b of both blocks.  Steps k and k+1 share one barrier: rows
-  // k, k+1 and columns k, k+1 as they stand before step k are broadcast
-  // through LDS (double buffered), and every thread forms from them the
-  // values step k leaves in row k+1 and column k+1 (c = a_{k+1,k} / a_kk,
-  // row k+1 - c row k, a_{i,k+1} - (a_ik / a_kk) a_{k,k+1}) with the same
-  // products and fused multiply-adds as the owners would, so the result is
-  // that of the step-by-step sweep, bit for bit.
-  const int ti = tid >> 4, tj = tid & 15;
-  double rl[NB][NB], rr[NB][NB];
-#pragma unroll
-  for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-    for (int ib = 0; ib < NB; ++ib) {
-      const int i = ti + 16 * ia, j = tj + 16 * ib;
-      double v;
-      if (i < F && j < F) v = Gs[i * 65 + j] + ((i == j) ? rho : 0.0);
-      else v = (i == j) ? 1.0 : 0.0;
-      rl[ia][ib] = v;
-      rr[ia][ib] = (i == j) ? 1.0 : 0.0;
-    }
-#pragma unroll
-  for (int kb = 0; kb < NB; ++kb) {
-    for (int kk = 0; kk < 16; kk += 2) {
-      const int k = 16 * kb + kk;
-      if (k >= F) break;
-      const bool two = k + 1 < F;
-      const int buf = (kk >> 1) & 1;
-      if (ti == kk || ti == kk + 1) {
-        const int w = ti - kk;
-#pragma unroll
-        for (int ib = 0; ib < NB; ++ib) {
-          rowbuf[buf][w][tj + 16 * ib] = rl[kb][ib];
-          rowbuf[buf][w][64 + tj + 16 * ib] = rr[kb][ib];
-        }
-      }
-      if (tj == kk || tj == kk + 1) {
-        const int w = tj - kk;
-#pragma unroll
-        for (int ia = 0; ia < NB; ++ia) colbuf[buf][w][ti + 16 * ia] = rl[ia][kb];
-      }
-      __syncthreads();
-      // (every LDS read of the pair is issued here, before any branch)
-      double akk = rowbuf[buf][0][k];
-      const double ak_k1 = rowbuf[buf][0][k + 1];   // a_{k,k+1}
-      const double ak1_k1 = rowbuf[buf][1][k + 1];  // a_{k+1,k+1}
-      const double ak1_k = colbuf[buf][0][k + 1];   // a_{k+1,k}
-      double rkl[NB], rkr[NB], r1l[NB], r1r[NB], cm[NB], cm1[NB];
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        rkl[ib] = rowbuf[buf][0][tj + 16 * ib];
-        rkr[ib] = rowbuf[buf][0][64 + tj + 16 * ib];
-        r1l[ib] = rowbuf[buf][1][tj + 16 * ib];
-        r1r[ib] = rowbuf[buf][1][64 + tj + 16 * ib];
-      }
-#pragma unroll
-      for (int ia = 0; ia < NB; ++ia) {
-        cm[ia] = colbuf[buf][0][ti + 16 * ia];
-        cm1[ia] = colbuf[buf][1][ti + 16 * ia];
-      }
-      if (!(akk > 0.0) || !isfinite(akk)) {
-        if (tid == 0) bad_sh = 1;
-        akk = 1.0;
-      }
-      const double inv = 1.0 / akk;
-      const double sc = 1.0 / sqrt(akk);
-      // step k applied to row k+1: its pivot and its values at my columns
-      const double c = ak1_k * inv;
-      double d2 = ak1_k1 - c * ak_k1;
-      if (two && (!(d2 > 0.0) || !isfinite(d2))) {
-        if (tid == 0) bad_sh = 1;
-        d2 = 1.0;
-      }
-      const double inv2 = 1.0 / d2;
-      const double sc2 = 1.0 / sqrt(d2);
-      double ul[NB], ur[NB];
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        ul[ib] = r1l[ib] - c * rkl[ib];
-        ur[ib] = r1r[ib] - c * rkr[ib];
-      }
-#pragma unroll
-      for (int ia = 0; ia < NB; ++ia) {
-        const int i = ti + 16 * ia;
-        if (i == k) {
-#pragma unroll
-          for (int ib = 0; ib < NB; ++ib) {
-            rl[ia][ib] = rkl[ib] * sc;
-            rr[ia][ib] = rkr[ib] * sc;
-          }
-        } else if (two && i == k + 1) {
-#pragma unroll
-          for (int ib = 0; ib < NB; ++ib) {
-            rl[ia][ib] = ul[ib] * sc2;
-            rr[ia][ib] = ur[ib] * sc2;
-          }
-        } else if (i > k && i < F) {
-          const double m = cm[ia] * inv;
-#pragma unroll
-          for (int ib = 0; ib < NB; ++ib) {
-            rl[ia][ib] -= m * rkl[ib];
-            rr[ia][ib] -= m * rkr[ib];
-          }
-          if (two) {
-            const double m2 = (cm1[ia] - m * ak_k1) * inv2;
-#pragma unroll
-            for (int ib = 0; ib < NB; ++ib) {
-              rl[ia][ib] -= m2 * ul[ib];
-              rr[ia][ib] -= m2 * ur[ib];
-            }
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  const bool bad = bad_sh != 0;
-  // Ginv = L^{-T} L^{-1} = (G + rho I)^{-1}: L^{-1} (lower triangular) goes
-  // through LDS, where G is no longer needed, and every thread forms its
-  // elements as sums over k in increasing order
-#pragma unroll
-  for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-    for (int ib = 0; ib < NB; ++ib) {
-      const int i = ti + 16 * ia, j = tj + 16 * ib;
-      if (i < F && j < F) Gs[i * 65 + j] = (j <= i) ? rr[ia][ib] : 0.0;
-    }
-  __syncthreads();
-  {
-    // k outermost: the NB x NB sums of a thread advance together (entries of
-    // L^{-1} above the diagonal are zero; rows/columns >= F are not read)
-    double m[NB][NB];
-#pragma unroll
-    for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) m[ia][ib] = 0.0;
-    for (int k = 0; k < F; ++k) {
-      double li[NB], lj[NB];
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        li[q] = (ti + 16 * q <= k) ? Gs[k * 65 + ti + 16 * q] : 0.0;
-        lj[q] = (tj + 16 * q <= k) ? Gs[k * 65 + tj + 16 * q] : 0.0;
-      }
-#pragma unroll
-      for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-        for (int ib = 0; ib < NB; ++ib) m[ia][ib] += li[ia] * lj[ib];
-    }
-#pragma unroll
-    for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        const int i = ti + 16 * ia, j = tj + 16 * ib;
-        if (i < F && j < F) a.Ginv[i * F + j] = bad ? 0.0 : m[ia][ib];
-      }
-    // Ginv 1 and 1^T Ginv 1 (the sum-to-one least-squares step uses them):
-    // Ginv through LDS, row sums in increasing column order
-    __syncthreads();
-#pragma unroll
-    for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        const int i = ti + 16 * ia, j = tj + 16 * ib;
-        if (i < F && j < F) Gs[i * 65 + j] = bad ? 0.0 : m[ia][ib];
-      }
-    __syncthreads();
-    if (tid < F) {
-      double r = 0.0;
-      for (int j = 0; j < F; ++j) r += Gs[tid * 65 + j];
-      a.Ginv[F * F + tid] = r;
-      sred[tid] = r;
-    }
-    __syncthreads();
+  // penalty (the trace summed by one wave)
+  if (tid < 64) {
+    double tr = 0.0;
+    if (a.policy == 0) tr = group_sum(tid < F ? S[tid * LD + tid] : 0.0, 64);
     if (tid == 0) {
-      double t = 0.0;
-      for (int f = 0; f < F; ++f) t += sred[f];
-      a.Ginv[F * F + F] = t;
+      const double rho_prev = a.rho_state[0];
+      double rho;
+      if (a.policy == 0) {
+        rho = tr / F;
+        if (!(rho > 0.0) || !isfinite(rho)) rho = a.rho0;
+      } else if (a.policy == 1) {
+        rho = a.rho0;
+      } else {
+        rho = rho_prev > 0.0 ? rho_prev : a.rho0;
+        if (a.fresh_mode && *a.fresh_mode) {
+          const double prim = sqrt(a.resid_mode[0]);
+          const double dual = rho * sqrt(a.resid_mode[1]);
+          if (prim > a.mu * dual) rho = rho * a.tau_incr;
+          else if (dual > a.mu * prim) rho = rho / a.tau_decr;
+          *a.fresh_mode = 0;
+        }
+      }
+      a.rho_state[1] = (rho_prev > 0.0) ? rho_prev : rho;
+      a.rho_state[0] = rho;
+      rho_sh = rho;
+    }
+  }
+  __syncthreads();
+  if (tid < F) S[tid * LD + tid] += rho_sh;
+  __syncthreads();
+
+  const int ta = tid >> 4, tb = tid & 15;   // entry (ta, tb) of a 16 x 16 block
+#pragma unroll 1
+  for (int K = 0; K < NB; ++K) {
+    const int k0 = 16 * K;
+    // P = S_KK^{-1}: lane (r, q) holds S_KK[r][4q .. 4q+3]
+    if (tid < 64) {
+      const int r = tid & 15, q = tid >> 4;
+      double x[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[c] = S[(k0 + r) * LD + k0 + 4 * q + c];
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int pq = p >> 2, pc = p & 3;
+        double piv = __shfl(x[pc], p + 16 * pq);
+        const double arp = __shfl(x[pc], r + 16 * pq);
+        double apc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) apc[c] = __shfl(x[c], p + 16 * q);
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          if (tid == 0) bad_sh = 1;
+          piv = 1.0;
+        }
+        const double inv = 1.0 / piv;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int col = 4 * q + c;
+          if (r == p) x[c] = (col == p) ? inv : apc[c] * inv;
+          else x[c] = (col == p) ? -arp * inv : x[c] - arp * (apc[c] * inv);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) S[(k0 + r) * LD + k0 + 4 * q + c] = x[c];
+    }
+    __syncthreads();
+    // D_J = P S_KJ for the other blocks J (slot m = J - (J > K))
+#pragma unroll
+    for (int J = 0; J < NB; ++J) {
+      if (J == K) continue;
+      const int m = J - (J > K ? 1 : 0);
+      double d = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) d += S[(k0 + ta) * LD + k0 + t] * S[(k0 + t) * LD + 16 * J + tb];
+      Dt[m * 16 * 17 + ta * 17 + tb] = d;
+    }
+    __syncthreads();
+    // S_IJ -= S_IK D_J and -S_IK P (kept in registers until every read of S_IK is done)
+    double nik[NB];
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+      nik[I] = 0.0;
+      if (I == K) continue;
+      double sik[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) sik[t] = S[(16 * I + ta) * LD + k0 + t];
+#pragma unroll
+      for (int J = 0; J < NB; ++J) {
+        if (J == K) continue;
+        const int m = J - (J > K ? 1 : 0);
+        double acc = S[(16 * I + ta) * LD + 16 * J + tb];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc -= sik[t] * Dt[m * 16 * 17 + t * 17 + tb];
+        S[(16 * I + ta) * LD + 16 * J + tb] = acc;
+      }
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) v += sik[t] * S[(k0 + t) * LD + k0 + tb];
+      nik[I] = -v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+      if (I == K) continue;
+      const int m = I - (I > K ? 1 : 0);
+      S[(16 * I + ta) * LD + k0 + tb] = nik[I];
+      S[(k0 + ta) * LD + 16 * I + tb] = Dt[m * 16 * 17 + ta * 17 + tb];
+    }
+    __syncthreads();
+  }
+  const bool bad = bad_sh != 0;
+  // Ginv (symmetrised), Ginv 1 and 1^T Ginv 1 (the sum-to-one least-squares
+  // step uses them): thread t sums a quarter of row t / 4
+  {
+    const int i = tid >> 2, c0 = (tid & 3) * 16;
+    double rs = 0.0;
+    if (i < F) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int j = c0 + c;
+        if (j < F) {
+          const double v = bad ? 0.0 : 0.5 * (S[i * LD + j] + S[j * LD + i]);
+          a.Ginv[i * F + j] = v;
+          rs += v;
+        }
+      }
+    }
+    rs = group_sum(rs, 4);
+    if ((tid & 3) == 0) {
+      if (i < F) a.Ginv[F * F + i] = rs;
+      sred[i] = (i < F) ? rs : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const double tot = group_sum(sred[tid], 64);
+      if (tid == 0) a.Ginv[F * F + F] = tot;
     }
     __syncthreads();   // sred is reused below
   }

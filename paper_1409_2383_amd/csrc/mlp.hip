@@ -218,8 +218,9 @@ __global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ s
 
 // Judge: per row, candidate h = y * scale (y the network output), u = 0 where
 // h > 0 and max(0, (hG - w)/rho) where h = 0; keep it if its NNLS KKT
-// violation ||min(h, hG - w)|| is smaller than the previous iterate's,
-// otherwise keep (H, U).  One lane group of FL lanes per row.  `uback`
+// violation in the units of h, ||min(h, (hG - w)/rho)|| (the change one
+// projected-gradient step of length 1/rho would make; zero exactly at the
+// solution), is smaller than the previous iterate's, otherwise keep (H, U).  One lane group of FL lanes per row.  `uback`
 // converts a written u to the scale the inner kernel expects on load.
 template <typename HT, int FL>
 __global__ __launch_bounds__(256) void k_judge(const float* __restrict__ Y,
@@ -258,8 +259,9 @@ __global__ __launch_bounds__(256) void k_judge(const float* __restrict__ Y,
   }
   gn -= w;
   go -= w;
-  const double kn = act ? fmin(hn, gn) : 0.0;
-  const double ko = act ? fmin(hp, go) : 0.0;
+  // KKT violation in the units of h: min(h, (hG - w) / rho)
+  const double kn = act ? fmin(hn, gn / rho) : 0.0;
+  const double ko = act ? fmin(hp, go / rho) : 0.0;
   const double sn = group_sum(kn * kn, FL);
   const double so = group_sum(ko * ko, FL);
   if (act && sn < so) {

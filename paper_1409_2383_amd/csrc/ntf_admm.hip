@@ -1330,7 +1330,10 @@ ntf_status ntf_inner_update(const double* W, void* H, void* U, int64_t rows, int
   ia.eps_abs = eps_abs;
   ia.eps_rel = eps_rel;
   ia.iters_out = iters_out;
-  ia.gram_part = reinterpret_cast<double*>(base + w.gpart);
+  // (the Gram and residual partials are not outputs of this call: no fused
+  // Gram partial, so both this call and ntf_inner_update_noalloc take the
+  // same kernel)
+  ia.gram_part = nullptr;
   ia.resid_part = reinterpret_cast<double*>(base + w.rpart);
   ia.flag = &ds->flag;
   const int rpb = inner_rows_per_block(FL);

@@ -8,6 +8,7 @@ wrote it.
     python tests/golden/make_golden.py c2       # 400^3, F = 20, FP32 data, 200 outer iterations
     python tests/golden/make_golden.py c3       # 1000 x 800 x 600, F = 64: converged RFE*
     python tests/golden/make_golden.py c5       # 16 tensors of the 256-tensor batch
+    python tests/golden/make_golden.py c5mixed  # the same with the batch's bf16 operand rounding
     python tests/golden/make_golden.py mixed    # 80 x 70 x 60, F = 12: exact and bf16-operand runs
 
 The c3 run needs ~12 GB of host memory and some tens of minutes; the others
@@ -152,6 +153,36 @@ def golden_c5(args):
             "outer_iters": outer, "tensors": out})
 
 
+def golden_c5_mixed(args):
+    """The same 16 tensors, the same start and T, but the MTTKRPs with the
+    batched path's operand rounding (per-slab bf16 X, bf16 C for modes 1-2,
+    B as two bf16 terms for mode 3; exact accumulation, FP64 otherwise)."""
+    outer = args.outer or 300
+    out = []
+    for t, dims, F, seed in c5_subset():
+        pt = ntf_synth.planted(dims, F, seed, snr_db=20.0, dtype=np.float32)
+        H0 = ntf_synth.init_factors(dims, F, seed, dtype=np.float32)
+        X = pt.X.astype(np.float64)
+        xn2 = _xnorm2(X)
+        st = orc.init_state([h.astype(np.float64) for h in H0])
+        opts = orc.Opts(inner_iters=10, mttkrp_operands="bf16_split")
+        trace = []
+        t0 = time.perf_counter()
+        for k in range(1, outer + 1):
+            orc.outer_step(pt.X, st, opts)
+            if k % 10 == 0:
+                trace.append([k, orc.rfe_expanded(X, st.H, xn2)])
+        print(f"c5 mixed tensor {t} {dims} F={F}: RFE {trace[-1][1]:.9f} after {outer} "
+              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+        out.append({"tensor": t, "dims": list(dims), "F": F, "seed": seed, "rfe_trace": trace})
+        del pt, X
+        _write("c5_subset16_mixed.json", {
+            "workload": "first 16 tensors of the 256-tensor batch (modes U{50..500}, F U{5..40}, "
+                        "U[0,1] factors, 20 dB), FP32 data and start, FP64 method with the batched "
+                        "path's bf16 operand rounding of the MTTKRPs, T=10, rho=tr(G)/F",
+            "outer_iters": outer, "tensors": out})
+
+
 def golden_mixed(args):
     """80 x 70 x 60, F = 12 Exponential(1) planted factors, 30 dB, T = 10:
     the exact method and the same method with the bfloat16 operand rounding
@@ -184,10 +215,11 @@ def golden_mixed(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c3", "c5", "mixed"])
+    ap.add_argument("which", choices=["c2", "c3", "c5", "c5mixed", "mixed"])
     ap.add_argument("--outer", type=int, default=0)
     args = ap.parse_args()
-    {"c2": golden_c2, "c3": golden_c3, "c5": golden_c5, "mixed": golden_mixed}[args.which](args)
+    {"c2": golden_c2, "c3": golden_c3, "c5": golden_c5, "c5mixed": golden_c5_mixed,
+     "mixed": golden_mixed}[args.which](args)
 
 
 if __name__ == "__main__":

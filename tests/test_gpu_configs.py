@@ -92,3 +92,55 @@ def test_config2_fit_after_200_iterations(dev, c2):
           f"relative {err:.2e}", flush=True)
     assert err <= 1e-6
     s.close()
+
+
+def test_config5_subset_fit_against_oracle(dev):
+    """The first 16 tensors of the 256-tensor batch, run together by the batched
+    solver (mixed precision, T = 10) for the stored number of outer
+    iterations, against two oracle runs from the same float32 start
+    (tests/golden/c5_subset16*.json, written by tests/golden/make_golden.py):
+
+    * the oracle with the batched path's operand rounding (bf16 X per slab,
+      bf16 C, B as two bf16 terms; exact accumulation): every tensor's RFE
+      within 1e-5 relative (what is left is FP32 accumulation);
+    * the exact FP64 oracle: every tensor's RFE gap within 1e-4 relative (the
+      headline target) or, where the operand rounding itself settles farther
+      from the exact fit, within 1.5x the rounded oracle's own gap plus 1e-6.
+    """
+    import ntf_synth
+    import paper_1409_2383_amd as ntf
+    path = os.path.join(GOLDEN, "c5_subset16.json")
+    path_m = os.path.join(GOLDEN, "c5_subset16_mixed.json")
+    if not (os.path.exists(path) and os.path.exists(path_m)):
+        pytest.skip("tests/golden/c5_subset16.json and c5_subset16_mixed.json not both written")
+    with open(path) as fh:
+        g = json.load(fh)
+    with open(path_m) as fh:
+        gm = json.load(fh)
+    outer = g["outer_iters"]
+    assert gm["outer_iters"] == outer and len(gm["tensors"]) == len(g["tensors"])
+    Xs, Hs, refs, refs_m = [], [], [], []
+    for t, tm in zip(g["tensors"], gm["tensors"]):
+        assert t["seed"] == tm["seed"]
+        dims, F = tuple(t["dims"]), t["F"]
+        pt = ntf_synth.planted(dims, F, t["seed"], snr_db=20.0, dtype=np.float32)
+        H0 = ntf_synth.init_factors(dims, F, t["seed"], dtype=np.float32)
+        Xs.append(torch.from_numpy(pt.X).to(dev))
+        Hs.append(to_dev(H0, dev))
+        refs.append(dict(t["rfe_trace"])[outer])
+        refs_m.append(dict(tm["rfe_trace"])[outer])
+        del pt
+    print(f"[c5] {len(Xs)} tensors of the batch, {outer} outer iterations", flush=True)
+    b = ntf.NtfBatch(Xs, Hs, opts=ntf.AdmmOptions(inner_iters=10, precision=ntf.PREC_BF16_MIXED))
+    b.step(outer)
+    assert b.sync() == 0
+    fits = b.fit()
+    for p, (r, ref, rm) in enumerate(zip(fits, refs, refs_m)):
+        print(f"[c5] tensor {p} {tuple(g['tensors'][p]['dims'])} F={g['tensors'][p]['F']}: "
+              f"RFE {r:.9f}; rounded oracle {rm:.9f} ({(r - rm) / rm:+.2e}); exact oracle "
+              f"{ref:.9f} ({(r - ref) / ref:+.2e}, rounded oracle {(rm - ref) / ref:+.2e})",
+              flush=True)
+    for p, (r, ref, rm) in enumerate(zip(fits, refs, refs_m)):
+        assert abs(r - rm) <= 1e-5 * rm, p
+        assert abs(r - ref) <= max(1e-4 * ref, 1.5 * abs(rm - ref) + 1e-6 * ref), p
+    b.close()
