@@ -22,14 +22,6 @@ __global__ __launch_bounds__(256) void k_inner(InnerK a) {
   inner_body<HT, FL>(a, (int64_t)blockIdx.x, smem_raw, (int)threadIdx.x);
 }
 
-// Value of lane l's v (wave-uniform l) in every lane.
-static __device__ __forceinline__ double lane_value(double v, int l) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
 // Register form of the inner sweep for 33 <= F <= 64 (FL = 64), used when
 // no Gram partial is fused and the projection is row-wise: one row per wave
 // (the same rows per block, 4, as k_inner at FL = 64), lane f holding column f
@@ -81,7 +73,7 @@ __global__ __launch_bounds__(256) void k_inner_reg64(InnerK a) {
     const double b = act ? w + rho * (h + u) : 0.0;
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < 64; ++r) s4[r & 3] += gc[r] * lane_value(b, r);
+    for (int r = 0; r < 64; ++r) s4[r & 3] += gc[r] * lane_value_d(b, r);
     double xn = (s4[0] + s4[1]) + (s4[2] + s4[3]);   // x = (G + rho I)^{-1} b
     if (a.proj == 2) {
       const double sx = group_sum(xn, 64);
@@ -242,6 +234,11 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   __shared__ int is_last;
   __shared__ double prep_lds[kPrepLdsDoubles];
   static_assert(kPrepLdsDoubles >= 64 * 64, "the Gram stage borrows the prepare LDS");
+  static_assert(NB * NB <= 16, "the reduced Gram of a thread feeds prep_body directly");
+  // the inputs that do not depend on this kernel's Gram, loaded before it
+  PrepIn<NB> in;
+  prep_load_b(a, tid, in);
+  bool have_a = false;
   if (a.gram_h) {
     // direct Gram: block b sums rows [b rpp, (b+1) rpp) of the updated factor
     // in FP64; the last block to finish reduces the partials (4 fixed groups)
@@ -294,8 +291,12 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int e = tid + 256 * k;
-      if (e < nent) a.gram_dst[e] = ((gs[0][k] + gs[1][k]) + gs[2][k]) + gs[3][k];
+      const double v = ((gs[0][k] + gs[1][k]) + gs[2][k]) + gs[3][k];
+      if (e < nent) a.gram_dst[e] = v;
+      // (entry e = tid + 256 k of gram_a is the one prep_body takes as ga[k])
+      if (k < NB * NB) in.ga[k] = (e < nent) ? v : 0.0;
     }
+    have_a = (a.gram_a == a.gram_dst);
     __threadfence_block();
     __syncthreads();
   } else if (a.gram_part) {
@@ -328,7 +329,8 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   } else if (blockIdx.x != 0) {
     return;
   }
-  prep_body<NB>(a, prep_lds, tid);
+  if (!have_a) prep_load_a(a, tid, in);
+  prep_body<NB>(a, prep_lds, tid, in);
 }
 
 hipError_t launch_prep(const PrepArgs& pa, int nblk, hipStream_t s) {

@@ -374,10 +374,62 @@ struct PrepK {
 // failure flag.
 constexpr int kPrepLdsDoubles = 64 * 65 + 3 * 16 * 17 + 256 + 2;
 
+// Global inputs of prep_body, loaded into registers ahead of it (the
+// per-problem prepare kernel issues these loads before its Gram phase, so
+// their latency overlaps that work): this thread's entries e = tid + 256 q of
+// gram_a and gram_b, and (thread 0) the penalty state.
+template <int NB>
+struct PrepIn {
+  double ga[NB * NB], gb[NB * NB];
+  double rho_prev, res0, res1;
+  int fresh;
+};
+
+template <int NB>
+__device__ __forceinline__ void prep_load_b(const PrepK& a, const int tid, PrepIn<NB>& in) {
+  const int F = a.F;
+#pragma unroll
+  for (int q = 0; q < NB * NB; ++q) {
+    const int e = tid + 256 * q;
+    in.gb[q] = (e < F * F) ? a.gram_b[e] : 0.0;
+  }
+  in.rho_prev = 0.0;
+  in.res0 = in.res1 = 0.0;
+  in.fresh = 0;
+  if (tid == 0) {
+    in.rho_prev = a.rho_state[0];
+    if (a.policy == 2 && a.fresh_mode) {
+      in.fresh = *a.fresh_mode;
+      in.res0 = a.resid_mode[0];
+      in.res1 = a.resid_mode[1];
+    }
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void prep_load_a(const PrepK& a, const int tid, PrepIn<NB>& in) {
+  const int F = a.F;
+#pragma unroll
+  for (int q = 0; q < NB * NB; ++q) {
+    const int e = tid + 256 * q;
+    in.ga[q] = (e < F * F) ? a.gram_a[e] : 0.0;
+  }
+}
+
+// 1 / x by the hardware reciprocal and two Newton steps (x positive and
+// normal: the pivots of an SPD matrix); within an ulp or two of 1.0 / x.
+static __device__ __forceinline__ double recip_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return r;
+}
+
 // Second half of the prepare step, run by one block of 256 threads: G =
 // gram_a (*) gram_b, the penalty, and Ginv = (G + rho I)^{-1} by in-place
 // Gauss-Jordan inversion in 16 x 16 blocks.  `lds` holds kPrepLdsDoubles
-// doubles.  Also called per work item by the batched persistent kernel.
+// doubles; `in` holds the global inputs (prep_load_a, prep_load_b).  Also
+// called per work item by the batched persistent kernel.
 //
 // Block step K (S padded with the identity to 16 NB x 16 NB):
 //   P = S_KK^{-1}                 (one wave: 16 scalar pivots in registers)
@@ -388,10 +440,11 @@ constexpr int kPrepLdsDoubles = 64 * 65 + 3 * 16 * 17 + 256 + 2;
 // diagonal entries of successive Schur complements of the symmetric positive
 // definite S, so a pivot that is not positive and finite means S is not
 // (numerically) positive definite: the failure flag is set and Ginv is zero.
-// The serial part is 16 NB scalar pivots inside one wave (lane shuffles, no
-// barriers); everything else is four barriers per block step.
+// The serial part is 16 NB scalar pivots inside one wave (lane reads and
+// shuffles, no barriers); everything else is four barriers per block step.
 template <int NB>
-__device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int tid) {
+__device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int tid,
+                                          const PrepIn<NB>& in) {
   constexpr int LD = 65;
   const int F = a.F;
   double* S = lds;                                    // [64][65]
@@ -401,29 +454,20 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
   int& bad_sh = *reinterpret_cast<int*>(&sred[257]);
   constexpr int N = 16 * NB;
 
-  {
-    double ga[NB * NB], gb[NB * NB];
 #pragma unroll
-    for (int q = 0; q < NB * NB; ++q) {
-      const int e = tid + 256 * q;
-      ga[q] = (e < F * F) ? a.gram_a[e] : 0.0;
-      gb[q] = (e < F * F) ? a.gram_b[e] : 0.0;
+  for (int q = 0; q < NB * NB; ++q) {
+    const int e = tid + 256 * q;
+    if (e < F * F) {
+      const int r = e / F, c = e - r * F;
+      const double gv = in.ga[q] * in.gb[q];
+      S[r * LD + c] = gv;
+      if (a.G_out) a.G_out[e] = gv;
     }
-#pragma unroll
-    for (int q = 0; q < NB * NB; ++q) {
-      const int e = tid + 256 * q;
-      if (e < F * F) {
-        const int r = e / F, c = e - r * F;
-        const double gv = ga[q] * gb[q];
-        S[r * LD + c] = gv;
-        if (a.G_out) a.G_out[e] = gv;
-      }
-    }
-    // identity padding of the rows and columns past F (up to 16 NB)
-    for (int e = tid; e < N * N; e += 256) {
-      const int r = e / N, c = e - r * N;
-      if (r >= F || c >= F) S[r * LD + c] = (r == c) ? 1.0 : 0.0;
-    }
+  }
+  // identity padding of the rows and columns past F (up to 16 NB)
+  for (int e = tid; e < N * N; e += 256) {
+    const int r = e / N, c = e - r * N;
+    if (r >= F || c >= F) S[r * LD + c] = (r == c) ? 1.0 : 0.0;
   }
   if (tid == 0) {
     bad_sh = 0;
@@ -436,7 +480,7 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
     double tr = 0.0;
     if (a.policy == 0) tr = group_sum(tid < F ? S[tid * LD + tid] : 0.0, 64);
     if (tid == 0) {
-      const double rho_prev = a.rho_state[0];
+      const double rho_prev = in.rho_prev;
       double rho;
       if (a.policy == 0) {
         rho = tr / F;
@@ -445,9 +489,9 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
         rho = a.rho0;
       } else {
         rho = rho_prev > 0.0 ? rho_prev : a.rho0;
-        if (a.fresh_mode && *a.fresh_mode) {
-          const double prim = sqrt(a.resid_mode[0]);
-          const double dual = rho * sqrt(a.resid_mode[1]);
+        if (in.fresh) {
+          const double prim = sqrt(in.res0);
+          const double dual = rho * sqrt(in.res1);
           if (prim > a.mu * dual) rho = rho * a.tau_incr;
           else if (dual > a.mu * prim) rho = rho / a.tau_decr;
           *a.fresh_mode = 0;
@@ -475,7 +519,7 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
 #pragma unroll
       for (int p = 0; p < 16; ++p) {
         const int pq = p >> 2, pc = p & 3;
-        double piv = __shfl(x[pc], p + 16 * pq);
+        double piv = lane_value_d(x[pc], p + 16 * pq);
         const double arp = __shfl(x[pc], r + 16 * pq);
         double apc[4];
 #pragma unroll
@@ -484,7 +528,7 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
           if (tid == 0) bad_sh = 1;
           piv = 1.0;
         }
-        const double inv = 1.0 / piv;
+        const double inv = recip_pos(piv);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int col = 4 * q + c;
@@ -507,7 +551,17 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
       Dt[m * 16 * 17 + ta * 17 + tb] = d;
     }
     __syncthreads();
-    // S_IJ -= S_IK D_J and -S_IK P (kept in registers until every read of S_IK is done)
+    // S_IJ -= S_IK D_J and -S_IK P (kept in registers until every read of S_IK
+    // is done); column tb of every D_J and of P is read once
+    double dcol[NB][16], pcol[16];
+#pragma unroll
+    for (int J = 0; J < NB; ++J) {
+      const int m = J - (J > K ? 1 : 0);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) dcol[J][t] = (J != K) ? Dt[m * 16 * 17 + t * 17 + tb] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) pcol[t] = S[(k0 + t) * LD + k0 + tb];
     double nik[NB];
 #pragma unroll
     for (int I = 0; I < NB; ++I) {
@@ -519,15 +573,14 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
 #pragma unroll
       for (int J = 0; J < NB; ++J) {
         if (J == K) continue;
-        const int m = J - (J > K ? 1 : 0);
         double acc = S[(16 * I + ta) * LD + 16 * J + tb];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc -= sik[t] * Dt[m * 16 * 17 + t * 17 + tb];
+        for (int t = 0; t < 16; ++t) acc -= sik[t] * dcol[J][t];
         S[(16 * I + ta) * LD + 16 * J + tb] = acc;
       }
       double v = 0.0;
 #pragma unroll
-      for (int t = 0; t < 16; ++t) v += sik[t] * S[(k0 + t) * LD + k0 + tb];
+      for (int t = 0; t < 16; ++t) v += sik[t] * pcol[t];
       nik[I] = -v;
     }
     __syncthreads();

@@ -517,7 +517,10 @@ __device__ __forceinline__ void prep_item(const ConstProb& P, const BatchK& a, i
   k.rho_state = P.rho + 2 * m;
   k.Ginv = P.Ginv;
   k.flag = a.flag;
-  prep_body<NB>(k, reinterpret_cast<double*>(lds), tid);
+  PrepIn<NB> in;
+  prep_load_b(k, tid, in);
+  prep_load_a(k, tid, in);
+  prep_body<NB>(k, reinterpret_cast<double*>(lds), tid, in);
 }
 
 // One function per item family, each loading the fields of the problem's

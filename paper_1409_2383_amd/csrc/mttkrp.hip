@@ -751,6 +751,40 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
 
 // P2[ic][j][f] = sum_{i in chunk ic} A[i][f] * T[i][j][f]; one thread per (j,f),
 // coalesced over the contiguous (j,f) index of each slab of T.
+// FP32 with F a multiple of 4: four consecutive columns per thread (16-byte
+// loads of T and of the A row), the slabs of the partial loaded eight at a
+// time before their products are added in slab order, one fused multiply-add
+// per slab and column as in k_mode2 (so the partials are bitwise the same).
+__global__ __launch_bounds__(256) void k_mode2v(const float4* __restrict__ Tin,
+                                                const float4* __restrict__ Ha, int I, int64_t JF4,
+                                                int F4, int ich, float4* __restrict__ P2) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= JF4) return;
+  const int f4 = (int)(idx % F4);
+  const int ic = blockIdx.y;
+  const int i0 = ic * ich, i1 = min(I, i0 + ich);
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int ib = i0; ib < i1; ib += 8) {
+    float4 tv[8], av[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = min(ib + q, i1 - 1);   // (past the partial's end: loaded, not used)
+      tv[q] = Tin[(int64_t)i * JF4 + idx];
+      av[q] = Ha[(int64_t)i * F4 + f4];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (ib + q < i1) {
+        acc.x = __builtin_fmaf(av[q].x, tv[q].x, acc.x);
+        acc.y = __builtin_fmaf(av[q].y, tv[q].y, acc.y);
+        acc.z = __builtin_fmaf(av[q].z, tv[q].z, acc.z);
+        acc.w = __builtin_fmaf(av[q].w, tv[q].w, acc.w);
+      }
+    }
+  }
+  P2[(int64_t)ic * JF4 + idx] = acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_mode2(const T* __restrict__ Tin, const T* __restrict__ Ha,
                                                int I, int64_t JF, int F, int ich,
@@ -1426,6 +1460,13 @@ hipError_t launch_pass1(const Plan& p, const void* X, const __bf16* Xr, const fl
 
 hipError_t launch_mode2(const Plan& p, const void* Tin, const void* Ha, void* P2, hipStream_t s) {
   const int64_t JF = p.J * p.F;
+  if (p.prec != PREC_F64 && p.F % 4 == 0) {
+    const int64_t JF4 = JF / 4;
+    dim3 grid4((unsigned)cdiv(JF4, 256), (unsigned)p.nich2);
+    hipLaunchKernelGGL(k_mode2v, grid4, dim3(256), 0, s, (const float4*)Tin, (const float4*)Ha,
+                       (int)p.I, JF4, p.F / 4, p.ich2, (float4*)P2);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)cdiv(JF, 256), (unsigned)p.nich2);
   if (p.prec == PREC_F64)
     hipLaunchKernelGGL(k_mode2<double>, grid, dim3(256), 0, s, (const double*)Tin,

@@ -122,6 +122,14 @@ static __device__ __forceinline__ T group_sum(T v, int width) {
   return v;
 }
 
+// Value of lane l's v (wave-uniform l) in every lane.
+static __device__ __forceinline__ double lane_value_d(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Sum of the partials p = g, g+G, g+2G, ... < nparts of one element, in
 // increasing p (one group of the fixed-order grouped reductions).
 template <typename PT>
