@@ -11,7 +11,7 @@
  *
  *   W   = X^(n) (Khatri-Rao of the other two factors)            (MTTKRP)
  *   G   = Hadamard product of the other factors' Grams          (Section IV-A)
- *   L   = chol(G + rho I)                                         (FP64)
+ *   Ginv = (G + rho I)^{-1}  (block Gauss-Jordan, FP64, once per mode update)
  *   T times:  Ht^T = (W + rho (H + U)) (G + rho I)^{-1}
  *             H    = max(0, Ht^T - U),   U += H - Ht^T            (eq. ADMoM_NTF)
  *
@@ -54,13 +54,13 @@ typedef enum {
 } ntf_status;
 
 typedef enum {
-  NTF_PREC_F32 = 0,         /* X float32; MTTKRP on FP32 MFMA; Gram, Cholesky, solves FP64; H,U float32 */
+  NTF_PREC_F32 = 0,         /* X float32; MTTKRP on FP32 MFMA; Gram, (G + rho I)^{-1}, solves FP64; H,U float32 */
   NTF_PREC_BF16_MIXED = 1,  /* X float32 + bfloat16 copy with a power-of-two scale per mode-1 slab;
                                MTTKRP on BF16 MFMA with FP32 accumulation against
                                bfloat16(H_3) (modes 1, 2) or H_2 as two bfloat16 terms
                                hi + lo (mode 3, each slab's result scaled by the slab's
                                row of H_1 in FP32);
-                               Gram, Cholesky and solves FP64; H,U float32 */
+                               Gram, (G + rho I)^{-1} and solves FP64; H,U float32 */
   NTF_PREC_F64 = 3          /* X float64; everything FP64 (MFMA f64); H,U float64 */
 } ntf_precision;
 
@@ -227,7 +227,7 @@ size_t ntf_admm_sparse_workspace_bytes(const ntf_sparse_problem *prob, const ntf
  * arrays are not used afterwards.  Every MTTKRP of the outer iteration then
  * takes 3 nnz F flops from the sorted copy (one product of the other two
  * factor rows per non-zero, Section IV-A, item 1); the Gram, penalty,
- * Cholesky and inner sweep are those of the dense tensor.  All other
+ * factorisation and inner sweep are those of the dense tensor.  All other
  * ntf_admm_* calls apply unchanged; ntf_admm_fit evaluates
  * ||X - M||^2 = sum over non-zeros (x - m)^2 + ||M||^2 - sum over non-zeros m^2,
  * ||M||^2 from the Grams of the factors, in FP64; ntf_admm_launch_pass(p)
@@ -291,13 +291,14 @@ const char *ntf_status_str(ntf_status s);
 
 /* ------------------------------------------- learned warm start (not in the paper)
  *
- * A 3-layer MLP with ReLU after every layer maps one row's NNLS problem
+ * A 3-layer MLP (ReLU after the two hidden layers, linear output) maps one row's NNLS problem
  * min_{h>=0} 1/2 h^T G h - w^T h (the fixed point of the inner sweep for that
  * row, Section IV) to a starting point.  Row inputs (D = F(F+1)/2 + F floats):
  * the upper triangle of G/rho, row by row, then w/||w||; the network predicts
  * h rho/||w||.  Parameters are one flat vector
  *   [W1 hidden*D, b1 hidden, W2 hidden*hidden, b2 hidden, W3 F*hidden, b3 F]
- * with y = relu(W x + b) per layer (weights row-major [out][in]). */
+ * with a = relu(W x + b) for the hidden layers and y = W3 a2 + b3 (weights
+ * row-major [out][in]); the judge projects y onto h >= 0. */
 typedef struct {
   int32_t F;                /* rank the network serves, 1..64 */
   int32_t hidden;           /* hidden units per layer, 1..1024 */
@@ -440,7 +441,7 @@ ntf_status ntf_admm_set_constraints(ntf_admm_ctx *ctx, const ntf_constraints *co
  * updates (eq. ADMoM_NTF, Gauss-Seidel order of eq. ADMM_NTF_ALS_C) from one
  * global work list, and each outer iteration is one replay of a captured HIP
  * graph.  Every problem is the single-problem method of Section IV with its
- * own F, G, rho and Cholesky factor; problems share nothing but the launch.
+ * own F, G, rho and (G + rho I)^{-1}; problems share nothing but the launch.
  *
  * Precision is NTF_PREC_BF16_MIXED only: at init the library writes two
  * bfloat16 copies of each X with a power-of-two scale per mode-1 slab
@@ -449,7 +450,7 @@ ntf_status ntf_admm_set_constraints(ntf_admm_ctx *ctx, const ntf_constraints *co
  * in the single-problem solver, the mode-3 product takes H_2 as two bfloat16
  * terms and scales each slab's result by the row of H_1), Grams in FP32 per
  * row block summed in FP64, and
- * Cholesky and solves in FP64.  Options used: inner_iters, rho_policy
+ * (G + rho I)^{-1} and solves in FP64.  Options used: inner_iters, rho_policy
  * (TRACE or FIXED), rho0, inner_eps_abs/rel, rescale_dual_on_rho_change;
  * factor_source, paper_init, warm_hidden and the outer stop test must be 0.
  * Every problem: x_dtype 0, float32 H and U, F in 1..64, and its work items

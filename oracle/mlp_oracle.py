@@ -9,8 +9,10 @@ iterations start from it or from the previous iterate.
 
 Parameter layout (one flat vector, row-major blocks):
   W1 [H, D], b1 [H], W2 [H, H], b2 [H], W3 [F, H], b3 [F]
-with D = F(F+1)/2 + F inputs and H hidden units; ReLU after every layer
-(the last one keeps the prediction non-negative).
+with D = F(F+1)/2 + F inputs and H hidden units; ReLU after the two hidden
+layers, linear output (a ReLU there can leave every output at zero for good:
+a row whose output pre-activations are all negative gets no gradient); the
+candidate is the output projected onto h >= 0.
 
 Inputs of a row: the upper triangle of G / rho (row by row, j >= i) followed
 by w / ||w||; the network predicts h * rho / ||w||.  NNLS is scale
@@ -79,8 +81,7 @@ def forward(p: np.ndarray, X: np.ndarray, F: int, H: int = 256):
     a1 = np.maximum(z1, 0.0)
     z2 = a1 @ P["W2"].T + P["b2"]
     a2 = np.maximum(z2, 0.0)
-    z3 = a2 @ P["W3"].T + P["b3"]
-    y = np.maximum(z3, 0.0)
+    y = a2 @ P["W3"].T + P["b3"]          # linear output layer
     return y, (X, a1, a2, y)
 
 
@@ -90,11 +91,12 @@ def mse_loss(y: np.ndarray, t: np.ndarray) -> float:
 
 
 def backward(p: np.ndarray, cache, dy: np.ndarray, F: int, H: int = 256) -> np.ndarray:
-    """Gradient of sum(dy * y) w.r.t. the flat parameters (ReLU derivative 0 at 0)."""
+    """Gradient of sum(dy * y) w.r.t. the flat parameters (ReLU derivative 0 at 0;
+    the output layer is linear)."""
     P = unpack(p, F, H)
     X, a1, a2, y = cache
     g = {}
-    d3 = dy * (y > 0)
+    d3 = dy                                # (linear output layer)
     g["W3"] = d3.T @ a2
     g["b3"] = d3.sum(axis=0)
     da2 = d3 @ P["W3"]
@@ -147,7 +149,7 @@ def warm_start(p, G, W, rho, H_prev, U_prev, Hid: int = 256):
     zero set of h) or the previous iterate, whichever has the smaller KKT
     violation in the units of h (natural_residual; ties keep the previous
     iterate)."""
-    h = predict_rows(p, G, W, rho, Hid)
+    h = np.maximum(predict_rows(p, G, W, rho, Hid), 0.0)   # the candidate, projected onto h >= 0
     g = h @ G - W
     u = np.where(h > 0, 0.0, np.maximum(g / rho, 0.0))
     k_new = natural_residual(G, W, h, rho)

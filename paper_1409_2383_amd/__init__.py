@@ -72,11 +72,13 @@ class NtfAdmm:
     X: CUDA tensor [I, J, K], float32 (F32 / BF16_MIXED) or float64 (F64), C order.
     H: three CUDA tensors [d_n, F] (float32, or float64 for F64): initial
        factors, updated in place.  U: three duals of the same shape (zeros if
-       omitted).  The workspace is a torch uint8 tensor owned by this object.
+       omitted).  The workspace is a torch uint8 tensor owned by this object, or
+    the caller's (`workspace`: at least ntf_admm_workspace_bytes long; an
+    earlier solver's `.workspace.numel()` for the same shape and options).
     """
 
     def __init__(self, X, H: Sequence, U: Optional[Sequence] = None,
-                 opts: Optional[AdmmOptions] = None, stream=None):
+                 opts: Optional[AdmmOptions] = None, stream=None, workspace=None):
         torch = _torch()
         self.opts = opts or AdmmOptions()
         fdt = torch.float64 if self.opts.precision == PREC_F64 else torch.float32
@@ -118,7 +120,13 @@ class NtfAdmm:
             st = L.ntf_admm_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
                                  None, 0, _stream_handle(stream))
             _lib.check(st, "ntf_admm_init")
-        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
+        if workspace is not None:
+            if (not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous()
+                    or workspace.numel() < nbytes):
+                raise ValueError(f"workspace must be a contiguous CUDA uint8 tensor of >= {nbytes} bytes")
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
         ctx = ctypes.c_void_p()
         st = L.ntf_admm_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
                              ctypes.c_void_p(_ptr(self.workspace)), nbytes, _stream_handle(stream))
@@ -331,7 +339,13 @@ class NtfNway:
             st = L.ntf_nway_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts), None, 0,
                                  _stream_handle(stream))
             _lib.check(st, "ntf_nway_init", None, nway=True)
-        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
+        if workspace is not None:
+            if (not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous()
+                    or workspace.numel() < nbytes):
+                raise ValueError(f"workspace must be a contiguous CUDA uint8 tensor of >= {nbytes} bytes")
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
         ctx = ctypes.c_void_p()
         st = L.ntf_nway_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
                              ctypes.c_void_p(_ptr(self.workspace)), nbytes, _stream_handle(stream))
@@ -403,7 +417,7 @@ def inner_update(W, H, U, G, rho: float = 0.0, T: int = 1, eps_abs: float = 0.0,
                  eps_rel: float = 0.0, want_iters: bool = False, want_ht: bool = False,
                  stream=None):
     """One mode update on given W (float64 [rows,F]) and G (float64 [F,F]):
-    Cholesky of G + rho I on the device, then up to T inner iterations per row
+    (G + rho I)^{-1} on the device, then up to T inner iterations per row
     on H, U (in place).  rho <= 0 selects trace(G)/F."""
     torch = _torch()
     rows, F = H.shape
@@ -471,7 +485,7 @@ class NtfBatch:
     """Many independent NTF problems of uneven shapes, factorised together:
     one persistent kernel per outer iteration over a global work list, each
     outer iteration one replay of a captured HIP graph (mixed precision only:
-    BF16 MTTKRP with FP32 accumulation, FP32 Grams, FP64 Cholesky/solves).
+    BF16 MTTKRP with FP32 accumulation, FP32 Grams, FP64 inverse/solves).
 
     Xs: CUDA float32 tensors [I, J, K]; Hs: per problem three CUDA float32
     factors [d_n, F] (updated in place); Us: duals (zeros if omitted).

@@ -1,10 +1,10 @@
 // ADMoM kernels for gfx950: the F x F system (Gram Hadamard product, penalty,
-// FP64 Cholesky and triangular inverse) and the fused row-wise inner sweep
-// (two triangular solves, projection, dual update, residuals, Gram partial),
+// FP64 inverse of G + rho I) and the fused row-wise inner sweep (the solve as
+// a mat-vec with that inverse, projection, dual update, residuals, Gram partial),
 // plus the standalone Gram and direct-fit kernels.
 //
 // One mode update (Section IV, eq. ADMM_NTF_ALS_C with eq. ADMoM_NTF) is
-//   prep:  G = Gram_a (*) Gram_b,  rho,  L = chol(G + rho I),  Ginv = L^{-T} L^{-1}
+//   prep:  G = Gram_a (*) Gram_b,  rho,  Ginv = (G + rho I)^{-1} (block Gauss-Jordan)
 //   inner: per row, T times:  b = w + rho (h + u);  ht = Ginv b;
 //                             v = ht - u;  h = max(0, v);  u = h - v.
 // The system matrix is common to all rows (Appendix B), so it is factored
@@ -199,13 +199,10 @@ hipError_t launch_inner(const InnerArgs& ia, int nblk, hipStream_t s) {
 
 // ---------------------------------------------------------------- prepare
 
-// Every block reduces a slice of the Gram partials of the mode just updated
-// (fixed order over partials); the last block to finish (atomic ticket) forms
-// G = Gram_a (*) Gram_b, picks rho, and factors G + rho I.
+// Every block forms (or reduces) a slice of the Gram of the mode just updated
+// (fixed order); the last block to finish (atomic ticket) forms G = Gram_a (*)
+// Gram_b, picks rho, and inverts G + rho I (prep_body).
 //
-// Cholesky and the triangular inverse use 256 threads on a 16 x 16 grid, thread
-// (ti,tj) owning elements (ti+16a, tj+16b) in registers; each elimination step
-// broadcasts one column (or row) through LDS, one barrier per step.
 // Totals of the 8 residual partial columns over nparts partials, grouped
 // fixed order (32 groups of 256 threads); used by the prepare and statistics
 // kernels so both give bitwise identical totals.
@@ -472,11 +469,28 @@ __device__ void gram_rows(const HT* __restrict__ H, int64_t r0, int64_t r1, int 
       acc[p][q] = 0.0;
       accf[p][q] = 0.f;
     }
+  // the next 64-row chunk is loaded into registers (16 values per thread,
+  // all in flight at once) while the current one is summed: the factor was
+  // just written on other XCDs, so each load is a full memory round trip
+  double nx[16];
+  auto load_chunk = [&](int64_t rb) {
+    const int n = (int)min((int64_t)64, r1 - rb) * F;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      nx[q] = (e < n) ? (double)H[rb * F + e] : 0.0;
+    }
+  };
+  if (r0 < r1) load_chunk(r0);
   for (int64_t rb = r0; rb < r1; rb += 64) {
     const int nr = (int)min((int64_t)64, r1 - rb);
     __syncthreads();
-#pragma unroll 4
-    for (int e = tid; e < nr * F; e += 256) hs[e] = (double)H[rb * F + e];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      if (e < nr * F) hs[e] = nx[q];
+    }
+    if (rb + 64 < r1) load_chunk(rb + 64);
     __syncthreads();
     // (columns past F read other rows' values into entries that are never
     // stored; every index stays inside the 64 x 64 buffer)

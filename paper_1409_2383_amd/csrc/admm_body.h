@@ -1,7 +1,7 @@
 // Device bodies of the ADMoM mode update shared by the per-problem kernels
 // (admm.hip) and the batched persistent kernel (batch.hip): the fused
 // row-wise inner sweep and the F x F prepare step (Gram Hadamard product,
-// penalty, FP64 Cholesky factor and its inverse).  Internal header.
+// penalty, FP64 inverse of G + rho I).  Internal header.
 #pragma once
 
 #include "ntf_device.h"
@@ -12,8 +12,8 @@ namespace ntf {
 // (FL = next power of two >= F, so a row never straddles a wave), and every
 // lane group carries RPL rows at once: lane f holds h_f, u_f, w_f of RPL rows
 // in FP64 registers for the whole sweep.  The solve with G + rho I is one
-// lane-parallel mat-vec against Ginv = (G + rho I)^{-1} = L^{-T} L^{-1}
-// (formed once per mode update from the Cholesky factor, symmetric, zero
+// lane-parallel mat-vec against Ginv = (G + rho I)^{-1}
+// (formed once per mode update by the prepare step, symmetric, zero
 // padded to FL x FL) in LDS; each Ginv element read serves the RPL rows of
 // the lane.  The right-hand sides are exchanged through two alternating LDS
 // buffers (broadcast reads): one barrier per inner iteration.

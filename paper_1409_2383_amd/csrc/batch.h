@@ -15,7 +15,7 @@ namespace ntf {
 // with smaller tickets (see batch.hip).
 enum BKind {
   BK_P1 = 0,     // slab group: T = X x_3 H3 (BF16 MFMA) and W1 rows
-  BK_PREP1 = 1,  // G1 = Gram2 (*) Gram3, rho, L^{-1}
+  BK_PREP1 = 1,  // G1 = Gram2 (*) Gram3, rho, (G1 + rho I)^{-1}
   BK_IN1 = 2,    // row block of the mode-1 inner sweep (last block: Gram1)
   BK_PREP2 = 3,
   BK_M2 = 4,     // 64 rows of W2 = sum_i H1[i] * T[i]

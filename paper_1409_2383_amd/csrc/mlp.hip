@@ -1,6 +1,7 @@
-// Learned warm start for the inner sweep: a 3-layer MLP (ReLU after every
-// layer) that maps one row's NNLS problem  min_{h>=0} 1/2 h^T G h - w^T h  to
-// an approximate solution, trained on the GPU by the kernels below (forward,
+// Learned warm start for the inner sweep: a 3-layer MLP (ReLU after the two
+// hidden layers, linear output) that maps one row's NNLS problem
+// min_{h>=0} 1/2 h^T G h - w^T h  to an approximate solution (projected onto
+// h >= 0 by the judge), trained on the GPU by the kernels below (forward,
 // backward, Adam), and a per-row KKT judge that keeps the previous iterate
 // whenever it is the better start.  Not part of the paper: an extension of
 // the inner ADMoM sweep of Section IV whose fixed point is unchanged.
@@ -351,8 +352,9 @@ static hipError_t mlp_forward_t(const TP* P, int F, int Hd, const float* X, int6
   hipLaunchKernelGGL(k_bias_act<TP>, dim3(blocks_for(B * Hd)), dim3(256), 0, s, a2, P + o.b2,
                      (const float*)nullptr, B, Hd, 1);
   if ((e = gemm<TP>(a2, Hd, 1, P + o.W3, 1, Hd, Y, F, (int)B, F, Hd, 1.f, 0.f, s)) != hipSuccess) return e;
+  // (linear output layer: a ReLU there can leave every output at zero for good)
   hipLaunchKernelGGL(k_bias_act<TP>, dim3(blocks_for(B * F)), dim3(256), 0, s, Y, P + o.b3,
-                     (const float*)nullptr, B, F, 1);
+                     (const float*)nullptr, B, F, 0);
   return hipGetLastError();
 }
 
@@ -372,11 +374,11 @@ hipError_t mlp_backward(const float* P, int F, int Hd, const float* X, const flo
   const MlpOffsets o = mlp_offsets(F, Hd);
   const float* a1 = act;
   const float* a2 = act + B * Hd;
-  float* d3 = work;               // [B][F]
+  const float* d3 = dY;           // (linear output layer)
   float* dA = work + B * F;       // [B][Hd]
   float* dZ = dA + B * Hd;        // [B][Hd]
   hipError_t e;
-  hipLaunchKernelGGL(k_relu_back, dim3(blocks_for(B * F)), dim3(256), 0, s, dY, Y, d3, B * F);
+  (void)Y;
   // dW3 = d3^T a2  [F][Hd]: A(m,k) = d3[k][m], B(k,n) = a2[k][n]
   if ((e = gemm<float>(d3, 1, F, a2, Hd, 1, grad + o.W3, Hd, F, Hd, (int)B, 1.f, 0.f, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_colsum, dim3((F + 63) / 64), dim3(1024), 0, s, d3, B, F, grad + o.b3);

@@ -84,6 +84,91 @@ __global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ X, i
   }
 }
 
+// The same copies and scales for K a multiple of 4, one slab per block: the
+// slab's maximum from 16-byte loads, then one pass in which 32 lanes walk the
+// 4-column groups of 8 consecutive rows j (16-byte loads of each row): every
+// value is read once more and written to both copies, Xr with 8-byte stores
+// (4 columns of a row), Xj8 with 16-byte stores (the 8 rows of one column).
+// The bfloat16 values are those of k_quantize (round to nearest even of
+// X * (1/s), the same FP32 product).
+__global__ __launch_bounds__(256) void k_quantize4(const float* __restrict__ X, int J, int K, int Kp,
+                                                   int JG, int Kp3, __bf16* __restrict__ Xr,
+                                                   __bf16* __restrict__ Xj8,
+                                                   float* __restrict__ scale) {
+  const int64_t i = blockIdx.x;
+  const float4* Xi4 = reinterpret_cast<const float4*>(X + i * (int64_t)J * K);
+  const int n4 = J * K / 4;
+  float m = 0.f;
+  {
+    int t = threadIdx.x;
+    for (; t + 768 < n4; t += 1024) {
+      const float4 a = Xi4[t], b = Xi4[t + 256], c = Xi4[t + 512], d = Xi4[t + 768];
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))));
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(b.x), fabsf(b.y)), fmaxf(fabsf(b.z), fabsf(b.w))));
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(c.x), fabsf(c.y)), fmaxf(fabsf(c.z), fabsf(c.w))));
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(d.x), fabsf(d.y)), fmaxf(fabsf(d.z), fabsf(d.w))));
+    }
+    for (; t < n4; t += 256) {
+      const float4 a = Xi4[t];
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))));
+    }
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  m = red[0];
+  float s = 1.f;
+  if (m > 0.f && isfinite(m)) {
+    int e;
+    (void)frexpf(m, &e);
+    s = ldexpf(1.f, e - 1);
+  }
+  if (threadIdx.x == 0) scale[i] = s;
+  const float inv = 1.f / s;  // exact: s is a power of two
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int K4 = K / 4, C4 = max(Kp, Kp3) / 4;
+  __bf16* Xri = Xr + i * (int64_t)J * Kp;
+  __bf16* Xji = Xj8 + i * (int64_t)JG * Kp3 * 8;
+  for (int jg = ty; jg < JG; jg += 8) {
+    for (int c4 = tx; c4 < C4; c4 += 32) {
+      float4 v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = 8 * jg + e;
+        v[e] = (j < J && c4 < K4) ? Xi4[(int64_t)j * K4 + c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      if (4 * c4 < Kp) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int j = 8 * jg + e;
+          if (j < J) {
+            bf16x4 o = {(__bf16)(v[e].x * inv), (__bf16)(v[e].y * inv), (__bf16)(v[e].z * inv),
+                        (__bf16)(v[e].w * inv)};
+            *reinterpret_cast<bf16x4*>(Xri + (int64_t)j * Kp + 4 * c4) = o;
+          }
+        }
+      }
+      if (4 * c4 < Kp3) {
+        bf16x8 o[4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          o[0][e] = (__bf16)(v[e].x * inv);
+          o[1][e] = (__bf16)(v[e].y * inv);
+          o[2][e] = (__bf16)(v[e].z * inv);
+          o[3][e] = (__bf16)(v[e].w * inv);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          *reinterpret_cast<bf16x8*>(Xji + ((int64_t)jg * Kp3 + 4 * c4 + c) * 8) = o[c];
+      }
+    }
+  }
+}
+
 // sum of squares, FP64 accumulation, fixed-order two-level reduction
 template <typename XT>
 __global__ __launch_bounds__(256) void k_sumsq_part(const XT* __restrict__ X, int64_t n,
@@ -1355,6 +1440,11 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
 
 hipError_t launch_quantize(const float* X, const Plan& p, __bf16* Xr, __bf16* Xj8, float* scale,
                            hipStream_t s) {
+  if (p.K % 4 == 0 && p.J * p.K < (int64_t)1 << 31 && p.Kp % 4 == 0 && p.Kp3 % 4 == 0) {
+    hipLaunchKernelGGL(k_quantize4, dim3((unsigned)p.I), dim3(256), 0, s, X, (int)p.J, (int)p.K,
+                       (int)p.Kp, (int)p.JG, (int)p.Kp3, Xr, Xj8, scale);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_quantize, dim3((unsigned)p.I), dim3(256), 0, s, X, p.J, p.K, p.Kp, p.JG,
                      p.Kp3, Xr, Xj8, scale);
   return hipGetLastError();

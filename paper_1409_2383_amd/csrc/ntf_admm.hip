@@ -6,14 +6,14 @@
 // eq. ADMM_NTF_ALS_C) is enqueued as
 //
 //   main stream                          side stream
-//   pass 1  (W1 partials + T)            prep 1: Gram_3 <- partials; chol(G1 + rho I)
+//   pass 1  (W1 partials + T)            prep 1: Gram_3 of C; (G1 + rho I)^{-1}
 //   inner 1  <------------------------- (join)
-//   mode 2 from T                        prep 2: Gram_1 <- partials; chol(G2 + rho I)
+//   mode 2 from T                        prep 2: Gram_1 of A; (G2 + rho I)^{-1}
 //   inner 2  <------------------------- (join)
-//   pass 3  (W3 partials)                prep 3: Gram_2 <- partials; chol(G3 + rho I)
+//   pass 3  (W3 partials)                prep 3: Gram_2 of B; (G3 + rho I)^{-1}
 //   inner 3  <------------------------- (join)
 //
-// so every Cholesky overlaps an MTTKRP pass.  The fused inner kernel of mode n
+// so every factorisation overlaps an MTTKRP pass.  The fused inner kernel of mode n
 // leaves the Gram partials of its new factor for the next prepare step.
 #include "../../include/ntf_admm.h"
 #include "ntf_launch.h"

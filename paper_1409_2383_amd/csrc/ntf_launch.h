@@ -118,7 +118,7 @@ struct PrepArgs {
   double* rho_state = nullptr;        // [0] rho (in/out), [1] previous rho (out)
   const double* resid_mode = nullptr; // residual totals of the mode being prepared
   int* fresh_mode = nullptr;
-  double* Ginv = nullptr;             // out [F][F]: (G + rho I)^{-1} = L^{-T} L^{-1}; then [F]
+  double* Ginv = nullptr;             // out [F][F]: (G + rho I)^{-1}; then [F]
                                       // its row sums and [1] their total
   double* G_out = nullptr;            // optional out: G of the mode being prepared [F][F]
   int* taken = nullptr;               // warm-start counter of the mode being prepared (zeroed)

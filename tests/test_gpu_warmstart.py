@@ -166,13 +166,21 @@ def test_judge_matches_reference(dev):
     s.close()
 
 
-def test_trained_network_gain_small(dev):
+def test_trained_network_measured(dev):
     # Train on a few small tensors of the learned-warm-start workload's kind
-    # and report inner iterations to the 1e-6 row residual test on held-out
-    # tensors, with and without the network (the number the benchmark
-    # reports at full size).  Asserted: the judge never makes things worse
-    # by more than noise, and the network is picked for some rows.
+    # and measure, on held-out tensors, the inner iterations to the 1e-6 row
+    # residual test with and without the network (the numbers the full-size
+    # evaluation reports) and how close its predictions are to the converged
+    # row solutions.  No gain is asserted: measured at full size the network
+    # saves nothing (F = 8, 16: -0.01%; F = 32: +2% inner iterations) and at
+    # this size it costs about 0.5%, because a start with a smaller KKT
+    # violation but a wrong zero pattern can take the sweep longer.  Asserted:
+    # the network learned (loss down), the judge took it for some rows, and
+    # the run with the network reaches the same fit as the run without it
+    # (the network changes only where each row's sweep starts).
     from paper_1409_2383_amd import warmstart as ws
+    import paper_1409_2383_amd as ntf
+    import ntf_synth
     F = 8
     specs = [((40 + 7 * t, 50 - 3 * t, 45 + 2 * t), F, 300 + t) for t in range(10)]
     pairs = ws.generate_pairs(specs[:8], F, outer=4)
@@ -180,6 +188,28 @@ def test_trained_network_gain_small(dev):
     hist = ws.train(net, pairs, epochs=8, batch=512)
     assert hist[-1] < hist[0]
     ev = ws.evaluate(specs[8:], F, net, outer=8, eps=1e-6, cap=2000)
-    print("warm-start evaluation:", ev)
-    assert ev["taken_frac"] > 0.0
-    assert ev["warm"] <= 1.05 * ev["plain"]
+    acc = ws.prediction_error(net, ws.generate_pairs(specs[8:], F, outer=2))
+    print("warm-start evaluation:", ev, acc, flush=True)
+    assert ev["taken_frac"] > 0.0 and acc["rows"] > 0
+    # same fit with and without the network after 8 outer iterations
+    dims, _, seed = specs[9]
+    pt = ntf_synth.planted(dims, F, seed, snr_db=20.0, dtype=np.float32)
+    H0 = ntf_synth.init_factors(dims, F, seed, dtype=np.float32)
+    X = torch.from_numpy(pt.X).to(dev)
+    fits = []
+    for warm in (False, True):
+        H = [torch.from_numpy(h).to(dev) for h in H0]
+        s = ntf.NtfAdmm(X, H, opts=ntf.AdmmOptions(inner_iters=2000, precision=ntf.PREC_F32,
+                                                   inner_eps_abs=1e-6, inner_eps_rel=1e-6,
+                                                   warm_hidden=64 if warm else 0))
+        if warm:
+            import ctypes
+            from paper_1409_2383_amd import _lib
+            st = net.struct(True)
+            _lib.check(_lib.lib().ntf_admm_set_warmstart(s._ctx, ctypes.byref(st)), "set_warmstart", s._ctx)
+        for _ in range(8):
+            s.step()
+        fits.append(s.fit())
+        s.close()
+    print("fit without / with the network:", fits, flush=True)
+    assert abs(fits[1] - fits[0]) <= 1e-4 * fits[0]
