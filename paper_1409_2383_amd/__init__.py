@@ -339,13 +339,7 @@ class NtfNway:
             st = L.ntf_nway_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts), None, 0,
                                  _stream_handle(stream))
             _lib.check(st, "ntf_nway_init", None, nway=True)
-        if workspace is not None:
-            if (not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous()
-                    or workspace.numel() < nbytes):
-                raise ValueError(f"workspace must be a contiguous CUDA uint8 tensor of >= {nbytes} bytes")
-            self.workspace = workspace
-        else:
-            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
         ctx = ctypes.c_void_p()
         st = L.ntf_nway_init(ctypes.byref(ctx), ctypes.byref(pr), ctypes.byref(self._copts),
                              ctypes.c_void_p(_ptr(self.workspace)), nbytes, _stream_handle(stream))

@@ -10,7 +10,7 @@
 //   P1 (slab groups) --------------+--> IN1 (row blocks) --+--> M2 --> IN2 --+--> P3 --> IN3
 //   PREP1 -------------------------+                       +--> PREP2 ---^   +--> PREP3 --^
 //
-// (PREPn: G_n = Gram (*) Gram of the other two modes, rho, L^{-1}; INn: the
+// (PREPn: G_n = Gram (*) Gram of the other two modes, rho, (G_n + rho I)^{-1}; INn: the
 // fused inner sweep of mode n; P1: T = X x_3 H3 and the W1 rows; M2: W2
 // from T and the new H1; P3: W3 partials from the new H1 and H2).  The list
 // is sorted so that every item depends only on items with smaller tickets,
@@ -434,19 +434,21 @@ __device__ __forceinline__ void m2_item(const ConstProb& P, int idx, const int t
   const int64_t JF = (int64_t)J * F;
   const float* __restrict__ A = P.H[0];
   const float* __restrict__ Tb = P.T + (int64_t)j0 * F;
+  // (sixteen slabs of loads in flight per thread: one item streams I rows of
+  // T through one block, so its rate is the loads in flight over the latency)
   for (int e = tid; e < E; e += 256) {
     const int f = e % F;
     double s = 0.0;
     int i = 0;
-    for (; i + 4 <= I; i += 4) {
-      float t[4], a[4];
+    for (; i + 16 <= I; i += 16) {
+      float t[16], a[16];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 16; ++q) {
         t[q] = Tb[(int64_t)(i + q) * JF + e];
         a[q] = A[(int64_t)(i + q) * F + f];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s += (double)a[q] * (double)t[q];
+      for (int q = 0; q < 16; ++q) s += (double)a[q] * (double)t[q];
     }
     for (; i < I; ++i) s += (double)A[(int64_t)i * F + f] * (double)Tb[(int64_t)i * JF + e];
     P.W[1][(int64_t)j0 * F + e] = s;
