@@ -342,6 +342,50 @@ def write_traffic(fetch_csv, write_csv, calib_mib, workload, arm, pass_bytes, cm
     return out
 
 
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+                 "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def write_mfma(pmc_csv, workload, arm, pass_ms, pass_flops, cmd):
+    """Turns a rocprofv3 --pmc run of MFMA_COUNTERS into per-launch MFMA work of
+    each MTTKRP kernel: flops = MOPS x 512 (rocprofv3's MfmaFlops* definition),
+    busy fraction = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 1024 SIMDs)
+    (its MfmaUtil), achieved TFLOP/s = counted flops / the kernel's average time
+    from the same workload's timing run.  GRBM_GUI_ACTIVE comes summed over the
+    eight XCDs in the per-dispatch CSV (about 8 x 2.2 GHz x the kernel time), so
+    the busy fraction divides it by 8 (the counter's per-XCD maximum in
+    MfmaUtil's definition)."""
+    tab = _counter_means(pmc_csv)
+    peak = {"mixed": 2500.0, "fp32": 157.3}[arm]
+    dtype = {"mixed": "BF16", "fp32": "F32"}[arm]
+    lines = [f"# MFMA work per launch, {workload} {arm} arm", "",
+             "Command (run from the repository root, NTF_NO_GRAPH=1):", "", "    " + cmd, "",
+             f"Dense {dtype} MFMA peak of MI355X: {peak} TFLOP/s.  Counted flops are what the",
+             "MFMA instructions issued (padding and, in mixed pass 3, both bfloat16 terms",
+             "included); algorithmic flops are 2 IJK F per MTTKRP (mixed pass 3: two terms).", "",
+             "| kernel | MOPS (x512 flops) | counted GFLOP | algorithmic GFLOP | avg ms | achieved TFLOP/s "
+             "| frac of peak | MFMA busy fraction (counters) |", "|---|---|---|---|---|---|---|---|"]
+    out = {}
+    for name, needle in PASS_KERNELS.items():
+        if name == "mode2":
+            continue
+        vals = {c: [v for k, v in tab.items() if needle in k[0] and k[1] == c] for c in MFMA_COUNTERS}
+        if any(len(v) != 1 for v in vals.values()):
+            raise SystemExit(f"expected one kernel matching {needle!r}: {vals}")
+        mops = vals[f"SQ_INSTS_VALU_MFMA_MOPS_{dtype}"][0][0]
+        busy = vals["SQ_VALU_MFMA_BUSY_CYCLES"][0][0] / (vals["GRBM_GUI_ACTIVE"][0][0] / 8.0 * 1024.0)
+        flops = mops * 512.0
+        tf = flops / (pass_ms[name] * 1e-3) / 1e12
+        out[name] = {"mops": mops, "flops": flops, "algorithmic_flops": pass_flops[name],
+                     "avg_ms": pass_ms[name], "tflops": tf, "frac": tf / peak, "busy": busy}
+        lines.append(f"| {name} | {mops:.4g} | {flops / 1e9:.1f} | {pass_flops[name] / 1e9:.1f} | "
+                     f"{pass_ms[name]:.4f} | {tf:.1f} | {tf / peak:.3f} | {busy:.3f} |")
+    lines += ["", f"Source hash of the kernels measured: `{src_hash(MTTKRP_SOURCES)}`.", ""]
+    with open(os.path.join(ROOT, "profiles", f"mfma_{workload}_{arm}.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    return out
+
+
 def write_kernel_stats(stats_csv, workload, arm, cmd):
     """Short text summary of a rocprofv3 --kernel-trace --stats run."""
     import csv
@@ -370,6 +414,19 @@ def summarize(args):
                + ("" if args.workload in ("s1", "n4") else
                   (f" --arm {args.arm}" if args.arm else " --single-arm")))
         write_kernel_stats(args.write_kernel_stats, args.workload, arm, cmd)
+    if args.write_mfma:
+        csv_path, timing_json = args.write_mfma
+        with open(timing_json) as fh:
+            tj = json.loads(fh.read().strip().splitlines()[-1])
+        pass_ms = tj["arms"][arm]["pass_ms"]
+        I, J, K = wl["dims"]
+        F = wl["F"]
+        alg = 2.0 * I * J * K * F
+        pass_flops = {"pass1": alg, "pass3": alg * (2 if arm == "mixed" else 1)}
+        cmd = (f"timeout -s KILL 180 rocprofv3 --pmc {' '.join(MFMA_COUNTERS)} --output-format csv "
+               f"-d gpurun_out/pmc_mfma_{arm} -o run -- python3 bench.py --workload {args.workload} "
+               f"--steps 2 --warmup 1 --pass-reps 3 --no-cpu-baseline --no-ttt --arm {arm}")
+        write_mfma(csv_path, args.workload, arm, pass_ms, pass_flops, cmd)
     if args.write_traffic:
         import paper_1409_2383_amd as ntf
         if args.copy_calib_mib <= 0:
@@ -715,12 +772,15 @@ def main():
     ap.add_argument("--arm", default="", help="run this arm only (e.g. fp32, mixed)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into profiles/ and exit")
+    ap.add_argument("--write-mfma", nargs=2, metavar=("PMC_CSV", "TIMING_JSON"),
+                    help="summarise a rocprofv3 --pmc run of the MFMA counters into profiles/ and exit "
+                         "(kernel times from a bench.py line of the same arm)")
     ap.add_argument("--write-kernel-stats", metavar="STATS_CSV",
                     help="summarise a rocprofv3 --kernel-trace --stats run into profiles/ and exit")
     ap.add_argument("--batch-n", type=int, default=0, help="batched workload: number of tensors")
     ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the autotuner")
     args = ap.parse_args()
-    if args.write_traffic or args.write_kernel_stats:
+    if args.write_traffic or args.write_kernel_stats or args.write_mfma:
         summarize(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -490,8 +490,10 @@ __device__ void gram_rows(const HT* __restrict__ H, int64_t r0, int64_t r1, int 
       const int e = tid + 256 * q;
       if (e < nr * F) hs[e] = nx[q];
     }
-    if (rb + 64 < r1) load_chunk(rb + 64);
     __syncthreads();
+    // (issued after the barrier, which would otherwise wait for them: they
+    // arrive during the sums below)
+    if (rb + 64 < r1) load_chunk(rb + 64);
     // (columns past F read other rows' values into entries that are never
     // stored; every index stays inside the 64 x 64 buffer)
     if (gram_f32) {

@@ -99,17 +99,23 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
   // and every path issues the same loads (the cursor stays on its last tile
   // past the wave's end and re-reads in-bounds data nothing consumes): the
   // wait before a step then covers that step's loads only.
-  int l_t = wave, l_kb = 0;
+  int l_t = wave, l_kb = 0, l_sl = 0;
   const __bf16* l_slab = P.Xr;
   int l_off[MT];
   auto set_rows = [&](int t) {
     const int sl = t / nrg, rg = t - sl * nrg;
+    l_sl = sl;
     l_slab = P.Xr + (int64_t)(s0 + sl) * J * Kp;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Kp + 8 * g) * 2;
   };
+  // each step's loads also bring its slab's scale (the tile epilogue then
+  // reads it from a register instead of waiting on a load of its own)
+  const __amdgpu_buffer_rsrc_t srs = uniform_rsrc(P.scale, P.I * 4);
   bf16x8 xv[U][2][MT];
-  auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+  float as[U];
+  auto load_next = [&](bf16x8 (&dst)[2][MT], float& sdst) {
+    sdst = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(srs, (s0 + l_sl) * 4, 0, 0));
     const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(l_slab, J * Kp * 2);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -130,7 +136,7 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
   if (total > 0) {
     set_rows(l_t);
 #pragma unroll
-    for (int u = 0; u < U; ++u) load_next(xv[u]);
+    for (int u = 0; u < U; ++u) load_next(xv[u], as[u]);
   }
   for (int e = tid; e < KC * FP; e += 256) {
     const int kk = e / FP, f = e - kk * FP;
@@ -191,11 +197,11 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], c1, acc[mt][ft]);
           }
-          if (reload) load_next(xv[u]);
+          const float sc = as[u];   // (read before the reload rewrites it)
+          if (reload) load_next(xv[u], as[u]);
           if (++c_step == nsteps) {
             const int sl = c_t / nrg, rg = c_t - sl * nrg;
             const int i = s0 + sl;
-            const float sc = P.scale[i];
             if (sl != cur_sl) {
               flush();
               cur_sl = sl;
@@ -281,6 +287,8 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
   const int myrg = nrg > wave ? (nrg - wave + 3) / 4 : 0;
   const int nchunk = (JC + JCH - 1) / JCH;
   const __amdgpu_buffer_rsrc_t ars = uniform_rsrc(Ha, P.I * F * 4);
+  const __amdgpu_buffer_rsrc_t srs = uniform_rsrc(P.scale, P.I * 4);
+  const int aof = lane < F ? lane * 4 : kBufferOOB;
   const __amdgpu_buffer_rsrc_t wrs = uniform_rsrc(P.W3p + (int64_t)idx * K * F, K * F * 4);
 
   for (int chk = 0; chk < nchunk; ++chk) {
@@ -298,8 +306,15 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Jp + 8 * g) * 2;
     };
+    // Each step's loads also bring the slab's row of H1 (lane l: H1[i, l]) and
+    // its scale, so the end of a slab takes its coefficients from registers
+    // instead of waiting on loads issued behind U steps of tensor loads.
     bf16x8 xv[U][2][MT];
-    auto load_next = [&](bf16x8 (&dst)[2][MT]) {
+    float ar[U], as[U];
+    auto load_next = [&](bf16x8 (&dst)[2][MT], float& adst, float& sdst) {
+      const int li = s0 + l_sl;
+      adst = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ars, li * F * 4 + aof, 0, 0));
+      sdst = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(srs, li * 4, 0, 0));
       const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(P.Xt + (int64_t)(s0 + l_sl) * K * Jp, K * Jp * 2);
 #pragma unroll
       for (int h = 0; h < 2; ++h)
@@ -324,7 +339,7 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
     if (total > 0) {
       set_rows();
 #pragma unroll
-      for (int u = 0; u < U; ++u) load_next(xv[u]);
+      for (int u = 0; u < U; ++u) load_next(xv[u], ar[u], as[u]);
     }
     __syncthreads();   // the previous chunk's MFMAs are done with the tiles
     for (int e = tid; e < jw * FP; e += 256) {
@@ -364,17 +379,20 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[mt][ft] = mma_bf16(xv[u][1][mt], l1, acc[mt][ft]);
         }
-        if (reload) load_next(xv[u]);
+        // (the coefficients are read out of ar[u], as[u] before the reload
+        // writes the next step's values into the same registers)
+        const bool last = c_step + 1 == nsteps;
+        float coefs[FT];
+        if (last) {
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft) coefs[ft] = as[u] * __shfl(ar[u], ft * 16 + n);
+        }
+        if (reload) load_next(xv[u], ar[u], as[u]);
         if (++c_step == nsteps) {
           // end of a slab: scale by s_i * H1[i, f] and accumulate
-          const int i = s0 + c_sl;
-          const float sc = P.scale[i];
 #pragma unroll
           for (int ft = 0; ft < FT; ++ft) {
-            const int f = ft * 16 + n;
-            const float h = __builtin_bit_cast(
-                float, __builtin_amdgcn_raw_buffer_load_b32(ars, f < F ? (i * F + f) * 4 : kBufferOOB, 0, 0));
-            const float coef = sc * h;
+            const float coef = coefs[ft];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
