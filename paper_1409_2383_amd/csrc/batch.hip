@@ -637,7 +637,7 @@ __device__ __forceinline__ void wait_count(int* c, int need, const BatchK& a) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_batch(BatchK a) {
+__global__ __launch_bounds__(256, 2) void k_batch(BatchK a) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ unsigned s_ticket;
   __shared__ int s_last;

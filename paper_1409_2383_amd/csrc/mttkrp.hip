@@ -1135,7 +1135,8 @@ __global__ __launch_bounds__(512) void k_pass3_bf16s(const __bf16* __restrict__ 
                                                      int ngroups, int jcg, int bpc) {
   constexpr int FP = FT * 16;
   constexpr int MT = 4;
-  constexpr int U = 4;
+  // (two steps in flight: measured 204 us against 209 with four, 242 with six)
+  constexpr int U = 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

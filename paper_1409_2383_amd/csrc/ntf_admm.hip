@@ -406,12 +406,20 @@ static void prep_args(ntf_admm_ctx* c, int m, PrepArgs& a) {
   a.counter = &ds->counter[m];
 }
 
-static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
+static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a, bool from_p1 = false) {
   const Plan& p = c->plan;
   const int64_t d[3] = {p.I, p.J, p.K};
   DevState* ds = c->dstate();
   a = InnerArgs();
-  {
+  if (from_p1) {
+    // W_1 summed by the inner sweep itself from pass 1's partials [I][nch][F]
+    // (in chunk order), and written out for the statistics
+    a.part = c->ws + c->lay.P1;
+    a.part_f64 = c->hf64();
+    a.pstride = p.F;
+    a.rowstride = (int64_t)p.nch1 * p.F;
+    a.nparts = p.nch1;
+  } else {
     // W_m was reduced from the MTTKRP partials by the grouped reduction
     a.part = c->ws + c->lay.W[m];
     a.part_f64 = 1;
@@ -419,7 +427,7 @@ static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
     a.rowstride = p.F;
     a.nparts = 1;
   }
-  a.Wout = nullptr;
+  a.Wout = from_p1 ? c->at<double>(c->lay.W[0]) : nullptr;
   a.H = c->prob.H[m];
   a.U = c->prob.U[m];
   a.Pout = (c->opts.factor_source == 1) ? (void*)(c->ws + c->lay.prim[m]) : nullptr;
@@ -447,10 +455,10 @@ static void inner_args(ntf_admm_ctx* c, int m, InnerArgs& a) {
 // every row in its projection: each inner iteration is the row-wise solve
 // (projection deferred) followed by the whole-factor projection, then the
 // Gram partials of the updated factor.
-static ntf_status enqueue_inner(ntf_admm_ctx* c, int m, hipStream_t ms) {
+static ntf_status enqueue_inner(ntf_admm_ctx* c, int m, hipStream_t ms, bool from_p1 = false) {
   const Plan& p = c->plan;
   InnerArgs ia;
-  inner_args(c, m, ia);
+  inner_args(c, m, ia, from_p1);
   if (c->cons.kind[m] != NTF_CONS_CARDINALITY) {
     NTF_HIP(c, launch_inner(ia, p.nblk_inner[m], ms));
     return NTF_OK;
@@ -557,15 +565,19 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
   NTF_HIP(c, hipEventRecord(c->ev_prep[0], c->s1));
   NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, ms));
-  NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P1, c->hf64(), p.F, (int64_t)p.nch1 * p.F,
-                                    p.nch1, p.I, p.F, c->at<double>(c->lay.W[0]), ms, 16));
+  // The warm start reads W_1 before the inner sweep: reduce it first.  Without
+  // it the inner sweep sums pass 1's (few, per row-chunk) partials itself.
+  const bool w1_in_inner = !c->warm_on;
+  if (!w1_in_inner)
+    NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P1, c->hf64(), p.F, (int64_t)p.nch1 * p.F,
+                                      p.nch1, p.I, p.F, c->at<double>(c->lay.W[0]), ms, 16));
   NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[0], 0));
   if (c->warm_on) {
     ntf_status w = enqueue_warm(c, 0, ms);
     if (w != NTF_OK) return w;
   }
   {
-    ntf_status st = enqueue_inner(c, 0, ms);
+    ntf_status st = enqueue_inner(c, 0, ms, w1_in_inner);
     if (st != NTF_OK) return st;
   }
   // mode 2 (B)
