@@ -231,7 +231,6 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   __shared__ int is_last;
   __shared__ double prep_lds[kPrepLdsDoubles];
   static_assert(kPrepLdsDoubles >= 64 * 64, "the Gram stage borrows the prepare LDS");
-  static_assert(NB * NB <= 16, "the reduced Gram of a thread feeds prep_body directly");
   // the inputs that do not depend on this kernel's Gram, loaded before it
   PrepIn<NB> in;
   prep_load_b(a, tid, in);
@@ -261,37 +260,37 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
       if (a.fresh_dst) *a.fresh_dst = 1;
     }
     // group g sums partials g, g+4, ... in order, the four group sums are
-    // added in order (the order of the 4-group reduction kernel); the loads
-    // of four partials for all sixteen entries of a thread go out together
+    // added in order (the order of the 4-group reduction kernel); each thread
+    // reduces the entries of its prep_body tile, the loads of four partials
+    // for all of them going out together
     const int nent = F * F;
-    double gs[4][16];
+    double gs[4][NB * NB];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int k = 0; k < 16; ++k) gs[g][k] = 0.0;
+      for (int k = 0; k < NB * NB; ++k) gs[g][k] = 0.0;
     for (int p0 = 0; p0 < a.gram_nb; p0 += 4) {
-      double v[4][16];
+      double v[4][NB * NB];
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int e = tid + 256 * k;
-          v[g][k] = (p0 + g < a.gram_nb && e < nent) ? a.gram_scratch[(int64_t)(p0 + g) * nent + e] : 0.0;
+        for (int k = 0; k < NB * NB; ++k) {
+          const int e = prep_entry<NB>(F, tid, k);
+          v[g][k] = (p0 + g < a.gram_nb && e >= 0) ? a.gram_scratch[(int64_t)(p0 + g) * nent + e] : 0.0;
         }
 #pragma unroll
       for (int g = 0; g < 4; ++g)
         if (p0 + g < a.gram_nb) {
 #pragma unroll
-          for (int k = 0; k < 16; ++k) gs[g][k] += v[g][k];
+          for (int k = 0; k < NB * NB; ++k) gs[g][k] += v[g][k];
         }
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int e = tid + 256 * k;
+    for (int k = 0; k < NB * NB; ++k) {
+      const int e = prep_entry<NB>(F, tid, k);
       const double v = ((gs[0][k] + gs[1][k]) + gs[2][k]) + gs[3][k];
-      if (e < nent) a.gram_dst[e] = v;
-      // (entry e = tid + 256 k of gram_a is the one prep_body takes as ga[k])
-      if (k < NB * NB) in.ga[k] = (e < nent) ? v : 0.0;
+      if (e >= 0) a.gram_dst[e] = v;
+      in.ga[k] = (e >= 0) ? v : 0.0;
     }
     have_a = (a.gram_a == a.gram_dst);
     __threadfence_block();

@@ -369,15 +369,16 @@ struct PrepK {
   double* gram_scratch;
 };
 
-// LDS of prep_body: S [64][65] (G + rho I, inverted in place), the blocks
-// D_J = P S_KJ of one block step [3][16][17], a reduction buffer, rho and the
-// failure flag.
-constexpr int kPrepLdsDoubles = 64 * 65 + 3 * 16 * 17 + 256 + 2;
+// LDS of prep_body: S [64][65] (the inverse, for the symmetrised write-out;
+// during the elimination it holds the broadcast rows [2][16][64]; the Gram
+// stage of the prepare kernel borrows it too), the diagonal of G [64], a
+// reduction buffer [256], rho.
+constexpr int kPrepLdsDoubles = 64 * 65 + 64 + 256 + 1;
 
 // Global inputs of prep_body, loaded into registers ahead of it (the
 // per-problem prepare kernel issues these loads before its Gram phase, so
-// their latency overlaps that work): this thread's entries e = tid + 256 q of
-// gram_a and gram_b, and (thread 0) the penalty state.
+// their latency overlaps that work): this thread's tile of gram_a and gram_b
+// (prep_entry) and (thread 0) the penalty state.
 template <int NB>
 struct PrepIn {
   double ga[NB * NB], gb[NB * NB];
@@ -385,13 +386,22 @@ struct PrepIn {
   int fresh;
 };
 
+// Entry q of a thread's tile: thread (ti, tj) = (tid / 16, tid % 16) holds
+// the entries (ti + 16 a, tj + 16 b), a, b < NB, q = a NB + b.  Returns the
+// row-major index in an F x F matrix, or -1 past F.
+template <int NB>
+__device__ __forceinline__ int prep_entry(int F, int tid, int q) {
+  const int r = (tid >> 4) + 16 * (q / NB), c = (tid & 15) + 16 * (q % NB);
+  return (r < F && c < F) ? r * F + c : -1;
+}
+
 template <int NB>
 __device__ __forceinline__ void prep_load_b(const PrepK& a, const int tid, PrepIn<NB>& in) {
   const int F = a.F;
 #pragma unroll
   for (int q = 0; q < NB * NB; ++q) {
-    const int e = tid + 256 * q;
-    in.gb[q] = (e < F * F) ? a.gram_b[e] : 0.0;
+    const int e = prep_entry<NB>(F, tid, q);
+    in.gb[q] = (e >= 0) ? a.gram_b[e] : 0.0;
   }
   in.rho_prev = 0.0;
   in.res0 = in.res1 = 0.0;
@@ -411,8 +421,8 @@ __device__ __forceinline__ void prep_load_a(const PrepK& a, const int tid, PrepI
   const int F = a.F;
 #pragma unroll
   for (int q = 0; q < NB * NB; ++q) {
-    const int e = tid + 256 * q;
-    in.ga[q] = (e < F * F) ? a.gram_a[e] : 0.0;
+    const int e = prep_entry<NB>(F, tid, q);
+    in.ga[q] = (e >= 0) ? a.gram_a[e] : 0.0;
   }
 }
 
@@ -425,60 +435,98 @@ static __device__ __forceinline__ double recip_pos(double x) {
   return r;
 }
 
+// One Gauss-Jordan step on a thread's tile (below) with the pivot p in tile
+// row and column slot 0.  rowc[u] / rowr[s] hold row p as it stands before
+// the step at the thread's columns of slot u and at its rows of slot s (the
+// column p entries of those rows, by symmetry up to sign); sg[s] is -1 for
+// slots of tile rows before p's, +1 after; inv = 1 / pivot; own_r / own_c:
+// the thread holds row p / column p in slot 0, before_r: its slot-0 row
+// precedes p.
+template <int NB>
+__device__ __forceinline__ void gj_step(double (&M)[NB][NB], double inv, const double (&rowc)[NB],
+                                        const double (&rowr)[NB], const double (&sg)[NB], bool own_r,
+                                        bool own_c, bool before_r) {
+  double rs[NB], cv[NB];
+  cv[0] = before_r ? -rowr[0] : rowr[0];
+#pragma unroll
+  for (int s = 1; s < NB; ++s) cv[s] = rowr[s] * sg[s];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) rs[u] = rowc[u] * inv;   // row p over the pivot
+  // every entry as if off row and column p, then column p and row p
+#pragma unroll
+  for (int s = 0; s < NB; ++s)
+#pragma unroll
+    for (int u = 0; u < NB; ++u) M[s][u] = __builtin_fma(-cv[s], rs[u], M[s][u]);
+#pragma unroll
+  for (int s = 0; s < NB; ++s) M[s][0] = own_c ? -cv[s] * inv : M[s][0];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) M[0][u] = own_r ? rs[u] : M[0][u];
+  M[0][0] = (own_r && own_c) ? inv : M[0][0];
+}
+
+static __device__ __forceinline__ double pivot_recip(double piv, bool& bad) {
+  if (!(piv > 0.0) || !isfinite(piv)) {
+    bad = true;
+    piv = 1.0;
+  }
+  return recip_pos(piv);
+}
+
 // Second half of the prepare step, run by one block of 256 threads: G =
-// gram_a (*) gram_b, the penalty, and Ginv = (G + rho I)^{-1} by in-place
-// Gauss-Jordan inversion in 16 x 16 blocks.  `lds` holds kPrepLdsDoubles
-// doubles; `in` holds the global inputs (prep_load_a, prep_load_b).  Also
-// called per work item by the batched persistent kernel.
+// gram_a (*) gram_b, the penalty, and Ginv = (G + rho I)^{-1} by Gauss-Jordan
+// elimination on the matrix held in registers, a tile of NB x NB entries per
+// thread (prep_entry).  `lds` holds kPrepLdsDoubles doubles; `in` holds the
+// global inputs (prep_load_a, prep_load_b).  Also called per work item by the
+// batched persistent kernel.
 //
-// Block step K (S padded with the identity to 16 NB x 16 NB):
-//   P = S_KK^{-1}                 (one wave: 16 scalar pivots in registers)
-//   D_J = P S_KJ                  (J != K)
-//   S_IJ -= S_IK D_J,  S_IK <- -S_IK P   (I, J != K)
-//   S_KJ <- D_J,  S_KK <- P
-// which leaves S^{-1} after the last step.  No pivoting: the pivots are the
-// diagonal entries of successive Schur complements of the symmetric positive
-// definite S, so a pivot that is not positive and finite means S is not
-// (numerically) positive definite: the failure flag is set and Ginv is zero.
-// The serial part is 16 NB scalar pivots inside one wave (lane reads and
-// shuffles, no barriers); everything else is four barriers per block step.
+// Step p = 0 .. F-1 on M (initially S = G + rho I):
+//   M[p][p] <- 1 / M[p][p],   M[p][j] <- M[p][j] / M[p][p],
+//   M[i][p] <- -M[i][p] / M[p][p],   M[i][j] <- M[i][j] - M[i][p] M[p][j] / M[p][p]
+// leaves S^{-1}.  Before step p, with A the leading p x p block of the
+// symmetric S = [A B; B^T D], M = [A^{-1}, A^{-1} B; -B^T A^{-1}, D - B^T A^{-1} B],
+// so column p is row p with the sign changed above row p: only rows are
+// broadcast.  Steps go in pairs: every thread writes its slot-0 tile row to
+// LDS (rows p and p + 1 among them, as they stand before step p), one
+// barrier, then each thread forms row p + 1 after step p itself where it
+// reads it (the same operations its owners apply) and applies both steps.
+// The tile slots rotate by one after each tile row, so the pivot's tile row
+// and column are always slot 0.  No pivoting: the pivots are diagonal
+// entries of successive Schur complements of the SPD S, so a pivot that is
+// not positive and finite means S is not (numerically) positive definite:
+// the failure flag is set and Ginv is zero.
 template <int NB>
 __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int tid,
                                           const PrepIn<NB>& in) {
   constexpr int LD = 65;
   const int F = a.F;
-  double* S = lds;                                    // [64][65]
-  double* Dt = lds + 64 * LD;                         // [3][16][17]
-  double* sred = Dt + 3 * 16 * 17;                    // [256]
+  const int ti = tid >> 4, tj = tid & 15;
+  double* S = lds;                 // [64][65]
+  double* Rall = lds;              // [2][16][64] during the elimination
+  double* Dg = lds + 64 * LD;      // [64]
+  double* sred = Dg + 64;          // [256]
   double& rho_sh = sred[256];
-  int& bad_sh = *reinterpret_cast<int*>(&sred[257]);
-  constexpr int N = 16 * NB;
 
+  double M[NB][NB];
 #pragma unroll
-  for (int q = 0; q < NB * NB; ++q) {
-    const int e = tid + 256 * q;
-    if (e < F * F) {
-      const int r = e / F, c = e - r * F;
-      const double gv = in.ga[q] * in.gb[q];
-      S[r * LD + c] = gv;
-      if (a.G_out) a.G_out[e] = gv;
+  for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+      const int q = ia * NB + ib;
+      const int e = prep_entry<NB>(F, tid, q);
+      const double gv = (e >= 0) ? in.ga[q] * in.gb[q] : 0.0;
+      M[ia][ib] = gv;
+      if (e >= 0) {
+        if (a.G_out) a.G_out[e] = gv;
+        if (ia == ib && ti == tj) Dg[ti + 16 * ia] = gv;
+      }
     }
-  }
-  // identity padding of the rows and columns past F (up to 16 NB)
-  for (int e = tid; e < N * N; e += 256) {
-    const int r = e / N, c = e - r * N;
-    if (r >= F || c >= F) S[r * LD + c] = (r == c) ? 1.0 : 0.0;
-  }
-  if (tid == 0) {
-    bad_sh = 0;
-    if (a.taken) *a.taken = 0;
-  }
+  if (tid == 0 && a.taken) *a.taken = 0;
   __syncthreads();
 
   // penalty (the trace summed by one wave)
   if (tid < 64) {
     double tr = 0.0;
-    if (a.policy == 0) tr = group_sum(tid < F ? S[tid * LD + tid] : 0.0, 64);
+    if (a.policy == 0) tr = group_sum(tid < F ? Dg[tid] : 0.0, 64);
     if (tid == 0) {
       const double rho_prev = in.rho_prev;
       double rho;
@@ -503,97 +551,122 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
     }
   }
   __syncthreads();
-  if (tid < F) S[tid * LD + tid] += rho_sh;
-  __syncthreads();
-
-  const int ta = tid >> 4, tb = tid & 15;   // entry (ta, tb) of a 16 x 16 block
-#pragma unroll 1
-  for (int K = 0; K < NB; ++K) {
-    const int k0 = 16 * K;
-    // P = S_KK^{-1}: lane (r, q) holds S_KK[r][4q .. 4q+3]
-    if (tid < 64) {
-      const int r = tid & 15, q = tid >> 4;
-      double x[4];
+  {
+    const double rho = rho_sh;
+    if (ti == tj) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) x[c] = S[(k0 + r) * LD + k0 + 4 * q + c];
-#pragma unroll
-      for (int p = 0; p < 16; ++p) {
-        const int pq = p >> 2, pc = p & 3;
-        double piv = lane_value_d(x[pc], p + 16 * pq);
-        const double arp = __shfl(x[pc], r + 16 * pq);
-        double apc[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) apc[c] = __shfl(x[c], p + 16 * q);
-        if (!(piv > 0.0) || !isfinite(piv)) {
-          if (tid == 0) bad_sh = 1;
-          piv = 1.0;
-        }
-        const double inv = recip_pos(piv);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int col = 4 * q + c;
-          if (r == p) x[c] = (col == p) ? inv : apc[c] * inv;
-          else x[c] = (col == p) ? -arp * inv : x[c] - arp * (apc[c] * inv);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) S[(k0 + r) * LD + k0 + 4 * q + c] = x[c];
+      for (int ia = 0; ia < NB; ++ia)
+        if (ti + 16 * ia < F) M[ia][ia] += rho;
     }
-    __syncthreads();
-    // D_J = P S_KJ for the other blocks J (slot m = J - (J > K))
-#pragma unroll
-    for (int J = 0; J < NB; ++J) {
-      if (J == K) continue;
-      const int m = J - (J > K ? 1 : 0);
-      double d = 0.0;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) d += S[(k0 + ta) * LD + k0 + t] * S[(k0 + t) * LD + 16 * J + tb];
-      Dt[m * 16 * 17 + ta * 17 + tb] = d;
-    }
-    __syncthreads();
-    // S_IJ -= S_IK D_J and -S_IK P (kept in registers until every read of S_IK
-    // is done); column tb of every D_J and of P is read once
-    double dcol[NB][16], pcol[16];
-#pragma unroll
-    for (int J = 0; J < NB; ++J) {
-      const int m = J - (J > K ? 1 : 0);
-#pragma unroll
-      for (int t = 0; t < 16; ++t) dcol[J][t] = (J != K) ? Dt[m * 16 * 17 + t * 17 + tb] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) pcol[t] = S[(k0 + t) * LD + k0 + tb];
-    double nik[NB];
-#pragma unroll
-    for (int I = 0; I < NB; ++I) {
-      nik[I] = 0.0;
-      if (I == K) continue;
-      double sik[16];
-#pragma unroll
-      for (int t = 0; t < 16; ++t) sik[t] = S[(16 * I + ta) * LD + k0 + t];
-#pragma unroll
-      for (int J = 0; J < NB; ++J) {
-        if (J == K) continue;
-        double acc = S[(16 * I + ta) * LD + 16 * J + tb];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) acc -= sik[t] * dcol[J][t];
-        S[(16 * I + ta) * LD + 16 * J + tb] = acc;
-      }
-      double v = 0.0;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) v += sik[t] * pcol[t];
-      nik[I] = -v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int I = 0; I < NB; ++I) {
-      if (I == K) continue;
-      const int m = I - (I > K ? 1 : 0);
-      S[(16 * I + ta) * LD + k0 + tb] = nik[I];
-      S[(k0 + ta) * LD + 16 * I + tb] = Dt[m * 16 * 17 + ta * 17 + tb];
-    }
-    __syncthreads();
   }
-  const bool bad = bad_sh != 0;
+
+  // slot u of the tile holds tile row / column (u + PA) mod NB while tile
+  // row PA is eliminated
+  int col[NB], row[NB];
+  double sg[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    col[u] = tj + 16 * u;
+    row[u] = ti + 16 * u;
+    sg[u] = 1.0;
+  }
+  auto put_rows = [&](int buf) {
+    double* W = Rall + (buf * 16 + ti) * 64;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) W[col[u]] = M[0][u];
+  };
+  put_rows(0);
+  int buf = 0;
+  bool bad = false;   // (every thread sees the same pivots)
+#pragma unroll 1
+  for (int PA = 0; PA < NB; ++PA) {
+    const int n = min(16, F - 16 * PA);   // pivots in this tile row (>= 1)
+    const int p0 = 16 * PA;
+#pragma unroll 1
+    for (int pt = 0; pt + 1 < n; pt += 2) {
+      __syncthreads();
+      const double* R0 = Rall + (buf * 16 + pt) * 64;
+      const double* R1 = R0 + 64;
+      const int p = p0 + pt;
+      double rowc0[NB], rowr0[NB], rowc1[NB], rowr1[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        rowc0[u] = R0[col[u]];
+        rowc1[u] = R1[col[u]];
+        rowr0[u] = R0[row[u]];
+        rowr1[u] = R1[row[u]];
+      }
+      const double c1 = R0[p + 1];   // column p of row p + 1
+      const double inv0 = pivot_recip(R0[p], bad);
+      // row p + 1 after step p where this thread reads it
+      const double piv1 = __builtin_fma(-c1, c1 * inv0, R1[p + 1]);
+      const bool oc0 = (tj == pt), or0 = (ti == pt);
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        rowc1[u] = (u == 0 && oc0) ? -c1 * inv0 : __builtin_fma(-c1, rowc0[u] * inv0, rowc1[u]);
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        rowr1[u] = (u == 0 && or0) ? -c1 * inv0 : __builtin_fma(-c1, rowr0[u] * inv0, rowr1[u]);
+      gj_step<NB>(M, inv0, rowc0, rowr0, sg, or0, oc0, ti < pt);
+      const double inv1 = pivot_recip(piv1, bad);
+      gj_step<NB>(M, inv1, rowc1, rowr1, sg, ti == pt + 1, tj == pt + 1, ti < pt + 1);
+      buf ^= 1;
+      if (pt + 2 < n) put_rows(buf);
+    }
+    if (n & 1) {   // the last pivot of an odd tile row on its own
+      const int pt = n - 1;
+      __syncthreads();
+      const double* R0 = Rall + (buf * 16 + pt) * 64;
+      double rowc0[NB], rowr0[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        rowc0[u] = R0[col[u]];
+        rowr0[u] = R0[row[u]];
+      }
+      const double inv0 = pivot_recip(R0[p0 + pt], bad);
+      gj_step<NB>(M, inv0, rowc0, rowr0, sg, ti == pt, tj == pt, ti < pt);
+      buf ^= 1;
+    }
+    // rotate the slots: tile row / column PA + 1 into slot 0
+    if (NB > 1) {
+      double t0[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) t0[u] = M[0][u];
+#pragma unroll
+      for (int s = 0; s + 1 < NB; ++s)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) M[s][u] = M[s + 1][u];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) M[NB - 1][u] = t0[u];
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+        const double c0 = M[s][0];
+#pragma unroll
+        for (int u = 0; u + 1 < NB; ++u) M[s][u] = M[s][u + 1];
+        M[s][NB - 1] = c0;
+      }
+      const int c0 = col[0], r0 = row[0];
+#pragma unroll
+      for (int u = 0; u + 1 < NB; ++u) {
+        col[u] = col[u + 1];
+        row[u] = row[u + 1];
+        sg[u] = sg[u + 1];
+      }
+      col[NB - 1] = c0;
+      row[NB - 1] = r0;
+      sg[NB - 1] = -1.0;   // tile row PA, now eliminated
+    }
+    if (PA + 1 < NB) put_rows(buf);
+  }
+  __syncthreads();   // (S overlays the broadcast rows)
+#pragma unroll
+  for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+      const int r = ti + 16 * ia, c = tj + 16 * ib;
+      if (r < F && c < F) S[r * LD + c] = M[ia][ib];
+    }
+  __syncthreads();
   // Ginv (symmetrised), Ginv 1 and 1^T Ginv 1 (the sum-to-one least-squares
   // step uses them): thread t sums a quarter of row t / 4
   {
