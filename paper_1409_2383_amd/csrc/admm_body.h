@@ -435,40 +435,60 @@ static __device__ __forceinline__ double recip_pos(double x) {
   return r;
 }
 
-// One Gauss-Jordan step on a thread's tile (below) with the pivot p in tile
-// row and column slot 0.  rowc[u] / rowr[s] hold row p as it stands before
-// the step at the thread's columns of slot u and at its rows of slot s (the
-// column p entries of those rows, by symmetry up to sign); sg[s] is -1 for
-// slots of tile rows before p's, +1 after; inv = 1 / pivot; own_r / own_c:
-// the thread holds row p / column p in slot 0, before_r: its slot-0 row
-// precedes p.
+// Factors of one Gauss-Jordan step on a thread's tile (below) with the pivot
+// p in tile row and column slot 0.  rowc[u] / rowr[s] hold row p as it
+// stands before the step at the thread's columns of slot u and at its rows of
+// slot s (the column p entries of those rows, by symmetry up to sign); sg[s]
+// is -1 for slots of tile rows before p's, +1 after; inv = 1 / pivot; own_r /
+// own_c: the thread holds row p / column p in slot 0, before_r: its slot-0
+// row precedes p.  Every entry becomes fma(-cv[s], rs[u], M[s][u]); row p and
+// column p go through the same form with their old value multiplied by 0
+// (kr, kc) and the factors replaced: cv = -1 on row p, rs = 1 / pivot on
+// column p.
 template <int NB>
-__device__ __forceinline__ void gj_step(double (&M)[NB][NB], double inv, const double (&rowc)[NB],
-                                        const double (&rowr)[NB], const double (&sg)[NB], bool own_r,
-                                        bool own_c, bool before_r) {
-  double rs[NB], cv[NB];
-  cv[0] = before_r ? -rowr[0] : rowr[0];
+struct GjStep {
+  double cv[NB], rs[NB], kr, kc;
+};
+
+template <int NB>
+__device__ __forceinline__ GjStep<NB> gj_factors(double inv, const double (&rowc)[NB],
+                                                 const double (&rowr)[NB], const double (&sg)[NB],
+                                                 bool own_r, bool own_c, bool before_r) {
+  GjStep<NB> g;
+  g.kr = own_r ? 0.0 : 1.0;
+  g.kc = own_c ? 0.0 : 1.0;
+  g.cv[0] = own_r ? -1.0 : (before_r ? -rowr[0] : rowr[0]);
+  g.rs[0] = own_c ? inv : rowc[0] * inv;
 #pragma unroll
-  for (int s = 1; s < NB; ++s) cv[s] = rowr[s] * sg[s];
+  for (int s = 1; s < NB; ++s) g.cv[s] = rowr[s] * sg[s];
 #pragma unroll
-  for (int u = 0; u < NB; ++u) rs[u] = rowc[u] * inv;   // row p over the pivot
-  // every entry as if off row and column p, then column p and row p
-#pragma unroll
-  for (int s = 0; s < NB; ++s)
-#pragma unroll
-    for (int u = 0; u < NB; ++u) M[s][u] = __builtin_fma(-cv[s], rs[u], M[s][u]);
-#pragma unroll
-  for (int s = 0; s < NB; ++s) M[s][0] = own_c ? -cv[s] * inv : M[s][0];
-#pragma unroll
-  for (int u = 0; u < NB; ++u) M[0][u] = own_r ? rs[u] : M[0][u];
-  M[0][0] = (own_r && own_c) ? inv : M[0][0];
+  for (int u = 1; u < NB; ++u) g.rs[u] = rowc[u] * inv;   // row p over the pivot
+  return g;
 }
 
-static __device__ __forceinline__ double pivot_recip(double piv, bool& bad) {
-  if (!(piv > 0.0) || !isfinite(piv)) {
-    bad = true;
-    piv = 1.0;
+// the step on tile row slot 0 (the row that is broadcast next)
+template <int NB>
+__device__ __forceinline__ void gj_row0(double (&M)[NB][NB], const GjStep<NB>& g) {
+  M[0][0] = __builtin_fma(-g.cv[0], g.rs[0], M[0][0] * (g.kr * g.kc));
+#pragma unroll
+  for (int u = 1; u < NB; ++u) M[0][u] = __builtin_fma(-g.cv[0], g.rs[u], M[0][u] * g.kr);
+}
+
+// the step on tile row slots 1 .. NB-1
+template <int NB>
+__device__ __forceinline__ void gj_rest(double (&M)[NB][NB], const GjStep<NB>& g) {
+#pragma unroll
+  for (int s = 1; s < NB; ++s) {
+    M[s][0] = __builtin_fma(-g.cv[s], g.rs[0], M[s][0] * g.kc);
+#pragma unroll
+    for (int u = 1; u < NB; ++u) M[s][u] = __builtin_fma(-g.cv[s], g.rs[u], M[s][u]);
   }
+}
+
+// (a pivot that is not positive and finite only sets the flag: the result is
+// discarded then, so what it does to the rest of the elimination is moot)
+static __device__ __forceinline__ double pivot_recip(double piv, bool& bad) {
+  bad |= !(piv > 0.0) || !isfinite(piv);
   return recip_pos(piv);
 }
 
@@ -562,18 +582,15 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
 
   // slot u of the tile holds tile row / column (u + PA) mod NB while tile
   // row PA is eliminated
-  int col[NB], row[NB];
   double sg[NB];
 #pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    col[u] = tj + 16 * u;
-    row[u] = ti + 16 * u;
-    sg[u] = 1.0;
-  }
+  for (int u = 0; u < NB; ++u) sg[u] = 1.0;
+  // a broadcast row is stored in slot order (slot u of column group tj at
+  // tj + 16 u), so every read below is a fixed offset from a lane base
   auto put_rows = [&](int buf) {
-    double* W = Rall + (buf * 16 + ti) * 64;
+    double* W = Rall + (buf * 16 + ti) * 64 + tj;
 #pragma unroll
-    for (int u = 0; u < NB; ++u) W[col[u]] = M[0][u];
+    for (int u = 0; u < NB; ++u) W[16 * u] = M[0][u];
   };
   put_rows(0);
   int buf = 0;
@@ -581,35 +598,61 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
 #pragma unroll 1
   for (int PA = 0; PA < NB; ++PA) {
     const int n = min(16, F - 16 * PA);   // pivots in this tile row (>= 1)
-    const int p0 = 16 * PA;
+    // Steps p and p + 1 together, as one step with the 2 x 2 pivot block
+    // P = [a b; b d] of rows and columns K = {p, p + 1}:
+    //   M_KK <- P^{-1},  M_Kj <- P^{-1} M_Kj,  M_iK <- -M_iK P^{-1},
+    //   M_ij <- M_ij - M_iK P^{-1} M_Kj
+    // (one reciprocal, of det P = a d - b^2 = a times the second pivot)
 #pragma unroll 1
     for (int pt = 0; pt + 1 < n; pt += 2) {
       __syncthreads();
       const double* R0 = Rall + (buf * 16 + pt) * 64;
       const double* R1 = R0 + 64;
-      const int p = p0 + pt;
       double rowc0[NB], rowr0[NB], rowc1[NB], rowr1[NB];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
-        rowc0[u] = R0[col[u]];
-        rowc1[u] = R1[col[u]];
-        rowr0[u] = R0[row[u]];
-        rowr1[u] = R1[row[u]];
+        rowc0[u] = R0[tj + 16 * u];
+        rowc1[u] = R1[tj + 16 * u];
+        rowr0[u] = R0[ti + 16 * u];
+        rowr1[u] = R1[ti + 16 * u];
       }
-      const double c1 = R0[p + 1];   // column p of row p + 1
-      const double inv0 = pivot_recip(R0[p], bad);
-      // row p + 1 after step p where this thread reads it
-      const double piv1 = __builtin_fma(-c1, c1 * inv0, R1[p + 1]);
-      const bool oc0 = (tj == pt), or0 = (ti == pt);
+      const double pa = R0[pt], pb = R0[pt + 1], pd = R1[pt + 1];
+      const double det = __builtin_fma(pa, pd, -(pb * pb));
+      bad |= !(pa > 0.0) || !isfinite(pa) || !(det > 0.0) || !isfinite(det);
+      const double rd = recip_pos(det);
+      const double q00 = pd * rd, q01 = -pb * rd, q11 = pa * rd;   // P^{-1}
+      const bool or0 = (ti == pt), or1 = (ti == pt + 1), oc0 = (tj == pt), oc1 = (tj == pt + 1);
+      // P^{-1} M_Kc at the thread's columns, -M_rK (signed rows p, p + 1 at
+      // its rows), with the substitutions that give rows and columns K
+      double w0[NB], w1[NB], c0[NB], c1[NB];
 #pragma unroll
-      for (int u = 0; u < NB; ++u)
-        rowc1[u] = (u == 0 && oc0) ? -c1 * inv0 : __builtin_fma(-c1, rowc0[u] * inv0, rowc1[u]);
+      for (int u = 0; u < NB; ++u) {
+        w0[u] = __builtin_fma(q00, rowc0[u], q01 * rowc1[u]);
+        w1[u] = __builtin_fma(q01, rowc0[u], q11 * rowc1[u]);
+      }
+      w0[0] = oc0 ? q00 : oc1 ? q01 : w0[0];
+      w1[0] = oc0 ? q01 : oc1 ? q11 : w1[0];
+      {
+        const double s0 = (ti < pt) ? -1.0 : 1.0;
+        c0[0] = or0 ? -1.0 : or1 ? 0.0 : rowr0[0] * s0;
+        c1[0] = or0 ? 0.0 : or1 ? -1.0 : rowr1[0] * s0;
+      }
 #pragma unroll
-      for (int u = 0; u < NB; ++u)
-        rowr1[u] = (u == 0 && or0) ? -c1 * inv0 : __builtin_fma(-c1, rowr0[u] * inv0, rowr1[u]);
-      gj_step<NB>(M, inv0, rowc0, rowr0, sg, or0, oc0, ti < pt);
-      const double inv1 = pivot_recip(piv1, bad);
-      gj_step<NB>(M, inv1, rowc1, rowr1, sg, ti == pt + 1, tj == pt + 1, ti < pt + 1);
+      for (int u = 1; u < NB; ++u) {
+        c0[u] = rowr0[u] * sg[u];
+        c1[u] = rowr1[u] * sg[u];
+      }
+      const double kr = (or0 || or1) ? 0.0 : 1.0, kc = (oc0 || oc1) ? 0.0 : 1.0;
+#pragma unroll
+      for (int sl = 0; sl < NB; ++sl)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          double m = M[sl][u];
+          if (sl == 0 && u == 0) m *= kr * kc;
+          else if (sl == 0) m *= kr;
+          else if (u == 0) m *= kc;
+          M[sl][u] = __builtin_fma(-c0[sl], w0[u], __builtin_fma(-c1[sl], w1[u], m));
+        }
       buf ^= 1;
       if (pt + 2 < n) put_rows(buf);
     }
@@ -620,11 +663,13 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
       double rowc0[NB], rowr0[NB];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
-        rowc0[u] = R0[col[u]];
-        rowr0[u] = R0[row[u]];
+        rowc0[u] = R0[tj + 16 * u];
+        rowr0[u] = R0[ti + 16 * u];
       }
-      const double inv0 = pivot_recip(R0[p0 + pt], bad);
-      gj_step<NB>(M, inv0, rowc0, rowr0, sg, ti == pt, tj == pt, ti < pt);
+      const double inv0 = pivot_recip(R0[pt], bad);
+      const GjStep<NB> g = gj_factors<NB>(inv0, rowc0, rowr0, sg, ti == pt, tj == pt, ti < pt);
+      gj_row0<NB>(M, g);
+      gj_rest<NB>(M, g);
       buf ^= 1;
     }
     // rotate the slots: tile row / column PA + 1 into slot 0
@@ -645,15 +690,8 @@ __device__ __forceinline__ void prep_body(const PrepK& a, double* lds, const int
         for (int u = 0; u + 1 < NB; ++u) M[s][u] = M[s][u + 1];
         M[s][NB - 1] = c0;
       }
-      const int c0 = col[0], r0 = row[0];
 #pragma unroll
-      for (int u = 0; u + 1 < NB; ++u) {
-        col[u] = col[u + 1];
-        row[u] = row[u + 1];
-        sg[u] = sg[u + 1];
-      }
-      col[NB - 1] = c0;
-      row[NB - 1] = r0;
+      for (int u = 0; u + 1 < NB; ++u) sg[u] = sg[u + 1];
       sg[NB - 1] = -1.0;   // tile row PA, now eliminated
     }
     if (PA + 1 < NB) put_rows(buf);
