@@ -221,8 +221,8 @@ static __device__ void resid_totals(const double* __restrict__ part, int nparts,
 }
 
 template <typename HT>
-__device__ void gram_rows(const HT* __restrict__ H, int64_t r0, int64_t r1, int F, int gram_f32,
-                          double* __restrict__ part, double* hs);
+__device__ void gram_rows_mfma(const HT* __restrict__ H, int64_t r0, int64_t r1, int F,
+                               double* __restrict__ part);
 
 template <int NB>
 __global__ __launch_bounds__(256) void k_prep(PrepK a) {
@@ -230,21 +230,21 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   const int tid = threadIdx.x;
   __shared__ int is_last;
   __shared__ double prep_lds[kPrepLdsDoubles];
-  static_assert(kPrepLdsDoubles >= 64 * 64, "the Gram stage borrows the prepare LDS");
   // the inputs that do not depend on this kernel's Gram, loaded before it
   PrepIn<NB> in;
   prep_load_b(a, tid, in);
   bool have_a = false;
   if (a.gram_h) {
     // direct Gram: block b sums rows [b rpp, (b+1) rpp) of the updated factor
-    // in FP64; the last block to finish reduces the partials (4 fixed groups)
+    // in FP64 on the matrix cores; the last block to finish reduces the
+    // partials (4 fixed groups)
     const int64_t r0 = (int64_t)blockIdx.x * a.gram_rpp;
     const int64_t r1 = min(a.gram_rows, r0 + a.gram_rpp);
     double* part = a.gram_scratch + (int64_t)blockIdx.x * F * F;
     if (a.h_f64)
-      gram_rows<double>(reinterpret_cast<const double*>(a.gram_h), r0, r1, F, 0, part, prep_lds);
+      gram_rows_mfma<double>(reinterpret_cast<const double*>(a.gram_h), r0, r1, F, part);
     else
-      gram_rows<float>(reinterpret_cast<const float*>(a.gram_h), r0, r1, F, 0, part, prep_lds);
+      gram_rows_mfma<float>(reinterpret_cast<const float*>(a.gram_h), r0, r1, F, part);
     if (blockIdx.x == 0) resid_totals(a.resid_part, a.nparts, a.resid_dst);
     __threadfence();
     __syncthreads();
@@ -541,6 +541,115 @@ __global__ __launch_bounds__(256) void k_gram_part(const HT* __restrict__ H, int
   __shared__ double hs[64 * 64];
   const int64_t r0 = (int64_t)blockIdx.x * rpp, r1 = min(rows, r0 + rpp);
   gram_rows<HT>(H, r0, r1, F, gram_f32, part + (int64_t)blockIdx.x * F * F, hs);
+}
+
+// One partial by the FP64 matrix cores: rows [r0, r1) of H into part[0 ..
+// F*F).  The F x F result is cut into 16 x 16 tiles (I, J), I <= J, dealt
+// round-robin to the 4 waves; a wave walks the rows 4 at a time, each step
+// one v_mfma_f64_16x16x4 per tile with operands read straight from H (lane
+// l: row l / 16 of the step, column 16 X + l % 16 of tile row / column X;
+// products of FP32 factors are exact in FP64).  Each entry is summed over
+// the rows in order, 4 rows per instruction; the result is written to both
+// triangles (the diagonal tiles from their upper half), so it is exactly
+// symmetric.  Used by the prepare step's direct Gram and by every Gram of the
+// dense path that must match it bitwise.
+template <typename HT>
+__device__ void gram_rows_mfma(const HT* __restrict__ H, int64_t r0, int64_t r1, int F,
+                               double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nbt = (F + 15) >> 4;
+  const int ntile = nbt * (nbt + 1) / 2;
+  // this wave's tiles (at most 3): t = wave, wave + 4, wave + 8
+  int tI[3], tJ[3];
+  bool on[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int t = wave + 4 * q;
+    on[q] = t < ntile;
+    int I = 0, rem = on[q] ? t : 0;
+    while (rem >= nbt - I) {   // (row-major order over I <= J)
+      rem -= nbt - I;
+      ++I;
+    }
+    tI[q] = I;
+    tJ[q] = I + rem;
+  }
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (on[0]) {
+    // operands of a step for tile q: row lk of the step, columns 16 tI + li
+    // (A) and 16 tJ + li (B), through a buffer resource over the step rows
+    // (rows past r1 and columns past F read as zeros)
+    constexpr int es = (int)sizeof(HT);
+    int oa[3], ob[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int ca = 16 * tI[q] + li, cb = 16 * tJ[q] + li;
+      oa[q] = (on[q] && ca < F) ? (lk * F + ca) * es : kBufferOOB;
+      ob[q] = (on[q] && cb < F) ? (lk * F + cb) * es : kBufferOOB;
+    }
+    constexpr int U = 8;   // steps of 4 rows per resource, all loads in flight
+    auto ld = [&](__amdgpu_buffer_rsrc_t rs, int off, int soff) -> double {
+      if constexpr (sizeof(HT) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, soff, 0));
+      else
+        return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, soff, 0));
+    };
+    for (int64_t rb = r0; rb < r1; rb += 4 * U) {
+      const int nr = (int)min((int64_t)(4 * U), r1 - rb);
+      const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(H + rb * F, nr * F * es);
+      double va[U][3], vb[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          va[u][q] = on[q] ? ld(rs, oa[q], u * 4 * F * es) : 0.0;
+          vb[u][q] = on[q] ? ld(rs, ob[q], u * 4 * F * es) : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if (on[q]) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u][q], vb[u][q], acc[q], 0, 0, 0);
+    }
+  }
+  // D[i][j] of a tile sits in lane j + 16 (i % 4), register i / 4
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (!on[q]) continue;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int i = 4 * rr + lk, j = li;
+      const int gi = 16 * tI[q] + i, gj = 16 * tJ[q] + j;
+      const double v = acc[q][rr];
+      if (gi < F && gj < F && (tI[q] != tJ[q] || i <= j)) {
+        part[gi * F + gj] = v;
+        part[gj * F + gi] = v;
+      }
+    }
+  }
+}
+
+template <typename HT>
+__global__ __launch_bounds__(256) void k_gram_mfma(const HT* __restrict__ H, int64_t rows, int F,
+                                                   int64_t rpp, double* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * rpp, r1 = min(rows, r0 + rpp);
+  gram_rows_mfma<HT>(H, r0, r1, F, part + (int64_t)blockIdx.x * F * F);
+}
+
+hipError_t launch_gram_direct(const void* H, int h_f64, int64_t rows, int F, int64_t rpp,
+                              double* part, hipStream_t s) {
+  const int nparts = (int)((rows + rpp - 1) / rpp);
+  if (h_f64)
+    hipLaunchKernelGGL(k_gram_mfma<double>, dim3(nparts), dim3(256), 0, s, (const double*)H, rows, F,
+                       rpp, part);
+  else
+    hipLaunchKernelGGL(k_gram_mfma<float>, dim3(nparts), dim3(256), 0, s, (const float*)H, rows, F,
+                       rpp, part);
+  return hipGetLastError();
 }
 
 void gram_split(int64_t rows, int64_t* rpp, int* nb) {

@@ -355,7 +355,7 @@ static hipError_t direct_gram(ntf_admm_ctx* c, int m, double* out, hipStream_t s
   int nb;
   gram_split(d[m], &rpp, &nb);
   double* gpart = c->at<double>(c->lay.gpart);
-  hipError_t e = launch_gram_part(c->feed(m), c->hf64(), d[m], p.F, rpp, 0, gpart, s);
+  hipError_t e = launch_gram_direct(c->feed(m), c->hf64(), d[m], p.F, rpp, gpart, s);
   if (e != hipSuccess) return e;
   return launch_reduce_partials(gpart, 1, (int64_t)p.F * p.F, p.F, nb, p.F, p.F, out, s, 4);
 }
@@ -651,7 +651,7 @@ static hipError_t finish_stats(ntf_admm_ctx* c, double* out) {
   int nb;
   gram_split(p.K, &rpp, &nb);
   double* gpart = c->at<double>(c->lay.gpart);
-  hipError_t e = launch_gram_part(c->feed(2), c->hf64(), p.K, p.F, rpp, 0, gpart, c->s0);
+  hipError_t e = launch_gram_direct(c->feed(2), c->hf64(), p.K, p.F, rpp, gpart, c->s0);
   if (e != hipSuccess) return e;
   return launch_finish(p.F, gpart, nb, c->at<double>(c->lay.rpart), p.nblk_inner[2],
                        c->at<double>(c->lay.gram[0]), c->at<double>(c->lay.gram[1]),

@@ -154,6 +154,10 @@ hipError_t launch_finish(int F, const double* gram_part, int gram_nparts, const 
 // Gram of a factor by rows: the partition (rows per partial, partials) the
 // prepare step's direct Gram uses for `rows` rows
 void gram_split(int64_t rows, int64_t* rpp, int* nb);
+// FP64 Gram partials by the matrix cores, the partition of gram_split (the
+// prepare step's direct Gram forms the same partials)
+hipError_t launch_gram_direct(const void* H, int h_f64, int64_t rows, int F, int64_t rpp,
+                              double* part, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 
 // Cardinality constraint (card.hip): from V, Ht^T and the factor before the
