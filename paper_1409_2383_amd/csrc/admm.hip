@@ -220,9 +220,9 @@ static __device__ void resid_totals(const double* __restrict__ part, int nparts,
   __syncthreads();
 }
 
-template <typename HT>
-__device__ void gram_rows_mfma(const HT* __restrict__ H, int64_t r0, int64_t r1, int F,
-                               double* __restrict__ part);
+template <typename HT, int NB>
+__device__ __forceinline__ void gram_rows_mfma(const HT* __restrict__ H, int64_t r0, int64_t r1, int F,
+                               double* __restrict__ part, double* lds);
 
 template <int NB>
 __global__ __launch_bounds__(256) void k_prep(PrepK a) {
@@ -230,6 +230,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
   const int tid = threadIdx.x;
   __shared__ int is_last;
   __shared__ double prep_lds[kPrepLdsDoubles];
+  static_assert(kPrepLdsDoubles >= kGramLdsDoubles, "the Gram stage borrows the prepare LDS");
   // the inputs that do not depend on this kernel's Gram, loaded before it
   PrepIn<NB> in;
   prep_load_b(a, tid, in);
@@ -241,11 +242,13 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
     const int64_t r0 = (int64_t)blockIdx.x * a.gram_rpp;
     const int64_t r1 = min(a.gram_rows, r0 + a.gram_rpp);
     double* part = a.gram_scratch + (int64_t)blockIdx.x * F * F;
-    if (a.h_f64)
-      gram_rows_mfma<double>(reinterpret_cast<const double*>(a.gram_h), r0, r1, F, part);
+    // (the block past the partials sums the residual partials meanwhile)
+    if (blockIdx.x == a.gram_nb)
+      resid_totals(a.resid_part, a.nparts, a.resid_dst);
+    else if (a.h_f64)
+      gram_rows_mfma<double, NB>(reinterpret_cast<const double*>(a.gram_h), r0, r1, F, part, prep_lds);
     else
-      gram_rows_mfma<float>(reinterpret_cast<const float*>(a.gram_h), r0, r1, F, part);
-    if (blockIdx.x == 0) resid_totals(a.resid_part, a.nparts, a.resid_dst);
+      gram_rows_mfma<float, NB>(reinterpret_cast<const float*>(a.gram_h), r0, r1, F, part, prep_lds);
     __threadfence();
     __syncthreads();
     if (tid == 0) {
@@ -364,7 +367,7 @@ hipError_t launch_prep(const PrepArgs& pa, int nblk, hipStream_t s) {
   k.gram_rpp = pa.gram_rpp;
   k.gram_nb = pa.gram_nb;
   k.gram_scratch = pa.gram_scratch;
-  const int grid = pa.gram_h ? pa.gram_nb : pa.gram_part ? nblk : 1;
+  const int grid = pa.gram_h ? pa.gram_nb + 1 : pa.gram_part ? nblk : 1;
   switch ((pa.F + 15) / 16) {
     case 1: hipLaunchKernelGGL(k_prep<1>, dim3(grid), dim3(256), 0, s, k); break;
     case 2: hipLaunchKernelGGL(k_prep<2>, dim3(grid), dim3(256), 0, s, k); break;
@@ -544,122 +547,136 @@ __global__ __launch_bounds__(256) void k_gram_part(const HT* __restrict__ H, int
 }
 
 // One partial by the FP64 matrix cores: rows [r0, r1) of H into part[0 ..
-// F*F).  The F x F result is cut into 16 x 16 tiles (I, J), I <= J, dealt
-// round-robin to the 4 waves; a wave walks the rows 4 at a time, each step
-// one v_mfma_f64_16x16x4 per tile with operands read straight from H (lane
-// l: row l / 16 of the step, column 16 X + l % 16 of tile row / column X;
-// products of FP32 factors are exact in FP64).  Each entry is summed over
-// the rows in order, 4 rows per instruction; the result is written to both
-// triangles (the diagonal tiles from their upper half), so it is exactly
-// symmetric.  Used by the prepare step's direct Gram and by every Gram of the
-// dense path that must match it bitwise.
-template <typename HT>
-__device__ void gram_rows_mfma(const HT* __restrict__ H, int64_t r0, int64_t r1, int F,
-                               double* __restrict__ part) {
+// F*F), NB = ceil(F / 16).  Wave w sums a quarter of the rows (in steps of 4
+// rows, 16 steps of loads in flight) into every 16 x 16 tile (I, J), I <= J,
+// one v_mfma_f64_16x16x4 per tile and step with operands read straight from H
+// (lane l: row l / 16 of the step, column 16 X + l % 16 of tile row / column
+// X; products of FP32 factors are exact in FP64); the four waves' tiles are
+// then added in wave order through LDS (kGramLdsDoubles) and written to both
+// triangles (the diagonal tiles from their upper half), so the partial is
+// exactly symmetric.  Used by the prepare step's direct Gram and by every
+// Gram of the dense path that must match it bitwise.
+template <typename HT, int NB>
+__device__ __forceinline__ void gram_rows_mfma(const HT* __restrict__ H, int64_t r0, int64_t r1, int F,
+                               double* __restrict__ part, double* lds) {
+  constexpr int NT = NB * (NB + 1) / 2;   // tiles I <= J, row-major
+  constexpr int es = (int)sizeof(HT);
+  constexpr int U = 16;                   // steps of loads in flight
+  constexpr int G = 4;                    // tiles per round of the wave sum
+  static_assert(4 * G * 4 * 64 <= kGramLdsDoubles, "LDS of the wave sum");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nbt = (F + 15) >> 4;
-  const int ntile = nbt * (nbt + 1) / 2;
-  // this wave's tiles (at most 3): t = wave, wave + 4, wave + 8
-  int tI[3], tJ[3];
-  bool on[3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int t = wave + 4 * q;
-    on[q] = t < ntile;
-    int I = 0, rem = on[q] ? t : 0;
-    while (rem >= nbt - I) {   // (row-major order over I <= J)
-      rem -= nbt - I;
-      ++I;
-    }
-    tI[q] = I;
-    tJ[q] = I + rem;
-  }
   const int li = lane & 15, lk = lane >> 4;
-  f64x4 acc[3];
+  const int64_t nsteps = (r1 > r0) ? (r1 - r0 + 3) / 4 : 0;
+  const int64_t per = (nsteps + 3) / 4;
+  const int64_t ws0 = min(nsteps, wave * per), ws1 = min(nsteps, ws0 + per);
+  int off[NB];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  if (on[0]) {
-    // operands of a step for tile q: row lk of the step, columns 16 tI + li
-    // (A) and 16 tJ + li (B), through a buffer resource over the step rows
-    // (rows past r1 and columns past F read as zeros)
-    constexpr int es = (int)sizeof(HT);
-    int oa[3], ob[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int ca = 16 * tI[q] + li, cb = 16 * tJ[q] + li;
-      oa[q] = (on[q] && ca < F) ? (lk * F + ca) * es : kBufferOOB;
-      ob[q] = (on[q] && cb < F) ? (lk * F + cb) * es : kBufferOOB;
-    }
-    constexpr int U = 8;   // steps of 4 rows per resource, all loads in flight
-    auto ld = [&](__amdgpu_buffer_rsrc_t rs, int off, int soff) -> double {
-      if constexpr (sizeof(HT) == 8)
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, soff, 0));
-      else
-        return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, soff, 0));
-    };
-    for (int64_t rb = r0; rb < r1; rb += 4 * U) {
-      const int nr = (int)min((int64_t)(4 * U), r1 - rb);
-      const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(H + rb * F, nr * F * es);
-      double va[U][3], vb[U][3];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          va[u][q] = on[q] ? ld(rs, oa[q], u * 4 * F * es) : 0.0;
-          vb[u][q] = on[q] ? ld(rs, ob[q], u * 4 * F * es) : 0.0;
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          if (on[q]) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u][q], vb[u][q], acc[q], 0, 0, 0);
-    }
+  for (int X = 0; X < NB; ++X) {
+    const int c = 16 * X + li;
+    off[X] = (c < F) ? (lk * F + c) * es : kBufferOOB;
   }
-  // D[i][j] of a tile sits in lane j + 16 (i % 4), register i / 4
+  f64x4 acc[NT];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    if (!on[q]) continue;
+  for (int t = 0; t < NT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t sb = ws0; sb < ws1; sb += U) {
+    const int ns = (int)min((int64_t)U, ws1 - sb);
+    const int64_t rb = r0 + 4 * sb;
+    const int nr = (int)min((int64_t)(4 * ns), r1 - rb);
+    const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(H + rb * F, nr * F * es);
+    HT v[U][NB];
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int i = 4 * rr + lk, j = li;
-      const int gi = 16 * tI[q] + i, gj = 16 * tJ[q] + j;
-      const double v = acc[q][rr];
-      if (gi < F && gj < F && (tI[q] != tJ[q] || i <= j)) {
-        part[gi * F + gj] = v;
-        part[gj * F + gi] = v;
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int X = 0; X < NB; ++X) {
+        if constexpr (sizeof(HT) == 8)
+          v[u][X] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off[X], u * 4 * F * es, 0));
+        else
+          v[u][X] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off[X], u * 4 * F * es, 0));
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (u < ns) {
+#pragma unroll
+        for (int I = 0; I < NB; ++I)
+#pragma unroll
+          for (int J = I; J < NB; ++J) {
+            const int t = I * NB - I * (I - 1) / 2 + (J - I);
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[u][I], (double)v[u][J], acc[t], 0, 0, 0);
+          }
       }
     }
   }
+  // ((w0 + w1) + w2) + w3 per entry, G tiles per round: every wave stores its
+  // tiles, then wave w adds up tile g0 + w.  D[i][j] of a tile sits in lane
+  // j + 16 (i % 4), register i / 4.
+#pragma unroll
+  for (int g0 = 0; g0 < NT; g0 += G) {
+    __syncthreads();
+#pragma unroll
+    for (int t = g0; t < g0 + G && t < NT; ++t)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) lds[((wave * G + (t - g0)) * 4 + rr) * 64 + lane] = acc[t][rr];
+    __syncthreads();
+    const int t = g0 + wave;
+    if (t < NT) {
+      int I = 0, rem = t;
+      while (rem >= NB - I) {
+        rem -= NB - I;
+        ++I;
+      }
+      const int J = I + rem;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const double* L = lds + ((t - g0) * 4 + rr) * 64 + lane;
+        const double vsum = ((L[0] + L[G * 4 * 64]) + L[2 * G * 4 * 64]) + L[3 * G * 4 * 64];
+        const int i = 4 * rr + lk, j = li;
+        const int gi = 16 * I + i, gj = 16 * J + j;
+        if (gi < F && gj < F && (I != J || i <= j)) {
+          part[gi * F + gj] = vsum;
+          part[gj * F + gi] = vsum;
+        }
+      }
+    }
+  }
+  __syncthreads();   // (the caller reuses the LDS)
+}
+
+template <typename HT, int NB>
+__global__ __launch_bounds__(256) void k_gram_mfma(const HT* __restrict__ H, int64_t rows, int F,
+                                                   int64_t rpp, double* __restrict__ part) {
+  __shared__ double lds[kGramLdsDoubles];
+  const int64_t r0 = (int64_t)blockIdx.x * rpp, r1 = min(rows, r0 + rpp);
+  gram_rows_mfma<HT, NB>(H, r0, r1, F, part + (int64_t)blockIdx.x * F * F, lds);
 }
 
 template <typename HT>
-__global__ __launch_bounds__(256) void k_gram_mfma(const HT* __restrict__ H, int64_t rows, int F,
-                                                   int64_t rpp, double* __restrict__ part) {
-  const int64_t r0 = (int64_t)blockIdx.x * rpp, r1 = min(rows, r0 + rpp);
-  gram_rows_mfma<HT>(H, r0, r1, F, part + (int64_t)blockIdx.x * F * F);
+static void launch_gram_mfma_t(const HT* H, int64_t rows, int F, int64_t rpp, double* part, int nparts,
+                               hipStream_t s) {
+  switch ((F + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_gram_mfma<HT, 1>), dim3(nparts), dim3(256), 0, s, H, rows, F, rpp, part); break;
+    case 2: hipLaunchKernelGGL((k_gram_mfma<HT, 2>), dim3(nparts), dim3(256), 0, s, H, rows, F, rpp, part); break;
+    case 3: hipLaunchKernelGGL((k_gram_mfma<HT, 3>), dim3(nparts), dim3(256), 0, s, H, rows, F, rpp, part); break;
+    default: hipLaunchKernelGGL((k_gram_mfma<HT, 4>), dim3(nparts), dim3(256), 0, s, H, rows, F, rpp, part); break;
+  }
 }
 
 hipError_t launch_gram_direct(const void* H, int h_f64, int64_t rows, int F, int64_t rpp,
                               double* part, hipStream_t s) {
   const int nparts = (int)((rows + rpp - 1) / rpp);
-  if (h_f64)
-    hipLaunchKernelGGL(k_gram_mfma<double>, dim3(nparts), dim3(256), 0, s, (const double*)H, rows, F,
-                       rpp, part);
-  else
-    hipLaunchKernelGGL(k_gram_mfma<float>, dim3(nparts), dim3(256), 0, s, (const float*)H, rows, F,
-                       rpp, part);
+  if (h_f64) launch_gram_mfma_t((const double*)H, rows, F, rpp, part, nparts, s);
+  else launch_gram_mfma_t((const float*)H, rows, F, rpp, part, nparts, s);
   return hipGetLastError();
 }
 
 void gram_split(int64_t rows, int64_t* rpp, int* nb) {
-  // partials of whole 64-row chunks: one chunk each up to 8 chunks, then at
-  // least two each and at most 16 partials.  The last block of the prepare
-  // step reads every partial back from the L2 of the XCD that wrote it, so
-  // fewer, longer partials pay while the factor is short; for long factors
-  // the row loop dominates and 16 blocks share it
+  // partials of whole 64-row chunks: at most 4 chunks (256 rows, one round of
+  // loads per wave) each while that gives at most 16 partials, then more.
+  // Up to 4 partials the last block of the prepare step reads them back in
+  // one round of loads (they were written on other XCDs: every load is a
+  // memory round trip)
   const int64_t chunks = (rows + 63) / 64;
-  const int64_t per = chunks <= 8 ? 1 : std::max<int64_t>(2, (chunks + 15) / 16);
+  const int64_t per = std::max<int64_t>((chunks + 15) / 16, std::min<int64_t>(4, (chunks + 3) / 4));
   *rpp = per * 64;
   *nb = (int)((rows + *rpp - 1) / *rpp);
 }

@@ -374,6 +374,9 @@ struct PrepK {
 // stage of the prepare kernel borrows it too), the diagonal of G [64], a
 // reduction buffer [256], rho.
 constexpr int kPrepLdsDoubles = 64 * 65 + 64 + 256 + 1;
+// LDS of the matrix-core Gram partial (gram_rows_mfma): 4 waves x 4 tiles of
+// 16 x 16 doubles
+constexpr int kGramLdsDoubles = 4 * 4 * 4 * 64;
 
 // Global inputs of prep_body, loaded into registers ahead of it (the
 // per-problem prepare kernel issues these loads before its Gram phase, so
