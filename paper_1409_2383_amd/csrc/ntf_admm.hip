@@ -55,7 +55,7 @@ struct Layout {
   size_t state = 0, T = 0, P1 = 0, P2 = 0, P3 = 0, W[3] = {0, 0, 0}, prim[3] = {0, 0, 0},
          gram[3] = {0, 0, 0}, ginv[3] = {0, 0, 0}, gpart = 0, rpart = 0, sumsq = 0, fitpart = 0,
          xr = 0, xj8 = 0, scale = 0, wx = 0, wy = 0, wact = 0, wscale = 0, wG[3] = {0, 0, 0},
-         card = 0, total = 0;
+         card = 0, order = 0, total = 0;
   // sparse tensors: per-mode sorted copies, MTTKRP segment carries, set-up sort scratch
   size_t sp_rec[3] = {0, 0, 0}, sp_val[3] = {0, 0, 0}, sp_tail[3] = {0, 0, 0}, sp_len[3] = {0, 0, 0},
          sp_heavy[3] = {0, 0, 0}, sp_nheavy = 0, sp_ch = 0, sp_ct = 0, sp_k0 = 0, sp_k1 = 0, sp_p0 = 0,
@@ -146,6 +146,7 @@ Layout make_layout(const Plan& p, const ntf_opts& o, int64_t nnz = -1) {
   L.gpart = c.take((size_t)std::max<int64_t>(maxblk, 16) * F * F * 8);
   L.rpart = c.take((size_t)maxblk * 8 * 8);
   L.sumsq = c.take((size_t)kSumsqParts * 8);
+  L.order = c.take(8);   // target of the one-element kernel that orders mode 2's launches
   // whole-factor projection (cardinality constraint): V, Ht^T and the factor
   // before the update, FP64 [rows][F] each, for the largest mode
   L.card = c.take((size_t)(3 * std::max(p.I, std::max(p.J, p.K)) * F) * 8);
@@ -549,6 +550,25 @@ static ntf_status enqueue_outer_sparse(ntf_admm_ctx* c, hipStream_t ms) {
   return NTF_OK;
 }
 
+// Whether a mode's MTTKRP pass is captured before its prepare step.  The
+// graph runs the node captured first on the launching queue, next to the
+// inner sweeps around it: the handoffs inner -> pass -> inner then take 5-6
+// us instead of 10-14 across queues.  The prepare step captured second must
+// still find CUs the pass leaves free (each pass block takes a CU: 512
+// threads and, in pass 3, most of the LDS); otherwise it would wait for the
+// whole pass, so the order stays prepare first.
+static bool pass_first(const ntf_admm_ctx* c, int m) {
+  const Plan& p = c->plan;
+  if (m == 1) return false;
+  const int64_t d[3] = {p.I, p.J, p.K};
+  int64_t rpp;
+  int nb;
+  gram_split(d[(m + 2) % 3], &rpp, &nb);
+  const int64_t pass = (m == 0) ? p.grid1
+                                : (p.prec == PREC_BF16 ? (int64_t)p.nch3 * p.bpc3 : (int64_t)p.nrc3 * p.nkg3);
+  return pass + nb + 1 <= cu_count();
+}
+
 // Enqueue one outer iteration on `ms` with the prepare kernels on s1.
 static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   if (c->sparse) return enqueue_outer_sparse(c, ms);
@@ -561,10 +581,14 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   // mode 1 (A): prepare on the side while pass 1 streams X
   NTF_HIP(c, hipEventRecord(c->ev_fork, ms));
   NTF_HIP(c, hipStreamWaitEvent(c->s1, c->ev_fork, 0));
+  const bool pf1 = pass_first(c, 0);
+  if (pf1)
+    NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, ms));
   prep_args(c, 0, pa);
   NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
   NTF_HIP(c, hipEventRecord(c->ev_prep[0], c->s1));
-  NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, ms));
+  if (!pf1)
+    NTF_HIP(c, launch_pass1(p, c->prob.X, xr, scale, c->feed(1), c->feed(2), T, c->ws + c->lay.P1, ms));
   // The warm start reads W_1 before the inner sweep: reduce it first.  Without
   // it the inner sweep sums pass 1's (few, per row-chunk) partials itself.
   const bool w1_in_inner = !c->warm_on;
@@ -586,6 +610,11 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   prep_args(c, 1, pa);
   NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
   NTF_HIP(c, hipEventRecord(c->ev_prep[1], c->s1));
+  // The mode-2 prepare step is the longer branch here.  A one-element kernel
+  // ahead of the mode-2 MTTKRP lets the prepare step's blocks be dispatched
+  // first, on CUs of their own: when the MTTKRP's blocks come first, the
+  // prepare step shares their CUs and takes 72 us instead of 55.
+  NTF_HIP(c, launch_fill(c->at<double>(c->lay.order), 1, 0.0, ms));
   NTF_HIP(c, launch_mode2(p, T, c->feed(0), c->ws + c->lay.P2, ms));
   NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P2, c->hf64(), p.J * p.F, p.F, p.nich2, p.J, p.F,
                                     c->at<double>(c->lay.W[1]), ms, 16));
@@ -601,10 +630,12 @@ static ntf_status enqueue_outer(ntf_admm_ctx* c, hipStream_t ms) {
   // mode 3 (C)
   NTF_HIP(c, hipEventRecord(c->ev_inner[1], ms));
   NTF_HIP(c, hipStreamWaitEvent(c->s1, c->ev_inner[1], 0));
+  const bool pf3 = pass_first(c, 2);
+  if (pf3) NTF_HIP(c, launch_pass3(p, c->prob.X, xj8, scale, c->feed(0), c->feed(1), c->ws + c->lay.P3, ms));
   prep_args(c, 2, pa);
   NTF_HIP(c, launch_prep(pa, p.nprep, c->s1));
   NTF_HIP(c, hipEventRecord(c->ev_prep[2], c->s1));
-  NTF_HIP(c, launch_pass3(p, c->prob.X, xj8, scale, c->feed(0), c->feed(1), c->ws + c->lay.P3, ms));
+  if (!pf3) NTF_HIP(c, launch_pass3(p, c->prob.X, xj8, scale, c->feed(0), c->feed(1), c->ws + c->lay.P3, ms));
   NTF_HIP(c, launch_reduce_partials(c->ws + c->lay.P3, c->hf64(), p.K * p.F, p.F, p.nrc3, p.K, p.F,
                                     c->at<double>(c->lay.W[2]), ms, 16));
   NTF_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[2], 0));
