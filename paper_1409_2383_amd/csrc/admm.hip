@@ -71,9 +71,17 @@ __global__ __launch_bounds__(256) void k_inner_reg64(InnerK a) {
   const double sqF = sqrt((double)F);
   for (int t = 0; t < a.T && !done; ++t) {   // (done is uniform over the wave)
     const double b = act ? w + rho * (h + u) : 0.0;
+    // (lane reads in batches of 16 into distinct scalar registers: one pair
+    // reused for every lane read serialises each FMA behind its read)
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < 64; ++r) s4[r & 3] += gc[r] * lane_value_d(b, r);
+    for (int r0 = 0; r0 < 64; r0 += 16) {
+      double bb[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) bb[k] = lane_value_d(b, r0 + k);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s4[k & 3] += gc[r0 + k] * bb[k];
+    }
     double xn = (s4[0] + s4[1]) + (s4[2] + s4[3]);   // x = (G + rho I)^{-1} b
     if (a.proj == 2) {
       const double sx = group_sum(xn, 64);
