@@ -1037,15 +1037,22 @@ __global__ __launch_bounds__(512, 2) void k_pass3s(const T* __restrict__ X, int6
   };
   T ha[PER], hb[PER];
   auto hload = [&](int e) {   // factor values of epoch e (zeros past the block's rows)
+    // (i, j) of the epoch's first row once per epoch (uniform), then 32-bit
+    // steps: rows of one epoch advance j by at most 63
+    const int64_t re = rbeg + 64LL * e;
+    const int ie = (int)(re / J), je = (int)(re - (int64_t)ie * J);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + nthr * q;
       const int rr = idx / FP, f = idx - rr * FP;
-      const int64_t r = rbeg + 64LL * e + rr;
       const bool ok = idx < 64 * FP && (64 * e + rr < nrows) && f < F;
-      const int64_t i = r / J, j = r - i * J;
-      const int oa = ok ? (int)(i * F + f) * (int)sizeof(T) : kBufferOOB;
-      const int ob = ok ? (int)(j * F + f) * (int)sizeof(T) : kBufferOOB;
+      int i = ie, j = je + rr;
+      while (j >= J) {   // (at most 63 / J + 1 times)
+        j -= J;
+        ++i;
+      }
+      const int oa = ok ? (i * F + f) * (int)sizeof(T) : kBufferOOB;
+      const int ob = ok ? (j * F + f) * (int)sizeof(T) : kBufferOOB;
       ha[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ars, oa, 0, 0));
       hb[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(brs, ob, 0, 0));
     }
