@@ -12,6 +12,16 @@
 // and takes pass 1 (contraction over the trailing group) then the mode-2
 // reduction over the leading group; mode N views it as (I_1, prod I_2..I_{N-1},
 // I_N) and takes pass 3.  FP32 and FP64 only.
+//
+// Two consecutive middle modes n, n+1 share one pass inside an outer
+// iteration.  Mode n+1's view (prod up to n, I_{n+1}, prod after n+1) has
+// pass 1 contract the trailing group into T and, in its epilogue, weight T by
+// H_{n+1} and sum over I_{n+1}: that is X contracted with every factor after
+// n, indexed by (modes up to n).  Mode n's MTTKRP is then a reduction of
+// those rows over the modes before n, and mode n+1's is the mode-2 reduction
+// of the same T (T holds no factor of modes up to n+1, so it is still valid
+// after mode n's update).  One pass over X instead of two, and the pass that
+// remains contracts a short trailing group whose factor fits in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,6 +67,7 @@ struct Group {
 
 struct ModeView {
   int kind = 0;        // 0: pass 1 (mode 1 of the view); 1: pass 1 + mode 2; 2: pass 3
+  int pair = 0;        // kind 1 only: 1 = first of a pair (from mode n+1's pass), 2 = second
   Group g[3];          // the three view modes
   Plan plan;
 };
@@ -136,6 +147,11 @@ bool make_setup(Setup& s, const ntf_nway_problem* pr, const ntf_opts* o, int cus
       return false;
     }
   }
+  // middle modes paired from the second mode on: (1, 2), (3, 4), ...
+  for (int n = 1; n + 1 <= N - 2; n += 2) {
+    s.v[n].pair = 1;
+    s.v[n + 1].pair = 2;
+  }
   return true;
 }
 
@@ -153,7 +169,8 @@ NwLayout make_layout(const Setup& s, const ntf_opts& o) {
       t = std::max(t, (size_t)(p.I * p.J * F) * es);
       p1 = std::max(p1, (size_t)(p.I * p.nch1 * F) * es);
     }
-    if (s.v[n].kind == 1) p2 = std::max(p2, (size_t)((int64_t)p.nich2 * p.J * F) * es);
+    // (FP64 partials for the first mode of a pair, the pass precision otherwise)
+    if (s.v[n].kind == 1) p2 = std::max(p2, (size_t)((int64_t)p.nich2 * p.J * F) * 8);
     if (s.v[n].kind == 2) p3 = std::max(p3, (size_t)((int64_t)p.nrc3 * p.K * F) * es);
     for (int q = 0; q < 3; ++q)
       if (s.v[n].g[q].hi - s.v[n].g[q].lo > 1) kr = std::max(kr, (size_t)s.v[n].g[q].rows);
@@ -209,6 +226,32 @@ __global__ __launch_bounds__(256) void k_kr(KrK a) {
     v *= reinterpret_cast<const T*>(a.f[q])[i * a.F + f];
   }
   reinterpret_cast<T*>(a.out)[e] = v;
+}
+
+// The first mode n of a pair, from the pass of mode n+1's view: P1 holds, for
+// row r = a * In + j of that view (a over the modes before n, j over I_n) and
+// chunk c of I_{n+1}, the chunk's sum over l of H_{n+1}[l,:] T[r,l,:].  Partial
+// ac of the result sums rows a in [ac * ach, (ac+1) * ach) in increasing a:
+//   out[ac][j][f] = sum_a G0[a][f] * (sum_c P1[r][c][f])      (FP64)
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_reduce(const T* __restrict__ P1, int nch,
+                                                     const T* __restrict__ G0, int64_t A,
+                                                     int64_t In, int F, int ach,
+                                                     double* __restrict__ out) {
+  const int64_t JF = In * F;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= JF) return;
+  const int64_t j = idx / F;
+  const int f = (int)(idx - j * F);
+  const int64_t a0 = (int64_t)blockIdx.y * ach, a1 = a0 + ach < A ? a0 + ach : A;
+  double acc = 0.0;
+  for (int64_t a = a0; a < a1; ++a) {
+    const T* p = P1 + ((a * In + j) * nch) * F + f;
+    double w = 0.0;
+    for (int c = 0; c < nch; ++c) w += (double)p[(int64_t)c * F];
+    acc += (double)G0[a * F + f] * w;
+  }
+  out[(int64_t)blockIdx.y * JF + idx] = acc;
 }
 
 struct HprodK {
@@ -321,8 +364,10 @@ ntf_status group_factor(ntf_nway_ctx* c, const Group& g, const void* const* fac,
   return NTF_OK;
 }
 
-// W (FP64, [d_n][F]) = mode-n MTTKRP with the feed factors.
-ntf_status enqueue_mttkrp(ntf_nway_ctx* c, int n, double* W, hipStream_t s) {
+// W (FP64, [d_n][F]) = mode-n MTTKRP with the feed factors.  In an outer
+// iteration (`paired`) the second mode of a pair takes T from the first
+// mode's pass; called alone it runs its own pass.
+ntf_status enqueue_mttkrp(ntf_nway_ctx* c, int n, double* W, hipStream_t s, bool paired) {
   const ModeView& mv = c->su.v[n];
   const Plan& p = mv.plan;
   const void* fac[kMax];
@@ -339,12 +384,32 @@ ntf_status enqueue_mttkrp(ntf_nway_ctx* c, int n, double* W, hipStream_t s) {
     NW_HIP(c, launch_pass1(p, c->prob.X, nullptr, nullptr, g1, g2, T, c->ws + c->lay.P1, s));
     NW_HIP(c, launch_reduce_partials(c->ws + c->lay.P1, pf64, p.F, (int64_t)p.nch1 * p.F, p.nch1, p.I, p.F,
                                      W, s, 16));
+  } else if (mv.kind == 1 && mv.pair == 1) {
+    // the pass of mode n+1's view (its mode-1 partials weight T by H_{n+1}),
+    // then the reduction over the modes before n
+    const ModeView& nv = c->su.v[n + 1];
+    const Plan& q = nv.plan;
+    if ((st = group_factor(c, nv.g[2], fac, c->ws + c->lay.krB, s, &g2)) != NTF_OK) return st;
+    NW_HIP(c, launch_pass1(q, c->prob.X, nullptr, nullptr, fac[n + 1], g2, T, c->ws + c->lay.P1, s));
+    if ((st = group_factor(c, mv.g[0], fac, c->ws + c->lay.krA, s, &g0)) != NTF_OK) return st;
+    double* P2 = c->at<double>(c->lay.P2);
+    const dim3 grid((unsigned)((p.J * p.F + 255) / 256), (unsigned)p.nich2);
+    if (pf64)
+      hipLaunchKernelGGL(k_pair_reduce<double>, grid, dim3(256), 0, s, c->at<const double>(c->lay.P1),
+                         q.nch1, (const double*)g0, p.I, p.J, p.F, p.ich2, P2);
+    else
+      hipLaunchKernelGGL(k_pair_reduce<float>, grid, dim3(256), 0, s, c->at<const float>(c->lay.P1),
+                         q.nch1, (const float*)g0, p.I, p.J, p.F, p.ich2, P2);
+    NW_HIP(c, hipGetLastError());
+    NW_HIP(c, launch_reduce_partials(P2, 1, p.J * p.F, p.F, p.nich2, p.J, p.F, W, s, 16));
   } else if (mv.kind == 1) {
     if ((st = group_factor(c, mv.g[0], fac, c->ws + c->lay.krA, s, &g0)) != NTF_OK) return st;
-    if ((st = group_factor(c, mv.g[2], fac, c->ws + c->lay.krB, s, &g2)) != NTF_OK) return st;
-    // pass 1 forms T = X x_3 (trailing group); its mode-1 partials (against
-    // this mode's own factor) are not used
-    NW_HIP(c, launch_pass1(p, c->prob.X, nullptr, nullptr, fac[n], g2, T, c->ws + c->lay.P1, s));
+    if (!(paired && mv.pair == 2)) {
+      if ((st = group_factor(c, mv.g[2], fac, c->ws + c->lay.krB, s, &g2)) != NTF_OK) return st;
+      // pass 1 forms T = X x_3 (trailing group); its mode-1 partials (against
+      // this mode's own factor) are not used
+      NW_HIP(c, launch_pass1(p, c->prob.X, nullptr, nullptr, fac[n], g2, T, c->ws + c->lay.P1, s));
+    }
     NW_HIP(c, launch_mode2(p, T, g0, c->ws + c->lay.P2, s));
     NW_HIP(c, launch_reduce_partials(c->ws + c->lay.P2, pf64, p.J * p.F, p.F, p.nich2, p.J, p.F, W, s, 16));
   } else {
@@ -406,7 +471,7 @@ ntf_status enqueue_outer(ntf_nway_ctx* c, hipStream_t ms) {
     pa.counter = &ds->counter[n];
     NW_HIP(c, launch_prep(pa, su.nprep, c->s1));
     NW_HIP(c, hipEventRecord(c->ev_prep[n], c->s1));
-    ntf_status st = enqueue_mttkrp(c, n, W, ms);
+    ntf_status st = enqueue_mttkrp(c, n, W, ms, true);
     if (st != NTF_OK) return st;
     NW_HIP(c, hipStreamWaitEvent(ms, c->ev_prep[n], 0));
     InnerArgs ia;
@@ -641,7 +706,7 @@ ntf_status ntf_nway_run(ntf_nway_ctx* c, int32_t max_outer, int32_t check_every,
 
 ntf_status ntf_nway_mttkrp(ntf_nway_ctx* c, int32_t mode, double* W_out) {
   if (!c || !W_out || mode < 0 || mode >= c->su.N) return NTF_E_INVAL;
-  return enqueue_mttkrp(c, mode, W_out, c->s0);
+  return enqueue_mttkrp(c, mode, W_out, c->s0, false);
 }
 
 ntf_status ntf_nway_fit(ntf_nway_ctx* c, double* rfe) {
