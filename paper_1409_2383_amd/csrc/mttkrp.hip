@@ -322,7 +322,7 @@ __global__ __launch_bounds__(512) void k_pass1(const T* __restrict__ X, int I, i
           const int f = ft * 16 + n;
           if (j < J && f < F) {
             const T v = acc[mt][ft][ii];
-            Tout[((int64_t)i * J + j) * F + f] = v;
+            if (Tout) Tout[((int64_t)i * J + j) * F + f] = v;
             part[ft] += Hb[(int64_t)j * F + f] * v;
           }
         }
@@ -790,11 +790,13 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
     if (reload) load_next(xv[u]);
     if (++c_step == nsteps) {
       // epilogue of item c_item: T rows (rows past J and columns past F get
-      // an offset past the slab: the hardware drops those stores) and this
-      // item's share of W1 against H2
+      // an offset past the slab: the hardware drops those stores; with no T
+      // output the resource is empty and drops them all) and this item's
+      // share of W1 against H2
       const int i = (int)(c_item / nch);
       const int ch = (int)(c_item - (int64_t)i * nch);
-      const __amdgpu_buffer_rsrc_t trs = uniform_rsrc(Tout + (int64_t)i * J * F, J * F * 4);
+      const __amdgpu_buffer_rsrc_t trs =
+          Tout ? uniform_rsrc(Tout + (int64_t)i * J * F, J * F * 4) : uniform_rsrc(P1, 0);
       float part[FT];
 #pragma unroll
       for (int ft = 0; ft < FT; ++ft) part[ft] = 0.f;
@@ -983,7 +985,12 @@ __global__ __launch_bounds__(512) void k_pass3(const T* __restrict__ X, int64_t 
 // then covers that step only).  The Khatri-Rao values of epoch e + 2 are
 // loaded during epoch e + 1's predecessor and stored to the free LDS buffer
 // after the epoch's MFMAs; each step's B operands are read one step ahead.
-template <typename T, int FT, int V>
+// With few 64-column k tiles (K <= 256) the waves also split the rows: RG row
+// groups of 8 / RG waves each (wave -> k tile wave % (8 / RG), row group
+// wave / (8 / RG)), group rg taking steps rg * 16/RG .. of every epoch, and
+// each group writes a partial of its own (P3 partial blockIdx.x * RG + rg),
+// so every wave streams X instead of two of eight.
+template <typename T, int FT, int V, int RG>
 __global__ __launch_bounds__(512, 2) void k_pass3s(const T* __restrict__ X, int64_t IJ, int J, int K,
                                                 int F, const T* __restrict__ Ha,
                                                 const T* __restrict__ Hb, T* __restrict__ P3,
@@ -998,12 +1005,17 @@ __global__ __launch_bounds__(512, 2) void k_pass3s(const T* __restrict__ X, int6
   __shared__ __align__(16) T KRs[2][64 * KRS];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int kw0 = (blockIdx.y * nw + wave) * 64;
+  constexpr int KT = 8 / RG;            // k tiles per block (eight waves)
+  constexpr int SPW = 16 / RG;          // steps of an epoch per wave
+  constexpr int UU = SPW < U ? SPW : U;
+  constexpr int EPG = U / UU;           // epochs per loop turn (the load ring stays compile-time)
+  const int kt = wave % KT, rg = wave / KT;
+  const int kw0 = (blockIdx.y * KT + kt) * 64;
   const bool kact = kw0 < K;
   const int64_t rbeg = (int64_t)blockIdx.x * rpc;
   const int nrows = (int)(min(IJ, rbeg + rpc) - rbeg);
-  const int nep = (nrows + 63) >> 6;
+  // (epochs past the block's rows read zeros: their products add exact zeros)
+  const int nep = (((nrows + 63) >> 6) + EPG - 1) / EPG * EPG;
   const int kl = kw0 + 4 * n;
   const __amdgpu_buffer_rsrc_t xrs = uniform_rsrc(X + rbeg * K, nrows * K * (int)sizeof(T));
   const __amdgpu_buffer_rsrc_t ars = uniform_rsrc(Ha, I * F * (int)sizeof(T));
@@ -1065,41 +1077,49 @@ __global__ __launch_bounds__(512, 2) void k_pass3s(const T* __restrict__ X, int6
       if (idx < 64 * FP) KRs[buf][rr * KRS + f] = ha[q] * hb[q];
     }
   };
+  // the wave's w-th step is step rg * SPW + w % SPW of epoch w / SPW
+  auto sabs = [&](int w) { return 16 * (w / SPW) + rg * SPW + (w % SPW); };
   hload(0);
   hstore(0);
   hload(1);
 #pragma unroll
-  for (int u = 0; u < U; ++u) xload(u, xv[u]);
+  for (int u = 0; u < U; ++u) xload(sabs(u), xv[u]);
   __syncthreads();
-  for (int e = 0; e < nep; ++e) {
-    const T* kb0 = KRs[e & 1] + g * KRS + n;
-    T bc[FT], bn[FT];
+  for (int e0 = 0; e0 < nep; e0 += EPG) {
 #pragma unroll
-    for (int ft = 0; ft < FT; ++ft) bc[ft] = kb0[ft * 16];
+    for (int ee = 0; ee < EPG; ++ee) {
+      const int e = e0 + ee;
+      const T* kb0 = KRs[e & 1] + g * KRS + n + (4 * rg * SPW) * KRS;
+      T bc[FT], bn[FT];
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) bc[ft] = kb0[ft * 16];
 #pragma unroll 1
-    for (int st0 = 0; st0 < 16; st0 += U) {
+      for (int st0 = 0; st0 < SPW; st0 += UU) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int st = st0 + u;
-        const int sn = min(st + 1, 15);   // the last step re-reads its own operands
+        for (int u = 0; u < UU; ++u) {
+          const int st = st0 + u;
+          const int slot = ee * UU + u;          // = (e * SPW + st) % U
+          const int sn = min(st + 1, SPW - 1);   // the last step re-reads its own operands
 #pragma unroll
-        for (int ft = 0; ft < FT; ++ft) bn[ft] = kb0[(4 * sn) * KRS + ft * 16];
-        if (kact) {
+          for (int ft = 0; ft < FT; ++ft) bn[ft] = kb0[(4 * sn) * KRS + ft * 16];
+          if (kact) {
 #pragma unroll
-          for (int ft = 0; ft < FT; ++ft)
+            for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[c][ft] = M::mma(xv[u][c], bc[ft], acc[c][ft]);
+              for (int c = 0; c < 4; ++c) acc[c][ft] = M::mma(xv[slot][c], bc[ft], acc[c][ft]);
+          }
+          xload(sabs(e * SPW + st + U), xv[slot]);
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft) bc[ft] = bn[ft];
         }
-        xload(16 * e + st + U, xv[u]);
-#pragma unroll
-        for (int ft = 0; ft < FT; ++ft) bc[ft] = bn[ft];
       }
+      if (e + 1 < nep) hstore((e + 1) & 1);
+      hload(e + 2);
+      __syncthreads();
     }
-    if (e + 1 < nep) hstore((e + 1) & 1);
-    hload(e + 2);
-    __syncthreads();
   }
   if (!kact) return;
+  const int64_t part = (int64_t)blockIdx.x * RG + rg;
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -1108,7 +1128,7 @@ __global__ __launch_bounds__(512, 2) void k_pass3s(const T* __restrict__ X, int6
       for (int ii = 0; ii < 4; ++ii) {
         const int k = kw0 + 4 * M::row(g, ii) + c;
         const int f = ft * 16 + n;
-        if (k < K && f < F) P3[((int64_t)blockIdx.x * K + k) * F + f] = acc[c][ft][ii];
+        if (k < K && f < F) P3[(part * K + k) * F + f] = acc[c][ft][ii];
       }
 }
 
@@ -1434,7 +1454,14 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
     int64_t nrc = std::max<int64_t>(1, 2LL * cus / p.nkg3);
     nrc = std::min<int64_t>(nrc, cdiv(units, 64));
     p.rpc3 = rup(cdiv(units, nrc), 64);
-    p.nrc3 = (int)cdiv(units, p.rpc3);
+    p.nb3 = (int)cdiv(units, p.rpc3);
+    // FP32 rows of even length whose block range fits 32-bit buffer offsets
+    // take the streaming form, whose waves also split the rows when there
+    // are at most four k tiles; one partial per row group of a block
+    p.s3 = prec == PREC_F32 && p.vec >= 2 && p.rpc3 * p.K * 4 < kBufferOOB &&
+           p.I * p.F * 4 < kBufferOOB && p.J * p.F * 4 < kBufferOOB;
+    p.rg3 = !p.s3 ? 1 : ktiles == 1 ? 8 : ktiles == 2 ? 4 : ktiles <= 4 ? 2 : 1;
+    p.nrc3 = p.nb3 * p.rg3;
   }
   // inner sweep
   int FL = 4;
@@ -1575,28 +1602,37 @@ hipError_t launch_mode2(const Plan& p, const void* Tin, const void* Ha, void* P2
   return hipGetLastError();
 }
 
+template <typename T, int FT, int RG>
+static void pass3_s(const Plan& p, const void* X, const void* Ha, const void* Hb, void* P3,
+                    hipStream_t s) {
+  const dim3 grid((unsigned)p.nb3, (unsigned)p.nkg3);
+  if (p.vec == 4)
+    hipLaunchKernelGGL((k_pass3s<float, FT, 4, RG>), grid, dim3(512), 0, s, (const float*)X,
+                       p.I * p.J, (int)p.J, (int)p.K, p.F, (const float*)Ha, (const float*)Hb,
+                       (float*)P3, p.rpc3, (int)p.I);
+  else
+    hipLaunchKernelGGL((k_pass3s<float, FT, 2, RG>), grid, dim3(512), 0, s, (const float*)X,
+                       p.I * p.J, (int)p.J, (int)p.K, p.F, (const float*)Ha, (const float*)Hb,
+                       (float*)P3, p.rpc3, (int)p.I);
+}
+
 template <typename T, int FT>
 static void pass3_t(const Plan& p, const void* X, const void* Ha, const void* Hb, void* P3,
                     hipStream_t s) {
   // FP32 rows of even length whose block range fits 32-bit buffer offsets:
-  // the streaming form (eight waves per block; waves past K only share the
-  // loads of the Khatri-Rao values)
+  // the streaming form (eight waves per block, rg3 row groups)
   if constexpr (sizeof(T) == 4) {
-    if (p.vec >= 2 && p.rpc3 * p.K * 4 < kBufferOOB && p.I * p.F * 4 < kBufferOOB &&
-        p.J * p.F * 4 < kBufferOOB) {
-      const int nw = 8;
-      if (p.vec == 4)
-        hipLaunchKernelGGL((k_pass3s<float, FT, 4>), dim3(p.nrc3, p.nkg3), dim3(64 * nw), 0, s,
-                           (const float*)X, p.I * p.J, (int)p.J, (int)p.K, p.F, (const float*)Ha,
-                           (const float*)Hb, (float*)P3, p.rpc3, (int)p.I);
-      else
-        hipLaunchKernelGGL((k_pass3s<float, FT, 2>), dim3(p.nrc3, p.nkg3), dim3(64 * nw), 0, s,
-                           (const float*)X, p.I * p.J, (int)p.J, (int)p.K, p.F, (const float*)Ha,
-                           (const float*)Hb, (float*)P3, p.rpc3, (int)p.I);
+    if (p.s3) {
+      switch (p.rg3) {
+        case 8: pass3_s<T, FT, 8>(p, X, Ha, Hb, P3, s); break;
+        case 4: pass3_s<T, FT, 4>(p, X, Ha, Hb, P3, s); break;
+        case 2: pass3_s<T, FT, 2>(p, X, Ha, Hb, P3, s); break;
+        default: pass3_s<T, FT, 1>(p, X, Ha, Hb, P3, s); break;
+      }
       return;
     }
   }
-  hipLaunchKernelGGL((k_pass3<T, FT>), dim3(p.nrc3, p.nkg3), dim3(64 * p.nw3), 0, s, (const T*)X,
+  hipLaunchKernelGGL((k_pass3<T, FT>), dim3(p.nb3, p.nkg3), dim3(64 * p.nw3), 0, s, (const T*)X,
                      p.I * p.J, (int)p.J, (int)p.K, p.F, (const T*)Ha, (const T*)Hb, (T*)P3,
                      p.rpc3, p.vec);
 }

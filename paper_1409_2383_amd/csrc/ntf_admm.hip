@@ -565,7 +565,7 @@ static bool pass_first(const ntf_admm_ctx* c, int m) {
   int nb;
   gram_split(d[(m + 2) % 3], &rpp, &nb);
   const int64_t pass = (m == 0) ? p.grid1
-                                : (p.prec == PREC_BF16 ? (int64_t)p.nch3 * p.bpc3 : (int64_t)p.nrc3 * p.nkg3);
+                                : (p.prec == PREC_BF16 ? (int64_t)p.nch3 * p.bpc3 : (int64_t)p.nb3 * p.nkg3);
   return pass + nb + 1 <= cu_count();
 }
 

@@ -32,8 +32,10 @@ struct Plan {
   // mode 2 from T
   int ich2 = 16, nich2 = 0;
   // pass 3 (mode-3 MTTKRP): waves per block, k-groups, row chunks
-  int nw3 = 0, nkg3 = 0, nrc3 = 0;
+  int nw3 = 0, nkg3 = 0, nrc3 = 0;  // nrc3: partials of P3
   int64_t rpc3 = 0;               // rows (FP32/FP64) or slabs (BF16) per block
+  int nb3 = 0, rg3 = 1;           // FP32/FP64: row blocks; row groups per block (one partial each)
+  bool s3 = false;                // FP32 streaming form
   int jcg3 = 0;                   // BF16: 8-row groups of j per chunk staged in LDS
   int nkt3 = 0, nch3 = 0, ngr3 = 0, bpc3 = 0;   // BF16: k tiles, j chunks, slab groups, blocks per chunk
   size_t lds3 = 0;
@@ -55,7 +57,8 @@ hipError_t launch_sumsq(const void* X, int x_is_f64, int64_t n, double* partial,
                         double* out, hipStream_t s);
 
 // ---- MTTKRP
-// pass 1: Tout [I*J][F] (T elem = float, or double for F64) and P1 [I][nch1][F]
+// pass 1: Tout [I*J][F] (T elem = float, or double for F64) and P1 [I][nch1][F];
+// FP32 and FP64 take Tout = nullptr when only P1 is wanted
 hipError_t launch_pass1(const Plan& p, const void* X, const __bf16* Xr, const float* scale,
                         const void* Hb, const void* Hc, void* Tout, void* P1, hipStream_t s);
 // mode 2 from T: P2 [nich2][J][F]

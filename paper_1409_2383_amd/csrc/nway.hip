@@ -44,6 +44,8 @@ int cu_count();
 namespace {
 
 constexpr int kMax = NTF_MAX_ORDER;
+// rows of the leading group per partial of the pair reduction (k_pair_reduce)
+constexpr int kPairRows = 4;
 
 struct NwState {
   double rho[kMax][2];
@@ -148,7 +150,10 @@ bool make_setup(Setup& s, const ntf_nway_problem* pr, const ntf_opts* o, int cus
     }
   }
   // middle modes paired from the second mode on: (1, 2), (3, 4), ...
+  // (a pair's reduction takes one grid row per kPairRows rows of the leading
+  // group: at most 65535)
   for (int n = 1; n + 1 <= N - 2; n += 2) {
+    if ((s.v[n].g[0].rows + kPairRows - 1) / kPairRows > 65535) continue;
     s.v[n].pair = 1;
     s.v[n + 1].pair = 2;
   }
@@ -165,12 +170,13 @@ NwLayout make_layout(const Setup& s, const ntf_opts& o) {
   int maxblk = 1;
   for (int n = 0; n < s.N; ++n) {
     const Plan& p = s.v[n].plan;
+    if (s.v[n].kind == 1) t = std::max(t, (size_t)(p.I * p.J * F) * es);
     if (s.v[n].kind != 2) {
-      t = std::max(t, (size_t)(p.I * p.J * F) * es);
       p1 = std::max(p1, (size_t)(p.I * p.nch1 * F) * es);
     }
-    // (FP64 partials for the first mode of a pair, the pass precision otherwise)
-    if (s.v[n].kind == 1) p2 = std::max(p2, (size_t)((int64_t)p.nich2 * p.J * F) * 8);
+    if (s.v[n].kind == 1) p2 = std::max(p2, (size_t)((int64_t)p.nich2 * p.J * F) * es);
+    // (FP64 partials of kPairRows rows each for the first mode of a pair)
+    if (s.v[n].pair == 1) p2 = std::max(p2, (size_t)(((p.I + kPairRows - 1) / kPairRows) * p.J * F) * 8);
     if (s.v[n].kind == 2) p3 = std::max(p3, (size_t)((int64_t)p.nrc3 * p.K * F) * es);
     for (int q = 0; q < 3; ++q)
       if (s.v[n].g[q].hi - s.v[n].g[q].lo > 1) kr = std::max(kr, (size_t)s.v[n].g[q].rows);
@@ -231,26 +237,39 @@ __global__ __launch_bounds__(256) void k_kr(KrK a) {
 // The first mode n of a pair, from the pass of mode n+1's view: P1 holds, for
 // row r = a * In + j of that view (a over the modes before n, j over I_n) and
 // chunk c of I_{n+1}, the chunk's sum over l of H_{n+1}[l,:] T[r,l,:].  Partial
-// ac of the result sums rows a in [ac * ach, (ac+1) * ach) in increasing a:
-//   out[ac][j][f] = sum_a G0[a][f] * (sum_c P1[r][c][f])      (FP64)
+// ac of the result takes rows a = kPairRows * ac + q, q = 0 .. kPairRows-1:
+//   out[ac][j][f] = sum_q G0[a][f] * (sum_c P1[r][c][f])     (FP64, q and c
+// increasing; the kPairRows rows' loads of one c are issued together).
 template <typename T>
 __global__ __launch_bounds__(256) void k_pair_reduce(const T* __restrict__ P1, int nch,
                                                      const T* __restrict__ G0, int64_t A,
-                                                     int64_t In, int F, int ach,
-                                                     double* __restrict__ out) {
+                                                     int64_t In, int F, double* __restrict__ out) {
   const int64_t JF = In * F;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= JF) return;
   const int64_t j = idx / F;
   const int f = (int)(idx - j * F);
-  const int64_t a0 = (int64_t)blockIdx.y * ach, a1 = a0 + ach < A ? a0 + ach : A;
-  double acc = 0.0;
-  for (int64_t a = a0; a < a1; ++a) {
-    const T* p = P1 + ((a * In + j) * nch) * F + f;
-    double w = 0.0;
-    for (int c = 0; c < nch; ++c) w += (double)p[(int64_t)c * F];
-    acc += (double)G0[a * F + f] * w;
+  const int64_t a0 = (int64_t)blockIdx.y * kPairRows;
+  const T* p[kPairRows];
+  bool ok[kPairRows];
+  double w[kPairRows];
+#pragma unroll
+  for (int q = 0; q < kPairRows; ++q) {
+    ok[q] = a0 + q < A;
+    p[q] = P1 + (((ok[q] ? a0 + q : a0) * In + j) * nch) * F + f;
+    w[q] = 0.0;
   }
+  for (int c = 0; c < nch; ++c) {
+    T v[kPairRows];
+#pragma unroll
+    for (int q = 0; q < kPairRows; ++q) v[q] = p[q][(int64_t)c * F];
+#pragma unroll
+    for (int q = 0; q < kPairRows; ++q) w[q] += (double)v[q];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPairRows; ++q)
+    if (ok[q]) acc += (double)G0[(a0 + q) * F + f] * w[q];
   out[(int64_t)blockIdx.y * JF + idx] = acc;
 }
 
@@ -381,7 +400,8 @@ ntf_status enqueue_mttkrp(ntf_nway_ctx* c, int n, double* W, hipStream_t s, bool
   if (mv.kind == 0) {
     if ((st = group_factor(c, mv.g[1], fac, c->ws + c->lay.krA, s, &g1)) != NTF_OK) return st;
     g2 = fac[c->su.N - 1];
-    NW_HIP(c, launch_pass1(p, c->prob.X, nullptr, nullptr, g1, g2, T, c->ws + c->lay.P1, s));
+    // (only the mode-1 partials are wanted: no T)
+    NW_HIP(c, launch_pass1(p, c->prob.X, nullptr, nullptr, g1, g2, nullptr, c->ws + c->lay.P1, s));
     NW_HIP(c, launch_reduce_partials(c->ws + c->lay.P1, pf64, p.F, (int64_t)p.nch1 * p.F, p.nch1, p.I, p.F,
                                      W, s, 16));
   } else if (mv.kind == 1 && mv.pair == 1) {
@@ -393,15 +413,16 @@ ntf_status enqueue_mttkrp(ntf_nway_ctx* c, int n, double* W, hipStream_t s, bool
     NW_HIP(c, launch_pass1(q, c->prob.X, nullptr, nullptr, fac[n + 1], g2, T, c->ws + c->lay.P1, s));
     if ((st = group_factor(c, mv.g[0], fac, c->ws + c->lay.krA, s, &g0)) != NTF_OK) return st;
     double* P2 = c->at<double>(c->lay.P2);
-    const dim3 grid((unsigned)((p.J * p.F + 255) / 256), (unsigned)p.nich2);
+    const int nparts = (int)((p.I + kPairRows - 1) / kPairRows);
+    const dim3 grid((unsigned)((p.J * p.F + 255) / 256), (unsigned)nparts);
     if (pf64)
       hipLaunchKernelGGL(k_pair_reduce<double>, grid, dim3(256), 0, s, c->at<const double>(c->lay.P1),
-                         q.nch1, (const double*)g0, p.I, p.J, p.F, p.ich2, P2);
+                         q.nch1, (const double*)g0, p.I, p.J, p.F, P2);
     else
       hipLaunchKernelGGL(k_pair_reduce<float>, grid, dim3(256), 0, s, c->at<const float>(c->lay.P1),
-                         q.nch1, (const float*)g0, p.I, p.J, p.F, p.ich2, P2);
+                         q.nch1, (const float*)g0, p.I, p.J, p.F, P2);
     NW_HIP(c, hipGetLastError());
-    NW_HIP(c, launch_reduce_partials(P2, 1, p.J * p.F, p.F, p.nich2, p.J, p.F, W, s, 16));
+    NW_HIP(c, launch_reduce_partials(P2, 1, p.J * p.F, p.F, nparts, p.J, p.F, W, s, 16));
   } else if (mv.kind == 1) {
     if ((st = group_factor(c, mv.g[0], fac, c->ws + c->lay.krA, s, &g0)) != NTF_OK) return st;
     if (!(paired && mv.pair == 2)) {
