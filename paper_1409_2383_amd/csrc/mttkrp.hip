@@ -669,6 +669,12 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
 // running U super steps (32 k) ahead across its items through a buffer
 // resource per slab; rows j >= J and k >= K read as zeros, so every path
 // issues the same loads and the wait before a step covers that step only.
+// Offsets past the data carry bit 31 (an offset no resource reaches), taken
+// from the sign of (limit - 1 - index) by plain integer arithmetic: a
+// select against a constant offset, or a comparison, lets the compiler split
+// the lanes into two loads into one register on divergent paths, each
+// followed by a wait for every load in flight.  The item cursors (slab, row
+// chunk) step by the grid stride in 32-bit scalar arithmetic.
 template <int FT, int MT, int V>
 __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, int I, int J, int K,
                                                    int F, const float* __restrict__ Hb,
@@ -698,20 +704,28 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
   const int64_t myitems = (nitems - first + stride - 1) / stride;
   const int nsteps = (K + 31) / 32;
   const int total = __builtin_amdgcn_readfirstlane((int)(myitems * nsteps));
+  // item = slab * nch + chunk; the grid stride as (slabs, chunks)
+  const int sd = __builtin_amdgcn_readfirstlane((int)(stride / nch));
+  const int sr = __builtin_amdgcn_readfirstlane((int)(stride - (int64_t)sd * nch));
+  const int i_first = __builtin_amdgcn_readfirstlane((int)(first / nch));
+  const int ch_first = __builtin_amdgcn_readfirstlane((int)(first - (int64_t)i_first * nch));
+  auto advance = [&](int& i, int& ch) {
+    ch += sr;
+    i += sd;
+    if (ch >= nch) {
+      ch -= nch;
+      ++i;
+    }
+  };
+  constexpr unsigned kPast = 0x80000000u;   // bit 31: past every resource
+  // kPast when idx >= lim (both non-negative and below 2^31), else 0
+  auto past = [](int idx, int lim) { return (unsigned)(lim - 1 - idx) & kPast; };
 
   // load cursor (the cursor stays on the last item past the wave's end and
   // re-reads in-bounds data that nothing consumes)
-  int64_t l_item = first;
+  int l_i = i_first, l_ch = ch_first;
   int l_kb = 0;
-  const float* l_slab = X;
-  int l_row[MT];
-  auto set_rows = [&](int64_t item) {
-    const int i = (int)(item / nch), ch = (int)(item - (int64_t)i * nch);
-    l_slab = X + (int64_t)i * J * K;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) l_row[mt] = ch * R + mt * 16 + n;
-  };
-  set_rows(l_item);
+  const float* l_slab = X + (int64_t)l_i * J * K;
   float xv[U][2][MT][4];
   auto load_next = [&](float (&dst)[2][MT][4]) {
     const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(l_slab, J * K * 4);
@@ -720,16 +734,18 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const int k = l_kb + 8 * g + 4 * h;
-        const bool rok = l_row[mt] < J;
+        const int row = l_ch * R + mt * 16 + n;
+        const unsigned base = (unsigned)(row * K + k) * 4u;
+        const unsigned rmask = past(row, J);
         if constexpr (V == 4) {
-          const int off = (rok && k < K) ? (l_row[mt] * K + k) * 4 : kBufferOOB;
+          const int off = (int)(base | rmask | past(k, K));
           const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
 #pragma unroll
           for (int c = 0; c < 4; ++c) dst[h][mt][c] = v[c];
         } else {
           typedef float f2 __attribute__((ext_vector_type(2)));
-          const int o0 = (rok && k < K) ? (l_row[mt] * K + k) * 4 : kBufferOOB;
-          const int o1 = (rok && k + 2 < K) ? (l_row[mt] * K + k + 2) * 4 : kBufferOOB;
+          const int o0 = (int)(base | rmask | past(k, K));
+          const int o1 = (int)((base + 8u) | rmask | past(k + 2, K));
           const f2 a = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, o0, 0, 0));
           const f2 b = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, o1, 0, 0));
           dst[h][mt][0] = a[0];
@@ -741,8 +757,13 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
     l_kb += 32;
     if (l_kb >= K) {
       l_kb = 0;
-      l_item += stride;
-      if (l_item < nitems) set_rows(l_item);
+      int ni = l_i, nc = l_ch;
+      advance(ni, nc);
+      if (ni < I) {
+        l_i = ni;
+        l_ch = nc;
+        l_slab = X + (int64_t)l_i * J * K;
+      }
     }
   };
 #pragma unroll
@@ -753,16 +774,15 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) acc[mt][ft] = M::zero();
-  int64_t c_item = first;
+  int c_i = i_first, c_ch = ch_first;
   int c_step = 0;
   const __amdgpu_buffer_rsrc_t hrs = uniform_rsrc(Hb, J * F * 4);
   float hbv[MT][FT][4];
   auto eoff = [&](int ch, int mt, int ft, int ii) {   // offset of (row, column) in a [J][F] slab
     const int j = ch * R + mt * 16 + M::row(g, ii), f = ft * 16 + n;
-    return (f < F && j < J) ? (j * F + f) * 4 : kBufferOOB;
+    return (int)(((unsigned)(j * F + f) * 4u) | past(f, F) | past(j, J));
   };
-  auto item_start = [&](int64_t item) {
-    const int ch = (int)(item - (item / nch) * nch);
+  auto item_start = [&](int ch) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -773,7 +793,7 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
               float, __builtin_amdgcn_raw_buffer_load_b32(hrs, eoff(ch, mt, ft, ii), 0, 0));
   };
   auto step = [&](int u, bool reload) {
-    if (c_step == 0) item_start(c_item);
+    if (c_step == 0) item_start(c_ch);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const float* cbase = Cs + (((c_step * 32) >> 2) + 2 * g + h) * FP * 4 + n * 4;
@@ -793,8 +813,7 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
       // an offset past the slab: the hardware drops those stores; with no T
       // output the resource is empty and drops them all) and this item's
       // share of W1 against H2
-      const int i = (int)(c_item / nch);
-      const int ch = (int)(c_item - (int64_t)i * nch);
+      const int i = c_i, ch = c_ch;
       const __amdgpu_buffer_rsrc_t trs =
           Tout ? uniform_rsrc(Tout + (int64_t)i * J * F, J * F * 4) : uniform_rsrc(P1, 0);
       float part[FT];
@@ -821,7 +840,7 @@ __global__ __launch_bounds__(512, 2) void k_pass1s(const float* __restrict__ X, 
         if (g == 0 && f < F) P1[((int64_t)i * nch + ch) * F + f] = part[ft];
       }
       c_step = 0;
-      c_item += stride;
+      advance(c_i, c_ch);
     }
   };
   const int full = total - total % U;
@@ -1349,6 +1368,13 @@ static bool stream1_ok(const Plan& p) {
          (p.J + 32) * p.F * 4 < (int64_t)kBufferOOB;
 }
 
+// FP32 pass 1 in the streaming form (k_pass1s): all of H3 in LDS, even rows,
+// a slab addressable by one buffer resource
+static bool stream1f_ok(const Plan& p) {
+  return p.KC1 >= p.K && p.vec >= 2 && p.J * p.K * 4 < (int64_t)kBufferOOB &&
+         p.J * p.F * 4 < (int64_t)kBufferOOB;
+}
+
 bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   if (F < 1 || F > 64) return false;
   p = Plan();
@@ -1402,6 +1428,9 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   }
   int occ = (int)std::min<size_t>(8, (160 * 1024) / std::max<size_t>(p.lds1 + 512, 1));
   if (prec == PREC_BF16) occ = std::min(occ, p.FT <= 2 ? 2 : 1);   // register-bound (kPass1Waves)
+  // the FP32 streaming form is register-bound at two blocks per CU: a larger
+  // grid only adds rounds of blocks that each stage H3 and stream a few items
+  if (prec == PREC_F32 && stream1f_ok(p)) occ = std::min(occ, 2);
   if (occ < 1) occ = 1;
   p.grid1 = (int)std::min<int64_t>(cdiv(p.ntiles1, 8), (int64_t)cus * occ);
   if (prec == PREC_BF16 && stream1_ok(p)) {
@@ -1501,9 +1530,7 @@ template <typename T, int FT, int MT>
 static hipError_t pass1_t(const Plan& p, const void* X, const void* Hb, const void* Hc, void* Tout,
                           void* P1, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
-    // all of H3 in LDS, even rows, slab addressable by one resource: the streaming form
-    if (p.KC1 >= p.K && p.vec >= 2 && p.J * p.K * 4 < (int64_t)kBufferOOB &&
-        p.J * p.F * 4 < (int64_t)kBufferOOB) {
+    if (stream1f_ok(p)) {
       auto kern = (p.vec == 4) ? k_pass1s<FT, MT, 4> : k_pass1s<FT, MT, 2>;
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)p.lds1);
