@@ -784,8 +784,8 @@ def main():
         summarize(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (the design notes say how "
+              "the path would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "c5":

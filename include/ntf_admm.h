@@ -50,7 +50,7 @@ typedef enum {
   NTF_E_WORKSPACE = -2,    /* workspace smaller than *_workspace_bytes */
   NTF_E_HIP = -3,          /* a HIP runtime call failed; see ntf_admm_last_error */
   NTF_E_NUMERIC = -4,      /* G + rho I not positive definite, or NaN/Inf met on device */
-  NTF_E_UNSUPPORTED = -5   /* valid request outside what this build implements */
+  NTF_E_UNSUPPORTED = -5   /* valid request outside what this library implements */
 } ntf_status;
 
 typedef enum {

@@ -1,6 +1,6 @@
 """FP64 CPU reference of the learned warm start (test infrastructure only).
 
-The warm start is not part of the paper; it is this build's extension of the
+The warm start is not part of the paper; it is this library's extension of the
 inner sweep (Section IV, eq. ADMoM_NTF): a small MLP maps one row's NNLS
 problem  min_{h >= 0} 1/2 h^T G h - w^T h  (G = G_n + rho I minus rho I, i.e.
 the Gram Hadamard product, and w a row of the MTTKRP) to an approximate
