@@ -406,21 +406,42 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
             // K and columns past F get offsets past the resource: dropped);
             // a later chunk adds to what the earlier ones stored
             const int rg = wave + 4 * c_rgc;
+            int offs[MT][FT][4];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+              for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) {
+                  const int k = rg * R + mt * 16 + 4 * g + ii;
+                  const int f = ft * 16 + n;
+                  offs[mt][ft][ii] = (k < K && f < F) ? (k * F + f) * 4 : kBufferOOB;
+                }
+            // a later chunk reads all of the earlier chunks' sums first (one
+            // wait for the lot, not one round trip per element)
+            float prev[MT][FT][4];
+            if (chk > 0) {
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+                  for (int ii = 0; ii < 4; ++ii)
+                    prev[mt][ft][ii] = __builtin_bit_cast(
+                        float, __builtin_amdgcn_raw_buffer_load_b32(wrs, offs[mt][ft][ii], 0, 0));
+            }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
               for (int ft = 0; ft < FT; ++ft) {
 #pragma unroll
                 for (int ii = 0; ii < 4; ++ii) {
-                  const int k = rg * R + mt * 16 + 4 * g + ii;
-                  const int f = ft * 16 + n;
-                  const int off = (k < K && f < F) ? (k * F + f) * 4 : kBufferOOB;
                   // (the element is copied out first: a bit cast of a vector
                   // element lvalue reads element 0 with this compiler)
                   float t = tot[mt][ft][ii];
-                  if (chk > 0)
-                    t = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wrs, off, 0, 0)) + t;
-                  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, t), wrs, off, 0, 0);
+                  if (chk > 0) t = prev[mt][ft][ii] + t;
+                  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, t), wrs,
+                                                        offs[mt][ft][ii], 0, 0);
                 }
                 tot[mt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
               }
