@@ -257,7 +257,11 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
       gram_rows_mfma<double, NB>(reinterpret_cast<const double*>(a.gram_h), r0, r1, F, part, prep_lds);
     else
       gram_rows_mfma<float, NB>(reinterpret_cast<const float*>(a.gram_h), r0, r1, F, part, prep_lds);
-    __threadfence();
+    // release before the ticket, acquire by the last block after it: the
+    // partials written here are visible to that block's loads (a full fence
+    // on both sides also wrote back the last block's L2 and invalidated the
+    // others': 3-4 us more on the mode-2 prepare step)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) {
       const unsigned ticket = atomicAdd(a.counter, 1u);
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
     }
     __syncthreads();
     if (!is_last) return;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (tid == 0) {
       *a.counter = 0u;
       if (a.fresh_dst) *a.fresh_dst = 1;
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
       __syncthreads();
     }
     if (blockIdx.x == 0) resid_totals(a.resid_part, a.nparts, a.resid_dst);
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // (as above)
     __syncthreads();
     if (tid == 0) {
       const unsigned ticket = atomicAdd(a.counter, 1u);
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepK a) {
     }
     __syncthreads();
     if (!is_last) return;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (tid == 0) {
       *a.counter = 0u;
       if (a.fresh_dst) *a.fresh_dst = 1;
