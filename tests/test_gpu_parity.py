@@ -282,6 +282,42 @@ def test_inner_update(dev, F, dtype):
     assert rel(Ud.cpu().numpy(), Ur) < max(tol, 1e-6)
 
 
+@pytest.mark.parametrize("F", [20, 64])
+@pytest.mark.parametrize("rho_frac", [1e-4, 1e-8])
+def test_inner_update_small_fixed_rho_near_singular(dev, F, rho_frac):
+    # The inner sweep multiplies by an explicit (G + rho I)^{-1}, formed by
+    # Gauss-Jordan without pivoting; the oracle solves with a Cholesky factor.
+    # With a fixed small rho and a nearly singular G (two columns of the
+    # factor equal up to 1e-6) the system's condition number reaches
+    # lambda_max / rho (1e6 to 1e10 here): both solutions then carry a forward
+    # error of order cond * eps, so they are compared within 64 F cond eps,
+    # and the device must not report a numeric failure.
+    import paper_1409_2383_amd as ntf
+    rng = np.random.default_rng(114 + F)
+    rows = 300
+    M = rng.random((F + 5, F))
+    M[:, 1] = M[:, 0] + 1e-6 * rng.standard_normal(F + 5)
+    G = M.T @ M
+    rho = rho_frac * np.trace(G) / F
+    ev = np.linalg.eigvalsh(G + rho * np.eye(F))
+    cond = ev[-1] / ev[0]
+    assert cond > 1e5
+    W = rng.standard_normal((rows, F)) * 3
+    H0 = rng.random((rows, F))
+    U0 = rng.random((rows, F)) * 0.1
+    Hd = torch.from_numpy(H0.copy()).to(dev)
+    Ud = torch.from_numpy(U0.copy()).to(dev)
+    ntf.inner_update(torch.from_numpy(W).to(dev), Hd, Ud, torch.from_numpy(G).to(dev), rho, 5)
+    Hr, Ur, _, _ = orc.inner_sweep(W, H0, U0, G, rho, 5)
+    tol = 64 * F * cond * np.finfo(np.float64).eps
+    eh = rel(Hd.cpu().numpy(), Hr)
+    eu = rel(Ud.cpu().numpy(), Ur)
+    print(f"[near-singular] F={F} rho/mean-diag={rho_frac:g} cond={cond:.3g} "
+          f"rel H {eh:.3g} U {eu:.3g} bound {tol:.3g}", flush=True)
+    assert np.isfinite(Hd.cpu().numpy()).all()
+    assert eh < tol and eu < tol
+
+
 def test_inner_update_early_stop_counts(dev):
     import paper_1409_2383_amd as ntf
     rng = np.random.default_rng(113)
