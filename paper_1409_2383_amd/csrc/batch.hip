@@ -60,7 +60,13 @@ size_t batch_lds_p3(const BProb& p) {
 // The batched kernel runs the inner sweep with one row per lane group
 // (256 / FL rows per block), which keeps its register budget within two
 // resident blocks per compute unit; latency is hidden by the other items.
-int batch_inner_rows(int FL) { return 256 / FL; }
+// At FL = 32 and 64 a lane group takes two rows (each LDS read of Ginv serves
+// both, and a block step loads Ginv for twice the rows): the sweep is bound by
+// LDS reads there (256-tensor batch 8.23 -> 7.87 ms per iteration with two
+// rows at FL = 64, 7.75 ms with two at FL = 32 as well).
+template <int FL>
+static constexpr int batch_inner_rpl() { return FL >= 32 ? 2 : 1; }
+int batch_inner_rows(int FL) { return (256 / FL) * (FL >= 32 ? 2 : 1); }
 size_t batch_lds_inner(int FL) {
   return (size_t)(FL * FL + 2 * batch_inner_rows(FL) * (FL + 1)) * sizeof(double);
 }
@@ -535,13 +541,13 @@ __device__ __forceinline__ void inner_item(const ConstProb& P, const BatchK& a, 
   k.resid_part = nullptr;
   k.flag = a.flag;
   k.dv = k.dx = k.dh0 = nullptr;
-  // ipi row blocks of 256 / FL rows; the barrier keeps one block's last LDS
+  // ipi row blocks of batch_inner_rows(FL) rows; the barrier keeps one block's last LDS
   // reads apart from the next block's first writes
   const int nb = (m == 0) ? P.n_in[0] : (m == 1) ? P.n_in[1] : P.n_in[2];
   const int b0 = idx * P.ipi, b1 = min(nb, b0 + P.ipi);
   for (int bid = b0; bid < b1; ++bid) {
     if (bid > b0) __syncthreads();
-    inner_body<float, FL, 1, 4, 1>(k, bid, lds, tid);
+    inner_body<float, FL, batch_inner_rpl<FL>(), 4, 1>(k, bid, lds, tid);
   }
 }
 
