@@ -105,7 +105,7 @@ static constexpr int inner_rows_per_block() { return (256 / FL) * inner_rpl<FL>(
 // partial to FP32 (-1: a.gram_f32 decides at run time).
 template <typename HT, int FL, int RPL = inner_rpl<FL>(), int CH = 8, int GF = -1>
 __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigned char* smem_raw,
-                                           const int tid) {
+                                           const int tid, const bool load_ginv = true) {
   constexpr int NG = 256 / FL;             // lane groups per block
   constexpr int RPB = NG * RPL;            // rows per block
   constexpr int BS = FL + 1;               // padded row stride of the exchange buffers
@@ -117,7 +117,9 @@ __device__ __forceinline__ void inner_body(const InnerK& a, int64_t bid, unsigne
   const int grp = tid / FL, f = tid - grp * FL;
   const int64_t row0 = bid * RPB;
 
-  {
+  // (a caller that runs several row blocks in turn with the same Ginv loads
+  // it for the first only: nothing below writes that LDS region)
+  if (load_ginv) {
     // all loads first, then the LDS writes (no serialised load-wait chain)
     constexpr int PER = (FL * FL + 255) / 256;
     double lv[PER];

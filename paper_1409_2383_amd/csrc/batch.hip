@@ -547,7 +547,7 @@ __device__ __forceinline__ void inner_item(const ConstProb& P, const BatchK& a, 
   const int b0 = idx * P.ipi, b1 = min(nb, b0 + P.ipi);
   for (int bid = b0; bid < b1; ++bid) {
     if (bid > b0) __syncthreads();
-    inner_body<float, FL, batch_inner_rpl<FL>(), 4, 1>(k, bid, lds, tid);
+    inner_body<float, FL, batch_inner_rpl<FL>(), 4, 1>(k, bid, lds, tid, bid == b0);
   }
 }
 
