@@ -42,7 +42,7 @@ struct BProb {
   int rpb;               // inner rows per row block
   int ipi;               // inner row blocks per item
   const __bf16* Xr;      // [I][J][Kp]  (k fastest, zero padded)
-  const __bf16* Xt;      // [I][K][Jp]  (j fastest, zero padded)
+  const __bf16* Xt;      // [I][Jp/8][K][8]  (eight consecutive j innermost, zero padded)
   const float* scale;    // [I] power-of-two slab scales
   float* H[3];
   float* U[3];

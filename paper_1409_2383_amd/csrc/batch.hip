@@ -302,15 +302,19 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
     const int nsteps = jw / 64;
     const int total = myrg * ns * nsteps;
 
-    // Loads through a buffer resource per slab, as in pass 1: rows k >= K and
-    // columns j >= Jp read as zeros, and past the wave's last step the cursor
-    // keeps re-reading its last (in-bounds) row group.
+    // Loads through a buffer resource per slab of the j-grouped copy
+    // Xg[i][Jp/8][K][8]: lane (n, g) reads the 8 values j = jj .. jj+7 (jj =
+    // step column + 8g) of row k as one 16-byte piece, and the 16 rows of a
+    // tile lie together, so a load instruction reads four runs of 256 bytes.
+    // Rows k >= K and columns j >= Jp take offsets with bit 31 set (past the
+    // resource: zeros), and past the wave's last step the cursor keeps
+    // re-reading its last (in-bounds) row group.
     int l_rgc = 0, l_sl = 0, l_kb = j0;
-    int l_off[MT];
+    int l_k[MT];
     auto set_rows = [&]() {
       const int rg = wave + 4 * l_rgc;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Jp + 8 * g) * 2;
+      for (int mt = 0; mt < MT; ++mt) l_k[mt] = rg * R + mt * 16 + n;
     };
     // Each step's loads also bring the slab's row of H1 (lane l: H1[i, l]) and
     // its scale, so the end of a slab takes its coefficients from registers
@@ -326,7 +330,9 @@ __device__ __forceinline__ void p3_item(const ConstProb& P, int idx, unsigned ch
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const int off = (l_kb + 8 * g + 32 * h < Jp) ? l_off[mt] + (l_kb + 32 * h) * 2 : kBufferOOB;
+          const int jj = l_kb + 32 * h + 8 * g;
+          const unsigned past = ((unsigned)(K - 1 - l_k[mt]) | (unsigned)(Jp - 1 - jj)) & 0x80000000u;
+          const int off = (int)(((unsigned)((jj >> 3) * K + l_k[mt]) * 16u) | past);
           dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
         }
       l_kb += 64;
@@ -785,8 +791,8 @@ hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s) {
 // ---------------------------------------------------------------- set-up
 
 // One block per slab: the power-of-two scale (max|X[i]|/s_i in [1,2)), the
-// k-fastest copy [J][Kp] and, through 32 x 32 LDS tiles, the j-fastest copy
-// [K][Jp]; padding is zero.
+// k-fastest copy [J][Kp] and, through 32 x 32 LDS tiles, the j-grouped copy
+// [Jp/8][K][8] (eight consecutive j innermost, then k); padding is zero.
 __global__ __launch_bounds__(256) void k_bquant(const float* __restrict__ X, int J, int K, int Kp,
                                                 int Jp, __bf16* __restrict__ Xr,
                                                 __bf16* __restrict__ Xt, float* __restrict__ scale) {
@@ -832,7 +838,7 @@ __global__ __launch_bounds__(256) void k_bquant(const float* __restrict__ X, int
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = k0 + tr + 8 * q, j = j0 + tc;
-        if (k < K) Xti[(int64_t)k * Jp + j] = (__bf16)tile[tc][tr + 8 * q];
+        if (k < K) Xti[((int64_t)(j >> 3) * K + k) * 8 + (j & 7)] = (__bf16)tile[tc][tr + 8 * q];
       }
     }
 }
