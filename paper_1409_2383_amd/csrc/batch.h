@@ -41,7 +41,7 @@ struct BProb {
   int ni[3];             // inner items per mode (ipi row blocks each)
   int rpb;               // inner rows per row block
   int ipi;               // inner row blocks per item
-  const __bf16* Xr;      // [I][J][Kp]  (k fastest, zero padded)
+  const __bf16* Xr;      // [I][Kp/8][J][8]  (eight consecutive k innermost, zero padded)
   const __bf16* Xt;      // [I][Jp/8][K][8]  (eight consecutive j innermost, zero padded)
   const float* scale;    // [I] power-of-two slab scales
   float* H[3];

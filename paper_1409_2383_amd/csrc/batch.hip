@@ -105,15 +105,21 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
   // and every path issues the same loads (the cursor stays on its last tile
   // past the wave's end and re-reads in-bounds data nothing consumes): the
   // wait before a step then covers that step's loads only.
+  // The copy is k-grouped, Xr[i][Kp/8][J][8] (eight consecutive k innermost,
+  // then j): lane (n, g) reads the 8 values k = kk .. kk+7 (kk = step column
+  // + 8g) of row j as one 16-byte piece and the 16 rows of a tile lie
+  // together, so a load instruction reads four runs of 256 bytes.  Rows
+  // j >= J and columns k >= Kp take offsets with bit 31 set (past the
+  // resource: zeros).
   int l_t = wave, l_kb = 0, l_sl = 0;
   const __bf16* l_slab = P.Xr;
-  int l_off[MT];
+  int l_j[MT];
   auto set_rows = [&](int t) {
     const int sl = t / nrg, rg = t - sl * nrg;
     l_sl = sl;
     l_slab = P.Xr + (int64_t)(s0 + sl) * J * Kp;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((rg * R + mt * 16 + n) * Kp + 8 * g) * 2;
+    for (int mt = 0; mt < MT; ++mt) l_j[mt] = rg * R + mt * 16 + n;
   };
   // each step's loads also bring its slab's scale (the tile epilogue then
   // reads it from a register instead of waiting on a load of its own)
@@ -127,7 +133,9 @@ __device__ __forceinline__ void p1_item(const ConstProb& P, int idx, unsigned ch
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        const int off = (l_kb + 8 * g + 32 * h < Kp) ? l_off[mt] + (l_kb + 32 * h) * 2 : kBufferOOB;
+        const int kk = l_kb + 32 * h + 8 * g;
+        const unsigned past = ((unsigned)(J - 1 - l_j[mt]) | (unsigned)(Kp - 1 - kk)) & 0x80000000u;
+        const int off = (int)(((unsigned)((kk >> 3) * J + l_j[mt]) * 16u) | past);
         dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
       }
     l_kb += 64;
@@ -791,7 +799,7 @@ hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s) {
 // ---------------------------------------------------------------- set-up
 
 // One block per slab: the power-of-two scale (max|X[i]|/s_i in [1,2)), the
-// k-fastest copy [J][Kp] and, through 32 x 32 LDS tiles, the j-grouped copy
+// k-grouped copy [Kp/8][J][8] and, through 32 x 32 LDS tiles, the j-grouped copy
 // [Jp/8][K][8] (eight consecutive j innermost, then k); padding is zero.
 __global__ __launch_bounds__(256) void k_bquant(const float* __restrict__ X, int J, int K, int Kp,
                                                 int Jp, __bf16* __restrict__ Xr,
@@ -822,7 +830,7 @@ __global__ __launch_bounds__(256) void k_bquant(const float* __restrict__ X, int
   __bf16* Xri = Xr + i * J * Kp;
   for (int64_t t = tid; t < (int64_t)J * Kp; t += 256) {
     const int64_t j = t / Kp, k = t - j * Kp;
-    Xri[t] = (__bf16)((k < K) ? Xi[j * K + k] * inv : 0.f);
+    Xri[((k >> 3) * J + j) * 8 + (k & 7)] = (__bf16)((k < K) ? Xi[j * K + k] * inv : 0.f);
   }
   __bf16* Xti = Xt + i * K * Jp;
   const int tr = tid >> 5, tc = tid & 31;
