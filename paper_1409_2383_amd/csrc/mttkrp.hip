@@ -41,8 +41,11 @@ static constexpr int kPass1Waves() { return FT <= 2 ? 4 : 2; }
 
 // bfloat16 copies of X with a power-of-two scale per mode-1 slab:
 //   s_i = 2^(e-1) where max|X[i]| = m * 2^e, m in [0.5, 1)  (so max|X[i]|/s_i in [1,2));
-//   Xr  [I][J][Kp]      row-major, k padded with zeros to Kp (multiple of 32);
+//   Xr  [I][Kp/8][J][8] groups of 8 consecutive k innermost, then j, k padded
+//                       with zeros to Kp (multiple of 32);
 //   Xj8 [I][JG][Kp3][8] groups of 8 consecutive j interleaved innermost, zero padded.
+// (A wave's 16 rows of one 8-column group are 256 contiguous bytes in either
+// copy, so a pass-1 or pass-3 load instruction reads four such runs.)
 __global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ X, int64_t J, int64_t K,
                                                   int64_t Kp, int64_t JG, int64_t Kp3,
                                                   __bf16* __restrict__ Xr, __bf16* __restrict__ Xj8,
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ X, i
   for (int64_t t = threadIdx.x; t < J * Kp; t += 256) {
     const int64_t j = t / Kp, k = t - j * Kp;
     const float v = (k < K) ? Xi[j * K + k] * inv : 0.f;
-    Xri[t] = (__bf16)v;
+    Xri[((k >> 3) * J + j) * 8 + (k & 7)] = (__bf16)v;
   }
   __bf16* Xji = Xj8 + i * JG * Kp3 * 8;
   for (int64_t t = threadIdx.x; t < JG * Kp3 * 8; t += 256) {
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(256) void k_quantize4(const float* __restrict__ X, 
           if (j < J) {
             bf16x4 o = {(__bf16)(v[e].x * inv), (__bf16)(v[e].y * inv), (__bf16)(v[e].z * inv),
                         (__bf16)(v[e].w * inv)};
-            *reinterpret_cast<bf16x4*>(Xri + (int64_t)j * Kp + 4 * c4) = o;
+            *reinterpret_cast<bf16x4*>(Xri + ((int64_t)(c4 >> 1) * J + j) * 8 + 4 * (c4 & 1)) = o;
           }
         }
       }
@@ -336,10 +339,10 @@ __global__ __launch_bounds__(512) void k_pass1(const T* __restrict__ X, int I, i
   }
 }
 
-// BF16: X from the row-major bfloat16 copy (Kp a multiple of 32, zero
+// BF16: X from the k-grouped bfloat16 copy (Kp a multiple of 32, zero
 // padded); C transposed in LDS as bf16 [FP][KC+8].  A super step covers 64 k:
-// lane (n,g) loads 32 contiguous bytes of its row (k = kb+16g .. kb+16g+15,
-// so every wave load covers whole 128-byte lines) and feeds them to two MFMAs,
+// lane (n,g) loads columns k = kb+16g .. kb+16g+15 of its row (two 16-byte
+// pieces, one from each of two 8-column groups) and feeds them to two MFMAs,
 // h = 0, 1, whose contraction slot of lane group g holds k = kb+16g+8h+e; the
 // matching B operands are one 32-byte LDS read per rank tile.  The slab scale
 // s_i is applied to the FP32 accumulator in the epilogue (exact).
@@ -386,13 +389,14 @@ __global__ __launch_bounds__(512) void k_pass1_bf16(const __bf16* __restrict__ X
         __syncthreads();
       }
       if (!has) continue;
+      // (row j's 8-column group q of slab i starts at Xr + ((i Kp/8 + q) J + j) 8)
       const __bf16* xrow[MT];
       bool rowok[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const int j = j0 + mt * 16 + n;
         rowok[mt] = j < J;
-        xrow[mt] = Xr + ((int64_t)i * J + (rowok[mt] ? j : 0)) * Kp + 16 * g;
+        xrow[mt] = Xr + ((int64_t)i * (Kp / 8) * J + (rowok[mt] ? j : 0)) * 8;
       }
       bf16x8 xv[U][2][MT];
       auto load_step = [&](int kb, bf16x8 (&dst)[2][MT]) {
@@ -401,7 +405,8 @@ __global__ __launch_bounds__(512) void k_pass1_bf16(const __bf16* __restrict__ X
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
             if (rowok[mt] && kb + 16 * g + 8 * h < kend) {
-              dst[h][mt] = *reinterpret_cast<const bf16x8*>(xrow[mt] + kb + 8 * h);
+              const int q = (kb + 16 * g + 8 * h) >> 3;
+              dst[h][mt] = *reinterpret_cast<const bf16x8*>(xrow[mt] + (int64_t)q * J * 8);
             } else {
 #pragma unroll
               for (int e = 0; e < 8; ++e) dst[h][mt][e] = (__bf16)0.f;
@@ -468,10 +473,12 @@ __global__ __launch_bounds__(512) void k_pass1_bf16(const __bf16* __restrict__ X
 // the run go through a per-slab buffer resource at lane offsets fixed for the
 // run.  The wave walks (slab, 64-k super step) as one continuous sequence with
 // U steps of loads in flight; every step issues the same loads (rows j >= J
-// lie past the slab, columns past Kp in the last super step get kBufferOOB),
+// and columns past Kp in the last super step get offsets past the resource),
 // so the wait before a step covers that step only.  The two MFMAs of a super
-// step contract its columns 0-31 and 32-63, so each load instruction reads 64
-// contiguous bytes of 16 rows (lane group g: columns 8g .. 8g+7 of a half).  The epilogue of a slab
+// step contract its columns 0-31 and 32-63 (lane group g: columns 8g .. 8g+7
+// of a half), so with the k-grouped copy each load instruction reads four
+// runs of 256 bytes, the 16 rows of four 8-column groups (with the row-major
+// copy it read 64-byte pieces of 16 rows: 0.277 -> 0.267 ms).  The epilogue of a slab
 // (T rows and the W1 partial of (i, ch)) stores through resources at offsets
 // that drop rows past J, columns past F and the lanes that hold no partial.
 // TS (F a multiple of 4, LDS to spare): the T rows of a slab go through a
@@ -555,10 +562,18 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
               float, __builtin_amdgcn_raw_buffer_load_b32(
                          hrs, (int)((unsigned)trow(mt, ii) + (unsigned)fo[ft]), 0, 0));
 
-    // load cursor: (slab l_sl of the run, super step at column l_kb)
+    // load cursor: (slab l_sl of the run, super step at column l_kb); lane
+    // (n, g) reads the 8 columns kk = l_kb + 32h + 8g .. of its row as one
+    // 16-byte piece of the k-grouped copy; rows past J and columns past Kp
+    // take offsets with bit 31 set (past the resource: zeros)
     int l_off[MT];
+    unsigned l_past[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) l_off[mt] = ((ch * R + mt * 16 + n) * Kp + 8 * g) * 2;
+    for (int mt = 0; mt < MT; ++mt) {
+      const int j = ch * R + mt * 16 + n;
+      l_off[mt] = (g * J + j) * 16;
+      l_past[mt] = (unsigned)(J - 1 - j) & 0x80000000u;
+    }
     int l_sl = 0, l_kb = 0;
     bf16x8 xv[U][2][MT];
     auto load_next = [&](bf16x8 (&dst)[2][MT]) {
@@ -568,9 +583,9 @@ __global__ __launch_bounds__(512, kPass1Waves<FT>()) void k_pass1_bf16s(const __
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          int off = l_off[mt] + (l_kb + 32 * h) * 2;
+          unsigned off = ((unsigned)l_off[mt] + (unsigned)(((l_kb + 32 * h) >> 3) * J * 16)) | l_past[mt];
           if (tail && l_kb + 8 * g + 32 * h >= Kp) off = kBufferOOB;
-          dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(l_rs, off, 0, 0));
+          dst[h][mt] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(l_rs, (int)off, 0, 0));
         }
       l_kb += 64;
       const bool wrap = l_kb >= Kp;
