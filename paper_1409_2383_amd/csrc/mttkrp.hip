@@ -87,13 +87,13 @@ __global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ X, i
   }
 }
 
-// The same copies and scales for K a multiple of 4, one slab per block: the
-// slab's maximum from 16-byte loads, then one pass in which 32 lanes walk the
-// 4-column groups of 8 consecutive rows j (16-byte loads of each row): every
-// value is read once more and written to both copies, Xr with 8-byte stores
-// (4 columns of a row), Xj8 with 16-byte stores (the 8 rows of one column).
-// The bfloat16 values are those of k_quantize (round to nearest even of
-// X * (1/s), the same FP32 product).
+// The same scales and the j-grouped copy for K a multiple of 4, one slab per
+// block: the slab's maximum from 16-byte loads, then one pass in which 32
+// lanes walk the 4-column groups of 8 consecutive rows j (16-byte loads of
+// each row): every value is read once more and written to Xj8 with 16-byte
+// stores (the 8 rows of one column).  k_xr_from_xj8 then forms the k-grouped
+// copy from it.  The bfloat16 values are those of k_quantize (round to
+// nearest even of X * (1/s), the same FP32 product).
 __global__ __launch_bounds__(256) void k_quantize4(const float* __restrict__ X, int J, int K, int Kp,
                                                    int JG, int Kp3, __bf16* __restrict__ Xr,
                                                    __bf16* __restrict__ Xj8,
@@ -133,8 +133,7 @@ __global__ __launch_bounds__(256) void k_quantize4(const float* __restrict__ X, 
   if (threadIdx.x == 0) scale[i] = s;
   const float inv = 1.f / s;  // exact: s is a power of two
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int K4 = K / 4, C4 = max(Kp, Kp3) / 4;
-  __bf16* Xri = Xr + i * (int64_t)J * Kp;
+  const int K4 = K / 4, C4 = Kp3 / 4;
   __bf16* Xji = Xj8 + i * (int64_t)JG * Kp3 * 8;
   for (int jg = ty; jg < JG; jg += 8) {
     for (int c4 = tx; c4 < C4; c4 += 32) {
@@ -143,17 +142,6 @@ __global__ __launch_bounds__(256) void k_quantize4(const float* __restrict__ X, 
       for (int e = 0; e < 8; ++e) {
         const int j = 8 * jg + e;
         v[e] = (j < J && c4 < K4) ? Xi4[(int64_t)j * K4 + c4] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-      if (4 * c4 < Kp) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int j = 8 * jg + e;
-          if (j < J) {
-            bf16x4 o = {(__bf16)(v[e].x * inv), (__bf16)(v[e].y * inv), (__bf16)(v[e].z * inv),
-                        (__bf16)(v[e].w * inv)};
-            *reinterpret_cast<bf16x4*>(Xri + ((int64_t)(c4 >> 1) * J + j) * 8 + 4 * (c4 & 1)) = o;
-          }
-        }
       }
       if (4 * c4 < Kp3) {
         bf16x8 o[4];
@@ -1517,11 +1505,50 @@ bool make_plan(Plan& p, int prec, const int64_t dims[3], int F, int cu_count) {
   return true;
 }
 
+// The k-grouped copy Xr[i][Kp/8][J][8] from the j-grouped one
+// Xj8[i][JG][Kp3][8]: both hold an 8 x 8 block (rows 8jg .. 8jg+7, columns
+// 8q .. 8q+7) as 128 contiguous bytes, transposed.  A group of 8 lanes takes
+// one block: lane l reads column 8q + l (16 bytes), the block goes through
+// LDS, and lane e writes row 8jg + e; blocks are numbered ((i, q), jg) with
+// jg fastest, so the 32 groups of a workgroup write 4 KB of one plane q in
+// order.  Columns past Kp3 are zeros, rows past J are not stored.
+__global__ __launch_bounds__(256) void k_xr_from_xj8(const __bf16* __restrict__ Xj8, int J, int JG,
+                                                     int Kp, int Kp3, int64_t nblocks,
+                                                     __bf16* __restrict__ Xr) {
+  __shared__ bf16x8 tile[32][8];
+  const int grp = threadIdx.x >> 3, l = threadIdx.x & 7;
+  const int64_t t = (int64_t)blockIdx.x * 32 + grp;
+  const bool ok = t < nblocks;
+  const int NQ = Kp / 8;
+  const int64_t iq = ok ? t / JG : 0;                  // slab * NQ + q
+  const int jg = ok ? (int)(t - iq * JG) : 0;
+  const int64_t slab = iq / NQ;
+  const int q = (int)(iq - slab * NQ);
+  const bf16x8 z = {};
+  const int k = 8 * q + l;
+  tile[grp][l] = (ok && k < Kp3)
+                     ? *reinterpret_cast<const bf16x8*>(Xj8 + ((slab * JG + jg) * (int64_t)Kp3 + k) * 8)
+                     : z;
+  __syncthreads();
+  const int j = 8 * jg + l;
+  if (ok && j < J) {
+    bf16x8 o;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) o[r] = tile[grp][r][l];
+    *reinterpret_cast<bf16x8*>(Xr + (iq * (int64_t)J + j) * 8) = o;
+  }
+}
+
 hipError_t launch_quantize(const float* X, const Plan& p, __bf16* Xr, __bf16* Xj8, float* scale,
                            hipStream_t s) {
   if (p.K % 4 == 0 && p.J * p.K < (int64_t)1 << 31 && p.Kp % 4 == 0 && p.Kp3 % 4 == 0) {
     hipLaunchKernelGGL(k_quantize4, dim3((unsigned)p.I), dim3(256), 0, s, X, (int)p.J, (int)p.K,
                        (int)p.Kp, (int)p.JG, (int)p.Kp3, Xr, Xj8, scale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nb = p.I * p.JG * (p.Kp / 8);   // 8 x 8 blocks, 32 per workgroup
+    hipLaunchKernelGGL(k_xr_from_xj8, dim3((unsigned)cdiv(nb, 32)), dim3(256), 0, s, Xj8, (int)p.J,
+                       (int)p.JG, (int)p.Kp, (int)p.Kp3, nb, Xr);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_quantize, dim3((unsigned)p.I), dim3(256), 0, s, X, p.J, p.K, p.Kp, p.JG,
