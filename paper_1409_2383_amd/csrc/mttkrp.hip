@@ -164,14 +164,28 @@ __global__ __launch_bounds__(256) void k_quantize4(const float* __restrict__ X, 
 template <typename XT>
 __global__ __launch_bounds__(256) void k_sumsq_part(const XT* __restrict__ X, int64_t n,
                                                     double* __restrict__ part) {
-  double acc = 0.0;
+  // eight interleaved sums per thread (eight loads in flight; one sum had
+  // each load wait for the previous add), added in a fixed order
+  constexpr int V = 8;
+  double acc[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) acc[q] = 0.0;
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += stride) {
-    const double v = (double)X[t];
-    acc += v * v;
+  int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; t + (V - 1) * stride < n; t += V * stride) {
+    double v[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) v[q] = (double)X[t + q * stride];
+#pragma unroll
+    for (int q = 0; q < V; ++q) acc[q] += v[q] * v[q];
   }
+  for (; t < n; t += stride) {
+    const double v = (double)X[t];
+    acc[0] += v * v;
+  }
+  const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __shared__ double red[256];
-  red[threadIdx.x] = acc;
+  red[threadIdx.x] = a;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -180,13 +194,14 @@ __global__ __launch_bounds__(256) void k_sumsq_part(const XT* __restrict__ X, in
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// (lane l sums partials l, l + 64, .. in order, then the lanes' sums are
+// added by a fixed butterfly; one lane walking all partials took 60 us)
 __global__ __launch_bounds__(64) void k_sum_parts(const double* __restrict__ part, int nparts,
                                                   double* __restrict__ out) {
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += part[p];
-    *out = s;
-  }
+  double s = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += 64) s += part[p];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0) *out = s;
 }
 
 // ---------------------------------------------------------------- pass 1
