@@ -220,6 +220,14 @@ def time_to_target(torch, ntf, Xd, H0, T, arms, dev, star, max_outer=400, tol=1e
         Ub = [torch.zeros_like(h) for h in Hb]
         wsb = torch.empty(ws_bytes[arm], dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
+        # (untimed: about 5 ms of device work queued right before the clock
+        # starts, so the arm's set-up does not start on a GPU that went idle
+        # during the host-side allocations; one run had its first ten steps
+        # at twice the usual time without it)
+        spin = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        for _ in range(80):
+            spin.mul_(1.0000001)
+        del spin
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
         solver, H = make_solver(ntf, torch, Xd, H0, base, T, dev,
