@@ -26,7 +26,7 @@ namespace {
 constexpr int kMaxSpi1 = 16;          // pass-1 slabs per item (LDS for the W1 partials)
 constexpr int64_t kDefaultElems1 = 256 * 1024;
 constexpr int64_t kDefaultElems3 = 1024 * 1024;
-constexpr int kInnerRowsPerItem = 32;   // rows of one inner-sweep work item (at least one block)
+constexpr int kInnerRowsPerItem = 64;   // rows of one inner-sweep work item (at least one block; 32 measured 0.6% slower)
 constexpr long long kSpinLimit = 1ll << 22;   // polls (>= 50 ns each) before a wait gives up
 constexpr size_t kLdsMax = 156 * 1024;   // dynamic LDS; the kernel also has ~2 KB static
 
