@@ -41,7 +41,10 @@ def _solver(pt, H0, dev, opts):
 SHAPES_F64 = [((40, 40, 40), 5), ((37, 70, 45), 20), ((5, 3, 130), 33), ((17, 1, 9), 1),
               ((66, 64, 65), 64), ((130, 9, 4), 7)]
 SHAPES_F32 = [((37, 70, 45), 20), ((50, 130, 64), 17), ((23, 40, 61), 64), ((9, 13, 7), 3),
-              ((70, 200, 100), 48)]
+              ((70, 200, 100), 48), ((20, 30, 150), 24), ((11, 17, 202), 40), ((12, 25, 90), 16)]
+# (the last three: pass 3 with three and four 64-column k tiles, whose eight
+# waves split the rows into two groups, and rows of an even length that is not
+# a multiple of four, read in 8-byte pieces)
 # (the last three: H2^T staged in two chunks of j at F = 64 and F = 40, and
 # three 64-row tiles of k with a ragged tail)
 SHAPES_BF16 = [((37, 70, 45), 20), ((33, 90, 100), 64), ((9, 13, 7), 3), ((20, 64, 96), 32),
