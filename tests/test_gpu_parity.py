@@ -48,7 +48,8 @@ SHAPES_F32 = [((37, 70, 45), 20), ((50, 130, 64), 17), ((23, 40, 61), 64), ((9, 
 # (the last three: H2^T staged in two chunks of j at F = 64 and F = 40, and
 # three 64-row tiles of k with a ragged tail)
 SHAPES_BF16 = [((37, 70, 45), 20), ((33, 90, 100), 64), ((9, 13, 7), 3), ((20, 64, 96), 32),
-               ((3, 1500, 70), 64), ((5, 2700, 19), 40), ((40, 33, 130), 8)]
+               ((3, 1500, 70), 64), ((5, 2700, 19), 40), ((40, 33, 130), 8), ((4, 40, 1400), 64)]
+# (the last: H3^T too long for LDS at F = 64, so pass 1 takes its chunked form)
 
 
 @pytest.mark.parametrize("dims,F", SHAPES_F64)
