@@ -104,8 +104,12 @@ def test_nway_fp32_run_tracks_the_oracle(dev):
     st = orc.init_state([h.astype(np.float64) for h in H0])
     orc.run(X.astype(np.float64), st, orc.Opts(inner_iters=5), 40)
     r_orc = orc.rfe(X.astype(np.float64), st.H)
-    print(f"[nway] fp32 4-way 40 iterations: RFE gpu {r_gpu:.6f} oracle {r_orc:.6f}", flush=True)
-    assert abs(r_gpu - r_orc) < 1e-4 * r_orc
+    print(f"[nway] fp32 4-way 40 iterations: RFE gpu {r_gpu:.10f} oracle {r_orc:.10f} "
+          f"rel gap {abs(r_gpu - r_orc) / r_orc:.3e}", flush=True)
+    # FP32 target 1e-6 relative on the fit (measured gap about 1e-9; the
+    # oracle itself moves by about 1e-10 when its start is moved by one
+    # float32 rounding, so the run is not chaotic at this length)
+    assert abs(r_gpu - r_orc) < 1e-6 * r_orc
     s.close()
 
 
